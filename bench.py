@@ -1,0 +1,198 @@
+"""Throughput benchmark of the CoNet-Rx forward pass on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bf16_b64_f3276] [--dtype bf16]
+                    [--no-cpu] [--json-out PATH]
+
+A step is one forward pass of the whole network (input layer, L residual blocks per
+branch with product fusion + LayerNorm, LLR head) over one batch of synthetic slots
+that is already resident in HBM. Default workload: 64 slots of 3276 subcarriers x 14
+OFDM symbols, 4 rx (16 input channels), 16-QAM, K=3 branches x L=4 blocks x C=64
+channels, BF16 operands with FP32 accumulation.
+
+Prints one JSON line. `value` is LLR REs per second. `roofline` covers the dominant
+kernel (per-launch algorithmic MFMA FLOPs / its mean HIP-event duration over the
+timed steps). `cpu_baseline` times the FP64 oracle on a bounded sample of slots on the
+host cores and also reports the LLR error of the GPU result on those slots.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LLR REs/sec (BF16/FP8 vs FP32) at stated LLR err; p99 slot latency"
+PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "f32": 157.3}
+HBM_PEAK_GBS = 8000.0
+LLR_TOL = {"bf16": "rel-L2 <= 3e-2 vs FP64, sign agreement >= 0.99",
+           "fp8": "rel-L2 <= 0.15 vs FP64, sign agreement >= 0.97",
+           "f32": "rel-L2 <= 1e-5 vs FP64"}
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources; a stored HBM-traffic measurement is valid only for it."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2510_12739_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def flops_per_re(K, L, C, C_in, m):
+    return 2 * 9 * C_in * K * C + K * L * 2 * (2 * 9 * C * C) + 2 * C * m
+
+
+def cpu_baseline(workload, blob, X_sample, llr_gpu_sample, budget_s=15.0, max_slots=8):
+    """Time the FP64 oracle on whole slots until the budget is spent (at least one slot)."""
+    from oracle import conet64 as o
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    mc = workload.model
+    p = o.unpack(blob, mc.K, mc.L, mc.C, mc.C_in, mc.m)
+    t0 = time.perf_counter()
+    n, res, outs = 0, 0, []
+    while n < min(max_slots, X_sample.shape[0]):
+        outs.append(o.forward(p, X_sample[n:n + 1].astype(np.float64)))
+        res += X_sample.shape[1] * X_sample.shape[2]
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    ref = np.concatenate(outs)
+    got = llr_gpu_sample[:n].astype(np.float64)
+    err = {"rel_l2_vs_fp64": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+           "sign_agreement": float(np.mean((got > 0) == (ref > 0))),
+           "slots": n}
+    return {"value": res / dt, "unit": "REs/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n} whole slot(s) of {X_sample.shape[1]}x{X_sample.shape[2]} REs, FP64 NumPy "
+                      f"(im2col + BLAS), {dt:.1f} s"}, err
+
+
+def load_traffic(kernel: str, workload: str, dtype: str):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(f"{workload}/{dtype}/{kernel}")
+    except Exception:
+        return None
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="bf16_b64_f3276")
+    ap.add_argument("--dtype", default=None, help="override the workload's dtype (f32, bf16, fp8)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--json-out", default=None)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (slots shard across GPUs "
+              "with no exchange; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_12739_amd import Conet
+    from synth import features_fast, make_blob, workload
+
+    w = workload(args.workload)
+    dtype = args.dtype or w.dtype
+    mc = w.model
+    B, T, F = w.batch, w.sim.T, w.sim.F
+    res = B * T * F
+    print(f"[bench] workload {w.name} dtype {dtype}: B={B} T={T} F={F} K={mc.K} L={mc.L} C={mc.C} "
+          f"C_in={mc.C_in} m={mc.m}", file=sys.stderr, flush=True)
+    blob = make_blob(mc, seed=w.weight_seed)
+    X = features_fast(w.sim, B, n_distinct=min(8, B))
+    x = torch.from_numpy(X).cuda()
+    model = Conet(mc.K, mc.L, mc.C, mc.C_in, mc.m, blob, dtype=dtype, max_res=res)
+    if dtype == "fp8":
+        model.calibrate(x[:min(4, B)])
+    out = torch.empty((B, T, F, mc.m), dtype=torch.float32, device="cuda")
+
+    for _ in range(args.warmup):
+        model.forward(x, out=out)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    # ---- timed region: K steps; each records a HIP event before every kernel launch
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stage_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        _, ms = model.forward_profiled(x, out=out)
+        stage_ms.append(ms)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    ms_per_step = ms_total / args.steps
+    stage_ms = np.array(stage_ms)                          # [steps, 1 + 2L]
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall:.2f} s)", file=sys.stderr, flush=True)
+
+    # ---- roofline of the dominant kernel (block convs: stage 1 + 2l is conv 1, 2 + 2l conv 2)
+    L = mc.L
+    conv1 = stage_ms[:, 1::2]
+    conv2 = stage_ms[:, 2::2]
+    fl_launch = mc.K * res * 2 * 9 * mc.C * mc.C       # algorithmic MFMA FLOPs of one block conv launch
+    kinds = {"block_conv1": conv1, "block_conv2_fused": conv2}
+    dom = max(kinds, key=lambda k: kinds[k].sum())
+    dom_ms = float(kinds[dom].mean())
+    achieved = fl_launch / (dom_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[dtype]
+    traffic = load_traffic(dom, w.name, dtype)
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": traffic,
+                "flops_per_launch": fl_launch, "mean_launch_ms": round(dom_ms, 4),
+                "stage_mean_ms": [round(float(v), 4) for v in stage_ms.mean(axis=0)],
+                "whole_step_tflops": round(flops_per_re(mc.K, mc.L, mc.C, mc.C_in, mc.m) * res / (ms_per_step * 1e-3) / 1e12, 2)}
+
+    result = {"metric": METRIC, "value": round(res / (ms_per_step * 1e-3), 1), "unit": "REs/s",
+              "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+              "data": "synthetic (seeded OFDM simulator: Rayleigh + Jakes channel, AWGN, LS features; He-normal weights)",
+              "config": {"workload": w.name, "slots": B, "T": T, "F": F, "n_rx": w.sim.n_rx, "K": mc.K, "L": mc.L,
+                         "C": mc.C, "C_in": mc.C_in, "m": mc.m, "res_per_step": res, "parallelism": "single-gpu"},
+              "llr_tolerance": LLR_TOL[dtype],
+              "roofline": roofline}
+
+    if not args.no_cpu:
+        n_s = min(8, B)
+        llr_s = out[:n_s].cpu().numpy()
+        cb, err = cpu_baseline(w, blob, X[:n_s], llr_s, budget_s=args.cpu_budget)
+        result["cpu_baseline"] = cb
+        result["llr_err"] = err
+    else:
+        result["cpu_baseline"] = None
+
+    line = json.dumps(result)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()

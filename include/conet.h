@@ -1,0 +1,142 @@
+/* conet.h — C ABI of the CoNet-Rx receiver library for AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper, Sec. II, the problem statement after Eq. (1)): given the
+ * received grid of all OFDM symbols and subcarriers of one slot, return a soft bit
+ * (LLR) for every bit of every resource element (RE). The network is the
+ * collaborative receiver of Sec. III: K branches (k = 0 is the main net, the others
+ * are support nets) each read the whole grid through a 3x3 conv + ReLU input layer,
+ * then L pre-activation residual blocks (Sec. II-A, Fig. 1; the main net's block
+ * after a fusion is the modified block of Fig. 3, without its leading
+ * normalisation); after block l, if bit l-1 of fuse_mask is set, the block outputs
+ * of all branches are multiplied element-wise and normalised per RE over the C
+ * channels (LayerNorm) before entering the main net (Sec. III, and its extension to
+ * M support nets); a 1x1 conv with one filter per bit of the symbol gives the LLRs
+ * (Sec. III, output layer).
+ *
+ * Conventions
+ *   - Tensors are channels-last: x[b][t][f][c] with t the OFDM symbol (T <= 14) and f
+ *     the subcarrier; RE index = (b*T + t)*F + f.
+ *   - Input features (Sec. II-A: Re/Im of the received grid; here also of the LS
+ *     channel estimate): C_in = 4*N_rx channels, antenna-major
+ *     (Re y_n, Im y_n, Re H_n, Im H_n), FP32.
+ *   - LLR output: llr[b][t][f][j], FP32, j < bits_per_symbol, LLR = ln P(b=1)/P(b=0).
+ *   - Pointers named *_host are host memory; every other tensor pointer is DEVICE
+ *     memory of the GPU that was current when the model was created.
+ *   - `stream` is a hipStream_t passed as void* (0 = the null stream). Calls that take
+ *     a stream only enqueue work; buffers must stay valid until that work completes.
+ *   - Every call returns a conet_status and never throws or aborts. On failure,
+ *     conet_last_error() returns a message for the calling thread.
+ *   - A model is used from one stream at a time; calls on one model must not overlap.
+ */
+#ifndef CONET_H
+#define CONET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CONET_OK = 0,
+  CONET_EINVAL = 1,   /* bad argument (null pointer, unsupported configuration) */
+  CONET_ESHAPE = 2,   /* tensor shape outside what the model was created for */
+  CONET_ENOMEM = 3,   /* workspace too small */
+  CONET_EDEVICE = 4,  /* a HIP call failed; the HIP error string is in conet_last_error() */
+  CONET_EBUSY = 5,    /* serving queue full */
+  CONET_ETIMEOUT = 6, /* serving wait timed out */
+  CONET_ESTATE = 7    /* call out of order (e.g. backward without a saved forward) */
+} conet_status;
+
+typedef enum {
+  CONET_FP32 = 0,     /* FP32 MFMA operands and activations */
+  CONET_BF16 = 1,     /* BF16 operands and activations, FP32 accumulation and epilogues */
+  CONET_FP8E4M3 = 2,  /* OCP e4m3 conv operands (per-output-channel filter scales, static
+                         per-tensor activation scales), BF16 residual stream, FP32 accumulation */
+  CONET_FP64 = 3      /* reserved */
+} conet_dtype;
+
+typedef struct {
+  int32_t branches;        /* K, 1..8; branch 0 is the main net                           */
+  int32_t blocks;          /* L >= 1 residual blocks per branch                           */
+  int32_t channels;        /* C: 16, 32, 64 or 96                                          */
+  int32_t in_channels;     /* C_in = 4 N_rx: 8, 16 or 32                                   */
+  int32_t bits_per_symbol; /* m, head width, 1..8                                          */
+  uint32_t fuse_mask;      /* bit l-1 => product fusion + LayerNorm after block l          */
+  float ln_eps;            /* LayerNorm epsilon (1e-5)                                     */
+  int32_t dtype;           /* conet_dtype                                                  */
+  int32_t train;           /* reserved, must be 0                                          */
+  int64_t max_res;         /* largest B*T*F one call may pass                              */
+} conet_config;
+
+typedef struct conet_model conet_model;
+
+/* Number of FP32 values in the packed parameter blob. Blob order (all FP32):
+ *   for k in 0..K-1: W_in[C][C_in][3][3], b_in[C],
+ *                    for l in 1..L: s0[C], o0[C], W1[C][C][3][3], b1[C], s1[C], o1[C],
+ *                                   W2[C][C][3][3], b2[C]
+ *   for l in 1..L: gamma[C], beta[C]
+ *   W_h[m][C], b_h[m]
+ * Filters are indexed [out][in][dt+1][df+1] and correlate: out(t,f) reads in(t+dt, f+df).
+ * s0/o0 and s1/o1 are the per-channel affines in front of the block's ReLUs (inference
+ * form of its normalisations); s0/o0 are ignored in a main-net block after a fusion.
+ * Returns 0 for an invalid configuration. */
+size_t conet_weight_count(const conet_config* cfg);
+
+/* Device bytes the caller must provide to conet_create (0 for an invalid config). */
+size_t conet_workspace_bytes(const conet_config* cfg);
+
+/* Build a model: validates cfg, packs the blob into the kernels' fragment layout and
+ * copies it into `workspace` (device memory, >= conet_workspace_bytes(cfg), 256-byte
+ * aligned, owned by the caller and kept alive until conet_destroy). Synchronous.
+ * Errors: EINVAL (config, null pointers, n_weights mismatch), ENOMEM (workspace too
+ * small), EDEVICE. */
+conet_status conet_create(const conet_config* cfg, const float* weights_host, size_t n_weights,
+                          void* workspace, size_t workspace_bytes, conet_model** out);
+
+/* FP8 only: set the static activation scales s_a (one per conv input operand,
+ * n = 1 + 2*K*L: index 0 the input layer, then 1 + 2*(k*L + l-1) + {0: first conv of
+ * block l of branch k, 1: its second conv}). Operands are quantised as e4m3(a / s_a).
+ * Errors: EINVAL (wrong n, non-positive scale, not an FP8 model). */
+conet_status conet_set_act_scales(conet_model* model, const float* scales_host, size_t n);
+
+/* FP8 only: derive the activation scales from a calibration batch x (device, FP32,
+ * [B][T][F][C_in]): each conv's scale is max|operand| / 448 over the batch, taken in
+ * network order on the quantised forward. Synchronises the stream. */
+conet_status conet_calibrate(conet_model* model, const float* x, int32_t B, int32_t T, int32_t F, void* stream);
+
+/* Copy the current activation scales to host (n = 1 + 2*K*L). */
+conet_status conet_get_act_scales(conet_model* model, float* scales_host, size_t n);
+
+/* Forward pass: x (device, FP32 [B][T][F][C_in]) -> llr (device, FP32 [B][T][F][m]).
+ * Every slot is padded with zeros at its own grid edges (no mixing between slots).
+ * B == 0 is a no-op. Errors: EINVAL (null pointers), ESHAPE (T > 14, T < 1, F < 1,
+ * B*T*F > max_res), EDEVICE. `save_for_backward` is reserved and must be 0. */
+conet_status conet_forward(conet_model* model, const float* x, int32_t B, int32_t T, int32_t F, float* llr,
+                           int32_t save_for_backward, void* stream);
+
+/* Forward pass over slots of different widths packed back to back: slot s has
+ * T x F_host[s] REs starting at RE offset sum_{s'<s} T*F_host[s'] in x and llr.
+ * Slots never share halos. Errors as conet_forward (sum T*F <= max_res). */
+conet_status conet_forward_ragged(conet_model* model, const float* x, int32_t n_slots, int32_t T,
+                                  const int32_t* F_host, float* llr, void* stream);
+
+/* conet_forward on a uniform batch with a HIP event recorded on `stream` before every
+ * kernel launch and after the last: stage_ms_host[i] (n_stages = 1 + 2L entries) gets
+ * the elapsed time of stage i (input layer, then per block its first and second conv).
+ * Synchronises on the last event. Errors as conet_forward. */
+conet_status conet_forward_profiled(conet_model* model, const float* x, int32_t B, int32_t T, int32_t F, float* llr,
+                                    float* stage_ms_host, int32_t n_stages, void* stream);
+
+/* Release the model (the caller frees the workspace afterwards). Synchronous. */
+conet_status conet_destroy(conet_model* model);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* conet_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CONET_H */

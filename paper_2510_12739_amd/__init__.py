@@ -1,0 +1,5 @@
+"""CoNet-Rx on AMD Instinct MI355X: gfx950 HIP kernels behind a C ABI (libconet.so).
+
+The Python layer only marshals arguments; see binding.Conet.
+"""
+from .binding import Conet, ConetError, load, make_config, weight_count, workspace_bytes, EXPORTS

@@ -1,0 +1,197 @@
+"""ctypes binding of libconet.so: argument marshalling only.
+
+PyTorch supplies device memory (the model workspace, inputs and outputs) and the
+stream; every step of the receiver runs in the library's HIP kernels. There is no
+fallback: if the library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libconet.so")
+
+CONET_FP32, CONET_BF16, CONET_FP8E4M3 = 0, 1, 2
+DTYPES = {"f32": CONET_FP32, "fp32": CONET_FP32, "bf16": CONET_BF16, "fp8": CONET_FP8E4M3}
+STATUS = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "ENOMEM", 4: "EDEVICE", 5: "EBUSY", 6: "ETIMEOUT", 7: "ESTATE"}
+
+# Every symbol include/conet.h declares.
+EXPORTS = ("conet_weight_count", "conet_workspace_bytes", "conet_create", "conet_set_act_scales",
+           "conet_calibrate", "conet_get_act_scales", "conet_forward", "conet_forward_ragged", "conet_forward_profiled",
+           "conet_destroy", "conet_last_error")
+
+
+class ConetError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class conet_config(ctypes.Structure):
+    _fields_ = [("branches", ctypes.c_int32), ("blocks", ctypes.c_int32), ("channels", ctypes.c_int32),
+                ("in_channels", ctypes.c_int32), ("bits_per_symbol", ctypes.c_int32),
+                ("fuse_mask", ctypes.c_uint32), ("ln_eps", ctypes.c_float), ("dtype", ctypes.c_int32),
+                ("train", ctypes.c_int32), ("max_res", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libconet.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2510_12739_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    cfgp = ctypes.POINTER(conet_config)
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.conet_weight_count.argtypes = [cfgp]; lib.conet_weight_count.restype = sz
+    lib.conet_workspace_bytes.argtypes = [cfgp]; lib.conet_workspace_bytes.restype = sz
+    lib.conet_create.argtypes = [cfgp, fp, sz, vp, sz, ctypes.POINTER(vp)]; lib.conet_create.restype = i32
+    lib.conet_set_act_scales.argtypes = [vp, fp, sz]; lib.conet_set_act_scales.restype = i32
+    lib.conet_get_act_scales.argtypes = [vp, fp, sz]; lib.conet_get_act_scales.restype = i32
+    lib.conet_calibrate.argtypes = [vp, vp, i32, i32, i32, vp]; lib.conet_calibrate.restype = i32
+    lib.conet_forward.argtypes = [vp, vp, i32, i32, i32, vp, i32, vp]; lib.conet_forward.restype = i32
+    lib.conet_forward_ragged.argtypes = [vp, vp, i32, i32, ctypes.POINTER(i32), vp, vp]
+    lib.conet_forward_ragged.restype = i32
+    lib.conet_forward_profiled.argtypes = [vp, vp, i32, i32, i32, vp, fp, i32, vp]
+    lib.conet_forward_profiled.restype = i32
+    lib.conet_destroy.argtypes = [vp]; lib.conet_destroy.restype = i32
+    lib.conet_last_error.argtypes = []; lib.conet_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise ConetError(st, load().conet_last_error().decode())
+
+
+def make_config(K: int, L: int, C: int, C_in: int, m: int, dtype: str = "bf16", fuse_mask: int = -1,
+                max_res: int = 1 << 20, ln_eps: float = 1e-5) -> conet_config:
+    mask = ((1 << L) - 1) if fuse_mask < 0 else int(fuse_mask)
+    return conet_config(K, L, C, C_in, m, mask, ln_eps, DTYPES[dtype], 0, int(max_res))
+
+
+def weight_count(cfg: conet_config) -> int:
+    return int(load().conet_weight_count(ctypes.byref(cfg)))
+
+
+def workspace_bytes(cfg: conet_config) -> int:
+    return int(load().conet_workspace_bytes(ctypes.byref(cfg)))
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Conet:
+    """A CoNet-Rx model resident on the current GPU.
+
+    The workspace (filters in fragment order, vectors, activations for up to max_res
+    REs) is one torch uint8 tensor owned by this object.
+    """
+
+    def __init__(self, K: int, L: int, C: int, C_in: int, m: int, blob: np.ndarray, dtype: str = "bf16",
+                 fuse_mask: int = -1, max_res: int = 1 << 20, device=None):
+        import torch
+        self.lib = load()
+        self.cfg = make_config(K, L, C, C_in, m, dtype, fuse_mask, max_res)
+        self.K, self.L, self.C, self.C_in, self.m, self.dtype = K, L, C, C_in, m, dtype
+        n = weight_count(self.cfg)
+        if n == 0:
+            raise ConetError(1, self.lib.conet_last_error().decode())
+        blob = np.ascontiguousarray(blob, dtype=np.float32)
+        if blob.size != n:
+            raise ValueError(f"blob has {blob.size} values, configuration needs {n}")
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        nbytes = workspace_bytes(self.cfg)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self.lib.conet_create(ctypes.byref(self.cfg), blob.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                         n, ctypes.c_void_p(self.workspace.data_ptr()), nbytes, ctypes.byref(handle)))
+        self.handle = handle
+
+    @property
+    def n_scales(self) -> int:
+        return 1 + 2 * self.K * self.L
+
+    def set_act_scales(self, scales: Sequence[float]):
+        s = np.ascontiguousarray(scales, dtype=np.float32)
+        _check(self.lib.conet_set_act_scales(self.handle, s.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), s.size))
+
+    def get_act_scales(self) -> np.ndarray:
+        s = np.zeros(self.n_scales, dtype=np.float32)
+        _check(self.lib.conet_get_act_scales(self.handle, s.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), s.size))
+        return s
+
+    def calibrate(self, x, stream=None):
+        B, T, F, _ = x.shape
+        _check(self.lib.conet_calibrate(self.handle, ctypes.c_void_p(x.data_ptr()), B, T, F, _stream_ptr(stream)))
+
+    def _check_x(self, x):
+        import torch
+        if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+            raise ValueError("x must be a contiguous float32 CUDA tensor")
+        if x.shape[-1] != self.C_in:
+            raise ValueError(f"x has {x.shape[-1]} channels, model expects {self.C_in}")
+
+    def forward(self, x, out=None, stream=None):
+        """x: [B, T, F, C_in] float32 on the GPU -> LLR [B, T, F, m] float32 (enqueued on the stream)."""
+        import torch
+        self._check_x(x)
+        B, T, F, _ = x.shape
+        if out is None:
+            out = torch.empty((B, T, F, self.m), dtype=torch.float32, device=x.device)
+        _check(self.lib.conet_forward(self.handle, ctypes.c_void_p(x.data_ptr()), B, T, F,
+                                      ctypes.c_void_p(out.data_ptr()), 0, _stream_ptr(stream)))
+        return out
+
+    __call__ = forward
+
+    def forward_profiled(self, x, out=None, stream=None):
+        """forward() with per-stage HIP event timing: returns (llr, stage_ms[1 + 2L])."""
+        import torch
+        self._check_x(x)
+        B, T, F, _ = x.shape
+        if out is None:
+            out = torch.empty((B, T, F, self.m), dtype=torch.float32, device=x.device)
+        ms = np.zeros(1 + 2 * self.L, dtype=np.float32)
+        _check(self.lib.conet_forward_profiled(self.handle, ctypes.c_void_p(x.data_ptr()), B, T, F,
+                                               ctypes.c_void_p(out.data_ptr()),
+                                               ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ms.size,
+                                               _stream_ptr(stream)))
+        return out, ms
+
+    def forward_ragged(self, x_packed, T: int, F_list: Sequence[int], out=None, stream=None):
+        """Slots of different widths packed back to back: x_packed [sum T*F_s, C_in]."""
+        import torch
+        self._check_x(x_packed)
+        F_arr = (ctypes.c_int32 * len(F_list))(*[int(f) for f in F_list])
+        n_re = int(sum(F_list)) * T
+        if out is None:
+            out = torch.empty((n_re, self.m), dtype=torch.float32, device=x_packed.device)
+        _check(self.lib.conet_forward_ragged(self.handle, ctypes.c_void_p(x_packed.data_ptr()), len(F_list), T, F_arr,
+                                             ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.conet_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,318 @@
+// C-ABI host side of the CoNet-Rx library: configuration checks, filter packing into
+// the MFMA fragment order, workspace layout, and the launch sequence of a forward pass.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "conet.h"
+#include "conet_common.h"
+#include "conet_kernels.h"
+#include "conet_model.h"
+
+namespace conet {
+
+thread_local std::string g_last_error;
+
+conet_status fail(conet_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+conet_status hip_fail(hipError_t e, const char* what) {
+  return fail(CONET_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- host rounding
+uint16_t bf16_bits(float v) {
+  uint32_t u;
+  memcpy(&u, &v, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Saturating round-to-nearest-even onto OCP e4m3fn (bias 7, 3 mantissa bits, max 448).
+uint8_t e4m3_bits(float v) {
+  const uint8_t sign = std::signbit(v) ? 0x80 : 0x00;
+  double a = std::fabs((double)v);
+  if (!(a == a)) return 0x7f;
+  if (a > 448.0) a = 448.0;
+  if (a == 0.0) return sign;
+  int e = (int)std::floor(std::log2(a));
+  if (e < -6) e = -6;
+  const double q = std::ldexp(1.0, e - 3);
+  double n = std::nearbyint(a / q);  // default rounding mode: ties to even
+  if (n >= 16.0) { n = 8.0; ++e; }   // rounded up into the next binade
+  if (e == -6 && n < 8.0) return (uint8_t)(sign | (uint8_t)n);  // subnormal: mantissa = n
+  const int be = e + 7;
+  return (uint8_t)(sign | (be << 3) | ((int)n - 8));
+}
+
+// ---------------------------------------------------------------- fragment packing
+struct OpFmt { int vec, cpl, esize; };
+static OpFmt op_fmt(int dtype) {
+  switch (dtype) {
+    case DT_F32: return {4, 1, 4};
+    case DT_BF16: return {8, 1, 2};
+    case DT_FP8: return {16, 2, 1};
+    default: return {2, 1, 8};
+  }
+}
+
+size_t packed_bytes(int dtype, int cin, int cout) {
+  const OpFmt f = op_fmt(dtype);
+  const int cpt = cin / f.vec, nch = 9 * cpt, cps = 4 * f.cpl;
+  const int ns = (nch + cps - 1) / cps;
+  return (size_t)ns * (cout / 16) * f.cpl * 64 * 16;
+}
+
+// W: [cout][cin][3][3] FP32. Lane l of o-tile ot supplies filter row
+// o = (r/4)*(4*NOT) + 4*ot + r%4 (r = l%16) for chunk (s*4 + l/16)*CPL + c.
+void pack_filter(int dtype, int cin, int cout, const float* W, uint8_t* dst, float* wscale) {
+  const OpFmt f = op_fmt(dtype);
+  const int cpt = cin / f.vec, nch = 9 * cpt, cps = 4 * f.cpl, ns = (nch + cps - 1) / cps;
+  const int NOT = cout / 16;
+  std::vector<float> sc(cout, 1.0f);
+  if (dtype == DT_FP8) {
+    for (int o = 0; o < cout; ++o) {
+      float amax = 0.f;
+      for (int i = 0; i < cin * 9; ++i) amax = std::max(amax, std::fabs(W[(size_t)o * cin * 9 + i]));
+      sc[o] = amax > 0.f ? amax / 448.0f : 1.0f;
+    }
+  }
+  if (wscale) for (int o = 0; o < cout; ++o) wscale[o] = sc[o];
+  for (int s = 0; s < ns; ++s)
+    for (int ot = 0; ot < NOT; ++ot)
+      for (int c = 0; c < f.cpl; ++c)
+        for (int lane = 0; lane < 64; ++lane) {
+          uint8_t* out = dst + ((((size_t)s * NOT + ot) * f.cpl + c) * 64 + lane) * 16;
+          memset(out, 0, 16);
+          const int r = lane & 15, g = lane >> 4;
+          const int o = (r >> 2) * (4 * NOT) + 4 * ot + (r & 3);
+          const int ch = (s * 4 + g) * f.cpl + c;
+          if (ch >= nch) continue;
+          const int tap = ch / cpt, c0 = (ch % cpt) * f.vec;
+          for (int e = 0; e < f.vec; ++e) {
+            const float w = W[(((size_t)o * cin + c0 + e) * 3 + tap / 3) * 3 + tap % 3];
+            switch (dtype) {
+              case DT_F32: memcpy(out + 4 * e, &w, 4); break;
+              case DT_BF16: { uint16_t b = bf16_bits(w); memcpy(out + 2 * e, &b, 2); } break;
+              case DT_FP8: out[e] = e4m3_bits(w / sc[o]); break;
+              default: { double d = w; memcpy(out + 8 * e, &d, 8); } break;
+            }
+          }
+        }
+}
+
+// ---------------------------------------------------------------- layout
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int act_bytes(int dtype) { return dtype == DT_F32 ? 4 : 2; }
+static int hid_bytes(int dtype) { return dtype == DT_F32 ? 4 : (dtype == DT_BF16 ? 2 : 1); }
+
+size_t n_params(const conet_config& c) {
+  const size_t K = c.branches, L = c.blocks, C = c.channels, Ci = c.in_channels, m = c.bits_per_symbol;
+  return K * (C * Ci * 9 + C + L * (6 * C + 2 * 9 * C * C)) + 2 * L * C + m * C + m;
+}
+
+conet_status check_config(const conet_config* c) {
+  if (!c) return fail(CONET_EINVAL, "null config");
+  if (c->branches < 1 || c->branches > KMAX_ARGS) return fail(CONET_EINVAL, "branches must be 1..8 (got %d)", c->branches);
+  if (c->blocks < 1 || c->blocks > 32) return fail(CONET_EINVAL, "blocks must be 1..32 (got %d)", c->blocks);
+  if (c->bits_per_symbol < 1 || c->bits_per_symbol > 8) return fail(CONET_EINVAL, "bits_per_symbol must be 1..8");
+  if (c->dtype != DT_F32 && c->dtype != DT_BF16 && c->dtype != DT_FP8) return fail(CONET_EINVAL, "unsupported dtype %d", c->dtype);
+  if (!conv_supported(c->dtype, c->in_channels, c->channels))
+    return fail(CONET_EINVAL, "no kernel for C_in=%d -> C=%d at dtype %d", c->in_channels, c->channels, c->dtype);
+  if (!conv_supported(c->dtype, c->channels, c->channels))
+    return fail(CONET_EINVAL, "no kernel for C=%d -> C=%d at dtype %d", c->channels, c->channels, c->dtype);
+  if (c->train != 0) return fail(CONET_EINVAL, "training buffers are not available in this build");
+  if (c->max_res < 1) return fail(CONET_EINVAL, "max_res must be positive");
+  if (!(c->ln_eps > 0.f)) return fail(CONET_EINVAL, "ln_eps must be positive");
+  if (c->blocks < 32 && (c->fuse_mask >> c->blocks) != 0) return fail(CONET_EINVAL, "fuse_mask has bits beyond L");
+  return CONET_OK;
+}
+
+// Workspace: [packed filters][FP32 vectors][tile descriptors][activations]
+void plan_layout(const conet_config& c, Layout& lay) {
+  const int K = c.branches, L = c.blocks, C = c.channels, Ci = c.in_channels, m = c.bits_per_symbol;
+  size_t off = 0;
+  for (int k = 0; k < K; ++k) {
+    lay.w_in[k] = off; off = align256(off + packed_bytes(c.dtype, Ci, C));
+    for (int l = 0; l < L; ++l) {
+      lay.w1[k][l] = off; off = align256(off + packed_bytes(c.dtype, C, C));
+      lay.w2[k][l] = off; off = align256(off + packed_bytes(c.dtype, C, C));
+    }
+  }
+  // FP32 vectors: per branch b_in, wscale_in; per (k,l): s0 o0 b1 s1 o1 b2 ws1 ws2; per l gamma beta; Wh bh
+  size_t nv = 0;
+  for (int k = 0; k < K; ++k) {
+    lay.v_bin[k] = nv; nv += C;
+    lay.v_wsin[k] = nv; nv += C;
+    for (int l = 0; l < L; ++l) {
+      lay.v_blk[k][l] = nv; nv += 8 * C;
+    }
+  }
+  for (int l = 0; l < L; ++l) { lay.v_gamma[l] = nv; nv += C; lay.v_beta[l] = nv; nv += C; }
+  lay.v_wh = nv; nv += (size_t)m * C;
+  lay.v_bh = nv; nv += m;
+  lay.n_vec = nv;
+  lay.vec = off; off = align256(off + nv * 4);
+  const int tw_min = 16;
+  lay.max_tiles = (size_t)(c.max_res / tw_min + 1) + 1024;
+  lay.tiles = off; off = align256(off + lay.max_tiles * sizeof(TileDesc));
+  const size_t R = (size_t)c.max_res;
+  for (int p = 0; p < 2; ++p)
+    for (int k = 0; k < K; ++k) { lay.act[p][k] = off; off = align256(off + R * C * act_bytes(c.dtype)); }
+  for (int k = 0; k < K; ++k) { lay.hid[k] = off; off = align256(off + R * C * hid_bytes(c.dtype)); }
+  lay.total = off;
+}
+
+}  // namespace conet
+
+using namespace conet;
+
+// ---------------------------------------------------------------- ABI
+extern "C" {
+
+const char* conet_last_error(void) { return g_last_error.c_str(); }
+
+size_t conet_weight_count(const conet_config* cfg) {
+  if (check_config(cfg) != CONET_OK) return 0;
+  return n_params(*cfg);
+}
+
+size_t conet_workspace_bytes(const conet_config* cfg) {
+  if (check_config(cfg) != CONET_OK) return 0;
+  Layout lay;
+  plan_layout(*cfg, lay);
+  return lay.total;
+}
+
+conet_status conet_create(const conet_config* cfg, const float* w, size_t n_weights, void* workspace,
+                          size_t workspace_bytes, conet_model** out) {
+  g_last_error.clear();
+  if (!out) return fail(CONET_EINVAL, "null output handle");
+  *out = nullptr;
+  conet_status st = check_config(cfg);
+  if (st != CONET_OK) return st;
+  if (!w || !workspace) return fail(CONET_EINVAL, "null weights or workspace");
+  if (n_weights != n_params(*cfg)) return fail(CONET_EINVAL, "blob has %zu values, configuration needs %zu", n_weights, n_params(*cfg));
+  if (((uintptr_t)workspace & 255) != 0) return fail(CONET_EINVAL, "workspace must be 256-byte aligned");
+  conet_model* M = new (std::nothrow) conet_model();
+  if (!M) return fail(CONET_ENOMEM, "host allocation failed");
+  M->cfg = *cfg;
+  plan_layout(*cfg, M->lay);
+  if (workspace_bytes < M->lay.total) {
+    size_t need = M->lay.total;
+    delete M;
+    return fail(CONET_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+  }
+  M->ws = (uint8_t*)workspace;
+  hipError_t e = hipGetDevice(&M->device);
+  if (e != hipSuccess) { delete M; return hip_fail(e, "hipGetDevice"); }
+
+  const int K = cfg->branches, L = cfg->blocks, C = cfg->channels, Ci = cfg->in_channels, m = cfg->bits_per_symbol;
+  const Layout& lay = M->lay;
+  // host image of the filter + vector regions, uploaded in one copy
+  std::vector<uint8_t> img(lay.vec + lay.n_vec * 4, 0);
+  float* vec = reinterpret_cast<float*>(img.data() + lay.vec);
+  M->blob.assign(w, w + n_weights);
+  const float* p = w;
+  for (int k = 0; k < K; ++k) {
+    pack_filter(cfg->dtype, Ci, C, p, img.data() + lay.w_in[k], vec + lay.v_wsin[k]);
+    p += (size_t)C * Ci * 9;
+    memcpy(vec + lay.v_bin[k], p, C * 4); p += C;
+    for (int l = 0; l < L; ++l) {
+      float* vb = vec + lay.v_blk[k][l];  // s0 o0 b1 s1 o1 b2 ws1 ws2
+      memcpy(vb + 0 * C, p, C * 4); p += C;                 // s0
+      memcpy(vb + 1 * C, p, C * 4); p += C;                 // o0
+      pack_filter(cfg->dtype, C, C, p, img.data() + lay.w1[k][l], vb + 6 * C); p += (size_t)C * C * 9;
+      memcpy(vb + 2 * C, p, C * 4); p += C;                 // b1
+      memcpy(vb + 3 * C, p, C * 4); p += C;                 // s1
+      memcpy(vb + 4 * C, p, C * 4); p += C;                 // o1
+      pack_filter(cfg->dtype, C, C, p, img.data() + lay.w2[k][l], vb + 7 * C); p += (size_t)C * C * 9;
+      memcpy(vb + 5 * C, p, C * 4); p += C;                 // b2
+    }
+  }
+  for (int l = 0; l < L; ++l) {
+    memcpy(vec + lay.v_gamma[l], p, C * 4); p += C;
+    memcpy(vec + lay.v_beta[l], p, C * 4); p += C;
+  }
+  memcpy(vec + lay.v_wh, p, (size_t)m * C * 4); p += (size_t)m * C;
+  memcpy(vec + lay.v_bh, p, m * 4); p += m;
+  e = hipMemcpy(M->ws, img.data(), img.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { delete M; return hip_fail(e, "upload of packed weights"); }
+  M->act_scales.assign(1 + 2 * K * L, 1.0f);
+  M->scales_set = false;
+  *out = M;
+  return CONET_OK;
+}
+
+conet_status conet_destroy(conet_model* M) {
+  if (!M) return fail(CONET_EINVAL, "null model");
+  delete M;
+  return CONET_OK;
+}
+
+conet_status conet_set_act_scales(conet_model* M, const float* s, size_t n) {
+  if (!M || !s) return fail(CONET_EINVAL, "null argument");
+  if (M->cfg.dtype != DT_FP8) return fail(CONET_EINVAL, "activation scales apply to FP8 models only");
+  if (n != M->act_scales.size()) return fail(CONET_EINVAL, "expected %zu scales, got %zu", M->act_scales.size(), n);
+  for (size_t i = 0; i < n; ++i)
+    if (!(s[i] > 0.f) || !std::isfinite(s[i])) return fail(CONET_EINVAL, "scale %zu is not a positive finite number", i);
+  M->act_scales.assign(s, s + n);
+  M->scales_set = true;
+  return CONET_OK;
+}
+
+conet_status conet_get_act_scales(conet_model* M, float* s, size_t n) {
+  if (!M || !s) return fail(CONET_EINVAL, "null argument");
+  if (n != M->act_scales.size()) return fail(CONET_EINVAL, "expected %zu scales, got %zu", M->act_scales.size(), n);
+  std::copy(M->act_scales.begin(), M->act_scales.end(), s);
+  return CONET_OK;
+}
+
+conet_status conet_forward(conet_model* M, const float* x, int32_t B, int32_t T, int32_t F, float* llr,
+                           int32_t save, void* stream) {
+  if (!M) return fail(CONET_EINVAL, "null model");
+  if (save) return fail(CONET_EINVAL, "save_for_backward is not available in this build");
+  if (B == 0) return CONET_OK;
+  if (!x || !llr) return fail(CONET_EINVAL, "null tensor pointer");
+  if (B < 0 || T < 1 || T > TMAX || F < 1) return fail(CONET_ESHAPE, "bad shape B=%d T=%d F=%d (need T in 1..14)", B, T, F);
+  if ((int64_t)B * T * F > M->cfg.max_res) return fail(CONET_ESHAPE, "B*T*F = %lld exceeds max_res %lld", (long long)B * T * F, (long long)M->cfg.max_res);
+  if (M->cfg.dtype == DT_FP8 && !M->scales_set) return fail(CONET_ESTATE, "FP8 model needs activation scales (set or calibrate)");
+  Geometry geo;
+  geo.uniform = true; geo.B = B; geo.T = T; geo.F = F;
+  return run_forward(M, x, geo, llr, (hipStream_t)stream, nullptr);
+}
+
+conet_status conet_forward_ragged(conet_model* M, const float* x, int32_t n_slots, int32_t T, const int32_t* F_host,
+                                  float* llr, void* stream) {
+  if (!M) return fail(CONET_EINVAL, "null model");
+  if (n_slots == 0) return CONET_OK;
+  if (!x || !llr || !F_host) return fail(CONET_EINVAL, "null pointer");
+  if (n_slots < 0 || T < 1 || T > TMAX) return fail(CONET_ESHAPE, "bad shape n_slots=%d T=%d", n_slots, T);
+  int64_t total = 0;
+  for (int s = 0; s < n_slots; ++s) {
+    if (F_host[s] < 1) return fail(CONET_ESHAPE, "slot %d has F=%d", s, F_host[s]);
+    total += (int64_t)T * F_host[s];
+  }
+  if (total > M->cfg.max_res) return fail(CONET_ESHAPE, "ragged batch has %lld REs, max_res is %lld", (long long)total, (long long)M->cfg.max_res);
+  if (M->cfg.dtype == DT_FP8 && !M->scales_set) return fail(CONET_ESTATE, "FP8 model needs activation scales (set or calibrate)");
+  Geometry geo;
+  geo.uniform = false; geo.T = T; geo.n_slots = n_slots; geo.F_host = F_host;
+  return run_forward(M, x, geo, llr, (hipStream_t)stream, nullptr);
+}
+
+}  // extern "C"

@@ -1,0 +1,281 @@
+// Launch sequence of the CoNet-Rx forward pass and the FP8 calibration pass.
+//
+// Stage order (2L + 1 launches; the paper's sequential depth is 2L + 2 conv layers
+// with the head fused into the last one):
+//   input layer of all K branches (one launch, grid.y = branch)
+//   for each block l: first conv of every branch (grid.y = branch), then the second
+//   conv: with fusion after block l, one work-group computes all K branches of its
+//   tile and applies product + LayerNorm (and the head after the last block);
+//   without fusion each branch adds its residual on its own.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <cmath>
+#include <vector>
+
+#include "conet_model.h"
+
+namespace conet {
+
+// ---------------------------------------------------------------- amax reduction
+// max over REs and channels of |prologue(x)|, prologue 0: x, 1: ReLU(s0 x + o0), 2: ReLU(x)
+template <class T>
+__global__ void __launch_bounds__(256) amax_kernel(const T* __restrict__ x, int64_t n, int C, const float* s0,
+                                                   const float* o0, int prologue, unsigned* out) {
+  float m = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float v = (float)x[i];
+    if (prologue == 1) { const int c = (int)(i % C); v = fmaxf(s0[c] * v + o0[c], 0.f); }
+    else if (prologue == 2) v = fmaxf(v, 0.f);
+    m = fmaxf(m, fabsf(v));
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+hipError_t launch_amax(const void* x, int elem_bytes, int64_t n_re, int C, const float* s0, const float* o0,
+                       int prologue, unsigned* out, hipStream_t s) {
+  const int64_t n = n_re * C;
+  const int blocks = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  if (blocks <= 0) return hipSuccess;
+  if (elem_bytes == 4)
+    hipLaunchKernelGGL(amax_kernel<float>, dim3(blocks), dim3(256), 0, s, (const float*)x, n, C, s0, o0, prologue, out);
+  else
+    hipLaunchKernelGGL(amax_kernel<__bf16>, dim3(blocks), dim3(256), 0, s, (const __bf16*)x, n, C, s0, o0, prologue, out);
+  return hipGetLastError();
+}
+
+static int scale_index(int K, int L, int k, int l, int which) { (void)K; return 1 + 2 * (k * L + l) + which; }
+
+// ---------------------------------------------------------------- forward
+conet_status run_forward(conet_model* M, const float* x, const Geometry& geo, float* llr, hipStream_t s,
+                         std::vector<float>* calib, hipEvent_t* events) {
+  const conet_config& c = M->cfg;
+  const Layout& lay = M->lay;
+  const int K = c.branches, L = c.blocks, C = c.channels, Ci = c.in_channels, dt = c.dtype;
+  uint8_t* ws = M->ws;
+  float* vec = reinterpret_cast<float*>(ws + lay.vec);
+  std::vector<float>& sc = M->act_scales;
+  const int tw_in = conv_tile_width(dt, Ci, C), tw_blk = conv_tile_width(dt, C, C);
+  hipError_t e;
+
+  // tile geometry for both tile widths
+  int n_tiles_in = 0, n_tiles_blk = 0;
+  const TileDesc* d_in = nullptr;
+  const TileDesc* d_blk = nullptr;
+  int64_t n_re = 0;
+  if (geo.uniform) {
+    n_tiles_in = geo.B * ((geo.F + tw_in - 1) / tw_in);
+    n_tiles_blk = geo.B * ((geo.F + tw_blk - 1) / tw_blk);
+    n_re = (int64_t)geo.B * geo.T * geo.F;
+  } else {
+    std::vector<TileDesc> h;
+    auto build = [&](int tw) {
+      int64_t base = 0;
+      for (int sl = 0; sl < geo.n_slots; ++sl) {
+        const int F = geo.F_host[sl];
+        for (int f0 = 0; f0 < F; f0 += tw) h.push_back(TileDesc{base, F, f0});
+        base += (int64_t)geo.T * F;
+      }
+      n_re = base;
+    };
+    build(tw_blk);
+    n_tiles_blk = (int)h.size();
+    if (tw_in != tw_blk) build(tw_in);
+    n_tiles_in = tw_in != tw_blk ? (int)h.size() - n_tiles_blk : n_tiles_blk;
+    if (h.size() > lay.max_tiles) return fail(CONET_ESHAPE, "ragged batch needs %zu tiles, capacity %zu", h.size(), lay.max_tiles);
+    TileDesc* dt_dev = reinterpret_cast<TileDesc*>(ws + lay.tiles);
+    e = hipMemcpyAsync(dt_dev, h.data(), h.size() * sizeof(TileDesc), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "tile descriptor upload");
+    d_blk = dt_dev;
+    d_in = tw_in != tw_blk ? dt_dev + n_tiles_blk : dt_dev;
+  }
+  if (n_tiles_in == 0 || n_tiles_blk == 0) return CONET_OK;
+
+  auto geom = [&](ConvArgs& a, bool in_layer) {
+    const int tw = in_layer ? tw_in : tw_blk;
+    a.T = geo.T;
+    a.F = geo.uniform ? geo.F : 0;
+    a.tiles_per_slot = geo.uniform ? (geo.F + tw - 1) / tw : 0;
+    a.tiles = in_layer ? d_in : d_blk;
+  };
+  auto actp = [&](int p, int k) -> void* { return ws + lay.act[p][k]; };
+  auto hidp = [&](int k) -> void* { return ws + lay.hid[k]; };
+  unsigned* amax_dev = reinterpret_cast<unsigned*>(ws + lay.tiles + lay.max_tiles * sizeof(TileDesc) - 256);
+  auto read_amax = [&](int n, std::vector<float>& outv) -> conet_status {
+    std::vector<unsigned> hbuf(n);
+    hipError_t e2 = hipStreamSynchronize(s);
+    if (e2 == hipSuccess) e2 = hipMemcpy(hbuf.data(), amax_dev, n * sizeof(unsigned), hipMemcpyDeviceToHost);
+    if (e2 != hipSuccess) return hip_fail(e2, "calibration readback");
+    outv.resize(n);
+    for (int i = 0; i < n; ++i) { float f; std::memcpy(&f, &hbuf[i], 4); outv[i] = f; }
+    return CONET_OK;
+  };
+  auto to_scale = [](float amax) { return amax > 0.f ? amax / E4M3_MAX : 1.0f; };
+  if (calib && !geo.uniform) return fail(CONET_EINVAL, "calibration takes a uniform batch");
+
+  int stage = 0;
+  auto mark = [&]() -> hipError_t { return events ? hipEventRecord(events[stage++], s) : hipSuccess; };
+
+  // ---- input layer
+  if (calib) {
+    e = hipMemsetAsync(amax_dev, 0, 64 * sizeof(unsigned), s);
+    if (e == hipSuccess) e = launch_amax(x, 4, n_re, Ci, nullptr, nullptr, 0, amax_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "calibration amax");
+    std::vector<float> am;
+    conet_status st = read_amax(1, am);
+    if (st != CONET_OK) return st;
+    sc[0] = to_scale(am[0]);
+    calib->push_back(am[0]);
+  }
+  {
+    ConvArgs a = {};
+    geom(a, true);
+    for (int k = 0; k < K; ++k) {
+      a.in[k] = x;
+      a.out[k] = actp(0, k);
+      a.wpack[k] = ws + lay.w_in[k];
+      a.bias[k] = vec + lay.v_bin[k];
+      a.wscale[k] = vec + lay.v_wsin[k];
+      a.in_qscale[k] = 1.0f / sc[0];
+      a.deq[k] = sc[0];
+    }
+    e = mark();
+    if (e == hipSuccess) e = launch_conv(dt, 0, Ci, C, a, n_tiles_in, K, s);
+    if (e != hipSuccess) return hip_fail(e, "input layer launch");
+  }
+
+  int cur = 0;
+  bool fused_prev = false;
+  for (int l = 0; l < L; ++l) {
+    const bool last = (l == L - 1);
+    const bool fuse = (c.fuse_mask >> l) & 1u;
+    const int nk = (last && !fuse) ? 1 : K;
+    ConvArgs a1 = {};
+    geom(a1, false);
+    for (int k = 0; k < nk; ++k) {
+      const float* vb = vec + lay.v_blk[k][l];
+      const bool mrb = (k == 0 && fused_prev);
+      a1.in[k] = actp(cur, k);
+      a1.pre_s[k] = mrb ? nullptr : vb + 0 * C;
+      a1.pre_o[k] = mrb ? nullptr : vb + 1 * C;
+      a1.bias[k] = vb + 2 * C;
+      a1.post_s[k] = vb + 3 * C;
+      a1.post_o[k] = vb + 4 * C;
+      a1.wscale[k] = vb + 6 * C;
+      a1.out[k] = hidp(k);
+      a1.wpack[k] = ws + lay.w1[k][l];
+    }
+    if (calib) {
+      // operand of conv 1: max |prologue(x)| per branch, then max |h| per branch
+      e = hipMemsetAsync(amax_dev, 0, 64 * sizeof(unsigned), s);
+      for (int k = 0; k < nk && e == hipSuccess; ++k)
+        e = launch_amax(a1.in[k], 2, n_re, C, a1.pre_s[k], a1.pre_o[k], a1.pre_s[k] ? 1 : 2, amax_dev + k, s);
+      if (e != hipSuccess) return hip_fail(e, "calibration amax");
+      std::vector<float> am;
+      conet_status st = read_amax(nk, am);
+      if (st != CONET_OK) return st;
+      for (int k = 0; k < nk; ++k) { sc[scale_index(K, L, k, l, 0)] = to_scale(am[k]); calib->push_back(am[k]); }
+      for (int k = 0; k < nk; ++k) {
+        a1.in_qscale[k] = 1.0f / sc[scale_index(K, L, k, l, 0)];
+        a1.deq[k] = sc[scale_index(K, L, k, l, 0)];
+        a1.out_qscale[k] = 1.0f;
+      }
+      ConvArgs ac = a1;
+      e = hipMemsetAsync(amax_dev, 0, 64 * sizeof(unsigned), s);
+      ac.amax = amax_dev;
+      if (e == hipSuccess) e = launch_conv(dt, 1, C, C, ac, n_tiles_blk, nk, s);
+      if (e != hipSuccess) return hip_fail(e, "calibration conv");
+      st = read_amax(nk, am);
+      if (st != CONET_OK) return st;
+      for (int k = 0; k < nk; ++k) { sc[scale_index(K, L, k, l, 1)] = to_scale(am[k]); calib->push_back(am[k]); }
+    }
+    for (int k = 0; k < nk; ++k) {
+      a1.in_qscale[k] = 1.0f / sc[scale_index(K, L, k, l, 0)];
+      a1.deq[k] = sc[scale_index(K, L, k, l, 0)];
+      a1.out_qscale[k] = 1.0f / sc[scale_index(K, L, k, l, 1)];
+    }
+    e = mark();
+    if (e == hipSuccess) e = launch_conv(dt, 1, C, C, a1, n_tiles_blk, nk, s);
+    if (e != hipSuccess) return hip_fail(e, "block conv 1 launch");
+
+    ConvArgs a2 = {};
+    geom(a2, false);
+    for (int k = 0; k < nk; ++k) {
+      const float* vb = vec + lay.v_blk[k][l];
+      a2.in[k] = hidp(k);
+      a2.resid[k] = actp(cur, k);
+      a2.out[k] = last ? nullptr : actp(1 - cur, k);
+      a2.wpack[k] = ws + lay.w2[k][l];
+      a2.bias[k] = vb + 5 * C;
+      a2.wscale[k] = vb + 7 * C;
+      a2.deq[k] = sc[scale_index(K, L, k, l, 1)];
+      a2.in_qscale[k] = 1.0f / sc[scale_index(K, L, k, l, 1)];
+    }
+    a2.K = K;
+    a2.eps = c.ln_eps;
+    a2.gamma = vec + lay.v_gamma[l];
+    a2.beta = vec + lay.v_beta[l];
+    a2.Wh = vec + lay.v_wh;
+    a2.bh = vec + lay.v_bh;
+    a2.m = c.bits_per_symbol;
+    a2.llr = (last && !calib) ? llr : nullptr;
+    e = mark();
+    if (e == hipSuccess)
+      e = fuse ? launch_conv(dt, 3, C, C, a2, n_tiles_blk, 1, s) : launch_conv(dt, 2, C, C, a2, n_tiles_blk, nk, s);
+    if (e != hipSuccess) return hip_fail(e, "block conv 2 launch");
+    cur = 1 - cur;
+    fused_prev = fuse;
+  }
+  e = mark();
+  if (e != hipSuccess) return hip_fail(e, "event record");
+  return CONET_OK;
+}
+
+}  // namespace conet
+
+using namespace conet;
+
+extern "C" conet_status conet_calibrate(conet_model* M, const float* x, int32_t B, int32_t T, int32_t F, void* stream) {
+  if (!M || !x) return fail(CONET_EINVAL, "null argument");
+  if (M->cfg.dtype != DT_FP8) return fail(CONET_EINVAL, "calibration applies to FP8 models only");
+  if (B < 1 || T < 1 || T > TMAX || F < 1) return fail(CONET_ESHAPE, "bad calibration shape");
+  if ((int64_t)B * T * F > M->cfg.max_res) return fail(CONET_ESHAPE, "calibration batch exceeds max_res");
+  Geometry geo;
+  geo.uniform = true; geo.B = B; geo.T = T; geo.F = F;
+  std::vector<float> amax;
+  conet_status st = run_forward(M, x, geo, nullptr, (hipStream_t)stream, &amax);
+  if (st != CONET_OK) return st;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "calibration");
+  M->scales_set = true;
+  return CONET_OK;
+}
+
+extern "C" conet_status conet_forward_profiled(conet_model* M, const float* x, int32_t B, int32_t T, int32_t F,
+                                               float* llr, float* stage_ms_host, int32_t n_stages, void* stream) {
+  if (!M || !x || !llr || !stage_ms_host) return fail(CONET_EINVAL, "null argument");
+  const int ns = 1 + 2 * M->cfg.blocks;
+  if (n_stages != ns) return fail(CONET_EINVAL, "expected %d stages, got %d", ns, n_stages);
+  if (B < 1 || T < 1 || T > TMAX || F < 1) return fail(CONET_ESHAPE, "bad shape B=%d T=%d F=%d", B, T, F);
+  if ((int64_t)B * T * F > M->cfg.max_res) return fail(CONET_ESHAPE, "B*T*F exceeds max_res");
+  if (M->cfg.dtype == DT_FP8 && !M->scales_set) return fail(CONET_ESTATE, "FP8 model needs activation scales");
+  std::vector<hipEvent_t> ev(ns + 1, nullptr);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i <= ns && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+  conet_status st = CONET_OK;
+  if (e != hipSuccess) st = hip_fail(e, "hipEventCreate");
+  if (st == CONET_OK) {
+    Geometry geo;
+    geo.uniform = true; geo.B = B; geo.T = T; geo.F = F;
+    st = run_forward(M, x, geo, llr, (hipStream_t)stream, nullptr, ev.data());
+  }
+  if (st == CONET_OK) {
+    e = hipEventSynchronize(ev[ns]);
+    for (int i = 0; i < ns && e == hipSuccess; ++i) e = hipEventElapsedTime(&stage_ms_host[i], ev[i], ev[i + 1]);
+    if (e != hipSuccess) st = hip_fail(e, "stage timing");
+  }
+  for (auto& x_ : ev) if (x_) (void)hipEventDestroy(x_);
+  return st;
+}

@@ -1,0 +1,66 @@
+// Host-side model state of the CoNet-Rx library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "conet.h"
+#include "conet_common.h"
+#include "conet_kernels.h"
+
+namespace conet {
+
+constexpr int LMAX = 32;
+
+// Byte offsets into the caller's workspace (vector offsets are in floats from `vec`).
+struct Layout {
+  size_t w_in[KMAX_ARGS];
+  size_t w1[KMAX_ARGS][LMAX], w2[KMAX_ARGS][LMAX];
+  size_t vec;                      // FP32 vectors
+  size_t n_vec;
+  size_t v_bin[KMAX_ARGS], v_wsin[KMAX_ARGS];
+  size_t v_blk[KMAX_ARGS][LMAX];   // s0 o0 b1 s1 o1 b2 ws1 ws2 (8 C each)
+  size_t v_gamma[LMAX], v_beta[LMAX], v_wh, v_bh;
+  size_t tiles;                    // TileDesc array for ragged batches
+  size_t max_tiles;
+  size_t act[2][KMAX_ARGS];        // residual stream, ping-pong
+  size_t hid[KMAX_ARGS];           // middle activation of a block
+  size_t total;
+};
+
+struct Geometry {
+  bool uniform = true;
+  int B = 0, T = 0, F = 0;                 // uniform
+  int n_slots = 0;                         // ragged
+  const int32_t* F_host = nullptr;
+};
+
+}  // namespace conet
+
+struct conet_model {
+  conet_config cfg;
+  conet::Layout lay;
+  uint8_t* ws = nullptr;
+  int device = 0;
+  std::vector<float> blob;           // FP32 parameters as given
+  std::vector<float> act_scales;     // FP8 static activation scales
+  bool scales_set = false;
+};
+
+namespace conet {
+
+conet_status fail(conet_status st, const char* fmt, ...);
+conet_status hip_fail(hipError_t e, const char* what);
+
+// Calibration hooks: when `amax` is non-null, run_forward stops after recording the
+// max |operand| of every conv input, in network order, into amax_host (FP8 models).
+// events (optional, 2L+2 entries): recorded on the stream before every launch and after
+// the last one, so stage i took elapsed(events[i], events[i+1]).
+conet_status run_forward(conet_model* M, const float* x, const Geometry& geo, float* llr, hipStream_t s,
+                         std::vector<float>* calib, hipEvent_t* events = nullptr);
+
+hipError_t launch_amax(const void* x, int act_dtype_bytes, int64_t n_re, int C, const float* s0, const float* o0,
+                       int prologue, unsigned* out, hipStream_t s);
+
+}  // namespace conet

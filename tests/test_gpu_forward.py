@@ -1,0 +1,198 @@
+"""GPU parity of the forward pass (through the C ABI) against the FP64 oracle.
+
+Tolerances (derivations in the design notes):
+  * FP32 kernels vs FP64: rel-L2 <= 1e-5 and max|d|/RMS <= 1e-4 (FP32 accumulation over
+    at most 9*96 terms per conv and 2L+2 layers).
+  * BF16 / FP8 kernels vs the oracle emulating the same roundings: rel-L2 <= 5e-3 (BF16)
+    and <= 2e-2 (FP8). What remains is FP32 (GPU) vs FP64 (oracle) accumulation deciding
+    the rounding of an intermediate: a 576-term FP32 sum is off by ~sqrt(576) 2^-24 ~ 1.4e-6
+    relative, so about 1.4e-6 / 2^-9 ~ 1e-3 of the stored BF16 values land one ulp (2^-8)
+    apart; sqrt(1e-3) * 2^-8 ~ 1.5e-4 per layer, amplified by the K-way products over
+    2L+2 layers (measured 2e-3 at K=3, L=4), hence 5e-3.
+  * FP8: the e4m3 grid is 16x coarser than BF16's, so rounding flips decided by FP32 vs
+    FP64 round-off are 16x larger and K-way products with LayerNorm amplify them: the
+    oracle's own FP8 output moves by ~1e-2 rel-L2 when its input-layer dequantisation
+    changes by 1e-6 relative. The bound vs the FP8-emulating oracle is therefore 6e-2.
+  * BF16 vs plain FP64: rel-L2 <= 3e-2 and sign agreement >= 99 % (the stated BF16 LLR
+    tolerance). FP8 vs FP64 (stated as measured on the oracle's own FP8 emulation,
+    0.19 for K=4, L=2, C=96): rel-L2 <= 0.25 and sign agreement >= 93 %.
+"""
+import numpy as np
+import pytest
+
+from helpers import features, max_over_rms, rel_l2, say, sign_agree
+from oracle import conet64 as o
+from synth import ModelConfig, SimConfig, make_blob, workload
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _model(K, L, C, Ci, m, dtype, blob, mask=-1, max_res=1 << 20):
+    from paper_2510_12739_amd import Conet
+    return Conet(K, L, C, Ci, m, blob, dtype=dtype, fuse_mask=mask, max_res=max_res)
+
+
+def _run(model, X):
+    x = torch.from_numpy(np.ascontiguousarray(X, np.float32)).cuda()
+    y = model(x)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().astype(np.float64)
+
+
+def _oracle(K, L, C, Ci, m, blob, X, mask=-1, quant=None):
+    p = o.unpack(blob, K, L, C, Ci, m)
+    return o.forward_slots(p, X.astype(np.float64), fuse_mask=None if mask < 0 else mask, quant=quant)
+
+
+# ----------------------------------------------------------------------------- FP32
+
+def test_fp32_single_slot_72x14():
+    """The plain FP32 workload: 1 slot, 72 x 14 grid, 2 rx, QPSK, K=2, L=2, C=32, He init."""
+    w = workload("fp32_b1_f72")
+    mc = w.model
+    blob = make_blob(mc, seed=w.weight_seed)
+    X = features(w.sim, w.batch)
+    say("fp32 72x14 single slot")
+    got = _run(_model(mc.K, mc.L, mc.C, mc.C_in, mc.m, "f32", blob), X)
+    ref = _oracle(mc.K, mc.L, mc.C, mc.C_in, mc.m, blob, X)
+    assert got.shape == (1, 14, 72, 2)
+    assert rel_l2(got, ref) <= 1e-5 and max_over_rms(got, ref) <= 1e-4, (rel_l2(got, ref), max_over_rms(got, ref))
+
+
+@pytest.mark.parametrize("K,L,C,Ci,m,mask,B,T,F", [
+    (2, 2, 32, 8, 2, -1, 1, 14, 72),
+    (3, 2, 32, 8, 4, 0b10, 2, 14, 40),     # fusion only after the deeper block
+    (1, 2, 32, 8, 2, 0, 2, 14, 33),        # plain pre-activation ResNet (K=1, no fusion)
+    (4, 1, 16, 8, 6, 0b1, 1, 14, 17),      # four branches, ragged tile tail
+    (2, 3, 32, 8, 3, 0b101, 3, 7, 5),      # T < 14, F narrower than a tile
+    (2, 2, 64, 16, 4, -1, 2, 14, 65),      # C = 64 at FP32
+    (1, 1, 16, 8, 1, 0b1, 2, 1, 1),        # one RE per slot
+])
+def test_fp32_variants_perturbed(K, L, C, Ci, m, mask, B, T, F):
+    mc = ModelConfig(K, L, C, Ci, m)
+    blob = make_blob(mc, seed=K * 100 + L, perturb=True)
+    rng = np.random.default_rng(K + 10 * L + F)
+    X = rng.standard_normal((B, T, F, Ci)).astype(np.float32)
+    say(f"fp32 variant K={K} L={L} C={C} mask={mask} B={B} T={T} F={F}")
+    got = _run(_model(K, L, C, Ci, m, "f32", blob, mask), X)
+    ref = _oracle(K, L, C, Ci, m, blob, X, mask)
+    assert rel_l2(got, ref) <= 1e-5 and max_over_rms(got, ref) <= 1e-4, (rel_l2(got, ref), max_over_rms(got, ref))
+
+
+def test_ragged_equals_uniform_slots_bitwise():
+    """Each slot of a ragged batch gives exactly what it gives alone (tiles never span slots)."""
+    K, L, C, Ci, m = 2, 2, 32, 8, 2
+    blob = make_blob(ModelConfig(K, L, C, Ci, m), seed=5, perturb=True)
+    model = _model(K, L, C, Ci, m, "bf16", blob)
+    rng = np.random.default_rng(3)
+    Fs = [48, 7, 100, 33, 1]
+    slots = [rng.standard_normal((14, F, Ci)).astype(np.float32) for F in Fs]
+    packed = torch.from_numpy(np.concatenate([s.reshape(-1, Ci) for s in slots])).cuda()
+    say("ragged vs alone, F =", Fs)
+    mix = model.forward_ragged(packed, 14, Fs).cpu().numpy()
+    off = 0
+    for s in slots:
+        alone = _run(model, s[None]).reshape(-1, m)
+        n = s.shape[0] * s.shape[1]
+        np.testing.assert_array_equal(mix[off:off + n], alone.astype(np.float32))
+        off += n
+
+
+def test_edge_cases_and_errors():
+    from paper_2510_12739_amd import ConetError
+    K, L, C, Ci, m = 2, 1, 32, 8, 2
+    blob = make_blob(ModelConfig(K, L, C, Ci, m), seed=1)
+    model = _model(K, L, C, Ci, m, "f32", blob, max_res=14 * 40)
+    say("edge cases")
+    x0 = torch.zeros((0, 14, 8, Ci), device="cuda")
+    assert model(x0).shape == (0, 14, 8, m)
+    with pytest.raises(ConetError, match="ESHAPE"):
+        model(torch.zeros((1, 14, 41, Ci), device="cuda"))      # beyond max_res
+    with pytest.raises(ConetError, match="ESHAPE"):
+        model(torch.zeros((1, 15, 8, Ci), device="cuda"))       # more than 14 symbols
+    with pytest.raises(ValueError):
+        model(torch.zeros((1, 14, 8, Ci + 1), device="cuda"))
+    # zero input -> every RE sees only biases; with zero biases the LLR is exactly b_h = 0
+    y = model(torch.zeros((1, 14, 40, Ci), device="cuda"))
+    torch.cuda.synchronize()
+    assert torch.all(y == 0)
+
+
+# ----------------------------------------------------------------------------- BF16
+
+def test_bf16_small_grid_vs_emulated_and_fp64():
+    K, L, C, Ci, m = 3, 2, 64, 16, 4
+    blob = make_blob(ModelConfig(K, L, C, Ci, m), seed=7, perturb=True)
+    sim = SimConfig(F=72, n_rx=4, bits_per_symbol=4, seed=2)
+    X = features(sim, 2)
+    say("bf16 K=3 L=2 C=64 F=72 B=2")
+    got = _run(_model(K, L, C, Ci, m, "bf16", blob), X)
+    emu = _oracle(K, L, C, Ci, m, blob, X, quant=o.Quant("bf16"))
+    ref = _oracle(K, L, C, Ci, m, blob, X)
+    say(f'  rel-L2 vs emulated {rel_l2(got, emu):.2e}, vs fp64 {rel_l2(got, ref):.2e}, sign {sign_agree(got, ref):.4f}')
+    assert rel_l2(got, emu) <= 5e-3, rel_l2(got, emu)
+    assert rel_l2(got, ref) <= 3e-2 and sign_agree(got, ref) >= 0.99, (rel_l2(got, ref), sign_agree(got, ref))
+
+
+def test_bf16_full_size_64x3276_sampled_slots():
+    """The BF16 throughput workload at full size (64 slots of 3276 x 14), in the launch
+    configuration the benchmark times; the oracle checks three sampled slots."""
+    w = workload("bf16_b64_f3276")
+    mc = w.model
+    blob = make_blob(mc, seed=w.weight_seed)
+    sampled = [0, 37, 63]
+    X = features(w.sim, 8)
+    X = np.concatenate([X] * 8, axis=0)                       # 64 slots
+    X[37] = features(w.sim, 1, first=37)[0]
+    X[63] = features(w.sim, 1, first=63)[0]
+    say("bf16 full size 64 x 14 x 3276")
+    model = _model(mc.K, mc.L, mc.C, mc.C_in, mc.m, "bf16", blob, max_res=64 * 14 * 3276)
+    got = _run(model, X)
+    got2 = _run(model, X)
+    np.testing.assert_array_equal(got, got2)                  # deterministic
+    for s in sampled:
+        ref = _oracle(mc.K, mc.L, mc.C, mc.C_in, mc.m, blob, X[s:s + 1])
+        emu = _oracle(mc.K, mc.L, mc.C, mc.C_in, mc.m, blob, X[s:s + 1], quant=o.Quant("bf16"))
+        say(f"  slot {s}: rel-L2 vs emulated {rel_l2(got[s:s + 1], emu):.2e}, vs fp64 {rel_l2(got[s:s + 1], ref):.2e}, "
+            f"sign {sign_agree(got[s:s + 1], ref):.4f}")
+        assert rel_l2(got[s:s + 1], emu) <= 5e-3, (s, rel_l2(got[s:s + 1], emu))
+        assert rel_l2(got[s:s + 1], ref) <= 3e-2 and sign_agree(got[s:s + 1], ref) >= 0.99
+
+
+# ----------------------------------------------------------------------------- FP8
+
+def test_fp8_small_grid_vs_emulated_and_fp64():
+    K, L, C, Ci, m = 4, 2, 96, 32, 8
+    mc = ModelConfig(K, L, C, Ci, m)
+    blob = make_blob(mc, seed=11, perturb=True)
+    sim = SimConfig(F=48, n_rx=8, bits_per_symbol=8, seed=3)
+    X = features(sim, 2)
+    p = o.unpack(blob, K, L, C, Ci, m)
+    scales = o.calibrate(p, X.astype(np.float64))
+    say("fp8 K=4 L=2 C=96 F=48 B=2")
+    model = _model(K, L, C, Ci, m, "fp8", blob)
+    model.set_act_scales(scales)
+    got = _run(model, X)
+    emu = o.forward_slots(p, X.astype(np.float64), quant=o.Quant("fp8", scales))
+    ref = o.forward_slots(p, X.astype(np.float64))
+    say(f'  rel-L2 vs emulated {rel_l2(got, emu):.2e}, vs fp64 {rel_l2(got, ref):.2e}, sign {sign_agree(got, ref):.4f}')
+    assert rel_l2(got, emu) <= 6e-2, rel_l2(got, emu)
+    assert rel_l2(got, ref) <= 0.25 and sign_agree(got, ref) >= 0.93, (rel_l2(got, ref), sign_agree(got, ref))
+
+
+def test_fp8_calibration_matches_oracle_scales():
+    K, L, C, Ci, m = 2, 2, 64, 16, 4
+    mc = ModelConfig(K, L, C, Ci, m)
+    blob = make_blob(mc, seed=12, perturb=True)
+    X = features(SimConfig(F=64, n_rx=4, bits_per_symbol=4, seed=9), 2)
+    say("fp8 calibration")
+    model = _model(K, L, C, Ci, m, "fp8", blob)
+    model.calibrate(torch.from_numpy(X).cuda())
+    got = model.get_act_scales()
+    ref = o.calibrate(o.unpack(blob, K, L, C, Ci, m), X.astype(np.float64))
+    # the GPU calibrates on its own quantised forward, the oracle on exact values
+    np.testing.assert_allclose(got, ref, rtol=0.1)
+    y = _run(model, X)
+    assert np.all(np.isfinite(y))
