@@ -152,15 +152,29 @@ def main():
     stage_ms = np.array(stage_ms)                          # [steps, 1 + 2L]
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall:.2f} s)", file=sys.stderr, flush=True)
 
-    # ---- roofline of the dominant kernel (block convs: stage 1 + 2l is conv 1, 2 + 2l conv 2)
-    L = mc.L
-    conv1 = stage_ms[:, 1::2]
-    conv2 = stage_ms[:, 2::2]
-    fl_launch = mc.K * res * 2 * 9 * mc.C * mc.C       # algorithmic MFMA FLOPs of one block conv launch
-    kinds = {"block_conv1": conv1, "block_conv2_fused": conv2}
-    dom = max(kinds, key=lambda k: kinds[k].sum())
-    dom_ms = float(kinds[dom].mean())
-    achieved = fl_launch / (dom_ms * 1e-3) / 1e12
+    # ---- roofline of the dominant kernel. Stages: input layer, then per block
+    # [conv 1 of all branches, conv 2 of the supports (or of all branches without
+    # fusion), conv 2 of the main branch with product fusion + LayerNorm (+ head)].
+    mask = mc.mask
+    blk_fl = res * 2 * 9 * mc.C * mc.C                   # MFMA FLOPs of one block conv over one branch
+    kinds = {"block_conv1": [], "block_conv2_supports": [], "block_conv2_main_fused": []}
+    for l in range(mc.L):
+        fused = (mask >> l) & 1
+        last = l == mc.L - 1
+        c1 = stage_ms[:, 1 + 3 * l]
+        kinds["block_conv1"].append((c1, (mc.K if (fused or not last) else 1) * blk_fl))
+        if fused:
+            if mc.K > 1:
+                kinds["block_conv2_supports"].append((stage_ms[:, 2 + 3 * l], (mc.K - 1) * blk_fl))
+            kinds["block_conv2_main_fused"].append((stage_ms[:, 3 + 3 * l], blk_fl))
+        else:
+            kinds["block_conv2_supports"].append((stage_ms[:, 2 + 3 * l], (1 if last else mc.K) * blk_fl))
+    tot = {k: sum(float(ms.sum()) for ms, _ in v) for k, v in kinds.items() if v}
+    dom = max(tot, key=tot.get)
+    launches = kinds[dom]
+    fl_launch = float(np.mean([fl for _, fl in launches]))
+    dom_ms = float(np.mean([ms.mean() for ms, _ in launches]))
+    achieved = float(np.mean([fl / (ms.mean() * 1e-3) for ms, fl in launches])) / 1e12
     peak = PEAK_TFLOPS[dtype]
     traffic = load_traffic(dom, w.name, dtype)
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",

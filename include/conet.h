@@ -123,8 +123,11 @@ conet_status conet_forward_ragged(conet_model* model, const float* x, int32_t n_
                                   const int32_t* F_host, float* llr, void* stream);
 
 /* conet_forward on a uniform batch with a HIP event recorded on `stream` before every
- * kernel launch and after the last: stage_ms_host[i] (n_stages = 1 + 2L entries) gets
- * the elapsed time of stage i (input layer, then per block its first and second conv).
+ * kernel launch and after the last: stage_ms_host[i] (n_stages = 1 + 3L entries) gets
+ * the elapsed time of stage i: the input layer, then per block (a) its first conv over
+ * all branches, (b) the second conv of the support branches (with fusion) or of all
+ * branches (without), (c) the second conv of the main branch with the product fusion,
+ * LayerNorm and, after the last block, the LLR head (0 without fusion).
  * Synchronises on the last event. Errors as conet_forward. */
 conet_status conet_forward_profiled(conet_model* model, const float* x, int32_t B, int32_t T, int32_t F, float* llr,
                                     float* stage_ms_host, int32_t n_stages, void* stream);

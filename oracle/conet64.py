@@ -282,9 +282,10 @@ def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Opti
                 lev["h"].append(h); lev["mrb"].append(mrb)
         last = (l == L)
         if fused_after(mask, l):
-            P = np.ones_like(O[0])
-            for k in range(K):
-                P = P * O[k]
+            # the support outputs enter the product as stored (rounded under emulation)
+            P = O[0].copy()
+            for k in range(1, K):
+                P = P * q.store(O[k])
             mu = P.mean(axis=-1, keepdims=True)
             var = ((P - mu) ** 2).mean(axis=-1, keepdims=True)
             sig = np.sqrt(var + LN_EPS)

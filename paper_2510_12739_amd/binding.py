@@ -160,13 +160,13 @@ class Conet:
     __call__ = forward
 
     def forward_profiled(self, x, out=None, stream=None):
-        """forward() with per-stage HIP event timing: returns (llr, stage_ms[1 + 2L])."""
+        """forward() with per-stage HIP event timing: returns (llr, stage_ms[1 + 3L])."""
         import torch
         self._check_x(x)
         B, T, F, _ = x.shape
         if out is None:
             out = torch.empty((B, T, F, self.m), dtype=torch.float32, device=x.device)
-        ms = np.zeros(1 + 2 * self.L, dtype=np.float32)
+        ms = np.zeros(1 + 3 * self.L, dtype=np.float32)
         _check(self.lib.conet_forward_profiled(self.handle, ctypes.c_void_p(x.data_ptr()), B, T, F,
                                                ctypes.c_void_p(out.data_ptr()),
                                                ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ms.size,

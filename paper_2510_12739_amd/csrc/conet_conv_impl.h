@@ -1,15 +1,15 @@
 // 3x3 implicit-GEMM convolution kernels of the CoNet-Rx forward pass (gfx950).
 //
 // One work-group owns one tile: a slot, all of its T <= 14 OFDM symbols and TW
-// consecutive subcarriers. The tile's input (with a one-RE zero halo on every side,
-// padding taken inside the slot) is staged once into LDS in the MFMA operand type;
-// the optional pre-activation prologue (affine + ReLU, or ReLU) and FP8 quantisation
-// are applied during staging. Each wave then runs the GEMM
+// consecutive subcarriers, for one branch. The tile's input (with a one-RE zero halo
+// on every side, padding taken inside the slot) is staged once into LDS in the MFMA
+// operand type; the pre-activation prologue (affine + ReLU, or ReLU) and FP8
+// quantisation are applied while staging. Each wave then runs the GEMM
 //     D^T[o, re] = sum_k W[o, k] * X^T[k, re],   k = (tap, channel)
 // on 16x16 MFMA tiles: the A operand is the filter, pre-packed on the host in the
-// exact per-lane fragment order (one coalesced 16-byte load per lane), and the B
-// operand is read from LDS as 16-byte chunks of consecutive channels at the
-// tap-shifted position. The epilogue works on FP32 accumulators in registers:
+// exact per-lane fragment order (one coalesced 16-byte load per lane, prefetched one
+// K step ahead), and the B operand is read from LDS as 16-byte chunks of consecutive
+// channels at the tap-shifted position. The epilogue works on FP32 accumulators:
 // bias, per-channel affine, ReLU, residual add, the K-way product fusion with the
 // per-RE channel LayerNorm, and the 1x1 LLR head.
 //
@@ -17,6 +17,10 @@
 // holds channel g*4*NOT + 4*ot + i, so every lane owns 4*NOT consecutive channels of
 // one RE and stores them with wide vector writes. The host packs filters with the
 // same permutation.
+//
+// Register budget: every kernel is built for two work-groups per CU (<= 256 VGPR +
+// AGPR per lane, LDS tile <= 80 KB), so one work-group's staging overlaps the other's
+// MFMA loop.
 #pragma once
 #include "conet_common.h"
 #include "conet_kernels.h"
@@ -26,7 +30,6 @@ namespace conet {
 // ---------------------------------------------------------------- vector IO helpers
 template <class T>
 __device__ __forceinline__ void load_vals(const T* p, float* v, int n) {
-  // n consecutive elements (n * sizeof(T) is a multiple of 8 bytes, 8-byte aligned)
   if constexpr (sizeof(T) == 4) {
 #pragma unroll
     for (int i = 0; i < n; i += 4) {
@@ -45,11 +48,6 @@ __device__ __forceinline__ void load_vals(const T* p, float* v, int n) {
 #pragma unroll
     for (int i = 0; i < n; ++i) v[i] = (float)p[i];
   }
-}
-
-__device__ __forceinline__ void load_vals(const double* p, double* v, int n) {
-#pragma unroll
-  for (int i = 0; i < n; ++i) v[i] = p[i];
 }
 
 template <class T, class V>
@@ -96,86 +94,101 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
   return (bid & 7) * (nb >> 3) + (bid >> 3);
 }
 
+// ---------------------------------------------------------------- shapes
+template <class A, int CIN>
+constexpr int lds_pitch() {
+  int p = CIN * (int)sizeof(typename A::Op);
+  return ((p / 16) % 2 == 0) ? p + 16 : p;  // odd multiple of 16 B: conflict-free 16-B reads
+}
+
+// 32 subcarriers per tile unless the halo tile would not leave room for two
+// work-groups per CU, or the channel count would exceed the per-lane register budget.
+template <class A, int CIN, int COUT>
+constexpr int tile_w() {
+  return (COUT > 64 || TROWS * 34 * lds_pitch<A, CIN>() > 80 * 1024) ? 16 : 32;
+}
+
 // ---------------------------------------------------------------- staging
-// Stage the (TROWS) x (TW+2) halo tile of `in` (CIN channels of InT per RE) into LDS
-// as Op with row pitch PITCH bytes, applying prologue and quantisation.
+// Stage the TROWS x (TW+2) halo tile of `in` (CIN channels of InT per RE) into LDS as
+// Op with PITCH bytes per position. Thread `tid` always handles the same channel chunk
+// (its prologue parameters stay in registers); loads are issued in batches of NB
+// positions before any is consumed, so their latencies overlap.
 template <class A, class InT, int CIN, int TW, int PITCH, int NT>
 __device__ __forceinline__ void stage_tile(uint8_t* lds, const InT* __restrict__ in, const TileDesc& td, int T,
                                            int prologue, const float* __restrict__ ps, const float* __restrict__ po,
                                            float qscale) {
   using Op = typename A::Op;
-  constexpr int EPC = 16 / sizeof(InT) < 4 ? 4 : 16 / sizeof(InT);  // elements per global chunk
-  constexpr int CPP = CIN / EPC;                                       // chunks per position
+  constexpr int EPC = 16 / sizeof(InT) < 4 ? 4 : 16 / (int)sizeof(InT);  // elements per 16-B global chunk
+  constexpr int CPP = CIN / EPC;                                          // chunks per position
   constexpr int NPOS = TROWS * (TW + 2);
-  static_assert(CIN % EPC == 0, "channel count must fill whole 16-byte chunks");
-  for (int idx = threadIdx.x; idx < NPOS * CPP; idx += NT) {
-    const int pos = idx / CPP, cc = idx - pos * CPP;
-    const int r = pos / (TW + 2), c = pos - r * (TW + 2);
-    const int t = r - 1, f = td.f0 + c - 1;
-    const int ch = cc * EPC;
-    float v[EPC];
-    if (t >= 0 && t < T && f >= 0 && f < td.F) {
-      const InT* src = in + (td.re_base + (int64_t)t * td.F + f) * CIN + ch;
-      if constexpr (std::is_same<InT, Op>::value && sizeof(InT) <= 4) {  // stored as the operand: copy
-        if (prologue == 0) {
-          *reinterpret_cast<i32x4*>(lds + r * (TW + 2) * PITCH + c * PITCH + ch * sizeof(Op)) =
-              *reinterpret_cast<const i32x4*>(src);
+  constexpr int PPR = NT / CPP;                                           // positions per round
+  constexpr int NIT = (NPOS + PPR - 1) / PPR;
+  constexpr int NB = 8;
+  static_assert(CIN % EPC == 0 && sizeof(InT) <= 4, "channel count must fill whole 16-byte chunks");
+  const int tid = threadIdx.x;
+  if (tid >= PPR * CPP) return;
+  const int cc = tid % CPP, p0 = tid / CPP, ch = cc * EPC;
+  constexpr bool COPY = std::is_same<InT, Op>::value;
+  float sv[EPC], ov[EPC];
+  if (prologue == 1) {
+#pragma unroll
+    for (int i = 0; i < EPC; ++i) { sv[i] = ps[ch + i]; ov[i] = po[ch + i]; }
+  }
+#pragma unroll 1
+  for (int b0 = 0; b0 < NIT; b0 += NB) {
+    i32x4 raw[NB];
+    bool ok[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int pos = p0 + (b0 + j) * PPR;
+      const int r = pos / (TW + 2), c = pos - r * (TW + 2);
+      const int t = r - 1, f = td.f0 + c - 1;
+      ok[j] = (b0 + j < NIT) && pos < NPOS && t >= 0 && t < T && f >= 0 && f < td.F;
+      raw[j] = i32x4{0, 0, 0, 0};
+      if (ok[j]) raw[j] = *reinterpret_cast<const i32x4*>(in + (td.re_base + (int64_t)t * td.F + f) * CIN + ch);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int pos = p0 + (b0 + j) * PPR;
+      if (b0 + j >= NIT || pos >= NPOS) continue;
+      uint8_t* dst = lds + pos * PITCH + ch * (int)sizeof(Op);
+      if constexpr (COPY) {
+        if (prologue == 0) {  // stored in the operand type already (zero where out of the slot)
+          *reinterpret_cast<i32x4*>(dst) = raw[j];
           continue;
         }
       }
-      if constexpr (sizeof(InT) == 1) {  // fp8 operand stored by the producer: copy bytes
-        *reinterpret_cast<i32x4*>(lds + r * (TW + 2) * PITCH + c * PITCH + ch) = *reinterpret_cast<const i32x4*>(src);
-        continue;
-      } else if constexpr (sizeof(InT) == 8) {
+      float v[EPC];
+      const InT* rv = reinterpret_cast<const InT*>(&raw[j]);
 #pragma unroll
-        for (int i = 0; i < EPC; ++i) v[i] = 0.f;
-        double dv[EPC];
+      for (int i = 0; i < EPC; ++i) v[i] = (float)rv[i];
+      if (prologue == 1) {
 #pragma unroll
-        for (int i = 0; i < EPC; ++i) dv[i] = (double)src[i];
-        if (prologue) {
+        for (int i = 0; i < EPC; ++i) v[i] = fmaxf(sv[i] * v[i] + ov[i], 0.f);
+      } else if (prologue == 2) {
 #pragma unroll
-          for (int i = 0; i < EPC; ++i) {
-            double z = prologue == 1 ? (double)ps[ch + i] * dv[i] + (double)po[ch + i] : dv[i];
-            dv[i] = z > 0.0 ? z : 0.0;
-          }
+        for (int i = 0; i < EPC; ++i) v[i] = fmaxf(v[i], 0.f);
+      }
+      if (!ok[j]) {
+#pragma unroll
+        for (int i = 0; i < EPC; ++i) v[i] = 0.f;  // zero padding applies after the prologue
+      }
+      if constexpr (sizeof(Op) == 1) {
+#pragma unroll
+        for (int i = 0; i < EPC; i += 4)
+          *reinterpret_cast<uint32_t*>(dst + i) =
+              pack4_e4m3(v[i] * qscale, v[i + 1] * qscale, v[i + 2] * qscale, v[i + 3] * qscale);
+      } else if constexpr (sizeof(Op) == 2) {
+#pragma unroll
+        for (int i = 0; i < EPC; i += 4) {
+          __bf16 bb[4] = {f2bf(v[i]), f2bf(v[i + 1]), f2bf(v[i + 2]), f2bf(v[i + 3])};
+          *reinterpret_cast<uint2*>(dst + 2 * i) = *reinterpret_cast<const uint2*>(bb);
         }
-        Op* dst = reinterpret_cast<Op*>(lds + r * (TW + 2) * PITCH + c * PITCH) + ch;
-#pragma unroll
-        for (int i = 0; i < EPC; ++i) dst[i] = (Op)dv[i];
-        continue;
       } else {
-        load_vals(src, v, EPC);
-        if (prologue == 1) {
 #pragma unroll
-          for (int i = 0; i < EPC; ++i) v[i] = fmaxf(ps[ch + i] * v[i] + po[ch + i], 0.f);
-        } else if (prologue == 2) {
-#pragma unroll
-          for (int i = 0; i < EPC; ++i) v[i] = fmaxf(v[i], 0.f);
-        }
+        for (int i = 0; i < EPC; i += 4)
+          *reinterpret_cast<float4*>(dst + 4 * i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
       }
-    } else {
-#pragma unroll
-      for (int i = 0; i < EPC; ++i) v[i] = 0.f;
-    }
-    uint8_t* dst = lds + r * (TW + 2) * PITCH + c * PITCH + ch * sizeof(Op);
-    if constexpr (sizeof(Op) == 1) {
-      static_assert(EPC % 4 == 0, "");
-#pragma unroll
-      for (int i = 0; i < EPC; i += 4)
-        *reinterpret_cast<uint32_t*>(dst + i) = pack4_e4m3(v[i] * qscale, v[i + 1] * qscale, v[i + 2] * qscale, v[i + 3] * qscale);
-    } else if constexpr (sizeof(Op) == 2) {
-#pragma unroll
-      for (int i = 0; i < EPC; i += 4) {
-        __bf16 b[4] = {f2bf(v[i]), f2bf(v[i + 1]), f2bf(v[i + 2]), f2bf(v[i + 3])};
-        *reinterpret_cast<uint2*>(dst + 2 * i) = *reinterpret_cast<const uint2*>(b);
-      }
-    } else if constexpr (sizeof(Op) == 4) {
-#pragma unroll
-      for (int i = 0; i < EPC; i += 4)
-        *reinterpret_cast<float4*>(dst + 4 * i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < EPC; ++i) reinterpret_cast<double*>(dst)[i] = (double)v[i];
     }
   }
 }
@@ -183,7 +196,7 @@ __device__ __forceinline__ void stage_tile(uint8_t* lds, const InT* __restrict__
 // ---------------------------------------------------------------- GEMM core
 // acc[mt][ot] += W (o-tile ot) x X^T (M-tile mt) over all K steps. M-tile mt of this
 // wave is global M-tile index wave + NW*mt: OFDM symbol t = idx / (TW/16), subcarrier
-// block cb = idx % (TW/16).
+// block cb = idx % (TW/16). Rows t >= T read the zero rows staged for them.
 template <class A, int CIN, int COUT, int TW, int PITCH, int NW>
 struct Gemm {
   static constexpr int NOT = COUT / 16;
@@ -198,70 +211,66 @@ struct Gemm {
 
   using AccV = typename A::AccV;
 
+  __device__ __forceinline__ static void load_a(i32x4 (&a)[NOT][A::CPL], const i32x4* __restrict__ wp, int s,
+                                                int lane) {
+#pragma unroll
+    for (int ot = 0; ot < NOT; ++ot)
+#pragma unroll
+      for (int c = 0; c < A::CPL; ++c) a[ot][c] = wp[((s * NOT + ot) * A::CPL + c) * 64 + lane];
+  }
+
   __device__ __forceinline__ static void run(AccV (&acc)[MT][NOT], const uint8_t* lds, const i32x4* __restrict__ wp,
-                                             int T, int wave, int lane) {
+                                             int wave, int lane) {
     const int g = lane >> 4, col = lane & 15;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int ot = 0; ot < NOT; ++ot) acc[mt][ot] = AccV{};
-    // base LDS byte offset of each of this wave's M-tiles for tap (0,0) (top-left)
+    // LDS byte offset of this lane's RE in each M-tile, for tap (-1, -1) (top-left)
     int base[MT];
-    bool live[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-      const int idx = wave + NW * mt;
+      int idx = wave + NW * mt;
+      if (idx >= MTOT) idx = MTOT - 1;  // surplus tile of an uneven split: recompute a real one
       const int t = idx / (TW / 16), cb = idx - t * (TW / 16);
-      live[mt] = (idx < MTOT) && (t < T);
       base[mt] = (t * (TW + 2) + cb * 16 + col) * PITCH;
     }
-#pragma unroll 2
+    i32x4 a0[NOT][A::CPL], a1[NOT][A::CPL];
+    load_a(a0, wp, 0, lane);
+#pragma unroll
     for (int s = 0; s < NS; ++s) {
-      i32x4 af[NOT][A::CPL];
-#pragma unroll
-      for (int ot = 0; ot < NOT; ++ot)
-#pragma unroll
-        for (int c = 0; c < A::CPL; ++c) af[ot][c] = wp[((s * NOT + ot) * A::CPL + c) * 64 + lane];
+      i32x4 (&ac)[NOT][A::CPL] = (s & 1) ? a1 : a0;
+      i32x4 (&an)[NOT][A::CPL] = (s & 1) ? a0 : a1;
+      if (s + 1 < NS) load_a(an, wp, s + 1, lane);
       int off[A::CPL];
 #pragma unroll
       for (int c = 0; c < A::CPL; ++c) {
         int ch = (s * 4 + g) * A::CPL + c;
-        if (ch >= NCH) ch = 4 * CPT;  // padding chunk: any in-tile address (weights are 0)
+        if (ch >= NCH) ch = 4 * CPT;  // padding chunk: any in-tile address (its weights are 0)
         const int tap = ch / CPT, c0 = (ch - tap * CPT) * A::VEC;
         off[c] = ((tap / 3) * (TW + 2) + (tap % 3)) * PITCH + c0 * (int)sizeof(typename A::Op);
       }
+      i32x4 bf[MT][A::CPL];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        if (!live[mt]) continue;
-        i32x4 bf[A::CPL];
+      for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int c = 0; c < A::CPL; ++c) bf[c] = *reinterpret_cast<const i32x4*>(lds + base[mt] + off[c]);
+        for (int c = 0; c < A::CPL; ++c) bf[mt][c] = *reinterpret_cast<const i32x4*>(lds + base[mt] + off[c]);
 #pragma unroll
-        for (int ot = 0; ot < NOT; ++ot) acc[mt][ot] = A::mma(af[ot], bf, acc[mt][ot]);
-      }
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int ot = 0; ot < NOT; ++ot) acc[mt][ot] = A::mma(ac[ot], bf[mt], acc[mt][ot]);
     }
   }
 };
 
-template <class A, int CIN>
-constexpr int lds_pitch() {
-  int p = CIN * (int)sizeof(typename A::Op);
-  return ((p / 16) % 2 == 0) ? p + 16 : p;
-}
-
-// 32 subcarriers per tile unless the halo tile would not leave room for two
-// work-groups per CU, or the per-lane register budget of wide channel counts.
-template <class A, int CIN, int COUT>
-constexpr int tile_w() {
-  return (COUT > 64 || TROWS * 34 * lds_pitch<A, CIN>() > 80 * 1024) ? 16 : 32;
-}
-
 // ---------------------------------------------------------------- the kernel
-// MODE: 0 input layer, 1 first conv of a block, 2 second conv (+ residual) per branch,
-// 3 second conv of all branches + product fusion + LayerNorm (+ head).
+// MODE 0: input layer            out = ReLU(conv(X) + b)
+// MODE 1: first conv of a block  out = ReLU(s1 (conv(prologue(x)) + b1) + o1)   (or its max, calibration)
+// MODE 2: second conv            out = x + conv(h) + b2; branch 0 of the last unfused block feeds the head
+// MODE 4: second conv of the main net + fusion: O0 = x0 + conv(h0) + b2, P = O0 * prod_k sup_k
+//         (the support outputs of this block, already stored), A = gamma LN(P) + beta -> out or head
 template <class A, int MODE, int CIN, int COUT, int TW, int NW>
-__global__ void __launch_bounds__(NW * 64) conv3x3_kernel(ConvArgs args) {
-  using Op = typename A::Op;
+__global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
   using Acc = typename A::Acc;
   using AccV = typename A::AccV;
   using Act = typename A::Act;
@@ -280,156 +289,102 @@ __global__ void __launch_bounds__(NW * 64) conv3x3_kernel(ConvArgs args) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, col = lane & 15;
   const int c0 = g * EPL;  // first channel owned by this lane
+  const int k = blockIdx.y + args.k_off;
 
-  // (t, f) of this lane's RE in each M-tile
-  auto re_of = [&](int mt, int& t, int& f) {
-    const int idx = wave + NW * mt;
-    t = idx / (TW / 16);
-    f = td.f0 + (idx - t * (TW / 16)) * 16 + col;
-  };
+  int prologue = 0;
+  if (MODE == 1) prologue = args.pre_s[k] ? 1 : 2;
+  stage_tile<A, InT, CIN, TW, PITCH, NT>(lds, reinterpret_cast<const InT*>(args.in[k]), td, T, prologue,
+                                         args.pre_s[k], args.pre_o[k], args.in_qscale[k]);
+  __syncthreads();
+  AccV acc[MT][NOT];
+  G::run(acc, lds, reinterpret_cast<const i32x4*>(args.wpack[k]), wave, lane);
 
-  if constexpr (MODE != 3) {
-    const int k = blockIdx.y;
-    const InT* in = reinterpret_cast<const InT*>(args.in[k]);
-    int prologue = 0;
-    if (MODE == 1) prologue = args.pre_s[k] ? 1 : 2;
-    stage_tile<A, InT, CIN, TW, PITCH, NT>(lds, in, td, T, prologue, args.pre_s[k], args.pre_o[k], args.in_qscale[k]);
-    __syncthreads();
-    AccV acc[MT][NOT];
-    G::run(acc, lds, reinterpret_cast<const i32x4*>(args.wpack[k]), T, wave, lane);
-
+  // per-lane epilogue parameters (this lane's EPL channels), loaded once
+  float pb[EPL], pq[EPL];
+  {
     const float* bias = args.bias[k];
     const float* ws = args.wscale[k];
-    const float deq = args.deq[k];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      int t, f;
-      re_of(mt, t, f);
-      if (wave + NW * mt >= G::MTOT || t >= T || f >= td.F) continue;
-      const int64_t re = td.re_base + (int64_t)t * td.F + f;
-      Acc v[EPL];
-#pragma unroll
-      for (int ot = 0; ot < NOT; ++ot)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int ch = c0 + 4 * ot + i;
-          Acc a = acc[mt][ot][i];
-          if constexpr (A::QUANT) a = a * (Acc)(deq * ws[ch]);
-          v[4 * ot + i] = a + (Acc)bias[ch];
-        }
-      if constexpr (MODE == 0) {
-#pragma unroll
-        for (int i = 0; i < EPL; ++i) v[i] = v[i] > (Acc)0 ? v[i] : (Acc)0;
-        store_vals(reinterpret_cast<Act*>(args.out[k]) + re * COUT + c0, v, EPL, 1.f);
-      } else if constexpr (MODE == 1) {
-        const float* s1 = args.post_s[k];
-        const float* o1 = args.post_o[k];
-#pragma unroll
-        for (int i = 0; i < EPL; ++i) {
-          Acc z = (Acc)s1[c0 + i] * v[i] + (Acc)o1[c0 + i];
-          v[i] = z > (Acc)0 ? z : (Acc)0;
-        }
-        if (args.amax) {  // calibration: record max |h| of this branch instead of storing
-          Acc mx = 0;
-#pragma unroll
-          for (int i = 0; i < EPL; ++i) mx = v[i] > mx ? v[i] : mx;
-          atomicMax(args.amax + k, __float_as_uint((float)mx));
-        } else {
-          store_vals(reinterpret_cast<Hid*>(args.out[k]) + re * COUT + c0, v, EPL, args.out_qscale[k]);
-        }
-      } else {  // MODE 2: residual add; branch 0 of the last block feeds the head
-        Acc x[EPL];
-        load_vals(reinterpret_cast<const Act*>(args.resid[k]) + re * COUT + c0, x, EPL);
-#pragma unroll
-        for (int i = 0; i < EPL; ++i) v[i] += x[i];
-        if (args.llr && k == 0) {
-          Acc part[8];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            part[j] = 0;
-            if (j < args.m)
-#pragma unroll
-              for (int i = 0; i < EPL; ++i) part[j] += (Acc)args.Wh[j * COUT + c0 + i] * v[i];
-          }
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            part[j] += __shfl_xor(part[j], 16);
-            part[j] += __shfl_xor(part[j], 32);
-          }
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            if (j < args.m && (j & 3) == g) args.llr[re * args.m + j] = (float)(part[j] + (Acc)args.bh[j]);
-        } else if (args.out[k]) {
-          store_vals(reinterpret_cast<Act*>(args.out[k]) + re * COUT + c0, v, EPL, 1.f);
-        }
-      }
+    for (int i = 0; i < EPL; ++i) {
+      pb[i] = bias[c0 + i];
+      pq[i] = A::QUANT ? args.deq[k] * ws[c0 + i] : 1.0f;
     }
-  } else {
-    // ---- all K branches of the second conv in this work-group, product held in registers
-    Acc P[MT][EPL];
+  }
+  float ps1[MODE == 1 ? EPL : 1], po1[MODE == 1 ? EPL : 1];
+  if constexpr (MODE == 1) {
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int i = 0; i < EPL; ++i) { ps1[i] = args.post_s[k][c0 + i]; po1[i] = args.post_o[k][c0 + i]; }
+  }
+  unsigned amax_bits = 0;
+
 #pragma unroll
-      for (int i = 0; i < EPL; ++i) P[mt][i] = (Acc)1;
-    for (int k = 0; k < args.K; ++k) {
-      if (k) __syncthreads();  // LDS reuse
-      stage_tile<A, InT, CIN, TW, PITCH, NT>(lds, reinterpret_cast<const InT*>(args.in[k]), td, T, 0, nullptr,
-                                             nullptr, args.in_qscale[k]);
-      __syncthreads();
-      AccV acc[MT][NOT];
-      G::run(acc, lds, reinterpret_cast<const i32x4*>(args.wpack[k]), T, wave, lane);
-      const float* bias = args.bias[k];
-      const float* ws = args.wscale[k];
-      const float deq = args.deq[k];
+  for (int mt = 0; mt < MT; ++mt) {
+    const int idx = wave + NW * mt;
+    const int t = idx / (TW / 16);
+    const int f = td.f0 + (idx - t * (TW / 16)) * 16 + col;
+    if (idx >= G::MTOT || t >= T || f >= td.F) continue;
+    const int64_t re = td.re_base + (int64_t)t * td.F + f;
+    Acc v[EPL];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        int t, f;
-        re_of(mt, t, f);
-        if (wave + NW * mt >= G::MTOT || t >= T || f >= td.F) continue;
-        const int64_t re = td.re_base + (int64_t)t * td.F + f;
-        Acc x[EPL], v[EPL];
-        load_vals(reinterpret_cast<const Act*>(args.resid[k]) + re * COUT + c0, x, EPL);
+    for (int ot = 0; ot < NOT; ++ot)
 #pragma unroll
-        for (int ot = 0; ot < NOT; ++ot)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int ch = c0 + 4 * ot + i;
-            Acc a = acc[mt][ot][i];
-            if constexpr (A::QUANT) a = a * (Acc)(deq * ws[ch]);
-            v[4 * ot + i] = x[4 * ot + i] + a + (Acc)bias[ch];
-          }
-        if (args.out[k] && k > 0) store_vals(reinterpret_cast<Act*>(args.out[k]) + re * COUT + c0, v, EPL, 1.f);
-        if (args.save_o[k]) store_vals(reinterpret_cast<Act*>(args.save_o[k]) + re * COUT + c0, v, EPL, 1.f);
-#pragma unroll
-        for (int i = 0; i < EPL; ++i) P[mt][i] *= v[i];
+      for (int i = 0; i < 4; ++i) {
+        Acc a = acc[mt][ot][i];
+        if constexpr (A::QUANT) a = a * (Acc)pq[4 * ot + i];
+        v[4 * ot + i] = a + (Acc)pb[4 * ot + i];
       }
-    }
-    // ---- per-RE LayerNorm over the C channels (4 lanes x EPL channels)
-    const Acc invC = (Acc)1 / (Acc)COUT;
+    if constexpr (MODE == 0) {
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      int t, f;
-      re_of(mt, t, f);
-      if (wave + NW * mt >= G::MTOT || t >= T || f >= td.F) continue;
-      const int64_t re = td.re_base + (int64_t)t * td.F + f;
-      Acc s = 0;
+      for (int i = 0; i < EPL; ++i) v[i] = v[i] > (Acc)0 ? v[i] : (Acc)0;
+      store_vals(reinterpret_cast<Act*>(args.out[k]) + re * COUT + c0, v, EPL, 1.f);
+    } else if constexpr (MODE == 1) {
 #pragma unroll
-      for (int i = 0; i < EPL; ++i) s += P[mt][i];
-      s += __shfl_xor(s, 16);
-      s += __shfl_xor(s, 32);
-      const Acc mu = s * invC;
-      Acc q = 0;
+      for (int i = 0; i < EPL; ++i) {
+        const Acc z = (Acc)ps1[i] * v[i] + (Acc)po1[i];
+        v[i] = z > (Acc)0 ? z : (Acc)0;
+      }
+      if (args.amax) {
+        float mx = 0.f;
 #pragma unroll
-      for (int i = 0; i < EPL; ++i) { const Acc d = P[mt][i] - mu; q += d * d; }
-      q += __shfl_xor(q, 16);
-      q += __shfl_xor(q, 32);
-      Acc rs;
-      if constexpr (sizeof(Acc) == 8) rs = (Acc)1 / sqrt(q * invC + (Acc)args.eps);
-      else rs = (Acc)1 / sqrtf(q * invC + (Acc)args.eps);
-      Acc v[EPL];
+        for (int i = 0; i < EPL; ++i) mx = fmaxf(mx, (float)v[i]);
+        amax_bits = max(amax_bits, __float_as_uint(mx));
+      } else {
+        store_vals(reinterpret_cast<Hid*>(args.out[k]) + re * COUT + c0, v, EPL, args.out_qscale[k]);
+      }
+    } else {
+      Acc x[EPL];
+      load_vals(reinterpret_cast<const Act*>(args.resid[k]) + re * COUT + c0, x, EPL);
 #pragma unroll
-      for (int i = 0; i < EPL; ++i) v[i] = (Acc)args.gamma[c0 + i] * (P[mt][i] - mu) * rs + (Acc)args.beta[c0 + i];
-      if (args.llr) {
+      for (int i = 0; i < EPL; ++i) v[i] += x[i];
+      bool head = false;
+      if constexpr (MODE == 2) {
+        head = args.llr && k == 0;
+        if (!head && args.out[k]) store_vals(reinterpret_cast<Act*>(args.out[k]) + re * COUT + c0, v, EPL, 1.f);
+      } else {  // MODE 4: product with the stored support outputs, then LayerNorm over C
+        for (int kk = 1; kk < args.K; ++kk) {
+          Acc sv[EPL];
+          load_vals(reinterpret_cast<const Act*>(args.sup[kk]) + re * COUT + c0, sv, EPL);
+#pragma unroll
+          for (int i = 0; i < EPL; ++i) v[i] *= sv[i];
+        }
+        Acc s = 0;
+#pragma unroll
+        for (int i = 0; i < EPL; ++i) s += v[i];
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        const Acc mu = s * ((Acc)1 / (Acc)COUT);
+        Acc q = 0;
+#pragma unroll
+        for (int i = 0; i < EPL; ++i) { const Acc d = v[i] - mu; q += d * d; }
+        q += __shfl_xor(q, 16);
+        q += __shfl_xor(q, 32);
+        const Acc rs = (Acc)1 / sqrtf((float)(q * ((Acc)1 / (Acc)COUT) + (Acc)args.eps));
+#pragma unroll
+        for (int i = 0; i < EPL; ++i) v[i] = (Acc)args.gamma[c0 + i] * (v[i] - mu) * rs + (Acc)args.beta[c0 + i];
+        head = args.llr != nullptr;
+        if (!head && args.out[0]) store_vals(reinterpret_cast<Act*>(args.out[0]) + re * COUT + c0, v, EPL, 1.f);
+      }
+      if (head) {
         Acc part[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -447,7 +402,12 @@ __global__ void __launch_bounds__(NW * 64) conv3x3_kernel(ConvArgs args) {
         for (int j = 0; j < 8; ++j)
           if (j < args.m && (j & 3) == g) args.llr[re * args.m + j] = (float)(part[j] + (Acc)args.bh[j]);
       }
-      if (args.out[0]) store_vals(reinterpret_cast<Act*>(args.out[0]) + re * COUT + c0, v, EPL, 1.f);
+    }
+  }
+  if constexpr (MODE == 1) {
+    if (args.amax) {  // calibration: one atomic per lane group
+      for (int o = 32; o > 0; o >>= 1) amax_bits = max(amax_bits, (unsigned)__shfl_xor((int)amax_bits, o));
+      if (lane == 0) atomicMax(args.amax + k, amax_bits);
     }
   }
 }
@@ -464,12 +424,14 @@ static hipError_t launch_one(ConvArgs& a, int n_tiles, int grid_y, hipStream_t s
 
 template <class A, int CIN, int COUT>
 static hipError_t launch_mode(int mode, ConvArgs& a, int n_tiles, int grid_y, hipStream_t s) {
-  switch (mode) {
-    case 0: return launch_one<A, 0, CIN, COUT>(a, n_tiles, grid_y, s);
-    case 1: return launch_one<A, 1, CIN, COUT>(a, n_tiles, grid_y, s);
-    case 2: return launch_one<A, 2, CIN, COUT>(a, n_tiles, grid_y, s);
-    case 3: return launch_one<A, 3, CIN, COUT>(a, n_tiles, grid_y, s);
+  if (CIN == COUT) {  // block convs
+    switch (mode) {
+      case 1: return launch_one<A, 1, CIN, COUT>(a, n_tiles, grid_y, s);
+      case 2: return launch_one<A, 2, CIN, COUT>(a, n_tiles, grid_y, s);
+      case 4: return launch_one<A, 4, CIN, COUT>(a, n_tiles, grid_y, s);
+    }
   }
+  if (mode == 0) return launch_one<A, 0, CIN, COUT>(a, n_tiles, grid_y, s);
   return hipErrorInvalidValue;
 }
 

@@ -1,12 +1,13 @@
 // Launch sequence of the CoNet-Rx forward pass and the FP8 calibration pass.
 //
-// Stage order (2L + 1 launches; the paper's sequential depth is 2L + 2 conv layers
-// with the head fused into the last one):
+// Stage order (the paper's sequential depth is 2L + 2 conv layers; the head is fused
+// into the last one):
 //   input layer of all K branches (one launch, grid.y = branch)
-//   for each block l: first conv of every branch (grid.y = branch), then the second
-//   conv: with fusion after block l, one work-group computes all K branches of its
-//   tile and applies product + LayerNorm (and the head after the last block);
-//   without fusion each branch adds its residual on its own.
+//   for each block l: first conv of every branch (grid.y = branch); then, with fusion
+//   after block l, the second conv of the support branches (their outputs are stored)
+//   followed by the second conv of the main branch, whose epilogue multiplies in the
+//   stored support outputs and applies the LayerNorm (and the head after the last
+//   block); without fusion, the second conv of every branch in one launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -206,7 +207,6 @@ conet_status run_forward(conet_model* M, const float* x, const Geometry& geo, fl
       const float* vb = vec + lay.v_blk[k][l];
       a2.in[k] = hidp(k);
       a2.resid[k] = actp(cur, k);
-      a2.out[k] = last ? nullptr : actp(1 - cur, k);
       a2.wpack[k] = ws + lay.w2[k][l];
       a2.bias[k] = vb + 5 * C;
       a2.wscale[k] = vb + 7 * C;
@@ -220,11 +220,35 @@ conet_status run_forward(conet_model* M, const float* x, const Geometry& geo, fl
     a2.Wh = vec + lay.v_wh;
     a2.bh = vec + lay.v_bh;
     a2.m = c.bits_per_symbol;
-    a2.llr = (last && !calib) ? llr : nullptr;
-    e = mark();
-    if (e == hipSuccess)
-      e = fuse ? launch_conv(dt, 3, C, C, a2, n_tiles_blk, 1, s) : launch_conv(dt, 2, C, C, a2, n_tiles_blk, nk, s);
-    if (e != hipSuccess) return hip_fail(e, "block conv 2 launch");
+    if (fuse) {
+      // support branches first (their outputs are stored: the next block's inputs and
+      // this block's product operands), then the main branch with the fusion epilogue
+      if (K > 1) {
+        ConvArgs as = a2;
+        for (int k = 1; k < K; ++k) as.out[k] = actp(1 - cur, k);
+        as.k_off = 1;
+        e = mark();
+        if (e == hipSuccess) e = launch_conv(dt, 2, C, C, as, n_tiles_blk, K - 1, s);
+        if (e != hipSuccess) return hip_fail(e, "support conv 2 launch");
+      } else {
+        e = mark();
+      }
+      ConvArgs am = a2;
+      for (int k = 1; k < K; ++k) am.sup[k] = actp(1 - cur, k);
+      am.out[0] = last ? nullptr : actp(1 - cur, 0);
+      am.llr = (last && !calib) ? llr : nullptr;
+      am.k_off = 0;
+      e = mark();
+      if (e == hipSuccess) e = launch_conv(dt, 4, C, C, am, n_tiles_blk, 1, s);
+      if (e != hipSuccess) return hip_fail(e, "fused conv 2 launch");
+    } else {
+      for (int k = 0; k < nk; ++k) a2.out[k] = last ? nullptr : actp(1 - cur, k);
+      a2.llr = (last && !calib) ? llr : nullptr;
+      e = mark();
+      if (e == hipSuccess) e = launch_conv(dt, 2, C, C, a2, n_tiles_blk, nk, s);
+      if (e == hipSuccess) e = mark();  // no third launch in an unfused block
+      if (e != hipSuccess) return hip_fail(e, "block conv 2 launch");
+    }
     cur = 1 - cur;
     fused_prev = fuse;
   }
@@ -256,7 +280,7 @@ extern "C" conet_status conet_calibrate(conet_model* M, const float* x, int32_t 
 extern "C" conet_status conet_forward_profiled(conet_model* M, const float* x, int32_t B, int32_t T, int32_t F,
                                                float* llr, float* stage_ms_host, int32_t n_stages, void* stream) {
   if (!M || !x || !llr || !stage_ms_host) return fail(CONET_EINVAL, "null argument");
-  const int ns = 1 + 2 * M->cfg.blocks;
+  const int ns = 1 + 3 * M->cfg.blocks;
   if (n_stages != ns) return fail(CONET_EINVAL, "expected %d stages, got %d", ns, n_stages);
   if (B < 1 || T < 1 || T > TMAX || F < 1) return fail(CONET_ESHAPE, "bad shape B=%d T=%d F=%d", B, T, F);
   if ((int64_t)B * T * F > M->cfg.max_res) return fail(CONET_ESHAPE, "B*T*F exceeds max_res");
