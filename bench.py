@@ -32,7 +32,7 @@ METRIC = "LLR REs/sec (BF16/FP8 vs FP32) at stated LLR err; p99 slot latency"
 PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "f32": 157.3}
 HBM_PEAK_GBS = 8000.0
 LLR_TOL = {"bf16": "rel-L2 <= 3e-2 vs FP64, sign agreement >= 0.99",
-           "fp8": "rel-L2 <= 0.15 vs FP64, sign agreement >= 0.97",
+           "fp8": "rel-L2 <= 0.25 vs FP64, sign agreement >= 0.93",
            "f32": "rel-L2 <= 1e-5 vs FP64"}
 
 
