@@ -93,6 +93,74 @@ def load_traffic(kernel: str, workload: str, dtype: str):
     return rec.get("bytes_per_launch")
 
 
+def serve_measure(loads=(0.5,), duration_s=1.5, n_streams=3, seed=13):
+    """Serving on the continuous-batching server: first a saturating burst gives the
+    capacity (requests/s); then, for each load fraction, Poisson arrivals at that
+    fraction of capacity for duration_s. Latency = submit -> LLRs in host memory."""
+    import threading
+    from paper_2510_12739_amd import Conet, Server
+    from synth import make_blob, workload
+    from synth.requests import make_requests, poisson_arrivals
+
+    w = workload("serve_bf16")
+    mc = w.model
+    model = Conet(mc.K, mc.L, mc.C, mc.C_in, mc.m, make_blob(mc, seed=w.weight_seed), dtype="bf16",
+                  max_res=14 * 3276)
+    pool = make_requests(32, seed=seed)
+    mean_res = float(np.mean([14 * 12 * r.n_prb for r in pool]))
+    srv = Server(model, mem_budget=16 << 30, n_streams=n_streams, max_batch_res=600_000, max_queue=1 << 16)
+
+    def run(arrivals):
+        pending, lock, done = [], threading.Lock(), threading.Event()
+
+        def collect():
+            i = 0
+            while True:
+                with lock:
+                    t = pending[i] if i < len(pending) else None
+                if t is None:
+                    if done.is_set() and i >= len(pending):
+                        return
+                    time.sleep(50e-6)
+                    continue
+                srv.wait(t)
+                i += 1
+        th = threading.Thread(target=collect)
+        th.start()
+        srv.reset_stats()
+        t0 = time.perf_counter()
+        for i, ta in enumerate(arrivals):
+            while time.perf_counter() - t0 < ta:
+                pass
+            r = pool[i % len(pool)]
+            t, _ = srv.submit(r.x, r.n_prb, r.n_rx, r.m)
+            with lock:
+                pending.append(t)
+        done.set()
+        th.join()
+        return srv.stats()
+
+    burst = run(np.zeros(600))
+    cap = burst["res_per_s"] / mean_res
+    out = {"workload": "serve_bf16", "requests": "n_PRB U{4..273} x 12 subcarriers x 14 symbols, n_rx {2,4}, "
+           "QPSK/16/64-QAM; K=3 L=4 C=64 BF16, inputs zero-padded to 16 channels, head width 6",
+           "lanes": n_streams, "capacity_req_s": round(cap, 1), "capacity_res_s": round(burst["res_per_s"], 1),
+           "points": []}
+    for f in loads:
+        rate = f * cap
+        n = max(200, int(rate * duration_s))
+        st = run(poisson_arrivals(rate, n, seed=int(f * 1000)))
+        out["points"].append({"load": f, "offered_req_s": round(rate, 1), "p50_us": round(st["p50_us"], 1),
+                              "p99_us": round(st["p99_us"], 1), "max_us": round(st["max_us"], 1),
+                              "res_per_s": round(st["res_per_s"], 1), "requests": int(st["completed"]),
+                              "mean_batch_requests": round(st["mean_batch_requests"], 2)})
+        print(f"[bench] serving load {f:.2f}: {rate:.0f} req/s, p50 {st['p50_us']:.0f} us, p99 {st['p99_us']:.0f} us",
+              file=sys.stderr, flush=True)
+    srv.close()
+    model.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +171,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--json-out", default=None)
+    ap.add_argument("--serve", action="store_true", help="only the serving load sweep (10 %% .. 120 %% of capacity)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving point of the default run")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device 3 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -121,6 +191,13 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path (slots shard across GPUs "
               "with no exchange; see the design notes). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        out = serve_measure(loads=(0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2), duration_s=2.0)
+        ok = [p["offered_req_s"] for p in out["points"] if p["p99_us"] < 500.0]
+        out["max_load_req_s_p99_under_500us"] = max(ok) if ok else None
+        print(json.dumps(out), flush=True)
+        return
 
     import torch
     from paper_2510_12739_amd import Conet
@@ -212,6 +289,11 @@ def main():
         result["llr_err"] = err
     else:
         result["cpu_baseline"] = None
+
+    if not args.no_serve and args.workload == "bf16_b64_f3276" and dtype == "bf16":
+        del model, x, out
+        torch.cuda.empty_cache()
+        result["serving"] = serve_measure(loads=(0.5,), duration_s=1.5)
 
     line = json.dumps(result)
     print(line, flush=True)

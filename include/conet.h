@@ -132,6 +132,63 @@ conet_status conet_forward_ragged(conet_model* model, const float* x, int32_t n_
 conet_status conet_forward_profiled(conet_model* model, const float* x, int32_t B, int32_t T, int32_t F, float* llr,
                                     float* stage_ms_host, int32_t n_stages, void* stream);
 
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of slot requests (one TTI each). A scheduler thread forms a
+ * ragged batch whenever one of the server's lanes (one HIP stream + its own activation
+ * buffers each) is free, taking queued requests in arrival order while their REs fit
+ * the lane (admission by memory); batches on different lanes overlap on the device.
+ * A request's LLRs do not depend on the other requests it is batched with. */
+typedef struct conet_server conet_server;
+
+typedef struct {
+  int32_t n_prb;            /* PRBs: F = 12 * n_prb subcarriers                              */
+  int32_t n_rx;             /* receive antennas; features have 4*n_rx channels (<= C_in), the
+                               missing antennas are zero-padded                               */
+  int32_t bits_per_symbol;  /* m of the request (<= the model's head width): LLR channels 0..m-1 */
+  int32_t T;                /* OFDM symbols (1..14; all requests of a server share T)        */
+  const float* x_host;      /* host [T][F][4*n_rx] FP32 features; read when the request is batched */
+  float* llr_host;          /* host [T][F][m] FP32 output; written before conet_serve_wait returns */
+  uint64_t tag;             /* caller's value, unused by the library                        */
+} conet_request;
+
+typedef struct {
+  double p50_us, p99_us, mean_us, max_us;  /* latency: submit -> LLRs in llr_host           */
+  double res_per_s;                        /* completed REs / (last completion - first submit) */
+  double mean_batch_requests;
+  uint64_t completed, rejected, batches;
+  int64_t lane_res;                        /* REs one lane admits                          */
+} conet_serve_stats;
+
+/* Start a server on `model` (which must outlive it): n_streams lanes of up to
+ * max_batch_res REs each, reduced until all lanes' device buffers fit mem_budget_bytes;
+ * at most max_queue requests wait. Allocates its device and pinned host buffers here,
+ * once. Errors: EINVAL, ENOMEM (budget too small for one RE per lane), ESTATE (FP8
+ * model without scales), EDEVICE. */
+conet_status conet_serve_create(conet_model* model, size_t mem_budget_bytes, int32_t n_streams, int32_t max_batch_res,
+                                int32_t max_queue, conet_server** out);
+
+/* Queue one request (non-blocking). The request's buffers belong to the library until
+ * conet_serve_wait returns for the ticket. Errors: EINVAL, ESHAPE (does not fit the
+ * model or a lane), EBUSY (queue full: retry later). */
+conet_status conet_serve_submit(conet_server* server, const conet_request* request, uint64_t* ticket);
+
+/* Wait for a ticket (timeout_us < 0: no limit). On success *latency_us (nullable) is the
+ * time from submit to the LLRs being in llr_host. Errors: ETIMEOUT (still pending; wait
+ * again), EINVAL (unknown or already-collected ticket), EDEVICE. */
+conet_status conet_serve_wait(conet_server* server, uint64_t ticket, int64_t timeout_us, double* latency_us);
+
+/* Latency percentiles and throughput since creation or the last reset. */
+conet_status conet_serve_get_stats(conet_server* server, conet_serve_stats* stats);
+conet_status conet_serve_reset_stats(conet_server* server);
+
+/* Stop (paused != 0) or resume forming new batches; batches in flight complete and
+ * submissions are still queued (up to max_queue) while paused. */
+conet_status conet_serve_pause(conet_server* server, int32_t paused);
+
+/* Drain queued and in-flight requests (resuming a paused server), stop the threads,
+ * free the server's buffers. */
+conet_status conet_serve_destroy(conet_server* server);
+
 /* Release the model (the caller frees the workspace afterwards). Synchronous. */
 conet_status conet_destroy(conet_model* model);
 

@@ -22,7 +22,8 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "ENOMEM", 4: "EDEVICE", 5: "EBUS
 # Every symbol include/conet.h declares.
 EXPORTS = ("conet_weight_count", "conet_workspace_bytes", "conet_create", "conet_set_act_scales",
            "conet_calibrate", "conet_get_act_scales", "conet_forward", "conet_forward_ragged", "conet_forward_profiled",
-           "conet_destroy", "conet_last_error")
+           "conet_serve_create", "conet_serve_submit", "conet_serve_wait", "conet_serve_get_stats",
+           "conet_serve_reset_stats", "conet_serve_pause", "conet_serve_destroy", "conet_destroy", "conet_last_error")
 
 
 class ConetError(RuntimeError):
@@ -36,6 +37,19 @@ class conet_config(ctypes.Structure):
                 ("in_channels", ctypes.c_int32), ("bits_per_symbol", ctypes.c_int32),
                 ("fuse_mask", ctypes.c_uint32), ("ln_eps", ctypes.c_float), ("dtype", ctypes.c_int32),
                 ("train", ctypes.c_int32), ("max_res", ctypes.c_int64)]
+
+
+class conet_request(ctypes.Structure):
+    _fields_ = [("n_prb", ctypes.c_int32), ("n_rx", ctypes.c_int32), ("bits_per_symbol", ctypes.c_int32),
+                ("T", ctypes.c_int32), ("x_host", ctypes.c_void_p), ("llr_host", ctypes.c_void_p),
+                ("tag", ctypes.c_uint64)]
+
+
+class conet_serve_stats(ctypes.Structure):
+    _fields_ = [("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double), ("mean_us", ctypes.c_double),
+                ("max_us", ctypes.c_double), ("res_per_s", ctypes.c_double), ("mean_batch_requests", ctypes.c_double),
+                ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("lane_res", ctypes.c_int64)]
 
 
 _lib = None
@@ -63,6 +77,17 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.conet_forward_ragged.restype = i32
     lib.conet_forward_profiled.argtypes = [vp, vp, i32, i32, i32, vp, fp, i32, vp]
     lib.conet_forward_profiled.restype = i32
+    lib.conet_serve_create.argtypes = [vp, sz, i32, i32, i32, ctypes.POINTER(vp)]
+    lib.conet_serve_create.restype = i32
+    lib.conet_serve_submit.argtypes = [vp, ctypes.POINTER(conet_request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.conet_serve_submit.restype = i32
+    lib.conet_serve_wait.argtypes = [vp, ctypes.c_uint64, i64, ctypes.POINTER(ctypes.c_double)]
+    lib.conet_serve_wait.restype = i32
+    lib.conet_serve_get_stats.argtypes = [vp, ctypes.POINTER(conet_serve_stats)]
+    lib.conet_serve_get_stats.restype = i32
+    lib.conet_serve_reset_stats.argtypes = [vp]; lib.conet_serve_reset_stats.restype = i32
+    lib.conet_serve_pause.argtypes = [vp, i32]; lib.conet_serve_pause.restype = i32
+    lib.conet_serve_destroy.argtypes = [vp]; lib.conet_serve_destroy.restype = i32
     lib.conet_destroy.argtypes = [vp]; lib.conet_destroy.restype = i32
     lib.conet_last_error.argtypes = []; lib.conet_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -189,6 +214,68 @@ class Conet:
         if getattr(self, "handle", None):
             self.lib.conet_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server over a Conet model (lanes = HIP streams with own buffers).
+
+    submit() copies nothing: the feature and LLR arrays are held until wait() returns.
+    """
+
+    def __init__(self, model: Conet, mem_budget: int = 8 << 30, n_streams: int = 2, max_batch_res: int = 1 << 20,
+                 max_queue: int = 4096):
+        self.lib = load()
+        self.model = model
+        h = ctypes.c_void_p()
+        _check(self.lib.conet_serve_create(model.handle, int(mem_budget), n_streams, int(max_batch_res),
+                                           int(max_queue), ctypes.byref(h)))
+        self.handle = h
+        self._held = {}
+
+    def submit(self, x: np.ndarray, n_prb: int, n_rx: int, m: int, out: Optional[np.ndarray] = None, T: int = 14):
+        """x: float32 [T, 12*n_prb, 4*n_rx] (C-contiguous). Returns (ticket, llr array [T, F, m])."""
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        F = 12 * n_prb
+        if x.shape != (T, F, 4 * n_rx):
+            raise ValueError(f"x has shape {x.shape}, expected {(T, F, 4 * n_rx)}")
+        if out is None:
+            out = np.empty((T, F, m), dtype=np.float32)
+        req = conet_request(n_prb, n_rx, m, T, x.ctypes.data, out.ctypes.data, 0)
+        t = ctypes.c_uint64()
+        _check(self.lib.conet_serve_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
+        self._held[t.value] = (x, out)
+        return t.value, out
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> float:
+        lat = ctypes.c_double()
+        st = self.lib.conet_serve_wait(self.handle, ctypes.c_uint64(ticket), int(timeout_us), ctypes.byref(lat))
+        if st != 6:                      # ETIMEOUT keeps the buffers held for a later wait
+            self._held.pop(ticket, None)
+        _check(st)
+        return lat.value
+
+    def stats(self) -> dict:
+        s = conet_serve_stats()
+        _check(self.lib.conet_serve_get_stats(self.handle, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in conet_serve_stats._fields_}
+
+    def reset_stats(self):
+        _check(self.lib.conet_serve_reset_stats(self.handle))
+
+    def pause(self, paused: bool = True):
+        _check(self.lib.conet_serve_pause(self.handle, 1 if paused else 0))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(self.lib.conet_serve_destroy(self.handle))
+            self.handle = None
+            self._held.clear()
 
     def __del__(self):
         try:

@@ -143,7 +143,31 @@ conet_status check_config(const conet_config* c) {
   return CONET_OK;
 }
 
-// Workspace: [packed filters][FP32 vectors][tile descriptors][activations]
+size_t arena_bytes(const conet_config& c, int64_t max_res) {
+  const size_t R = (size_t)max_res, C = c.channels, K = c.branches;
+  const size_t max_tiles = 2 * ((size_t)max_res / 16 + 4096);
+  size_t off = align256(max_tiles * sizeof(TileDesc)) + 256;           // descriptors + amax counters
+  off += 2 * K * align256(R * C * act_bytes(c.dtype));
+  off += K * align256(R * C * hid_bytes(c.dtype));
+  return off;
+}
+
+void arena_carve(const conet_config& c, int64_t max_res, uint8_t* base, Arena& ar) {
+  const size_t R = (size_t)max_res, C = c.channels;
+  const int K = c.branches;
+  ar.max_res = max_res;
+  ar.max_tiles = 2 * ((size_t)max_res / 16 + 4096);
+  size_t off = 0;
+  ar.tiles = reinterpret_cast<TileDesc*>(base + off);
+  off = align256(off + ar.max_tiles * sizeof(TileDesc));
+  ar.amax = reinterpret_cast<unsigned*>(base + off);
+  off += 256;
+  for (int p = 0; p < 2; ++p)
+    for (int k = 0; k < K; ++k) { ar.act[p][k] = base + off; off += align256(R * C * act_bytes(c.dtype)); }
+  for (int k = 0; k < K; ++k) { ar.hid[k] = base + off; off += align256(R * C * hid_bytes(c.dtype)); }
+}
+
+// Workspace: [packed filters][FP32 vectors][activation arena]
 void plan_layout(const conet_config& c, Layout& lay) {
   const int K = c.branches, L = c.blocks, C = c.channels, Ci = c.in_channels, m = c.bits_per_symbol;
   size_t off = 0;
@@ -168,13 +192,8 @@ void plan_layout(const conet_config& c, Layout& lay) {
   lay.v_bh = nv; nv += m;
   lay.n_vec = nv;
   lay.vec = off; off = align256(off + nv * 4);
-  const int tw_min = 16;
-  lay.max_tiles = (size_t)(c.max_res / tw_min + 1) + 1024;
-  lay.tiles = off; off = align256(off + lay.max_tiles * sizeof(TileDesc));
-  const size_t R = (size_t)c.max_res;
-  for (int p = 0; p < 2; ++p)
-    for (int k = 0; k < K; ++k) { lay.act[p][k] = off; off = align256(off + R * C * act_bytes(c.dtype)); }
-  for (int k = 0; k < K; ++k) { lay.hid[k] = off; off = align256(off + R * C * hid_bytes(c.dtype)); }
+  lay.arena = off;
+  off = align256(off + arena_bytes(c, c.max_res));
   lay.total = off;
 }
 
@@ -219,6 +238,7 @@ conet_status conet_create(const conet_config* cfg, const float* w, size_t n_weig
     return fail(CONET_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
   }
   M->ws = (uint8_t*)workspace;
+  arena_carve(*cfg, cfg->max_res, M->ws + M->lay.arena, M->arena);
   hipError_t e = hipGetDevice(&M->device);
   if (e != hipSuccess) { delete M; return hip_fail(e, "hipGetDevice"); }
 
@@ -294,7 +314,7 @@ conet_status conet_forward(conet_model* M, const float* x, int32_t B, int32_t T,
   if (M->cfg.dtype == DT_FP8 && !M->scales_set) return fail(CONET_ESTATE, "FP8 model needs activation scales (set or calibrate)");
   Geometry geo;
   geo.uniform = true; geo.B = B; geo.T = T; geo.F = F;
-  return run_forward(M, x, geo, llr, (hipStream_t)stream, nullptr);
+  return run_forward(M, M->arena, x, geo, llr, (hipStream_t)stream, nullptr);
 }
 
 conet_status conet_forward_ragged(conet_model* M, const float* x, int32_t n_slots, int32_t T, const int32_t* F_host,
@@ -312,7 +332,7 @@ conet_status conet_forward_ragged(conet_model* M, const float* x, int32_t n_slot
   if (M->cfg.dtype == DT_FP8 && !M->scales_set) return fail(CONET_ESTATE, "FP8 model needs activation scales (set or calibrate)");
   Geometry geo;
   geo.uniform = false; geo.T = T; geo.n_slots = n_slots; geo.F_host = F_host;
-  return run_forward(M, x, geo, llr, (hipStream_t)stream, nullptr);
+  return run_forward(M, M->arena, x, geo, llr, (hipStream_t)stream, nullptr);
 }
 
 }  // extern "C"

@@ -50,8 +50,8 @@ hipError_t launch_amax(const void* x, int elem_bytes, int64_t n_re, int C, const
 static int scale_index(int K, int L, int k, int l, int which) { (void)K; return 1 + 2 * (k * L + l) + which; }
 
 // ---------------------------------------------------------------- forward
-conet_status run_forward(conet_model* M, const float* x, const Geometry& geo, float* llr, hipStream_t s,
-                         std::vector<float>* calib, hipEvent_t* events) {
+conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const Geometry& geo, float* llr,
+                         hipStream_t s, std::vector<float>* calib, hipEvent_t* events) {
   const conet_config& c = M->cfg;
   const Layout& lay = M->lay;
   const int K = c.branches, L = c.blocks, C = c.channels, Ci = c.in_channels, dt = c.dtype;
@@ -85,8 +85,9 @@ conet_status run_forward(conet_model* M, const float* x, const Geometry& geo, fl
     n_tiles_blk = (int)h.size();
     if (tw_in != tw_blk) build(tw_in);
     n_tiles_in = tw_in != tw_blk ? (int)h.size() - n_tiles_blk : n_tiles_blk;
-    if (h.size() > lay.max_tiles) return fail(CONET_ESHAPE, "ragged batch needs %zu tiles, capacity %zu", h.size(), lay.max_tiles);
-    TileDesc* dt_dev = reinterpret_cast<TileDesc*>(ws + lay.tiles);
+    if (h.size() > ar.max_tiles) return fail(CONET_ESHAPE, "ragged batch needs %zu tiles, capacity %zu", h.size(), ar.max_tiles);
+    if (n_re > ar.max_res) return fail(CONET_ESHAPE, "ragged batch has %lld REs, buffers hold %lld", (long long)n_re, (long long)ar.max_res);
+    TileDesc* dt_dev = ar.tiles;
     e = hipMemcpyAsync(dt_dev, h.data(), h.size() * sizeof(TileDesc), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "tile descriptor upload");
     d_blk = dt_dev;
@@ -101,9 +102,10 @@ conet_status run_forward(conet_model* M, const float* x, const Geometry& geo, fl
     a.tiles_per_slot = geo.uniform ? (geo.F + tw - 1) / tw : 0;
     a.tiles = in_layer ? d_in : d_blk;
   };
-  auto actp = [&](int p, int k) -> void* { return ws + lay.act[p][k]; };
-  auto hidp = [&](int k) -> void* { return ws + lay.hid[k]; };
-  unsigned* amax_dev = reinterpret_cast<unsigned*>(ws + lay.tiles + lay.max_tiles * sizeof(TileDesc) - 256);
+  if (geo.uniform && n_re > ar.max_res) return fail(CONET_ESHAPE, "batch has %lld REs, buffers hold %lld", (long long)n_re, (long long)ar.max_res);
+  auto actp = [&](int p, int k) -> void* { return ar.act[p][k]; };
+  auto hidp = [&](int k) -> void* { return ar.hid[k]; };
+  unsigned* amax_dev = ar.amax;
   auto read_amax = [&](int n, std::vector<float>& outv) -> conet_status {
     std::vector<unsigned> hbuf(n);
     hipError_t e2 = hipStreamSynchronize(s);
@@ -269,7 +271,7 @@ extern "C" conet_status conet_calibrate(conet_model* M, const float* x, int32_t 
   Geometry geo;
   geo.uniform = true; geo.B = B; geo.T = T; geo.F = F;
   std::vector<float> amax;
-  conet_status st = run_forward(M, x, geo, nullptr, (hipStream_t)stream, &amax);
+  conet_status st = run_forward(M, M->arena, x, geo, nullptr, (hipStream_t)stream, &amax);
   if (st != CONET_OK) return st;
   hipError_t e = hipStreamSynchronize((hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "calibration");
@@ -293,7 +295,7 @@ extern "C" conet_status conet_forward_profiled(conet_model* M, const float* x, i
   if (st == CONET_OK) {
     Geometry geo;
     geo.uniform = true; geo.B = B; geo.T = T; geo.F = F;
-    st = run_forward(M, x, geo, llr, (hipStream_t)stream, nullptr, ev.data());
+    st = run_forward(M, M->arena, x, geo, llr, (hipStream_t)stream, nullptr, ev.data());
   }
   if (st == CONET_OK) {
     e = hipEventSynchronize(ev[ns]);

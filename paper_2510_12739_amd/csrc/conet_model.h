@@ -22,11 +22,18 @@ struct Layout {
   size_t v_bin[KMAX_ARGS], v_wsin[KMAX_ARGS];
   size_t v_blk[KMAX_ARGS][LMAX];   // s0 o0 b1 s1 o1 b2 ws1 ws2 (8 C each)
   size_t v_gamma[LMAX], v_beta[LMAX], v_wh, v_bh;
-  size_t tiles;                    // TileDesc array for ragged batches
-  size_t max_tiles;
-  size_t act[2][KMAX_ARGS];        // residual stream, ping-pong
-  size_t hid[KMAX_ARGS];           // middle activation of a block
+  size_t arena;                    // activation arena (see Arena)
   size_t total;
+};
+
+// Activation buffers of one forward in flight (the model's own, or a serving lane's).
+struct Arena {
+  void* act[2][KMAX_ARGS] = {};    // residual stream, ping-pong, [RE][C]
+  void* hid[KMAX_ARGS] = {};       // middle activation of a block
+  TileDesc* tiles = nullptr;       // ragged-batch tile descriptors
+  size_t max_tiles = 0;
+  int64_t max_res = 0;             // REs the buffers hold
+  unsigned* amax = nullptr;        // 64 calibration counters
 };
 
 struct Geometry {
@@ -46,6 +53,7 @@ struct conet_model {
   std::vector<float> blob;           // FP32 parameters as given
   std::vector<float> act_scales;     // FP8 static activation scales
   bool scales_set = false;
+  conet::Arena arena;                // activation buffers inside the workspace
 };
 
 namespace conet {
@@ -57,8 +65,13 @@ conet_status hip_fail(hipError_t e, const char* what);
 // max |operand| of every conv input, in network order, into amax_host (FP8 models).
 // events (optional, 2L+2 entries): recorded on the stream before every launch and after
 // the last one, so stage i took elapsed(events[i], events[i+1]).
-conet_status run_forward(conet_model* M, const float* x, const Geometry& geo, float* llr, hipStream_t s,
-                         std::vector<float>* calib, hipEvent_t* events = nullptr);
+conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const Geometry& geo, float* llr,
+                         hipStream_t s, std::vector<float>* calib, hipEvent_t* events = nullptr);
+
+// Bytes of activation buffers (plus descriptor capacity) for `max_res` REs.
+size_t arena_bytes(const conet_config& c, int64_t max_res);
+// Carve an Arena out of `base` (256-byte aligned, arena_bytes long).
+void arena_carve(const conet_config& c, int64_t max_res, uint8_t* base, Arena& ar);
 
 hipError_t launch_amax(const void* x, int act_dtype_bytes, int64_t n_re, int C, const float* s0, const float* o0,
                        int prologue, unsigned* out, hipStream_t s);

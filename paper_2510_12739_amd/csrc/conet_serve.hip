@@ -1,0 +1,421 @@
+// Continuous-batching server for CoNet-Rx slot requests.
+//
+// Requests (one TTI each, any PRB allocation, 2..N_rx antennas, any modulation up to the
+// model's head width) are queued by conet_serve_submit. A scheduler thread forms a
+// ragged batch whenever one of the server's lanes is free: it takes queued requests in
+// arrival order while their REs fit the lane's buffers (admission by memory; a request
+// never waits for a batch to fill), packs their features into the lane's pinned staging
+// buffer (zero-padding missing antennas), and enqueues H2D copy -> ragged forward ->
+// D2H copy on the lane's stream. Lanes run on separate streams, so a batch formed
+// while others are on the GPU overlaps with them on the device. Each lane has a
+// completion thread that waits for its batch, scatters the LLRs to the callers'
+// buffers and releases the waiters.
+//
+// Every slot is computed in tiles that never cross slot boundaries and each kernel's
+// arithmetic per RE does not depend on the other slots, so a request's LLRs are
+// identical whether it runs alone or inside any mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "conet.h"
+#include "conet_model.h"
+
+namespace conet {
+
+using clk = std::chrono::steady_clock;
+
+struct Pending {
+  conet_request req;
+  uint64_t ticket;
+  clk::time_point t_submit;
+  int64_t n_re;
+};
+
+struct Done {
+  bool done = false;
+  conet_status status = CONET_OK;
+  double latency_us = 0;
+};
+
+struct Lane {
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+  uint8_t* dev = nullptr;          // arena + x + llr
+  Arena arena;
+  float* x_dev = nullptr;          // [max_res][C_in]
+  float* llr_dev = nullptr;        // [max_res][m]
+  float* x_pin = nullptr;          // pinned staging
+  float* llr_pin = nullptr;
+  std::vector<Pending> batch;      // requests of the batch in flight
+  std::vector<int32_t> F;          // widths of the batch's slots
+  bool busy = false;               // a batch is assigned to the lane
+  bool launched = false;           // ... and its completion event is recorded
+  std::thread waiter;
+};
+
+}  // namespace conet
+
+struct conet_server {
+  conet_model* M = nullptr;
+  int device = 0;
+  int64_t lane_res = 0;
+  size_t max_queue = 0;
+  std::vector<conet::Lane> lanes;
+  std::mutex mu;
+  std::condition_variable cv_sched;   // queue grew or a lane became free
+  std::condition_variable cv_lane;    // a lane got work
+  std::condition_variable cv_done;    // a request completed
+  std::deque<conet::Pending> queue;
+  std::unordered_map<uint64_t, conet::Done> results;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  bool paused = false;                // no new batches are formed while set
+  std::thread scheduler;
+  // statistics
+  std::vector<double> lat_us;
+  uint64_t completed = 0, rejected = 0, batches = 0, batched_requests = 0;
+  int64_t res_done = 0;
+  bool have_first = false;
+  conet::clk::time_point t_first, t_last;
+  conet_status async_error = CONET_OK;
+};
+
+namespace conet {
+
+static void lane_wait_loop(conet_server* S, int li) {
+  Lane& ln = S->lanes[li];
+  hipSetDevice(S->device);
+  const int m = S->M->cfg.bits_per_symbol;
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_lane.wait(lk, [&] { return S->stop || ln.launched; });
+      if (!ln.launched && S->stop) return;
+    }
+    hipError_t e = hipEventSynchronize(ln.ev);
+    const auto t_done_gpu = clk::now();
+    // scatter LLRs: slot s's REs start at its offset; the head has m outputs per RE
+    int64_t off = 0;
+    for (auto& p : ln.batch) {
+      const int mq = p.req.bits_per_symbol;
+      if (e == hipSuccess) {
+        const float* src = ln.llr_pin + off * m;
+        float* dst = p.req.llr_host;
+        if (mq == m) {
+          memcpy(dst, src, sizeof(float) * p.n_re * m);
+        } else {
+          for (int64_t r = 0; r < p.n_re; ++r)
+            for (int j = 0; j < mq; ++j) dst[r * mq + j] = src[r * m + j];
+        }
+      }
+      off += p.n_re;
+    }
+    const auto t_done = clk::now();
+    (void)t_done_gpu;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (auto& p : ln.batch) {
+        Done& d = S->results[p.ticket];
+        d.done = true;
+        d.status = e == hipSuccess ? CONET_OK : CONET_EDEVICE;
+        d.latency_us = std::chrono::duration<double, std::micro>(t_done - p.t_submit).count();
+        if (e == hipSuccess) {
+          S->lat_us.push_back(d.latency_us);
+          ++S->completed;
+          S->res_done += p.n_re;
+        }
+      }
+      if (e != hipSuccess) S->async_error = CONET_EDEVICE;
+      S->t_last = t_done;
+      ln.batch.clear();
+      ln.launched = false;
+      ln.busy = false;
+    }
+    S->cv_done.notify_all();
+    S->cv_sched.notify_all();
+  }
+}
+
+// Form and launch one batch on lane `li` from the head of the queue (called with the lock held).
+static void launch_batch(conet_server* S, int li, std::unique_lock<std::mutex>& lk) {
+  Lane& ln = S->lanes[li];
+  const conet_config& c = S->M->cfg;
+  ln.batch.clear();
+  ln.F.clear();
+  int64_t res = 0;
+  while (!S->queue.empty() && res + S->queue.front().n_re <= S->lane_res) {
+    res += S->queue.front().n_re;
+    ln.batch.push_back(S->queue.front());
+    S->queue.pop_front();
+  }
+  if (ln.batch.empty()) return;
+  ln.busy = true;
+  ++S->batches;
+  S->batched_requests += ln.batch.size();
+  lk.unlock();
+  // pack features (zero-pad antennas beyond the request's) into pinned staging
+  const int Ci = c.in_channels, T = ln.batch[0].req.T;
+  int64_t off = 0;
+  for (auto& p : ln.batch) {
+    const int F = 12 * p.req.n_prb, ci = 4 * p.req.n_rx;
+    ln.F.push_back(F);
+    float* dst = ln.x_pin + off * Ci;
+    const float* src = p.req.x_host;
+    if (ci == Ci) {
+      memcpy(dst, src, sizeof(float) * p.n_re * Ci);
+    } else {
+      for (int64_t r = 0; r < p.n_re; ++r) {
+        memcpy(dst + r * Ci, src + r * ci, sizeof(float) * ci);
+        memset(dst + r * Ci + ci, 0, sizeof(float) * (Ci - ci));
+      }
+    }
+    off += p.n_re;
+  }
+  hipError_t e = hipMemcpyAsync(ln.x_dev, ln.x_pin, sizeof(float) * res * Ci, hipMemcpyHostToDevice, ln.stream);
+  conet_status st = e == hipSuccess ? CONET_OK : hip_fail(e, "serving H2D");
+  if (st == CONET_OK) {
+    Geometry geo;
+    geo.uniform = false;
+    geo.T = T;
+    geo.n_slots = (int)ln.F.size();
+    geo.F_host = ln.F.data();
+    st = run_forward(S->M, ln.arena, ln.x_dev, geo, ln.llr_dev, ln.stream, nullptr);
+  }
+  if (st == CONET_OK) {
+    e = hipMemcpyAsync(ln.llr_pin, ln.llr_dev, sizeof(float) * res * c.bits_per_symbol, hipMemcpyDeviceToHost,
+                       ln.stream);
+    if (e == hipSuccess) e = hipEventRecord(ln.ev, ln.stream);
+    if (e != hipSuccess) st = hip_fail(e, "serving D2H");
+  }
+  lk.lock();
+  if (st != CONET_OK) {  // fail the whole batch; the lane stays usable
+    for (auto& p : ln.batch) {
+      Done& d = S->results[p.ticket];
+      d.done = true;
+      d.status = st;
+    }
+    ln.batch.clear();
+    ln.busy = false;
+    S->cv_done.notify_all();
+    return;
+  }
+  ln.launched = true;
+  S->cv_lane.notify_all();
+}
+
+static void scheduler_loop(conet_server* S) {
+  hipSetDevice(S->device);
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    S->cv_sched.wait(lk, [&] {
+      if (S->stop) return true;
+      if (S->queue.empty() || S->paused) return false;
+      for (auto& ln : S->lanes) if (!ln.busy) return true;
+      return false;
+    });
+    if (S->stop) return;
+    for (size_t li = 0; li < S->lanes.size() && !S->queue.empty() && !S->paused; ++li)
+      if (!S->lanes[li].busy) launch_batch(S, (int)li, lk);
+  }
+}
+
+static size_t lane_bytes(const conet_config& c, int64_t res) {
+  auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  return a256(arena_bytes(c, res)) + a256(sizeof(float) * res * c.in_channels) +
+         a256(sizeof(float) * res * c.bits_per_symbol);
+}
+
+}  // namespace conet
+
+using namespace conet;
+
+extern "C" {
+
+conet_status conet_serve_create(conet_model* M, size_t mem_budget_bytes, int32_t n_streams, int32_t max_batch_res,
+                                 int32_t max_queue, conet_server** out) {
+  if (!M || !out) return fail(CONET_EINVAL, "null argument");
+  *out = nullptr;
+  if (n_streams < 1 || n_streams > 16) return fail(CONET_EINVAL, "n_streams must be 1..16");
+  if (max_batch_res < 1 || max_queue < 1) return fail(CONET_EINVAL, "max_batch_res and max_queue must be positive");
+  const conet_config& c = M->cfg;
+  if (c.dtype == DT_FP8 && !M->scales_set) return fail(CONET_ESTATE, "FP8 model needs activation scales");
+  // admission by memory: every lane holds buffers for lane_res REs within the budget
+  int64_t lane_res = max_batch_res;
+  while (lane_res > 1 && (size_t)n_streams * lane_bytes(c, lane_res) > mem_budget_bytes) lane_res /= 2;
+  if ((size_t)n_streams * lane_bytes(c, lane_res) > mem_budget_bytes)
+    return fail(CONET_ENOMEM, "memory budget %zu bytes cannot hold %d lanes", mem_budget_bytes, n_streams);
+  conet_server* S = new (std::nothrow) conet_server();
+  if (!S) return fail(CONET_ENOMEM, "host allocation failed");
+  S->M = M;
+  S->device = M->device;
+  S->lane_res = lane_res;
+  S->max_queue = (size_t)max_queue;
+  S->lanes.resize(n_streams);
+  hipError_t e = hipSetDevice(M->device);
+  for (auto& ln : S->lanes) {
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ln.ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc(&ln.dev, lane_bytes(c, lane_res));
+    if (e == hipSuccess) e = hipHostMalloc(&ln.x_pin, sizeof(float) * lane_res * c.in_channels, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&ln.llr_pin, sizeof(float) * lane_res * c.bits_per_symbol, hipHostMallocDefault);
+    if (e != hipSuccess) break;
+    auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    arena_carve(c, lane_res, ln.dev, ln.arena);
+    ln.x_dev = reinterpret_cast<float*>(ln.dev + a256(arena_bytes(c, lane_res)));
+    ln.llr_dev = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(ln.x_dev) + a256(sizeof(float) * lane_res * c.in_channels));
+  }
+  if (e != hipSuccess) {
+    conet_status st = hip_fail(e, "serving lane set-up");
+    for (auto& ln : S->lanes) {
+      if (ln.stream) hipStreamDestroy(ln.stream);
+      if (ln.ev) hipEventDestroy(ln.ev);
+      if (ln.dev) hipFree(ln.dev);
+      if (ln.x_pin) hipHostFree(ln.x_pin);
+      if (ln.llr_pin) hipHostFree(ln.llr_pin);
+    }
+    delete S;
+    return st;
+  }
+  for (int i = 0; i < n_streams; ++i) S->lanes[i].waiter = std::thread(lane_wait_loop, S, i);
+  S->scheduler = std::thread(scheduler_loop, S);
+  *out = S;
+  return CONET_OK;
+}
+
+conet_status conet_serve_submit(conet_server* S, const conet_request* r, uint64_t* ticket) {
+  if (!S || !r || !ticket) return fail(CONET_EINVAL, "null argument");
+  const conet_config& c = S->M->cfg;
+  if (!r->x_host || !r->llr_host) return fail(CONET_EINVAL, "null request buffer");
+  if (r->T < 1 || r->T > TMAX || r->n_prb < 1 || r->n_rx < 1 || 4 * r->n_rx > c.in_channels ||
+      r->bits_per_symbol < 1 || r->bits_per_symbol > c.bits_per_symbol)
+    return fail(CONET_ESHAPE, "request does not fit the model (T=%d n_prb=%d n_rx=%d m=%d)", r->T, r->n_prb, r->n_rx,
+                r->bits_per_symbol);
+  const int64_t n_re = (int64_t)r->T * 12 * r->n_prb;
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (n_re > S->lane_res) {
+    ++S->rejected;
+    return fail(CONET_ESHAPE, "request of %lld REs exceeds a lane's %lld", (long long)n_re, (long long)S->lane_res);
+  }
+  if (S->queue.size() >= S->max_queue) {
+    ++S->rejected;
+    return fail(CONET_EBUSY, "queue full (%zu requests)", S->max_queue);
+  }
+  if (!S->queue.empty() && S->queue.front().req.T != r->T)
+    return fail(CONET_ESHAPE, "all queued requests must share T");
+  Pending p;
+  p.req = *r;
+  p.ticket = S->next_ticket++;
+  p.t_submit = clk::now();
+  p.n_re = n_re;
+  if (!S->have_first) { S->have_first = true; S->t_first = p.t_submit; }
+  S->results[p.ticket] = Done();
+  S->queue.push_back(p);
+  *ticket = p.ticket;
+  S->cv_sched.notify_one();
+  return CONET_OK;
+}
+
+conet_status conet_serve_wait(conet_server* S, uint64_t ticket, int64_t timeout_us, double* latency_us) {
+  if (!S) return fail(CONET_EINVAL, "null server");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->results.find(ticket);
+  if (it == S->results.end()) return fail(CONET_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  auto ready = [&] { return S->results[ticket].done; };
+  if (timeout_us < 0) {
+    S->cv_done.wait(lk, ready);
+  } else if (!S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+    return fail(CONET_ETIMEOUT, "ticket %llu not done after %lld us", (unsigned long long)ticket, (long long)timeout_us);
+  }
+  Done d = S->results[ticket];
+  S->results.erase(ticket);
+  if (latency_us) *latency_us = d.latency_us;
+  if (d.status != CONET_OK) return fail(d.status, "request %llu failed on the device", (unsigned long long)ticket);
+  return CONET_OK;
+}
+
+conet_status conet_serve_get_stats(conet_server* S, conet_serve_stats* st) {
+  if (!S || !st) return fail(CONET_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  std::vector<double> v = S->lat_us;
+  memset(st, 0, sizeof(*st));
+  st->completed = S->completed;
+  st->rejected = S->rejected;
+  st->batches = S->batches;
+  st->mean_batch_requests = S->batches ? (double)S->batched_requests / S->batches : 0.0;
+  st->lane_res = S->lane_res;
+  if (!v.empty()) {
+    std::sort(v.begin(), v.end());
+    auto q = [&](double f) { return v[std::min(v.size() - 1, (size_t)(f * (v.size() - 1) + 0.5))]; };
+    st->p50_us = q(0.50);
+    st->p99_us = q(0.99);
+    st->max_us = v.back();
+    double s = 0;
+    for (double x : v) s += x;
+    st->mean_us = s / v.size();
+    const double span = std::chrono::duration<double>(S->t_last - S->t_first).count();
+    st->res_per_s = span > 0 ? S->res_done / span : 0.0;
+  }
+  return S->async_error;
+}
+
+conet_status conet_serve_reset_stats(conet_server* S) {
+  if (!S) return fail(CONET_EINVAL, "null server");
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->lat_us.clear();
+  S->completed = S->rejected = S->batches = S->batched_requests = 0;
+  S->res_done = 0;
+  S->have_first = false;
+  return CONET_OK;
+}
+
+conet_status conet_serve_pause(conet_server* S, int32_t paused) {
+  if (!S) return fail(CONET_EINVAL, "null server");
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->paused = paused != 0;
+  }
+  S->cv_sched.notify_all();
+  return CONET_OK;
+}
+
+conet_status conet_serve_destroy(conet_server* S) {
+  if (!S) return fail(CONET_EINVAL, "null server");
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->paused = false;
+    S->cv_sched.notify_all();
+    // let queued and in-flight batches finish
+    S->cv_done.wait(lk, [&] {
+      if (!S->queue.empty()) return false;
+      for (auto& ln : S->lanes) if (ln.busy) return false;
+      return true;
+    });
+    S->stop = true;
+  }
+  S->cv_sched.notify_all();
+  S->cv_lane.notify_all();
+  if (S->scheduler.joinable()) S->scheduler.join();
+  for (auto& ln : S->lanes) if (ln.waiter.joinable()) ln.waiter.join();
+  for (auto& ln : S->lanes) {
+    hipStreamSynchronize(ln.stream);
+    hipStreamDestroy(ln.stream);
+    hipEventDestroy(ln.ev);
+    hipFree(ln.dev);
+    hipHostFree(ln.x_pin);
+    hipHostFree(ln.llr_pin);
+  }
+  delete S;
+  return CONET_OK;
+}
+
+}  // extern "C"

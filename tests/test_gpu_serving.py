@@ -1,0 +1,140 @@
+"""Serving (continuous batching) through the C ABI: alone-vs-mix equality, parity, back-pressure,
+time-outs, admission by memory, and a short Poisson-load run."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from helpers import rel_l2, say, sign_agree
+from oracle import conet64 as o
+from synth import make_blob, workload
+from synth.requests import make_requests, poisson_arrivals
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def served():
+    from paper_2510_12739_amd import Conet
+    w = workload("serve_bf16")
+    mc = w.model
+    blob = make_blob(mc, seed=w.weight_seed)
+    model = Conet(mc.K, mc.L, mc.C, mc.C_in, mc.m, blob, dtype="bf16", max_res=14 * 3276)
+    return model, blob, mc
+
+
+def _padded(x, C_in):
+    T, F, ci = x.shape
+    out = np.zeros((T, F, C_in), np.float32)
+    out[..., :ci] = x
+    return out
+
+
+def test_alone_vs_mix_bitwise(served):
+    from paper_2510_12739_amd import Server
+    model, blob, mc = served
+    reqs = make_requests(24, seed=5)
+    say("serving: 24 requests in one burst, 2 lanes")
+    srv = Server(model, mem_budget=4 << 30, n_streams=2, max_batch_res=200_000)
+    tickets = [srv.submit(r.x, r.n_prb, r.n_rx, r.m) for r in reqs]
+    for t, _ in tickets:
+        srv.wait(t)
+    st = srv.stats()
+    assert st["completed"] == 24 and st["batches"] < 24       # requests were batched together
+    for r, (_, llr) in zip(reqs, tickets):
+        x = torch.from_numpy(_padded(r.x, mc.C_in)[None]).cuda()
+        alone = model(x)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(llr, alone.cpu().numpy()[0, ..., :r.m])
+    # and each request alone through the server
+    for r, (_, llr) in list(zip(reqs, tickets))[:4]:
+        t, out = srv.submit(r.x, r.n_prb, r.n_rx, r.m)
+        srv.wait(t)
+        np.testing.assert_array_equal(out, llr)
+    srv.close()
+
+
+def test_served_llrs_match_oracle(served):
+    from paper_2510_12739_amd import Server
+    model, blob, mc = served
+    reqs = make_requests(3, seed=7, prb_range=(4, 12))
+    srv = Server(model, mem_budget=2 << 30, n_streams=1, max_batch_res=100_000)
+    say("serving: oracle parity of 3 small requests")
+    outs = [srv.submit(r.x, r.n_prb, r.n_rx, r.m) for r in reqs]
+    for t, _ in outs:
+        srv.wait(t)
+    srv.close()
+    p = o.unpack(blob, mc.K, mc.L, mc.C, mc.C_in, mc.m)
+    for r, (_, llr) in zip(reqs, outs):
+        X = _padded(r.x, mc.C_in)[None].astype(np.float64)
+        emu = o.forward(p, X, quant=o.Quant("bf16"))[0, ..., :r.m]
+        ref = o.forward(p, X)[0, ..., :r.m]
+        assert rel_l2(llr, emu) <= 5e-3, rel_l2(llr, emu)
+        assert rel_l2(llr, ref) <= 3e-2 and sign_agree(llr, ref) >= 0.99
+
+
+def test_backpressure_timeout_and_rejection(served):
+    """Conditions forced from the host: a paused server queues, refuses beyond max_queue
+    (EBUSY), and a wait on a queued request times out (ETIMEOUT); resuming drains it."""
+    from paper_2510_12739_amd import ConetError, Server
+    model, blob, mc = served
+    reqs = make_requests(3, seed=10, prb_range=(4, 8))
+    say("serving: back-pressure and time-out")
+    srv = Server(model, mem_budget=2 << 30, n_streams=1, max_batch_res=50_000, max_queue=2)
+    srv.pause(True)
+    t1, _ = srv.submit(reqs[0].x, reqs[0].n_prb, reqs[0].n_rx, reqs[0].m)
+    t2, _ = srv.submit(reqs[1].x, reqs[1].n_prb, reqs[1].n_rx, reqs[1].m)
+    with pytest.raises(ConetError, match="EBUSY"):
+        srv.submit(reqs[2].x, reqs[2].n_prb, reqs[2].n_rx, reqs[2].m)
+    with pytest.raises(ConetError, match="ETIMEOUT"):
+        srv.wait(t1, timeout_us=1000)
+    srv.pause(False)
+    srv.wait(t1)
+    srv.wait(t2)
+    with pytest.raises(ConetError, match="EINVAL"):
+        srv.wait(t2)                                                # already collected
+    assert srv.stats()["rejected"] == 1
+    srv.close()
+    big = make_requests(1, seed=9, prb_range=(273, 273))[0]
+    srv = Server(model, mem_budget=2 << 30, n_streams=1, max_batch_res=14 * 100)
+    with pytest.raises(ConetError, match="ESHAPE"):
+        srv.submit(big.x, big.n_prb, big.n_rx, big.m)               # larger than a lane
+    srv.close()
+
+
+def test_admission_by_memory_budget(served):
+    from paper_2510_12739_amd import Server
+    model, blob, mc = served
+    srv = Server(model, mem_budget=64 << 20, n_streams=2, max_batch_res=1 << 20)
+    lane = srv.stats()["lane_res"]
+    assert 0 < lane < 1 << 20                   # the budget, not the request, sized the lanes
+    reqs = make_requests(4, seed=12, prb_range=(4, 20))
+    ts = [srv.submit(r.x, r.n_prb, r.n_rx, r.m)[0] for r in reqs]
+    for t in ts:
+        srv.wait(t)
+    srv.close()
+
+
+def test_poisson_load_reports_latency(served):
+    from paper_2510_12739_amd import Server
+    model, blob, mc = served
+    pool = make_requests(16, seed=13)
+    srv = Server(model, mem_budget=8 << 30, n_streams=3, max_batch_res=400_000)
+    arr = poisson_arrivals(2000.0, 600, seed=1)
+    say("serving: 600 Poisson arrivals at 2000/s")
+    tickets = []
+    t0 = time.perf_counter()
+    for i, ta in enumerate(arr):
+        while time.perf_counter() - t0 < ta:
+            pass
+        r = pool[i % len(pool)]
+        tickets.append(srv.submit(r.x, r.n_prb, r.n_rx, r.m)[0])
+    for t in tickets:
+        srv.wait(t)
+    st = srv.stats()
+    say(f"  p50 {st['p50_us']:.0f} us, p99 {st['p99_us']:.0f} us, {st['res_per_s'] / 1e6:.1f} M REs/s, "
+        f"{st['mean_batch_requests']:.2f} requests/batch")
+    assert st["completed"] == 600 and st["p50_us"] > 0 and st["p99_us"] >= st["p50_us"]
+    srv.close()
