@@ -66,7 +66,8 @@ typedef struct {
   uint32_t fuse_mask;      /* bit l-1 => product fusion + LayerNorm after block l          */
   float ln_eps;            /* LayerNorm epsilon (1e-5)                                     */
   int32_t dtype;           /* conet_dtype                                                  */
-  int32_t train;           /* reserved, must be 0                                          */
+  int32_t train;           /* 1 => FP32 master weights, gradients, Adam state, per-block saved
+                              activations (FP32 or BF16; C in {16,32,64}, C_in in {16,32}, K <= 4) */
   int64_t max_res;         /* largest B*T*F one call may pass                              */
 } conet_config;
 
@@ -111,8 +112,10 @@ conet_status conet_get_act_scales(conet_model* model, float* scales_host, size_t
 
 /* Forward pass: x (device, FP32 [B][T][F][C_in]) -> llr (device, FP32 [B][T][F][m]).
  * Every slot is padded with zeros at its own grid edges (no mixing between slots).
- * B == 0 is a no-op. Errors: EINVAL (null pointers), ESHAPE (T > 14, T < 1, F < 1,
- * B*T*F > max_res), EDEVICE. `save_for_backward` is reserved and must be 0. */
+ * B == 0 is a no-op. With save_for_backward = 1 (train models only) every block's
+ * input, middle activation and pre-fusion main output are kept for conet_backward, and
+ * x must stay valid until then. Errors: EINVAL (null pointers), ESHAPE (T > 14, T < 1,
+ * F < 1, B*T*F > max_res), ESTATE (save on an inference model), EDEVICE. */
 conet_status conet_forward(conet_model* model, const float* x, int32_t B, int32_t T, int32_t F, float* llr,
                            int32_t save_for_backward, void* stream);
 
@@ -131,6 +134,38 @@ conet_status conet_forward_ragged(conet_model* model, const float* x, int32_t n_
  * Synchronises on the last event. Errors as conet_forward. */
 conet_status conet_forward_profiled(conet_model* model, const float* x, int32_t B, int32_t T, int32_t F, float* llr,
                                     float* stage_ms_host, int32_t n_stages, void* stream);
+
+/* ---------------------------------------------------------------- training
+ * Reverse mode of the forward above (hand-written): the head, the per-RE LayerNorm,
+ * the product fusion (d O[k] = dP * prod_{j != k} O[j]), and per block the input
+ * gradient through both convs (flipped, transposed filters on the same implicit-GEMM
+ * kernels) and the filter gradients (a reduction over REs, in two deterministic
+ * stages). */
+
+/* Gradient of sum(llr * dllr) w.r.t. every parameter, from the last forward with
+ * save_for_backward = 1 (dllr: device FP32 [B][T][F][m] of that forward). Overwrites
+ * the gradient buffer (conet_grads). Errors: ESTATE (no saved forward, or an Adam step
+ * since), EDEVICE. */
+conet_status conet_backward(conet_model* model, const float* dllr, void* stream);
+
+/* Device views (model-owned, FP32, blob order) of the gradients and master weights. */
+conet_status conet_grads(conet_model* model, float** grads_dev, size_t* n);
+conet_status conet_master_weights(conet_model* model, float** weights_dev, size_t* n);
+
+/* One Adam step on the FP32 master copy (bias-corrected, step count kept by the model),
+ * then every filter pack and per-channel vector is regenerated from it. */
+conet_status conet_adam_step(conet_model* model, float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Copy the weights to host (n = conet_weight_count): the master copy of a train model,
+ * else the blob it was created from. Synchronises the device. */
+conet_status conet_get_weights(conet_model* model, float* weights_host, size_t n);
+
+/* Bitwise BCE with logits over data REs: loss_dev (1 float) = mean over the B slots'
+ * data REs (data_mask [T][F] nonzero; n_data_per_slot of them) and their m bits of
+ * max(z,0) - z b + log(1 + e^-|z|); dllr = (sigmoid(z) - b) / count on data REs, 0 on
+ * pilots. bits: device uint8 [B][T][F][m]. */
+conet_status conet_bce(conet_model* model, const float* llr, const uint8_t* bits, const uint8_t* data_mask, int32_t B,
+                       int32_t T, int32_t F, int64_t n_data_per_slot, float* dllr, float* loss_dev, void* stream);
 
 /* ---------------------------------------------------------------- serving
  * Continuous batching of slot requests (one TTI each). A scheduler thread forms a

@@ -23,7 +23,9 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "ENOMEM", 4: "EDEVICE", 5: "EBUS
 EXPORTS = ("conet_weight_count", "conet_workspace_bytes", "conet_create", "conet_set_act_scales",
            "conet_calibrate", "conet_get_act_scales", "conet_forward", "conet_forward_ragged", "conet_forward_profiled",
            "conet_serve_create", "conet_serve_submit", "conet_serve_wait", "conet_serve_get_stats",
-           "conet_serve_reset_stats", "conet_serve_pause", "conet_serve_destroy", "conet_destroy", "conet_last_error")
+           "conet_serve_reset_stats", "conet_serve_pause", "conet_serve_destroy", "conet_backward", "conet_grads",
+           "conet_master_weights", "conet_adam_step", "conet_get_weights", "conet_bce", "conet_destroy",
+           "conet_last_error")
 
 
 class ConetError(RuntimeError):
@@ -88,6 +90,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.conet_serve_reset_stats.argtypes = [vp]; lib.conet_serve_reset_stats.restype = i32
     lib.conet_serve_pause.argtypes = [vp, i32]; lib.conet_serve_pause.restype = i32
     lib.conet_serve_destroy.argtypes = [vp]; lib.conet_serve_destroy.restype = i32
+    lib.conet_backward.argtypes = [vp, vp, vp]; lib.conet_backward.restype = i32
+    lib.conet_grads.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(sz)]; lib.conet_grads.restype = i32
+    lib.conet_master_weights.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(sz)]
+    lib.conet_master_weights.restype = i32
+    lib.conet_adam_step.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
+    lib.conet_adam_step.restype = i32
+    lib.conet_get_weights.argtypes = [vp, fp, sz]; lib.conet_get_weights.restype = i32
+    lib.conet_bce.argtypes = [vp, vp, vp, vp, i32, i32, i32, i64, vp, vp, vp]; lib.conet_bce.restype = i32
     lib.conet_destroy.argtypes = [vp]; lib.conet_destroy.restype = i32
     lib.conet_last_error.argtypes = []; lib.conet_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -100,9 +110,9 @@ def _check(st: int):
 
 
 def make_config(K: int, L: int, C: int, C_in: int, m: int, dtype: str = "bf16", fuse_mask: int = -1,
-                max_res: int = 1 << 20, ln_eps: float = 1e-5) -> conet_config:
+                max_res: int = 1 << 20, ln_eps: float = 1e-5, train: bool = False) -> conet_config:
     mask = ((1 << L) - 1) if fuse_mask < 0 else int(fuse_mask)
-    return conet_config(K, L, C, C_in, m, mask, ln_eps, DTYPES[dtype], 0, int(max_res))
+    return conet_config(K, L, C, C_in, m, mask, ln_eps, DTYPES[dtype], 1 if train else 0, int(max_res))
 
 
 def weight_count(cfg: conet_config) -> int:
@@ -127,10 +137,11 @@ class Conet:
     """
 
     def __init__(self, K: int, L: int, C: int, C_in: int, m: int, blob: np.ndarray, dtype: str = "bf16",
-                 fuse_mask: int = -1, max_res: int = 1 << 20, device=None):
+                 fuse_mask: int = -1, max_res: int = 1 << 20, device=None, train: bool = False):
         import torch
         self.lib = load()
-        self.cfg = make_config(K, L, C, C_in, m, dtype, fuse_mask, max_res)
+        self.train = train
+        self.cfg = make_config(K, L, C, C_in, m, dtype, fuse_mask, max_res, train=train)
         self.K, self.L, self.C, self.C_in, self.m, self.dtype = K, L, C, C_in, m, dtype
         n = weight_count(self.cfg)
         if n == 0:
@@ -171,16 +182,60 @@ class Conet:
         if x.shape[-1] != self.C_in:
             raise ValueError(f"x has {x.shape[-1]} channels, model expects {self.C_in}")
 
-    def forward(self, x, out=None, stream=None):
-        """x: [B, T, F, C_in] float32 on the GPU -> LLR [B, T, F, m] float32 (enqueued on the stream)."""
+    def forward(self, x, out=None, stream=None, save: bool = False):
+        """x: [B, T, F, C_in] float32 on the GPU -> LLR [B, T, F, m] float32 (enqueued on the stream).
+
+        save=True (train models) keeps the activations for backward(); x must stay alive."""
         import torch
         self._check_x(x)
         B, T, F, _ = x.shape
         if out is None:
             out = torch.empty((B, T, F, self.m), dtype=torch.float32, device=x.device)
         _check(self.lib.conet_forward(self.handle, ctypes.c_void_p(x.data_ptr()), B, T, F,
-                                      ctypes.c_void_p(out.data_ptr()), 0, _stream_ptr(stream)))
+                                      ctypes.c_void_p(out.data_ptr()), 1 if save else 0, _stream_ptr(stream)))
+        if save:
+            self._saved_x = x
         return out
+
+    # ---- training
+    def _view(self, fn):
+        import torch
+        p, n = ctypes.c_void_p(), ctypes.c_size_t()
+        _check(fn(self.handle, ctypes.byref(p), ctypes.byref(n)))
+        off = p.value - self.workspace.data_ptr()
+        return self.workspace[off:off + 4 * n.value].view(torch.float32)
+
+    def grads(self):
+        """Gradient buffer (device FP32, blob order; overwritten by backward())."""
+        return self._view(self.lib.conet_grads)
+
+    def master(self):
+        """FP32 master weights (device, blob order)."""
+        return self._view(self.lib.conet_master_weights)
+
+    def backward(self, dllr, stream=None):
+        _check(self.lib.conet_backward(self.handle, ctypes.c_void_p(dllr.data_ptr()), _stream_ptr(stream)))
+        return self.grads()
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(self.lib.conet_adam_step(self.handle, lr, beta1, beta2, eps, _stream_ptr(stream)))
+
+    def get_weights(self) -> np.ndarray:
+        w = np.zeros(weight_count(self.cfg), dtype=np.float32)
+        _check(self.lib.conet_get_weights(self.handle, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), w.size))
+        return w
+
+    def bce(self, llr, bits, data_mask, n_data_per_slot: int, stream=None):
+        """Bitwise BCE on device: returns (loss tensor [1], dllr)."""
+        import torch
+        B, T, F, _ = llr.shape
+        dllr = torch.empty_like(llr)
+        loss = torch.empty(1, dtype=torch.float32, device=llr.device)
+        _check(self.lib.conet_bce(self.handle, ctypes.c_void_p(llr.data_ptr()), ctypes.c_void_p(bits.data_ptr()),
+                                  ctypes.c_void_p(data_mask.data_ptr()), B, T, F, int(n_data_per_slot),
+                                  ctypes.c_void_p(dllr.data_ptr()), ctypes.c_void_p(loss.data_ptr()),
+                                  _stream_ptr(stream)))
+        return loss, dllr
 
     __call__ = forward
 
@@ -282,3 +337,22 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def conet_function():
+    """torch.autograd.Function over a train-mode Conet: forward saves activations, backward
+    runs the library's hand-written reverse mode and returns the parameter gradient."""
+    import torch
+
+    class ConetFunction(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x, params, model):
+            ctx.model = model
+            return model.forward(x, save=True)
+
+        @staticmethod
+        def backward(ctx, dllr):
+            g = ctx.model.backward(dllr.contiguous())
+            return None, g.clone(), None
+
+    return ConetFunction

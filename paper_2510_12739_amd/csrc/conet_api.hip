@@ -116,9 +116,10 @@ void pack_filter(int dtype, int cin, int cout, const float* W, uint8_t* dst, flo
 }
 
 // ---------------------------------------------------------------- layout
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static int act_bytes(int dtype) { return dtype == DT_F32 ? 4 : 2; }
+size_t act_bytes_of(int dtype) { return (size_t)act_bytes(dtype); }
 static int hid_bytes(int dtype) { return dtype == DT_F32 ? 4 : (dtype == DT_BF16 ? 2 : 1); }
 
 size_t n_params(const conet_config& c) {
@@ -136,7 +137,15 @@ conet_status check_config(const conet_config* c) {
     return fail(CONET_EINVAL, "no kernel for C_in=%d -> C=%d at dtype %d", c->in_channels, c->channels, c->dtype);
   if (!conv_supported(c->dtype, c->channels, c->channels))
     return fail(CONET_EINVAL, "no kernel for C=%d -> C=%d at dtype %d", c->channels, c->channels, c->dtype);
-  if (c->train != 0) return fail(CONET_EINVAL, "training buffers are not available in this build");
+  if (c->train != 0 && c->train != 1) return fail(CONET_EINVAL, "train must be 0 or 1");
+  if (c->train) {
+    if (c->dtype != DT_F32 && c->dtype != DT_BF16) return fail(CONET_EINVAL, "training runs in FP32 or BF16");
+    if (c->channels != 16 && c->channels != 32 && c->channels != 64)
+      return fail(CONET_EINVAL, "training supports C = 16, 32, 64");
+    if (c->in_channels != 16 && c->in_channels != 32) return fail(CONET_EINVAL, "training supports C_in = 16, 32");
+    if (c->branches > 4) return fail(CONET_EINVAL, "training supports K <= 4");
+    if (c->blocks > 16) return fail(CONET_EINVAL, "training supports L <= 16");
+  }
   if (c->max_res < 1) return fail(CONET_EINVAL, "max_res must be positive");
   if (!(c->ln_eps > 0.f)) return fail(CONET_EINVAL, "ln_eps must be positive");
   if (c->blocks < 32 && (c->fuse_mask >> c->blocks) != 0) return fail(CONET_EINVAL, "fuse_mask has bits beyond L");
@@ -194,6 +203,7 @@ void plan_layout(const conet_config& c, Layout& lay) {
   lay.vec = off; off = align256(off + nv * 4);
   lay.arena = off;
   off = align256(off + arena_bytes(c, c.max_res));
+  if (c.train) off = align256(off + train_bytes(c, lay, off));
   lay.total = off;
 }
 
@@ -275,6 +285,11 @@ conet_status conet_create(const conet_config* cfg, const float* w, size_t n_weig
   if (e != hipSuccess) { delete M; return hip_fail(e, "upload of packed weights"); }
   M->act_scales.assign(1 + 2 * K * L, 1.0f);
   M->scales_set = false;
+  blob_offsets(*cfg, M->bo);
+  if (cfg->train) {
+    conet_status st = train_init(M);
+    if (st != CONET_OK) { delete M; return st; }
+  }
   *out = M;
   return CONET_OK;
 }
@@ -306,7 +321,7 @@ conet_status conet_get_act_scales(conet_model* M, float* s, size_t n) {
 conet_status conet_forward(conet_model* M, const float* x, int32_t B, int32_t T, int32_t F, float* llr,
                            int32_t save, void* stream) {
   if (!M) return fail(CONET_EINVAL, "null model");
-  if (save) return fail(CONET_EINVAL, "save_for_backward is not available in this build");
+  if (save && !M->cfg.train) return fail(CONET_ESTATE, "save_for_backward needs a model created with train = 1");
   if (B == 0) return CONET_OK;
   if (!x || !llr) return fail(CONET_EINVAL, "null tensor pointer");
   if (B < 0 || T < 1 || T > TMAX || F < 1) return fail(CONET_ESHAPE, "bad shape B=%d T=%d F=%d (need T in 1..14)", B, T, F);
@@ -314,6 +329,13 @@ conet_status conet_forward(conet_model* M, const float* x, int32_t B, int32_t T,
   if (M->cfg.dtype == DT_FP8 && !M->scales_set) return fail(CONET_ESTATE, "FP8 model needs activation scales (set or calibrate)");
   Geometry geo;
   geo.uniform = true; geo.B = B; geo.T = T; geo.F = F;
+  if (save) {
+    conet_status st = run_forward(M, M->train_arena, x, geo, llr, (hipStream_t)stream, nullptr, nullptr, true);
+    M->saved = st == CONET_OK;
+    M->saved_B = B; M->saved_T = T; M->saved_F = F;
+    M->saved_x = x;
+    return st;
+  }
   return run_forward(M, M->arena, x, geo, llr, (hipStream_t)stream, nullptr);
 }
 

@@ -268,14 +268,21 @@ struct Gemm {
 // MODE 1: first conv of a block  out = ReLU(s1 (conv(prologue(x)) + b1) + o1)   (or its max, calibration)
 // MODE 2: second conv            out = x + conv(h) + b2; branch 0 of the last unfused block feeds the head
 // MODE 4: second conv of the main net + fusion: O0 = x0 + conv(h0) + b2, P = O0 * prod_k sup_k
-//         (the support outputs of this block, already stored), A = gamma LN(P) + beta -> out or head
+//         (the support outputs of this block, already stored), A = gamma LN(P) + beta -> out or head;
+//         resid2 (training) also keeps O0
+// MODE 5: backward through the second conv: dh = convT(dO); dz1 = dh [h > 0]; out = dc1 = s1 dz1;
+//         partial sums of dz1 (h - o1) / s1, dz1, dc1 (-> ds1, do1, db1)
+// MODE 6: backward through the first conv: dpre = convT(dc1); with z0 = s0 x + o0 (x for an MRB),
+//         dz0 = dpre [z0 > 0]; out = dx = dO + s0 dz0 (dO + dz0 for an MRB), optionally times
+//         [x > 0]; partial sums of dz0 x, dz0, out (-> ds0, do0, and db_in at the input layer)
 template <class A, int MODE, int CIN, int COUT, int TW, int NW>
 __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
   using Acc = typename A::Acc;
   using AccV = typename A::AccV;
   using Act = typename A::Act;
   using Hid = typename A::Hid;
-  using InT = typename std::conditional<MODE == 0, float, typename std::conditional<MODE == 1, Act, Hid>::type>::type;
+  using InT = typename std::conditional<MODE == 0, float,
+                                        typename std::conditional<(MODE == 2 || MODE == 4), Hid, Act>::type>::type;
   constexpr int PITCH = lds_pitch<A, CIN>();
   constexpr int NT = NW * 64;
   using G = Gemm<A, CIN, COUT, TW, PITCH, NW>;
@@ -310,11 +317,26 @@ __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
       pq[i] = A::QUANT ? args.deq[k] * ws[c0 + i] : 1.0f;
     }
   }
-  float ps1[MODE == 1 ? EPL : 1], po1[MODE == 1 ? EPL : 1];
-  if constexpr (MODE == 1) {
+  constexpr bool AFF = (MODE == 1 || MODE == 5 || MODE == 6);
+  float ps1[AFF ? EPL : 1], po1[AFF ? EPL : 1];
+  bool mrb = false;
+  if constexpr (MODE == 1 || MODE == 5) {
 #pragma unroll
     for (int i = 0; i < EPL; ++i) { ps1[i] = args.post_s[k][c0 + i]; po1[i] = args.post_o[k][c0 + i]; }
+  } else if constexpr (MODE == 6) {
+    mrb = args.pre_s[k] == nullptr;
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+      ps1[i] = mrb ? 1.f : args.pre_s[k][c0 + i];
+      po1[i] = mrb ? 0.f : args.pre_o[k][c0 + i];
+    }
   }
+  constexpr int NPART = MODE == 5 ? 3 : (MODE == 6 ? 3 : 1);
+  float sums[NPART][(MODE == 5 || MODE == 6) ? EPL : 1];
+#pragma unroll
+  for (int q = 0; q < NPART; ++q)
+#pragma unroll
+    for (int i = 0; i < ((MODE == 5 || MODE == 6) ? EPL : 1); ++i) sums[q][i] = 0.f;
   unsigned amax_bits = 0;
 
 #pragma unroll
@@ -333,7 +355,36 @@ __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
         if constexpr (A::QUANT) a = a * (Acc)pq[4 * ot + i];
         v[4 * ot + i] = a + (Acc)pb[4 * ot + i];
       }
-    if constexpr (MODE == 0) {
+    if constexpr (MODE == 5) {  // dv = dh (the bias slot holds zeros for input-gradient convs)
+      Acc h[EPL];
+      load_vals(reinterpret_cast<const Hid*>(args.aux[k]) + re * COUT + c0, h, EPL);
+#pragma unroll
+      for (int i = 0; i < EPL; ++i) {
+        const Acc dz = h[i] > (Acc)0 ? v[i] : (Acc)0;
+        const Acc dc = dz * (Acc)ps1[i];
+        sums[0][i] += (float)(dz * (h[i] - (Acc)po1[i]) / (Acc)ps1[i]);
+        sums[1][i] += (float)dz;
+        sums[2][i] += (float)dc;
+        v[i] = dc;
+      }
+      store_vals(reinterpret_cast<Act*>(args.out[k]) + re * COUT + c0, v, EPL, 1.f);
+    } else if constexpr (MODE == 6) {
+      Acc x[EPL], dO[EPL];
+      load_vals(reinterpret_cast<const Act*>(args.aux[k]) + re * COUT + c0, x, EPL);
+      load_vals(reinterpret_cast<const Act*>(args.resid[k]) + re * COUT + c0, dO, EPL);
+#pragma unroll
+      for (int i = 0; i < EPL; ++i) {
+        const Acc z0 = (Acc)ps1[i] * x[i] + (Acc)po1[i];
+        const Acc dz = z0 > (Acc)0 ? v[i] : (Acc)0;
+        Acc dx = dO[i] + (Acc)ps1[i] * dz;
+        if (args.mask_out && !(x[i] > (Acc)0)) dx = (Acc)0;
+        sums[0][i] += mrb ? 0.f : (float)(dz * x[i]);
+        sums[1][i] += mrb ? 0.f : (float)dz;
+        sums[2][i] += (float)dx;
+        v[i] = dx;
+      }
+      store_vals(reinterpret_cast<Act*>(args.out[k]) + re * COUT + c0, v, EPL, 1.f);
+    } else if constexpr (MODE == 0) {
 #pragma unroll
       for (int i = 0; i < EPL; ++i) v[i] = v[i] > (Acc)0 ? v[i] : (Acc)0;
       store_vals(reinterpret_cast<Act*>(args.out[k]) + re * COUT + c0, v, EPL, 1.f);
@@ -359,8 +410,10 @@ __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
       bool head = false;
       if constexpr (MODE == 2) {
         head = args.llr && k == 0;
+        if (head && args.save_o0) store_vals(reinterpret_cast<Act*>(args.save_o0) + re * COUT + c0, v, EPL, 1.f);
         if (!head && args.out[k]) store_vals(reinterpret_cast<Act*>(args.out[k]) + re * COUT + c0, v, EPL, 1.f);
       } else {  // MODE 4: product with the stored support outputs, then LayerNorm over C
+        if (args.save_o0) store_vals(reinterpret_cast<Act*>(args.save_o0) + re * COUT + c0, v, EPL, 1.f);
         for (int kk = 1; kk < args.K; ++kk) {
           Acc sv[EPL];
           load_vals(reinterpret_cast<const Act*>(args.sup[kk]) + re * COUT + c0, sv, EPL);
@@ -404,6 +457,28 @@ __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
       }
     }
   }
+  if constexpr (MODE == 5 || MODE == 6) {
+    // reduce the per-lane sums over the 16 lanes that own the same channels, then one
+    // row of partial sums per wave (no atomics: the final reduction runs in a fixed order)
+#pragma unroll
+    for (int q = 0; q < NPART; ++q)
+#pragma unroll
+      for (int i = 0; i < EPL; ++i) {
+        float t = sums[q][i];
+        t += __shfl_xor(t, 1);
+        t += __shfl_xor(t, 2);
+        t += __shfl_xor(t, 4);
+        t += __shfl_xor(t, 8);
+        sums[q][i] = t;
+      }
+    if (col == 0) {
+      float* row = args.part[k] + ((size_t)blockIdx.x * NW + wave) * NPART * COUT;
+#pragma unroll
+      for (int q = 0; q < NPART; ++q)
+#pragma unroll
+        for (int i = 0; i < EPL; ++i) row[q * COUT + c0 + i] = sums[q][i];
+    }
+  }
   if constexpr (MODE == 1) {
     if (args.amax) {  // calibration: one atomic per lane group
       for (int o = 32; o > 0; o >>= 1) amax_bits = max(amax_bits, (unsigned)__shfl_xor((int)amax_bits, o));
@@ -429,6 +504,11 @@ static hipError_t launch_mode(int mode, ConvArgs& a, int n_tiles, int grid_y, hi
       case 1: return launch_one<A, 1, CIN, COUT>(a, n_tiles, grid_y, s);
       case 2: return launch_one<A, 2, CIN, COUT>(a, n_tiles, grid_y, s);
       case 4: return launch_one<A, 4, CIN, COUT>(a, n_tiles, grid_y, s);
+      case 5:
+      case 6:
+        if constexpr (sizeof(typename A::Op) == 1) return hipErrorInvalidValue;  // no FP8 training
+        else return mode == 5 ? launch_one<A, 5, CIN, COUT>(a, n_tiles, grid_y, s)
+                              : launch_one<A, 6, CIN, COUT>(a, n_tiles, grid_y, s);
     }
   }
   if (mode == 0) return launch_one<A, 0, CIN, COUT>(a, n_tiles, grid_y, s);

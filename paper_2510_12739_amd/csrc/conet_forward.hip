@@ -51,7 +51,7 @@ static int scale_index(int K, int L, int k, int l, int which) { (void)K; return 
 
 // ---------------------------------------------------------------- forward
 conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const Geometry& geo, float* llr,
-                         hipStream_t s, std::vector<float>* calib, hipEvent_t* events) {
+                         hipStream_t s, std::vector<float>* calib, hipEvent_t* events, bool save) {
   const conet_config& c = M->cfg;
   const Layout& lay = M->lay;
   const int K = c.branches, L = c.blocks, C = c.channels, Ci = c.in_channels, dt = c.dtype;
@@ -103,8 +103,14 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
     a.tiles = in_layer ? d_in : d_blk;
   };
   if (geo.uniform && n_re > ar.max_res) return fail(CONET_ESHAPE, "batch has %lld REs, buffers hold %lld", (long long)n_re, (long long)ar.max_res);
-  auto actp = [&](int p, int k) -> void* { return ar.act[p][k]; };
-  auto hidp = [&](int k) -> void* { return ar.hid[k]; };
+  // residual-stream buffers: ping-pong, or one per level when saving for the backward
+  int lvl = 0;  // block being launched
+  auto actp = [&](int p, int k) -> void* {
+    if (!save) return ar.act[p][k];
+    return ar.lvl_act[p == (lvl & 1) ? lvl : lvl + 1][k];
+  };
+  auto hidp = [&](int k) -> void* { return save ? ar.lvl_hid[lvl][k] : ar.hid[k]; };
+  if (save && !ar.levels) return fail(CONET_ESTATE, "no per-level buffers");
   unsigned* amax_dev = ar.amax;
   auto read_amax = [&](int n, std::vector<float>& outv) -> conet_status {
     std::vector<unsigned> hbuf(n);
@@ -152,6 +158,7 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
   int cur = 0;
   bool fused_prev = false;
   for (int l = 0; l < L; ++l) {
+    lvl = l;
     const bool last = (l == L - 1);
     const bool fuse = (c.fuse_mask >> l) & 1u;
     const int nk = (last && !fuse) ? 1 : K;
@@ -239,6 +246,7 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
       for (int k = 1; k < K; ++k) am.sup[k] = actp(1 - cur, k);
       am.out[0] = last ? nullptr : actp(1 - cur, 0);
       am.llr = (last && !calib) ? llr : nullptr;
+      am.save_o0 = save ? ar.lvl_o0[l] : nullptr;
       am.k_off = 0;
       e = mark();
       if (e == hipSuccess) e = launch_conv(dt, 4, C, C, am, n_tiles_blk, 1, s);
@@ -246,6 +254,7 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
     } else {
       for (int k = 0; k < nk; ++k) a2.out[k] = last ? nullptr : actp(1 - cur, k);
       a2.llr = (last && !calib) ? llr : nullptr;
+      a2.save_o0 = (save && last) ? ar.lvl_o0[l] : nullptr;
       e = mark();
       if (e == hipSuccess) e = launch_conv(dt, 2, C, C, a2, n_tiles_blk, nk, s);
       if (e == hipSuccess) e = mark();  // no third launch in an unfused block

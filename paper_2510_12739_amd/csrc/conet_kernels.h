@@ -43,6 +43,11 @@ struct ConvArgs {
   int tw;                          // subcarriers per tile (set by the launcher)
   const TileDesc* tiles;           // ragged batches: one descriptor per tile, else null
   unsigned* amax;                  // mode 1 calibration: per-branch max |output| (no store)
+  // backward (modes 5, 6)
+  const void* aux[KMAX_ARGS];      // mode 5: the block's saved h; mode 6: the block's saved input x
+  float* part[KMAX_ARGS];          // per-wave per-channel partial sums [gridDim.x * waves][NPART][C]
+  int mask_out;                    // mode 6: store dx * (x > 0) (input-layer ReLU adjoint)
+  void* save_o0;                   // mode 4 (training): also store the main output before fusion
 };
 
 // Subcarriers per tile used for a (dtype, C_in, C_out) conv.
@@ -50,7 +55,63 @@ int conv_tile_width(int dtype, int cin, int cout);
 bool conv_supported(int dtype, int cin, int cout);
 // mode: 0 input layer, 1 block conv 1, 2 block conv 2 (+ residual, + head on branch 0
 // if llr is set), 4 block conv 2 of the main net + product with the stored support
-// outputs + LayerNorm (+ head). Branch of a work-group: blockIdx.y + k_off.
+// outputs + LayerNorm (+ head); backward input-gradient convs (flipped, transposed
+// filters): 5 through the block's second conv (-> d of the first conv's output), 6
+// through its first conv (-> d of the block input). Branch: blockIdx.y + k_off.
 hipError_t launch_conv(int dtype, int mode, int cin, int cout, ConvArgs& a, int n_tiles, int grid_y, hipStream_t s);
+
+// ---------------------------------------------------------------- training kernels
+// Filter gradient of a 3x3 conv over a batch: dW[o][tap*CIN + ch] = sum_re dOut[re][o] *
+// In[re shifted by tap][ch] (In optionally through the block's pre-activation), and
+// db[o] = sum_re dOut[re][o]. Each work-group accumulates over its share of tiles and
+// writes one partial row; the sum over rows happens in reduce_launch (fixed order).
+struct WgradArgs {
+  const void* dout[KMAX_ARGS];     // [RE][COUT] Act
+  const void* in[KMAX_ARGS];       // [RE][CIN] Act, or FP32 features (input layer)
+  const float* pre_s[KMAX_ARGS];   // prologue on In: affine + ReLU; null with relu => ReLU only
+  const float* pre_o[KMAX_ARGS];
+  int prologue;                    // 0 none, 1 per-branch (affine if pre_s else ReLU)
+  float* part_w[KMAX_ARGS];        // [gridDim.x][COUT][9 * CIN]
+  float* part_b[KMAX_ARGS];        // [gridDim.x][COUT]
+  int T, F, tiles_per_slot, n_tiles, tw;
+};
+int wgrad_tile_width(int dtype);
+int wgrad_grid(int n_tiles);
+hipError_t launch_wgrad(int dtype, bool in_f32, int cin, int cout, WgradArgs& a, int grid_y, hipStream_t s);
+
+// Head / LayerNorm / product adjoint of one block (or the head alone after an unfused
+// last block). One thread per (RE, 16-channel quarter).
+struct FuseBwdArgs {
+  const float* dllr;               // [RE][m] (last block) or null
+  const void* dA;                  // [RE][C] gradient of the fused main activation (other blocks)
+  const void* O[KMAX_ARGS];        // block outputs: O[0] saved before fusion, O[k>0] stored supports
+  const void* dnext[KMAX_ARGS];    // k>0: gradients of the next block's support inputs (or null)
+  void* dO[KMAX_ARGS];             // out: gradients of the block outputs
+  const float* gamma;
+  const float* beta;
+  const float* Wh;                 // [m][C]
+  int m, K, C, fused, head;
+  float eps;
+  int64_t n_re;
+  float* part;                     // [gridDim.x][NP] partial sums: dgamma C, dbeta C, dWh m*C, dbh m
+};
+hipError_t launch_fuse_bwd(int dtype, FuseBwdArgs& a, int grid, hipStream_t s);
+
+// Sum of `rows` rows of `cols` floats (row stride `ld`) into dst[map(j)] (fixed order).
+// map: 0 identity; 1 filter: j = o*(9*cin) + tap*cin + ch -> ((o*cin + ch)*9 + tap).
+struct ReduceSeg {
+  const float* src;
+  float* dst;
+  int rows, cols, ld, map, cin;
+};
+hipError_t launch_reduce(const ReduceSeg* segs_dev, int n_segs, int max_cols, hipStream_t s);
+
+hipError_t launch_bce(const float* llr, const uint8_t* bits, const uint8_t* data_mask, int64_t n_re, int T, int F,
+                      int m, float inv_count, float* dllr, float* part, int grid, hipStream_t s);
+hipError_t launch_adam(float* w, const float* g, float* mo, float* ve, int64_t n, float lr, float b1, float b2,
+                       float eps, float bc1, float bc2, hipStream_t s);
+hipError_t launch_repack(const float* master, const int32_t* map, void* dst, int64_t n, int dtype, hipStream_t s);
+hipError_t launch_gather(const float* master, const int32_t* map, float* dst, int64_t n, hipStream_t s);
+hipError_t launch_sum(const float* x, int n, float* out, hipStream_t s);
 
 }  // namespace conet

@@ -23,7 +23,22 @@ struct Layout {
   size_t v_blk[KMAX_ARGS][LMAX];   // s0 o0 b1 s1 o1 b2 ws1 ws2 (8 C each)
   size_t v_gamma[LMAX], v_beta[LMAX], v_wh, v_bh;
   size_t arena;                    // activation arena (see Arena)
+  // training (cfg.train): FP32 master, gradients, Adam moments, input-gradient filter
+  // packs, index maps for regenerating packs from the master, scratch, saved levels
+  size_t tr_master, tr_grad, tr_m, tr_v, tr_zero;
+  size_t tr_wt1[KMAX_ARGS][LMAX], tr_wt2[KMAX_ARGS][LMAX], tr_wt_begin, tr_wt_end;
+  size_t tr_map_fwd, tr_map_bwd, tr_map_vec;
+  size_t tr_part_conv, tr_part_conv_rows, tr_part_w, tr_part_b, tr_part_fuse, tr_part_bce, tr_loss, tr_segs;
+  size_t tr_levels, tr_levels_bytes;
   size_t total;
+};
+
+// Blob offsets (in floats) of every parameter tensor.
+struct BlobOffsets {
+  size_t w_in[KMAX_ARGS], b_in[KMAX_ARGS];
+  size_t s0[KMAX_ARGS][LMAX], o0[KMAX_ARGS][LMAX], w1[KMAX_ARGS][LMAX], b1[KMAX_ARGS][LMAX];
+  size_t s1[KMAX_ARGS][LMAX], o1[KMAX_ARGS][LMAX], w2[KMAX_ARGS][LMAX], b2[KMAX_ARGS][LMAX];
+  size_t gamma[LMAX], beta[LMAX], wh, bh, n;
 };
 
 // Activation buffers of one forward in flight (the model's own, or a serving lane's).
@@ -34,6 +49,14 @@ struct Arena {
   size_t max_tiles = 0;
   int64_t max_res = 0;             // REs the buffers hold
   unsigned* amax = nullptr;        // 64 calibration counters
+  // training: one buffer per level instead of ping-pong, plus backward buffers
+  bool levels = false;
+  void* lvl_act[LMAX + 1][KMAX_ARGS] = {};  // level l = input of block l (l = 0: input-layer output)
+  void* lvl_hid[LMAX][KMAX_ARGS] = {};
+  void* lvl_o0[LMAX] = {};                   // main output of block l before fusion
+  void* g_dO[KMAX_ARGS] = {};
+  void* g_dc1[KMAX_ARGS] = {};
+  void* g_dx[2][KMAX_ARGS] = {};
 };
 
 struct Geometry {
@@ -54,6 +77,13 @@ struct conet_model {
   std::vector<float> act_scales;     // FP8 static activation scales
   bool scales_set = false;
   conet::Arena arena;                // activation buffers inside the workspace
+  conet::Arena train_arena;          // per-level buffers (train mode)
+  conet::BlobOffsets bo;
+  bool saved = false;                // a forward with save_for_backward is available
+  int64_t saved_B = 0;
+  int saved_T = 0, saved_F = 0;
+  int adam_steps = 0;
+  const float* saved_x = nullptr;    // features of the saved forward (caller keeps them alive)
 };
 
 namespace conet {
@@ -66,7 +96,16 @@ conet_status hip_fail(hipError_t e, const char* what);
 // events (optional, 2L+2 entries): recorded on the stream before every launch and after
 // the last one, so stage i took elapsed(events[i], events[i+1]).
 conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const Geometry& geo, float* llr,
-                         hipStream_t s, std::vector<float>* calib, hipEvent_t* events = nullptr);
+                         hipStream_t s, std::vector<float>* calib, hipEvent_t* events = nullptr, bool save = false);
+
+size_t align256(size_t x);
+size_t n_params(const conet_config& c);
+size_t act_bytes_of(int dtype);
+void blob_offsets(const conet_config& c, BlobOffsets& bo);
+size_t train_bytes(const conet_config& c, Layout& lay, size_t base);
+conet_status train_init(conet_model* M);
+void pack_filter(int dtype, int cin, int cout, const float* W, uint8_t* dst, float* wscale);
+size_t packed_bytes(int dtype, int cin, int cout);
 
 // Bytes of activation buffers (plus descriptor capacity) for `max_res` REs.
 size_t arena_bytes(const conet_config& c, int64_t max_res);

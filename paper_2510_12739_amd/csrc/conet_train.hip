@@ -1,0 +1,530 @@
+// Backward-pass and training kernels of CoNet-Rx (gfx950).
+//
+//  * wgrad_kernel: filter gradient of a 3x3 conv, dW[o][tap, ch] = sum over REs of
+//    dOut[re][o] * In[re + tap][ch]. The reduction runs over REs, so both operands are
+//    staged into LDS transposed (channel-major, RE-contiguous): an MFMA lane then reads
+//    VEC consecutive REs of one channel with one 16-byte load. Taps shifted along the
+//    subcarrier axis read two aligned 16-byte words and funnel-shift them. Each
+//    work-group loops over a share of the tiles and writes one partial row; the rows
+//    are summed in a fixed order by reduce_kernel (deterministic, no atomics).
+//  * fuse_bwd_kernel: adjoint of the head, the per-RE LayerNorm and the K-way product,
+//    dO[k] = dP * prod_{j != k} O[j] (no division, so exact zeros are handled).
+//  * bce_kernel, adam_kernel, repack_kernel, gather_kernel, reduce_kernel.
+#include <hip/hip_runtime.h>
+
+#include "conet_common.h"
+#include "conet_kernels.h"
+
+namespace conet {
+
+// ---------------------------------------------------------------- helpers
+template <class T>
+__device__ __forceinline__ float ldf(const T* p) { return (float)*p; }
+
+__device__ __forceinline__ void to_elems(const i32x4& raw, float* v, const float*) {
+  const float* f = reinterpret_cast<const float*>(&raw);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = f[i];
+}
+__device__ __forceinline__ void to_elems(const i32x4& raw, float* v, const __bf16*) {
+  const __bf16* b = reinterpret_cast<const __bf16*>(&raw);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = (float)b[i];
+}
+
+template <class E>
+__device__ __forceinline__ void st_elem(uint8_t* p, float v) {
+  if constexpr (sizeof(E) == 4) *reinterpret_cast<float*>(p) = v;
+  else *reinterpret_cast<__bf16*>(p) = f2bf(v);
+}
+
+// 16-byte window starting `s` elements into the 32 bytes lo:hi.
+template <class E>
+__device__ __forceinline__ i32x4 shift_window(const i32x4& lo, const i32x4& hi, int s) {
+  const unsigned w[8] = {(unsigned)lo[0], (unsigned)lo[1], (unsigned)lo[2], (unsigned)lo[3],
+                         (unsigned)hi[0], (unsigned)hi[1], (unsigned)hi[2], (unsigned)hi[3]};
+  i32x4 r;
+  if constexpr (sizeof(E) == 4) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r[i] = (int)(s == 0 ? w[i] : (s == 1 ? w[i + 1] : w[i + 2]));
+  } else {  // 2-byte elements: s = 1 is a 2-byte funnel shift, s = 2 a whole dword
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const unsigned a1 = __builtin_amdgcn_alignbyte(w[i + 1], w[i], 2);
+      r[i] = (int)(s == 0 ? w[i] : (s == 1 ? a1 : w[i + 1]));
+    }
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------- wgrad
+template <class A>
+constexpr int wg_tw() { return 4 * A::VEC; }  // subcarriers per tile: one MFMA K step per OFDM symbol
+
+template <class A, class InT, int CIN, int COUT>
+__global__ void __launch_bounds__(256, 1) wgrad_kernel(WgradArgs args) {
+  using E = typename A::Op;
+  using Act = typename A::Act;
+  using AccV = typename A::AccV;
+  constexpr int VEC = A::VEC, TW = wg_tw<A>(), NW = 4, NT = 256;
+  constexpr int ICOLS = TW + 8;                                    // TW+2 staged, room for shifted reads
+  constexpr int DS = TMAX * TW * (int)sizeof(E) + 16;              // dOut channel stride (bytes)
+  constexpr int IS = TROWS * ICOLS * (int)sizeof(E) + 16;          // In channel stride (bytes)
+  constexpr int NOT = COUT / 16, NKT = 9 * CIN / 16, KTW = (NKT + NW - 1) / NW;
+  constexpr int EPD = 16 / (int)sizeof(Act), CPD = COUT / EPD;     // dOut: elements / chunks per RE
+  constexpr int EPI = 16 / (int)sizeof(InT) < 4 ? 4 : 16 / (int)sizeof(InT), CPI = CIN / EPI;
+  static_assert(NT % CPD == 0 && NT % CPI == 0 && CIN % 16 == 0 && COUT % 16 == 0, "shape");
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  uint8_t* ldsD = lds;
+  uint8_t* ldsI = lds + COUT * DS;
+
+  const int k = blockIdx.y;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, col = lane & 15;
+  const Act* dout = reinterpret_cast<const Act*>(args.dout[k]);
+  const InT* in = reinterpret_cast<const InT*>(args.in[k]);
+  const int pro = args.prologue == 0 ? 0 : (args.pre_s[k] ? 1 : 2);
+  const int ccD = tid % CPD, ccI = tid % CPI;
+  float sv[EPI], ov[EPI];
+  if (pro == 1) {
+#pragma unroll
+    for (int i = 0; i < EPI; ++i) { sv[i] = args.pre_s[k][ccI * EPI + i]; ov[i] = args.pre_o[k][ccI * EPI + i]; }
+  }
+  AccV acc[NOT][KTW];
+#pragma unroll
+  for (int ot = 0; ot < NOT; ++ot)
+#pragma unroll
+    for (int j = 0; j < KTW; ++j) acc[ot][j] = AccV{};
+  float bsum[EPD];
+#pragma unroll
+  for (int i = 0; i < EPD; ++i) bsum[i] = 0.f;
+  const int T = args.T;
+
+  for (int tile = blockIdx.x; tile < args.n_tiles; tile += gridDim.x) {
+    const int b = tile / args.tiles_per_slot;
+    const int f0 = (tile - b * args.tiles_per_slot) * TW;
+    const int64_t re_base = (int64_t)b * T * args.F;
+    __syncthreads();  // the previous tile's LDS reads are done
+    // dOut tile [TMAX][TW] transposed to [o][t][c]
+    for (int idx = tid; idx < TMAX * TW * CPD; idx += NT) {
+      const int pos = idx / CPD;
+      const int t = pos / TW, c = pos - t * TW, f = f0 + c;
+      float v[EPD];
+      if (t < T && f < args.F) {
+        const i32x4 raw = *reinterpret_cast<const i32x4*>(dout + (re_base + (int64_t)t * args.F + f) * COUT + ccD * EPD);
+        to_elems(raw, v, (const Act*)nullptr);
+#pragma unroll
+        for (int i = 0; i < EPD; ++i) bsum[i] += v[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < EPD; ++i) v[i] = 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < EPD; ++i) st_elem<E>(ldsD + (ccD * EPD + i) * DS + (t * TW + c) * (int)sizeof(E), v[i]);
+    }
+    // In halo tile [TROWS][TW+2] (prologue, then zero padding) transposed to [ch][r][c]
+    for (int idx = tid; idx < TROWS * (TW + 2) * CPI; idx += NT) {
+      const int pos = idx / CPI;
+      const int r = pos / (TW + 2), c = pos - r * (TW + 2);
+      const int t = r - 1, f = f0 + c - 1;
+      float v[EPI];
+      if (t >= 0 && t < T && f >= 0 && f < args.F) {
+        const InT* src = in + (re_base + (int64_t)t * args.F + f) * CIN + ccI * EPI;
+        if constexpr (sizeof(InT) == 4) {
+          const float4 q = *reinterpret_cast<const float4*>(src);
+          v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+#pragma unroll
+          for (int i = 4; i < EPI; ++i) v[i] = 0.f;
+        } else {
+          to_elems(*reinterpret_cast<const i32x4*>(src), v, (const InT*)nullptr);
+        }
+        if (pro == 1) {
+#pragma unroll
+          for (int i = 0; i < EPI; ++i) v[i] = fmaxf(sv[i] * v[i] + ov[i], 0.f);
+        } else if (pro == 2) {
+#pragma unroll
+          for (int i = 0; i < EPI; ++i) v[i] = fmaxf(v[i], 0.f);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < EPI; ++i) v[i] = 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < EPI; ++i) st_elem<E>(ldsI + (ccI * EPI + i) * IS + (r * ICOLS + c) * (int)sizeof(E), v[i]);
+    }
+    __syncthreads();
+    for (int t = 0; t < T; ++t) {  // one MFMA K step per OFDM symbol: TW REs = 4 lane groups x VEC
+      i32x4 af[NOT];
+#pragma unroll
+      for (int ot = 0; ot < NOT; ++ot)
+        af[ot] = *reinterpret_cast<const i32x4*>(ldsD + (ot * 16 + col) * DS + (t * TW + g * VEC) * (int)sizeof(E));
+#pragma unroll
+      for (int j = 0; j < KTW; ++j) {
+        const int kt = wave + NW * j;
+        if (kt >= NKT) break;
+        const int tap = kt / (CIN / 16), ch = (kt - tap * (CIN / 16)) * 16 + col;
+        const int dt = tap / 3, s = tap - dt * 3;
+        const uint8_t* base = ldsI + ch * IS + ((t + dt) * ICOLS + g * VEC) * (int)sizeof(E);
+        const i32x4 lo = *reinterpret_cast<const i32x4*>(base);
+        i32x4 bfr = lo;
+        if (s != 0) bfr = shift_window<E>(lo, *reinterpret_cast<const i32x4*>(base + 16), s);
+#pragma unroll
+        for (int ot = 0; ot < NOT; ++ot) acc[ot][j] = A::mma(&af[ot], &bfr, acc[ot][j]);
+      }
+    }
+  }
+  // partial dW: D[o][k] in lane (col = k within the k-tile, rows 4g + i)
+  float* pw = args.part_w[k] + (size_t)blockIdx.x * COUT * 9 * CIN;
+#pragma unroll
+  for (int j = 0; j < KTW; ++j) {
+    const int kt = wave + NW * j;
+    if (kt >= NKT) break;
+#pragma unroll
+    for (int ot = 0; ot < NOT; ++ot)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) pw[(size_t)(ot * 16 + 4 * g + i) * 9 * CIN + kt * 16 + col] = acc[ot][j][i];
+  }
+  // partial db: threads with the same channel chunk hold disjoint RE sums
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(lds);
+#pragma unroll
+  for (int i = 0; i < EPD; ++i) red[tid * EPD + i] = bsum[i];
+  __syncthreads();
+  if (tid < COUT) {
+    const int cc = tid / EPD, i = tid - cc * EPD;
+    float sum = 0.f;
+    for (int t2 = cc; t2 < NT; t2 += CPD) sum += red[t2 * EPD + i];
+    args.part_b[k][(size_t)blockIdx.x * COUT + tid] = sum;
+  }
+}
+
+template <class A, class InT, int CIN, int COUT>
+static hipError_t launch_wgrad_t(WgradArgs& a, int grid_y, hipStream_t s) {
+  using E = typename A::Op;
+  constexpr int TW = wg_tw<A>();
+  constexpr size_t lds = (size_t)COUT * (TMAX * TW * sizeof(E) + 16) + (size_t)CIN * (TROWS * (TW + 8) * sizeof(E) + 16);
+  static_assert(lds <= 160 * 1024, "wgrad tiles exceed LDS");
+  a.tw = TW;
+  const int grid = wgrad_grid(a.n_tiles);
+  hipError_t e = hipFuncSetAttribute((const void*)wgrad_kernel<A, InT, CIN, COUT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((wgrad_kernel<A, InT, CIN, COUT>), dim3(grid, grid_y), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+int wgrad_tile_width(int dtype) { return dtype == DT_BF16 ? wg_tw<ArithBF16>() : wg_tw<ArithF32>(); }
+int wgrad_grid(int n_tiles) { return n_tiles < 256 ? n_tiles : 256; }
+
+hipError_t launch_wgrad(int dtype, bool in_f32, int cin, int cout, WgradArgs& a, int grid_y, hipStream_t s) {
+#define CONET_WG(CI, CO)                                                                          \
+  if (cin == CI && cout == CO) {                                                                  \
+    if (dtype == DT_BF16)                                                                         \
+      return in_f32 ? launch_wgrad_t<ArithBF16, float, CI, CO>(a, grid_y, s)                      \
+                    : launch_wgrad_t<ArithBF16, __bf16, CI, CO>(a, grid_y, s);                    \
+    if (dtype == DT_F32) return launch_wgrad_t<ArithF32, float, CI, CO>(a, grid_y, s);            \
+  }
+  CONET_WG(16, 32) CONET_WG(16, 64) CONET_WG(32, 32) CONET_WG(64, 64) CONET_WG(16, 16) CONET_WG(32, 64)
+#undef CONET_WG
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- head / LN / product adjoint
+template <class Act, int C, int KB>
+__global__ void __launch_bounds__(256) fuse_bwd_kernel(FuseBwdArgs a) {
+  constexpr int QC = C / 4;
+  const int tid = threadIdx.x, q = tid & 3, wave = tid >> 6;
+  const int c0 = q * QC;
+  const int m = a.m;
+  float gam[QC], bet[QC], bet_acc[QC], gam_acc[QC], wh_acc[8][QC], bh_acc[8];
+#pragma unroll
+  for (int i = 0; i < QC; ++i) {
+    gam[i] = a.fused ? a.gamma[c0 + i] : 1.f;
+    bet[i] = a.fused ? a.beta[c0 + i] : 0.f;
+    bet_acc[i] = 0.f;
+    gam_acc[i] = 0.f;
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    bh_acc[j] = 0.f;
+#pragma unroll
+    for (int i = 0; i < QC; ++i) wh_acc[j][i] = 0.f;
+  }
+  const float invC = 1.f / (float)C;
+  const int64_t nthr = (int64_t)gridDim.x * 64;
+  for (int64_t re = (int64_t)blockIdx.x * 64 + (tid >> 2); re < a.n_re; re += nthr) {
+    float O[KB][QC], P[QC];
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk) {
+      const Act* src = reinterpret_cast<const Act*>(a.O[kk]) + re * C + c0;
+#pragma unroll
+      for (int i = 0; i < QC; ++i) O[kk][i] = (float)src[i];
+    }
+#pragma unroll
+    for (int i = 0; i < QC; ++i) {
+      float p = O[0][i];
+#pragma unroll
+      for (int kk = 1; kk < KB; ++kk) p *= O[kk][i];
+      P[i] = p;
+    }
+    float ah[QC], rs = 1.f;
+    if (a.fused) {
+      float s = 0.f;
+#pragma unroll
+      for (int i = 0; i < QC; ++i) s += P[i];
+      s += __shfl_xor(s, 1);
+      s += __shfl_xor(s, 2);
+      const float mu = s * invC;
+      float v = 0.f;
+#pragma unroll
+      for (int i = 0; i < QC; ++i) { const float d = P[i] - mu; v += d * d; }
+      v += __shfl_xor(v, 1);
+      v += __shfl_xor(v, 2);
+      rs = 1.f / sqrtf(v * invC + a.eps);
+#pragma unroll
+      for (int i = 0; i < QC; ++i) ah[i] = (P[i] - mu) * rs;
+    }
+    // gradient of the block's main activation
+    float dA[QC];
+    if (a.head) {
+      float dl[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) dl[j] = j < m ? a.dllr[re * m + j] : 0.f;
+#pragma unroll
+      for (int i = 0; i < QC; ++i) {
+        float t = 0.f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (j < m) t += a.Wh[j * C + c0 + i] * dl[j];
+        dA[i] = t;
+      }
+      // head parameters: A = gamma ahat + beta (fused) or O[0] (unfused)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (j >= m) continue;
+        if (q == 0) bh_acc[j] += dl[j];
+#pragma unroll
+        for (int i = 0; i < QC; ++i) {
+          const float Av = a.fused ? gam[i] * ah[i] + bet[i] : O[0][i];
+          wh_acc[j][i] += dl[j] * Av;
+        }
+      }
+    } else {
+      const Act* src = reinterpret_cast<const Act*>(a.dA) + re * C + c0;
+#pragma unroll
+      for (int i = 0; i < QC; ++i) dA[i] = (float)src[i];
+    }
+    float dO[KB][QC];
+    if (a.fused) {
+      float g1 = 0.f, g2 = 0.f, gv[QC];
+#pragma unroll
+      for (int i = 0; i < QC; ++i) {
+        gam_acc[i] += dA[i] * ah[i];
+        bet_acc[i] += dA[i];
+        gv[i] = gam[i] * dA[i];
+        g1 += gv[i];
+        g2 += gv[i] * ah[i];
+      }
+      g1 += __shfl_xor(g1, 1);
+      g1 += __shfl_xor(g1, 2);
+      g2 += __shfl_xor(g2, 1);
+      g2 += __shfl_xor(g2, 2);
+      g1 *= invC;
+      g2 *= invC;
+#pragma unroll
+      for (int i = 0; i < QC; ++i) {
+        const float dP = (gv[i] - g1 - ah[i] * g2) * rs;
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) {
+          float others = 1.f;
+#pragma unroll
+          for (int jj = 0; jj < KB; ++jj)
+            if (jj != kk) others *= O[jj][i];
+          dO[kk][i] = dP * others;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < QC; ++i) {
+        dO[0][i] = dA[i];
+#pragma unroll
+        for (int kk = 1; kk < KB; ++kk) dO[kk][i] = 0.f;
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk) {
+      if (!a.dO[kk]) continue;
+      if (kk > 0 && a.dnext[kk]) {
+        const Act* src = reinterpret_cast<const Act*>(a.dnext[kk]) + re * C + c0;
+#pragma unroll
+        for (int i = 0; i < QC; ++i) dO[kk][i] += (float)src[i];
+      }
+      Act* dst = reinterpret_cast<Act*>(a.dO[kk]) + re * C + c0;
+#pragma unroll
+      for (int i = 0; i < QC; ++i) dst[i] = (Act)dO[kk][i];
+    }
+  }
+  // block partials: sum over the 16 REs of a wave sharing q, then over the 4 waves
+  const int NP = 2 * C + 8 * C + 8;
+  __shared__ float red[4][2 * C + 8 * C + 8];
+  auto wsum = [&](float x) {
+    x += __shfl_xor(x, 4);
+    x += __shfl_xor(x, 8);
+    x += __shfl_xor(x, 16);
+    x += __shfl_xor(x, 32);
+    return x;
+  };
+#pragma unroll
+  for (int i = 0; i < QC; ++i) {
+    const float ga = wsum(gam_acc[i]), ba = wsum(bet_acc[i]);
+    if ((tid & 63) < 4) { red[wave][c0 + i] = ga; red[wave][C + c0 + i] = ba; }
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+#pragma unroll
+    for (int i = 0; i < QC; ++i) {
+      const float w = wsum(wh_acc[j][i]);
+      if ((tid & 63) < 4) red[wave][2 * C + j * C + c0 + i] = w;
+    }
+    const float bsum = wsum(bh_acc[j]);
+    if ((tid & 63) == 0) red[wave][10 * C + j] = bsum;
+  }
+  __syncthreads();
+  for (int i = tid; i < NP; i += 256)
+    a.part[(size_t)blockIdx.x * NP + i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+}
+
+hipError_t launch_fuse_bwd(int dtype, FuseBwdArgs& a, int grid, hipStream_t s) {
+#define CONET_FB(E, C_, K_) \
+  if (a.C == C_ && a.K == K_) { hipLaunchKernelGGL((fuse_bwd_kernel<E, C_, K_>), dim3(grid), dim3(256), 0, s, a); return hipGetLastError(); }
+#define CONET_FBC(E, C_) CONET_FB(E, C_, 1) CONET_FB(E, C_, 2) CONET_FB(E, C_, 3) CONET_FB(E, C_, 4)
+  if (dtype == DT_BF16) { CONET_FBC(__bf16, 16) CONET_FBC(__bf16, 32) CONET_FBC(__bf16, 64) }
+  if (dtype == DT_F32) { CONET_FBC(float, 16) CONET_FBC(float, 32) CONET_FBC(float, 64) }
+#undef CONET_FBC
+#undef CONET_FB
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- reductions
+__global__ void __launch_bounds__(256) reduce_kernel(const ReduceSeg* segs) {
+  const ReduceSeg sg = segs[blockIdx.y];
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= sg.cols) return;
+  float s = 0.f;
+  for (int r = 0; r < sg.rows; ++r) s += sg.src[(size_t)r * sg.ld + j];
+  int dj = j;
+  if (sg.map == 1) {
+    const int kk = 9 * sg.cin;
+    const int o = j / kk, rem = j - o * kk, tap = rem / sg.cin, ch = rem - tap * sg.cin;
+    dj = (o * sg.cin + ch) * 9 + tap;
+  }
+  sg.dst[dj] = s;
+}
+
+hipError_t launch_reduce(const ReduceSeg* segs_dev, int n_segs, int max_cols, hipStream_t s) {
+  if (n_segs == 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_kernel, dim3((max_cols + 255) / 256, n_segs), dim3(256), 0, s, segs_dev);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- loss and optimiser
+// Bitwise BCE with logits over data REs: loss partial sums per block, d loss / d LLR.
+__global__ void __launch_bounds__(256) bce_kernel(const float* llr, const uint8_t* bits, const uint8_t* dmask,
+                                                  int64_t n, int T, int F, int m, float inv_count, float* dllr,
+                                                  float* part) {
+  float acc = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int64_t re = i / m;
+    const int f = (int)(re % F), t = (int)((re / F) % T);
+    const float z = llr[i], b = (float)bits[i];
+    const bool data = dmask[t * F + f] != 0;
+    const float l = fmaxf(z, 0.f) - z * b + log1pf(expf(-fabsf(z)));
+    const float sg = 1.f / (1.f + expf(-z));
+    dllr[i] = data ? (sg - b) * inv_count : 0.f;
+    if (data) acc += l;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  __shared__ float w[4];
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (w[0] + w[1] + w[2] + w[3]) * inv_count;
+}
+
+hipError_t launch_bce(const float* llr, const uint8_t* bits, const uint8_t* dmask, int64_t n_re, int T, int F, int m,
+                      float inv_count, float* dllr, float* part, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(bce_kernel, dim3(grid), dim3(256), 0, s, llr, bits, dmask, n_re * m, T, F, m, inv_count, dllr, part);
+  return hipGetLastError();
+}
+
+// Adam on the FP32 master copy (bias-corrected moments).
+__global__ void __launch_bounds__(256) adam_kernel(float* w, const float* g, float* mo, float* ve, int64_t n, float lr,
+                                                   float b1, float b2, float eps, float bc1, float bc2) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float gi = g[i];
+    const float m1 = b1 * mo[i] + (1.f - b1) * gi;
+    const float v1 = b2 * ve[i] + (1.f - b2) * gi * gi;
+    mo[i] = m1;
+    ve[i] = v1;
+    w[i] -= lr * (m1 / bc1) / (sqrtf(v1 / bc2) + eps);
+  }
+}
+
+hipError_t launch_adam(float* w, const float* g, float* mo, float* ve, int64_t n, float lr, float b1, float b2,
+                       float eps, float bc1, float bc2, hipStream_t s) {
+  const int grid = (int)((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048);
+  hipLaunchKernelGGL(adam_kernel, dim3(grid), dim3(256), 0, s, w, g, mo, ve, n, lr, b1, b2, eps, bc1, bc2);
+  return hipGetLastError();
+}
+
+// Fragment-ordered filters regenerated from the FP32 master: dst[e] = W[map[e]] (0 where map < 0).
+__global__ void __launch_bounds__(256) repack_kernel(const float* master, const int32_t* map, void* dst, int64_t n,
+                                                     int dtype) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int32_t j = map[i];
+    const float v = j >= 0 ? master[j] : 0.f;
+    if (dtype == DT_BF16) reinterpret_cast<__bf16*>(dst)[i] = f2bf(v);
+    else reinterpret_cast<float*>(dst)[i] = v;
+  }
+}
+
+hipError_t launch_repack(const float* master, const int32_t* map, void* dst, int64_t n, int dtype, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int grid = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(repack_kernel, dim3(grid), dim3(256), 0, s, master, map, dst, n, dtype);
+  return hipGetLastError();
+}
+
+// Per-channel vectors regenerated from the master: dst[i] = W[map[i]] where map >= 0.
+__global__ void __launch_bounds__(256) gather_kernel(const float* master, const int32_t* map, float* dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int32_t j = map[i];
+    if (j >= 0) dst[i] = master[j];
+  }
+}
+
+hipError_t launch_gather(const float* master, const int32_t* map, float* dst, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int grid = (int)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
+  hipLaunchKernelGGL(gather_kernel, dim3(grid), dim3(256), 0, s, master, map, dst, n);
+  return hipGetLastError();
+}
+
+// Sum of n floats into *out (one work-group, fixed order).
+__global__ void __launch_bounds__(256) sum_kernel(const float* x, int n, float* out) {
+  __shared__ float r[256];
+  float a = 0.f;
+  for (int i = threadIdx.x; i < n; i += 256) a += x[i];
+  r[threadIdx.x] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int i = 0; i < 256; ++i) t += r[i];
+    *out = t;
+  }
+}
+
+hipError_t launch_sum(const float* x, int n, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, s, x, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace conet
