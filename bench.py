@@ -161,6 +161,72 @@ def serve_measure(loads=(0.5,), duration_s=1.5, n_streams=3, seed=13):
     return out
 
 
+def train_bench(args):
+    """One training step = forward with saved activations + bitwise BCE + backward + Adam,
+    on a batch resident in HBM (the simulator's slots tiled to the batch size)."""
+    import torch
+    from paper_2510_12739_amd import Conet
+    from synth import make_blob, simulate_slot, workload
+    from synth.ofdm import data_mask
+
+    w = workload(args.workload)
+    mc = w.model
+    dtype = args.dtype or w.dtype
+    B, T, F = w.batch, w.sim.T, w.sim.F
+    res = B * T * F
+    nd = min(8, B)
+    slots = [simulate_slot(w.sim, s) for s in range(nd)]
+    reps = -(-B // nd)
+    X = np.concatenate([np.stack([s.features for s in slots])] * reps)[:B]
+    bits = np.concatenate([np.stack([s.bits for s in slots])] * reps)[:B]
+    dm = data_mask(T, F)
+    model = Conet(mc.K, mc.L, mc.C, mc.C_in, mc.m, make_blob(mc, seed=w.weight_seed), dtype=dtype, max_res=res,
+                  train=True)
+    x = torch.from_numpy(X).cuda()
+    bt = torch.from_numpy(bits).cuda()
+    dmt = torch.from_numpy(dm.astype(np.uint8)).cuda()
+    n_data = int(dm.sum())
+    llr = torch.empty((B, T, F, mc.m), dtype=torch.float32, device="cuda")
+
+    def step():
+        model.forward(x, out=llr, save=True)
+        loss, dllr = model.bce(llr, bt, dmt, n_data)
+        model.backward(dllr)
+        model.adam_step(lr=1e-3)
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    losses = []
+    ev0.record()
+    for _ in range(args.steps):
+        losses.append(step())
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    fl_fwd = flops_per_re(mc.K, mc.L, mc.C, mc.C_in, mc.m)
+    fl_bwd = 2 * mc.K * mc.L * 2 * (2 * 9 * mc.C * mc.C) + 2 * 9 * mc.C_in * mc.K * mc.C + 4 * mc.C * mc.m
+    tf = (fl_fwd + fl_bwd) * res / (ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[dtype]
+    result = {"metric": "training REs/sec (forward + BCE + backward + Adam)", "value": round(res / (ms * 1e-3), 1),
+              "unit": "REs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+              "data": "synthetic (seeded OFDM simulator; He-normal weights; FP32 master + Adam)",
+              "config": {"workload": w.name, "slots": B, "T": T, "F": F, "K": mc.K, "L": mc.L, "C": mc.C,
+                         "C_in": mc.C_in, "m": mc.m, "res_per_step": res, "parallelism": "single-gpu"},
+              "loss_first_last": [round(float(losses[0].cpu()), 5), round(float(losses[-1].cpu()), 5)],
+              "roofline": {"bound": "mfma", "kernel": "whole training step", "achieved": round(tf, 2), "peak": peak,
+                           "unit": "TFLOP/s", "frac": round(tf / peak, 4), "traffic": None,
+                           "flops_per_step": (fl_fwd + fl_bwd) * res}}
+    line = json.dumps(result)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(line + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +263,10 @@ def main():
         ok = [p["offered_req_s"] for p in out["points"] if p["p99_us"] < 500.0]
         out["max_load_req_s_p99_under_500us"] = max(ok) if ok else None
         print(json.dumps(out), flush=True)
+        return
+
+    if args.workload.startswith("train"):
+        train_bench(args)
         return
 
     import torch

@@ -71,6 +71,8 @@ size_t train_bytes(const conet_config& c, Layout& lay, size_t base) {
   lay.tr_part_bce = take((size_t)BCE_GRID * 4);
   lay.tr_loss = take(256);
   lay.tr_segs = take((size_t)MAX_SEGS * sizeof(ReduceSeg));
+  lay.tr_red_tmp_floats = (size_t)K * 64 * 1024 + (size_t)K * 2 * C * 9 * std::max(C, Ci) + 65536;
+  lay.tr_red_tmp = take(lay.tr_red_tmp_floats * 4);
   const size_t t_act = align256(R * C * act_bytes_of(c.dtype));
   lay.tr_levels = off;
   lay.tr_levels_bytes = t_act * ((size_t)(L + 1) * K + (size_t)L * K + L + 4 * (size_t)K);
@@ -223,13 +225,21 @@ static conet_status run_backward(conet_model* M, const float* dllr, hipStream_t 
 
   // every reduction of this backward, uploaded once; each launch consumes a contiguous range
   std::vector<ReduceSeg> segs;
-  struct Range { int first, n, max_cols; };
+  struct Range { int first, n, max_cols, max_chunks; size_t tmp_used; };
   std::vector<Range> ranges;
-  auto begin_range = [&]() { ranges.push_back({(int)segs.size(), 0, 0}); };
+  float* red_tmp = reinterpret_cast<float*>(ws + lay.tr_red_tmp);
+  bool tmp_overflow = false;
+  auto begin_range = [&]() { ranges.push_back({(int)segs.size(), 0, 0, 0, 0}); };
   auto add = [&](const float* src, float* dst, int rows, int cols, int ld, int map, int cin) {
-    segs.push_back({src, dst, rows, cols, ld, map, cin});
-    ranges.back().n++;
-    ranges.back().max_cols = std::max(ranges.back().max_cols, cols);
+    Range& r = ranges.back();
+    const int chunks = (rows + REDUCE_CHUNK - 1) / REDUCE_CHUNK;
+    const size_t need = (size_t)chunks * cols;
+    if (r.tmp_used + need > lay.tr_red_tmp_floats) tmp_overflow = true;
+    segs.push_back({src, dst, rows, cols, ld, map, cin, red_tmp + r.tmp_used});
+    r.tmp_used += need;
+    r.n++;
+    r.max_cols = std::max(r.max_cols, cols);
+    r.max_chunks = std::max(r.max_chunks, chunks);
   };
 
   hipError_t e = hipMemsetAsync(grad, 0, bo.n * 4, s);
@@ -287,12 +297,13 @@ static conet_status run_backward(conet_model* M, const float* dllr, hipStream_t 
     add(part_b + k * b_stride, grad + bo.b_in[k], wg_grid, C, C, 0, 0);
   }
   if ((int)segs.size() > MAX_SEGS) return fail(CONET_EINVAL, "too many reductions");
+  if (tmp_overflow) return fail(CONET_ESHAPE, "reduction scratch too small for this batch");
   e = hipMemcpyAsync(segs_dev, segs.data(), segs.size() * sizeof(ReduceSeg), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "reduction descriptors");
 
   auto reduce = [&](size_t ri) -> hipError_t {
     const Range& r = ranges[ri];
-    return launch_reduce(segs_dev + r.first, r.n, r.max_cols, s);
+    return launch_reduce(segs_dev + r.first, r.n, r.max_cols, r.max_chunks, s);
   };
 
   // gradient w.r.t. the input of block l+1 (level l+1), per branch; null above the last block

@@ -97,14 +97,17 @@ struct FuseBwdArgs {
 };
 hipError_t launch_fuse_bwd(int dtype, FuseBwdArgs& a, int grid, hipStream_t s);
 
-// Sum of `rows` rows of `cols` floats (row stride `ld`) into dst[map(j)] (fixed order).
+// Sum of `rows` rows of `cols` floats (row stride `ld`) into dst[map(j)], in a fixed
+// order: stage 1 sums chunks of 256 rows into tmp[chunk][cols], stage 2 sums the chunks.
 // map: 0 identity; 1 filter: j = o*(9*cin) + tap*cin + ch -> ((o*cin + ch)*9 + tap).
 struct ReduceSeg {
   const float* src;
   float* dst;
   int rows, cols, ld, map, cin;
+  float* tmp;                      // [ceil(rows / 256)][cols] (set by the host)
 };
-hipError_t launch_reduce(const ReduceSeg* segs_dev, int n_segs, int max_cols, hipStream_t s);
+constexpr int REDUCE_CHUNK = 256;
+hipError_t launch_reduce(const ReduceSeg* segs_dev, int n_segs, int max_cols, int max_chunks, hipStream_t s);
 
 hipError_t launch_bce(const float* llr, const uint8_t* bits, const uint8_t* data_mask, int64_t n_re, int T, int F,
                       int m, float inv_count, float* dllr, float* part, int grid, hipStream_t s);

@@ -29,6 +29,7 @@ struct Layout {
   size_t tr_wt1[KMAX_ARGS][LMAX], tr_wt2[KMAX_ARGS][LMAX], tr_wt_begin, tr_wt_end;
   size_t tr_map_fwd, tr_map_bwd, tr_map_vec;
   size_t tr_part_conv, tr_part_conv_rows, tr_part_w, tr_part_b, tr_part_fuse, tr_part_bce, tr_loss, tr_segs;
+  size_t tr_red_tmp, tr_red_tmp_floats;
   size_t tr_levels, tr_levels_bytes;
   size_t total;
 };

@@ -405,12 +405,32 @@ hipError_t launch_fuse_bwd(int dtype, FuseBwdArgs& a, int grid, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- reductions
-__global__ void __launch_bounds__(256) reduce_kernel(const ReduceSeg* segs) {
+// Stage 1: block (column block of 64, row chunk, segment); 256 threads = 64 columns x 4
+// row lanes, each lane sums every 4th row of the chunk, then the 4 lanes are combined.
+__global__ void __launch_bounds__(256) reduce_stage1(const ReduceSeg* segs) {
+  const ReduceSeg sg = segs[blockIdx.z];
+  const int chunks = (sg.rows + REDUCE_CHUNK - 1) / REDUCE_CHUNK;
+  const int ck = blockIdx.y;
+  if (ck >= chunks) return;
+  const int j = blockIdx.x * 64 + (threadIdx.x & 63), rl = threadIdx.x >> 6;
+  const int r0 = ck * REDUCE_CHUNK, r1 = min(sg.rows, r0 + REDUCE_CHUNK);
+  float a = 0.f;
+  if (j < sg.cols)
+    for (int r = r0 + rl; r < r1; r += 4) a += sg.src[(size_t)r * sg.ld + j];
+  __shared__ float red[4][64];
+  red[rl][threadIdx.x & 63] = a;
+  __syncthreads();
+  if (rl == 0 && j < sg.cols)
+    sg.tmp[(size_t)ck * sg.cols + j] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(256) reduce_stage2(const ReduceSeg* segs) {
   const ReduceSeg sg = segs[blockIdx.y];
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= sg.cols) return;
+  const int chunks = (sg.rows + REDUCE_CHUNK - 1) / REDUCE_CHUNK;
   float s = 0.f;
-  for (int r = 0; r < sg.rows; ++r) s += sg.src[(size_t)r * sg.ld + j];
+  for (int c = 0; c < chunks; ++c) s += sg.tmp[(size_t)c * sg.cols + j];
   int dj = j;
   if (sg.map == 1) {
     const int kk = 9 * sg.cin;
@@ -420,9 +440,10 @@ __global__ void __launch_bounds__(256) reduce_kernel(const ReduceSeg* segs) {
   sg.dst[dj] = s;
 }
 
-hipError_t launch_reduce(const ReduceSeg* segs_dev, int n_segs, int max_cols, hipStream_t s) {
+hipError_t launch_reduce(const ReduceSeg* segs_dev, int n_segs, int max_cols, int max_chunks, hipStream_t s) {
   if (n_segs == 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_kernel, dim3((max_cols + 255) / 256, n_segs), dim3(256), 0, s, segs_dev);
+  hipLaunchKernelGGL(reduce_stage1, dim3((max_cols + 63) / 64, max_chunks, n_segs), dim3(256), 0, s, segs_dev);
+  hipLaunchKernelGGL(reduce_stage2, dim3((max_cols + 255) / 256, n_segs), dim3(256), 0, s, segs_dev);
   return hipGetLastError();
 }
 
