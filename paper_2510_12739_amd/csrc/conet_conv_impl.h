@@ -219,6 +219,27 @@ struct Gemm {
       for (int c = 0; c < A::CPL; ++c) a[ot][c] = wp[((s * NOT + ot) * A::CPL + c) * 64 + lane];
   }
 
+  // LDS byte offset of this lane's B fragment (chunk c of K step s) relative to its
+  // M-tile base: the step's tap shift plus 16 bytes of consecutive channels
+  __device__ __forceinline__ static constexpr int b_off(int s, int c, int g) {
+    int ch = (s * 4 + g) * A::CPL + c;
+    if (ch >= NCH) ch = 4 * CPT;  // padding chunk: any in-tile address (its weights are 0)
+    const int tap = ch / CPT, c0 = (ch - tap * CPT) * A::VEC;
+    return ((tap / 3) * (TW + 2) + (tap % 3)) * PITCH + c0 * (int)sizeof(typename A::Op);
+  }
+
+  // Filter fragments are prefetched ADEPTH K steps ahead (a ring of ADEPTH + 1 buffers)
+  // when the registers allow it, else one step ahead.
+  static constexpr int ADEPTH = (MT * NOT * 4 + 3 * NOT * A::CPL * 4 + MT * A::CPL * 4 <= 200) ? 2 : 1;
+  // B fragments of the next step are prefetched (rolling) unless two chunks per MFMA
+  // (FP8) leave no registers for it; then each step issues its own B reads first.
+  static constexpr bool BROLL = A::CPL == 1;
+
+  // Software pipeline of one wave. The filter fragments of step s + ADEPTH are issued
+  // before step s's MFMAs; the B fragment of M-tile mt for step s + 1 is issued right
+  // after the last MFMA of step s that reads it, into the same registers, so about one
+  // step of MFMAs hides every load. Scheduling barriers keep the compiler from sinking
+  // the loads next to their uses.
   __device__ __forceinline__ static void run(AccV (&acc)[MT][NOT], const uint8_t* lds, const i32x4* __restrict__ wp,
                                              int wave, int lane) {
     const int g = lane >> 4, col = lane & 15;
@@ -235,30 +256,40 @@ struct Gemm {
       const int t = idx / (TW / 16), cb = idx - t * (TW / 16);
       base[mt] = (t * (TW + 2) + cb * 16 + col) * PITCH;
     }
-    i32x4 a0[NOT][A::CPL], a1[NOT][A::CPL];
-    load_a(a0, wp, 0, lane);
+    constexpr int NA = ADEPTH + 1;
+    i32x4 a[NA][NOT][A::CPL];
+    i32x4 b[MT][A::CPL];
+#pragma unroll
+    for (int d = 0; d < ADEPTH; ++d)
+      if (d < NS) load_a(a[d], wp, d, lane);
+    if constexpr (BROLL) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int c = 0; c < A::CPL; ++c) b[mt][c] = *reinterpret_cast<const i32x4*>(lds + base[mt] + b_off(0, c, g));
+    }
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      i32x4 (&ac)[NOT][A::CPL] = (s & 1) ? a1 : a0;
-      i32x4 (&an)[NOT][A::CPL] = (s & 1) ? a0 : a1;
-      if (s + 1 < NS) load_a(an, wp, s + 1, lane);
-      int off[A::CPL];
+      if (s + ADEPTH < NS) load_a(a[(s + ADEPTH) % NA], wp, s + ADEPTH, lane);
+      if constexpr (!BROLL) {
 #pragma unroll
-      for (int c = 0; c < A::CPL; ++c) {
-        int ch = (s * 4 + g) * A::CPL + c;
-        if (ch >= NCH) ch = 4 * CPT;  // padding chunk: any in-tile address (its weights are 0)
-        const int tap = ch / CPT, c0 = (ch - tap * CPT) * A::VEC;
-        off[c] = ((tap / 3) * (TW + 2) + (tap % 3)) * PITCH + c0 * (int)sizeof(typename A::Op);
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int c = 0; c < A::CPL; ++c)
+            b[mt][c] = *reinterpret_cast<const i32x4*>(lds + base[mt] + b_off(s, c, g));
       }
-      i32x4 bf[MT][A::CPL];
+      if constexpr (BROLL) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+      for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
-        for (int c = 0; c < A::CPL; ++c) bf[mt][c] = *reinterpret_cast<const i32x4*>(lds + base[mt] + off[c]);
+        for (int ot = 0; ot < NOT; ++ot) acc[mt][ot] = A::mma(a[s % NA][ot], b[mt], acc[mt][ot]);
+        if (BROLL && s + 1 < NS) {
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int ot = 0; ot < NOT; ++ot) acc[mt][ot] = A::mma(ac[ot], bf[mt], acc[mt][ot]);
+          for (int c = 0; c < A::CPL; ++c)
+            b[mt][c] = *reinterpret_cast<const i32x4*>(lds + base[mt] + b_off(s + 1, c, g));
+        }
+        if constexpr (BROLL) __builtin_amdgcn_sched_barrier(0);
+      }
     }
   }
 };
