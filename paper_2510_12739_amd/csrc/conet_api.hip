@@ -154,7 +154,7 @@ conet_status check_config(const conet_config* c) {
 
 size_t arena_bytes(const conet_config& c, int64_t max_res) {
   const size_t R = (size_t)max_res, C = c.channels, K = c.branches;
-  const size_t max_tiles = 2 * ((size_t)max_res / 16 + 4096);
+  const size_t max_tiles = 3 * ((size_t)max_res / 16 + 4096);
   size_t off = align256(max_tiles * sizeof(TileDesc)) + 256;           // descriptors + amax counters
   off += 2 * K * align256(R * C * act_bytes(c.dtype));
   off += K * align256(R * C * hid_bytes(c.dtype));
@@ -165,7 +165,7 @@ void arena_carve(const conet_config& c, int64_t max_res, uint8_t* base, Arena& a
   const size_t R = (size_t)max_res, C = c.channels;
   const int K = c.branches;
   ar.max_res = max_res;
-  ar.max_tiles = 2 * ((size_t)max_res / 16 + 4096);
+  ar.max_tiles = 3 * ((size_t)max_res / 16 + 4096);
   size_t off = 0;
   ar.tiles = reinterpret_cast<TileDesc*>(base + off);
   off = align256(off + ar.max_tiles * sizeof(TileDesc));

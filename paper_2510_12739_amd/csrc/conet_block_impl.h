@@ -1,0 +1,303 @@
+// Fused residual block of the CoNet-Rx forward pass (gfx950): both 3x3 convs of one
+// block of one branch in a single launch, with the hidden activation h kept in LDS.
+//
+// A block computes O = x + W2 * ReLU(s1 (W1 * pre(x) + b1) + o1) + b2 with
+// pre(x) = ReLU(s0 x + o0) (ReLU(x) on the main branch after a fusion). Run as two
+// convs, h makes a round trip through HBM and x is read twice; here one work-group
+// owns one tile (a slot, its T <= 14 symbols, TWO output subcarriers) and:
+//   1. stages pre(x) for subcarriers f0-2 .. f0+TWO+1 (two-RE halo) into LDS,
+//   2. runs conv 1 on the (14 x TWO+2) region that conv 2 needs (MFMA, h in registers),
+//   3. after a barrier, overwrites the x tile with h (zero outside the slot, rounded to
+//      the operand type exactly as a stored h would be),
+//   4. runs conv 2 on the 14 x TWO output region and finishes the block: residual add
+//      and, on the main branch of a fused block, the product with the stored support
+//      outputs, the LayerNorm and the LLR head.
+// HBM traffic per branch drops from five activation passes (x, h written, h read, x
+// read again, O written) to two plus the residual re-read, which hits L2 or the
+// last-level cache. The conv-1 halo recompute costs (TWO+2)/TWO of conv 1's MFMAs.
+//
+// M-tiles are 16 consecutive REs of a region flattened row-major (t, j), so they may
+// straddle two OFDM symbols; each lane computes its own LDS address, so the GEMM core
+// does not care. Both GEMMs use the register-pipelined core of the single-conv kernel.
+#pragma once
+#include "conet_conv_impl.h"
+
+namespace conet {
+
+// Output subcarriers per fused tile (0: no fused kernel for this type / width). The
+// x tile of TROWS x (TWO+4) positions must leave room for two work-groups per CU, and
+// conv 1's accumulators (ceil(14 (TWO+2) / 64) M-tiles per wave) must fit the
+// per-lane register budget.
+template <class A, int C>
+constexpr int block_tw() {
+  if constexpr (std::is_same<A, ArithBF16>::value) return C == 64 ? 30 : C == 32 ? 44 : C == 16 ? 60 : 0;
+  return 0;
+}
+
+// Raw 16-byte (or 8-byte) vectors holding one lane's EPL activation values of one RE.
+template <class Act, int EPL>
+using RawOf = typename std::conditional<(EPL * sizeof(Act)) % 16 == 0, i32x4, uint2>::type;
+
+template <class Act, class RawT, int EPL, class Acc>
+__device__ __forceinline__ void unpack_raw(const RawT* r, Acc* v) {
+  const Act* a = reinterpret_cast<const Act*>(r);
+#pragma unroll
+  for (int i = 0; i < EPL; ++i) v[i] = (Acc)(float)a[i];
+}
+
+// NSUP: support branches multiplied in by the main branch (K - 1; 0 otherwise).
+template <class A, int C, int TWO, bool MAIN, int NSUP>
+__global__ void __launch_bounds__(CONV_NW * 64, 2) block_kernel(BlockArgs args) {
+  using Acc = typename A::Acc;
+  using AccV = typename A::AccV;
+  using Act = typename A::Act;
+  using Op = typename A::Op;
+  constexpr int NW = CONV_NW, NT = NW * 64;
+  constexpr int XW = TWO + 4, HW = TWO + 2;  // LDS positions per row: x tile, h tile
+  constexpr int PITCH = lds_pitch<A, C>();
+  constexpr int Q1 = TMAX * HW, Q2 = TMAX * TWO;  // REs of the conv-1 and conv-2 regions
+  constexpr int M1 = (Q1 + 15) / 16, M2 = (Q2 + 15) / 16;
+  constexpr int MT1 = (M1 + NW - 1) / NW, MT2 = (M2 + NW - 1) / NW;
+  constexpr int NOT = C / 16, EPL = 4 * NOT;
+  using G1 = GemmCore<A, C, C, XW, PITCH, MT1>;
+  using G2 = GemmCore<A, C, C, HW, PITCH, MT2>;
+  static_assert(TROWS * XW * PITCH <= 80 * 1024, "x tile must leave room for two work-groups per CU");
+  static_assert((C * (int)sizeof(Op)) % 16 == 0, "h rows are written in 16-byte chunks");
+  __shared__ __attribute__((aligned(16))) uint8_t lds[TROWS * XW * PITCH];
+
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const TileDesc td = tile_of(args, bid);
+  const int T = args.T;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, col = lane & 15;
+  const int c0 = g * EPL;  // first channel owned by this lane
+  const int k = blockIdx.y + args.k_off;
+
+  // 1. pre(x) with a two-RE halo; LDS row r = symbol r - 1, column c = subcarrier f0 + c - 2
+  stage_tile<A, Act, C, XW, 2, PITCH, NT>(lds, reinterpret_cast<const Act*>(args.x[k]), td, T,
+                                          args.pre_s[k] ? 1 : 2, args.pre_s[k], args.pre_o[k], args.q1[k]);
+  __syncthreads();
+
+  // 2. conv 1 on RE q = t * HW + j of the region (symbol t, subcarrier f0 - 1 + j)
+  AccV acc1[MT1][NOT];
+  {
+    int base[MT1];
+#pragma unroll
+    for (int mt = 0; mt < MT1; ++mt) {
+      int q = (wave + NW * mt) * 16 + col;
+      if (q >= Q1) q = Q1 - 1;  // surplus lanes recompute a real RE (never written)
+      const int t = q / HW, j = q - t * HW;
+      base[mt] = (t * XW + j) * PITCH;  // tap (-1, -1): x row t (symbol t - 1), column j
+    }
+    G1::run(acc1, lds, reinterpret_cast<const i32x4*>(args.w1[k]), base, lane);
+  }
+  float pb[EPL], ps[EPL], po[EPL], pq[EPL];
+#pragma unroll
+  for (int i = 0; i < EPL; ++i) {
+    pb[i] = args.b1[k][c0 + i];
+    ps[i] = args.post_s[k][c0 + i];
+    po[i] = args.post_o[k][c0 + i];
+    pq[i] = A::QUANT ? args.deq1[k] * args.ws1[k][c0 + i] : 1.0f;
+  }
+  __syncthreads();  // every wave has read its last x operand: h may overwrite the tile
+
+  // 3. h = ReLU(s1 (conv + b1) + o1) into LDS row t + 1 (symbol t), column j; zero for
+  //    REs outside the slot (conv 2's zero padding)
+#pragma unroll
+  for (int mt = 0; mt < MT1; ++mt) {
+    const int q = (wave + NW * mt) * 16 + col;
+    if (wave + NW * mt >= M1 || q >= Q1) continue;
+    const int t = q / HW, j = q - t * HW;
+    const int f = td.f0 - 1 + j;
+    const bool valid = t < T && f >= 0 && f < td.F;
+    float v[EPL];
+#pragma unroll
+    for (int ot = 0; ot < NOT; ++ot)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int e = 4 * ot + i;
+        Acc a = acc1[mt][ot][i];
+        if constexpr (A::QUANT) a = a * (Acc)pq[e];
+        const float z = ps[e] * (float)(a + (Acc)pb[e]) + po[e];
+        v[e] = valid ? fmaxf(z, 0.f) : 0.f;
+      }
+    uint8_t* dst = lds + ((t + 1) * HW + j) * PITCH + c0 * (int)sizeof(Op);
+    if constexpr (sizeof(Op) == 2) {
+#pragma unroll
+      for (int i = 0; i < EPL; i += 8) {
+        __bf16 bb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) bb[u] = f2bf(v[i + u]);
+        *reinterpret_cast<i32x4*>(dst + 2 * i) = *reinterpret_cast<const i32x4*>(bb);
+      }
+    } else if constexpr (sizeof(Op) == 1) {
+      const float qs = args.q2[k];
+#pragma unroll
+      for (int i = 0; i < EPL; i += 8) {
+        uint2 w;
+        w.x = pack4_e4m3(v[i] * qs, v[i + 1] * qs, v[i + 2] * qs, v[i + 3] * qs);
+        w.y = pack4_e4m3(v[i + 4] * qs, v[i + 5] * qs, v[i + 6] * qs, v[i + 7] * qs);
+        *reinterpret_cast<uint2*>(dst + i) = w;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPL; i += 4)
+        *reinterpret_cast<float4*>(dst + 4 * i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+    }
+  }
+  {  // h rows of symbols -1 and 14 (rows t in [T, 14) were written as zeros above)
+    constexpr int CH = C * (int)sizeof(Op) / 16;  // 16-byte chunks per position
+    for (int i = threadIdx.x; i < 2 * HW * CH; i += NT) {
+      const int rr = i / (HW * CH), rem = i - rr * HW * CH;
+      const int j = rem / CH, ch = rem - j * CH;
+      *reinterpret_cast<i32x4*>(lds + ((rr ? TROWS - 1 : 0) * HW + j) * PITCH + ch * 16) = i32x4{0, 0, 0, 0};
+    }
+  }
+  __syncthreads();
+
+  // 4. conv 2 on RE q = t * TWO + j of the output region (symbol t, subcarrier f0 + j).
+  //    The block output's other inputs (the residual x and, on the main branch, the
+  //    support outputs) of the first PRE M-tiles are loaded into registers while the
+  //    MFMAs run; the rest are issued right after (all of them on a plain branch, then
+  //    PD M-tiles ahead on the main branch).
+  using RawT = RawOf<Act, EPL>;
+  constexpr int NR = EPL * (int)sizeof(Act) / (int)sizeof(RawT);
+  constexpr int NTEN = 1 + NSUP;
+  constexpr int PD = MAIN ? (MT2 < 2 ? MT2 : 2) : MT2;
+  RawT raw[PD][NTEN][NR];
+  auto re_of = [&](int mt, bool& ok) -> int64_t {
+    const int q = (wave + NW * mt) * 16 + col;
+    const int t = q / TWO, j = q - t * TWO;
+    const int f = td.f0 + j;
+    ok = wave + NW * mt < M2 && q < Q2 && t < T && f < td.F;
+    return td.re_base + (int64_t)t * td.F + f;
+  };
+  auto issue = [&](int mt) {
+    bool ok;
+    int64_t re = re_of(mt, ok);
+    if (!ok) re = td.re_base;  // any RE of the slot: loaded, never used
+    const RawT* p = reinterpret_cast<const RawT*>(reinterpret_cast<const Act*>(args.x[k]) + re * C + c0);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) raw[mt % PD][0][r] = p[r];
+#pragma unroll
+    for (int sidx = 1; sidx <= NSUP; ++sidx) {
+      const RawT* ps_ = reinterpret_cast<const RawT*>(reinterpret_cast<const Act*>(args.sup[sidx]) + re * C + c0);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) raw[mt % PD][sidx][r] = ps_[r];
+    }
+  };
+  constexpr int PRE = MAIN ? 1 : (PD < 3 ? PD : 3);  // as many as the GEMM's registers leave room for
+#pragma unroll
+  for (int d = 0; d < PRE; ++d) issue(d);
+  AccV acc2[MT2][NOT];
+  {
+    int base[MT2];
+#pragma unroll
+    for (int mt = 0; mt < MT2; ++mt) {
+      int q = (wave + NW * mt) * 16 + col;
+      if (q >= Q2) q = Q2 - 1;
+      const int t = q / TWO, j = q - t * TWO;
+      base[mt] = (t * HW + j) * PITCH;  // tap (-1, -1): h row t (symbol t - 1), column j
+    }
+    G2::run(acc2, lds, reinterpret_cast<const i32x4*>(args.w2[k]), base, lane);
+  }
+#pragma unroll
+  for (int d = PRE; d < PD; ++d) issue(d);
+#pragma unroll
+  for (int i = 0; i < EPL; ++i) {
+    pb[i] = args.b2[k][c0 + i];
+    pq[i] = A::QUANT ? args.deq2[k] * args.ws2[k][c0 + i] : 1.0f;
+  }
+  const bool head = MAIN ? args.llr != nullptr : (args.llr != nullptr && k == 0);
+
+  // 5. block output. The LayerNorm affine and the head (read by every M-tile) are
+  //    copied into the now free LDS tile once, instead of one global load per use.
+  const float* gam = args.gamma;
+  const float* bet = args.beta;
+  const float* wh = args.Wh;
+  const float* bhh = args.bh;
+  if (MAIN || head) {  // uniform over the work-group
+    __syncthreads();   // every wave has read its last h operand
+    float* pl = reinterpret_cast<float*>(lds);
+    const int nwh = args.m * C;
+    for (int i = threadIdx.x; i < 2 * C + nwh + 8; i += NT) {
+      float val;
+      if (i < C) val = MAIN ? args.gamma[i] : 0.f;
+      else if (i < 2 * C) val = MAIN ? args.beta[i - C] : 0.f;
+      else if (i < 2 * C + nwh) val = head ? args.Wh[i - 2 * C] : 0.f;
+      else val = (head && i - 2 * C - nwh < args.m) ? args.bh[i - 2 * C - nwh] : 0.f;
+      pl[i] = val;
+    }
+    __syncthreads();
+    gam = pl;
+    bet = pl + C;
+    wh = pl + 2 * C;
+    bhh = pl + 2 * C + nwh;
+  }
+#pragma unroll
+  for (int mt = 0; mt < MT2; ++mt) {
+    bool ok;
+    const int64_t re = re_of(mt, ok);
+    if (ok) {
+      Acc v[EPL];
+#pragma unroll
+      for (int ot = 0; ot < NOT; ++ot)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          Acc a = acc2[mt][ot][i];
+          if constexpr (A::QUANT) a = a * (Acc)pq[4 * ot + i];
+          v[4 * ot + i] = a + (Acc)pb[4 * ot + i];
+        }
+      finish_block<A, C, EPL, NSUP>(
+          v, re, c0, g, MAIN, [&](Acc* x) { unpack_raw<Act, RawT, EPL>(raw[mt % PD][0], x); },
+          [&](int kk, Acc* sv) { unpack_raw<Act, RawT, EPL>(raw[mt % PD][kk], sv); }, MAIN ? args.out[0] : args.out[k],
+          nullptr, head, NSUP + 1, gam, bet, args.eps, wh, bhh, args.llr, args.m);
+    }
+    if (mt + PD < MT2) issue(mt + PD);
+  }
+}
+
+template <class A, int C>
+static hipError_t launch_block_c(bool main, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+  constexpr int TWO = block_tw<A, C>();
+  if constexpr (TWO == 0) {
+    return hipErrorInvalidValue;
+  } else {
+    a.tw = TWO;
+    const dim3 grid(n_tiles, grid_y), blk(CONV_NW * 64);
+    if (!main) {
+      hipLaunchKernelGGL((block_kernel<A, C, TWO, false, 0>), grid, blk, 0, s, a);
+    } else {
+      switch (a.K) {
+        case 1: hipLaunchKernelGGL((block_kernel<A, C, TWO, true, 0>), grid, blk, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((block_kernel<A, C, TWO, true, 1>), grid, blk, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((block_kernel<A, C, TWO, true, 2>), grid, blk, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((block_kernel<A, C, TWO, true, 3>), grid, blk, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+      }
+    }
+    return hipGetLastError();
+  }
+}
+
+template <class A>
+hipError_t launch_block_dtype(bool main, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+  switch (C) {
+    case 16: return launch_block_c<A, 16>(main, a, n_tiles, grid_y, s);
+    case 32: return launch_block_c<A, 32>(main, a, n_tiles, grid_y, s);
+    case 64: return launch_block_c<A, 64>(main, a, n_tiles, grid_y, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class A>
+int block_tile_width_dtype(int C) {
+  switch (C) {
+    case 16: return block_tw<A, 16>();
+    case 32: return block_tw<A, 32>();
+    case 64: return block_tw<A, 64>();
+  }
+  return 0;
+}
+
+}  // namespace conet

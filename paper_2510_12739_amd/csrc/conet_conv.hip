@@ -1,4 +1,5 @@
-// Dtype dispatch of the 3x3 conv kernels (kernel bodies: conet_conv_impl.h).
+// Dtype dispatch of the 3x3 conv kernels (kernel bodies: conet_conv_impl.h) and of the
+// fused block kernel (conet_block_impl.h).
 #include "conet_kernels.h"
 
 namespace conet {
@@ -9,6 +10,8 @@ hipError_t launch_conv_fp8(int mode, int cin, int cout, ConvArgs& a, int n_tiles
 int conv_tile_width_f32(int cin, int cout);
 int conv_tile_width_bf16(int cin, int cout);
 int conv_tile_width_fp8(int cin, int cout);
+hipError_t launch_block_bf16(bool main, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
+int block_tile_width_bf16(int C);
 
 hipError_t launch_conv(int dtype, int mode, int cin, int cout, ConvArgs& a, int n_tiles, int grid_y, hipStream_t s) {
   switch (dtype) {
@@ -29,5 +32,15 @@ int conv_tile_width(int dtype, int cin, int cout) {
 }
 
 bool conv_supported(int dtype, int cin, int cout) { return conv_tile_width(dtype, cin, cout) > 0; }
+
+int block_tile_width(int dtype, int C, int K) {
+  if (K < 1 || K > BLOCK_KMAX) return 0;
+  return dtype == DT_BF16 ? block_tile_width_bf16(C) : 0;
+}
+
+hipError_t launch_block(int dtype, bool main, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+  if (dtype == DT_BF16) return launch_block_bf16(main, C, a, n_tiles, grid_y, s);
+  return hipErrorInvalidValue;
+}
 
 }  // namespace conet

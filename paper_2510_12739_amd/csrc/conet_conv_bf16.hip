@@ -1,5 +1,6 @@
-// BF16 instantiations of the 3x3 conv kernels (one translation unit per dtype).
-#include "conet_conv_impl.h"
+// BF16 instantiations of the 3x3 conv kernels and the fused block kernel (one
+// translation unit per dtype).
+#include "conet_block_impl.h"
 
 namespace conet {
 
@@ -8,5 +9,11 @@ hipError_t launch_conv_bf16(int mode, int cin, int cout, ConvArgs& a, int n_tile
 }
 
 int conv_tile_width_bf16(int cin, int cout) { return tile_width_dtype<ArithBF16>(cin, cout); }
+
+hipError_t launch_block_bf16(bool main, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+  return launch_block_dtype<ArithBF16>(main, C, a, n_tiles, grid_y, s);
+}
+
+int block_tile_width_bf16(int C) { return block_tile_width_dtype<ArithBF16>(C); }
 
 }  // namespace conet

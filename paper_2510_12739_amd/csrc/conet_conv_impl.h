@@ -77,7 +77,8 @@ __device__ __forceinline__ void store_vals(T* p, const V* v, int n, float qscale
 }
 
 // ---------------------------------------------------------------- tile mapping
-__device__ __forceinline__ TileDesc tile_of(const ConvArgs& a, int bid) {
+template <class Args>
+__device__ __forceinline__ TileDesc tile_of(const Args& a, int bid) {
   if (a.tiles) return a.tiles[bid];
   TileDesc d;
   const int b = bid / a.tiles_per_slot;
@@ -109,21 +110,22 @@ constexpr int tile_w() {
 }
 
 // ---------------------------------------------------------------- staging
-// Stage the TROWS x (TW+2) halo tile of `in` (CIN channels of InT per RE) into LDS as
-// Op with PITCH bytes per position. Thread `tid` always handles the same channel chunk
-// (its prologue parameters stay in registers); loads are issued in batches of NB
-// positions before any is consumed, so their latencies overlap.
-template <class A, class InT, int CIN, int TW, int PITCH, int NT>
+// Stage the TROWS x XW halo tile of `in` (CIN channels of InT per RE) into LDS as Op
+// with PITCH bytes per position: LDS row r holds OFDM symbol r - 1, column c holds
+// subcarrier f0 + c - COFF. Thread `tid` always handles the same channel chunk (its
+// prologue parameters stay in registers); loads are issued in batches of NB positions
+// before any is consumed, so their latencies overlap.
+template <class A, class InT, int CIN, int XW, int COFF, int PITCH, int NT>
 __device__ __forceinline__ void stage_tile(uint8_t* lds, const InT* __restrict__ in, const TileDesc& td, int T,
                                            int prologue, const float* __restrict__ ps, const float* __restrict__ po,
                                            float qscale) {
   using Op = typename A::Op;
   constexpr int EPC = 16 / sizeof(InT) < 4 ? 4 : 16 / (int)sizeof(InT);  // elements per 16-B global chunk
   constexpr int CPP = CIN / EPC;                                          // chunks per position
-  constexpr int NPOS = TROWS * (TW + 2);
+  constexpr int NPOS = TROWS * XW;
   constexpr int PPR = NT / CPP;                                           // positions per round
   constexpr int NIT = (NPOS + PPR - 1) / PPR;
-  constexpr int NB = 8;
+  constexpr int NB = NIT <= 24 ? NIT : 8;  // all of a thread's loads in flight at once when they fit
   static_assert(CIN % EPC == 0 && sizeof(InT) <= 4, "channel count must fill whole 16-byte chunks");
   const int tid = threadIdx.x;
   if (tid >= PPR * CPP) return;
@@ -141,8 +143,8 @@ __device__ __forceinline__ void stage_tile(uint8_t* lds, const InT* __restrict__
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int pos = p0 + (b0 + j) * PPR;
-      const int r = pos / (TW + 2), c = pos - r * (TW + 2);
-      const int t = r - 1, f = td.f0 + c - 1;
+      const int r = pos / XW, c = pos - r * XW;
+      const int t = r - 1, f = td.f0 + c - COFF;
       ok[j] = (b0 + j < NIT) && pos < NPOS && t >= 0 && t < T && f >= 0 && f < td.F;
       raw[j] = i32x4{0, 0, 0, 0};
       if (ok[j]) raw[j] = *reinterpret_cast<const i32x4*>(in + (td.re_base + (int64_t)t * td.F + f) * CIN + ch);
@@ -194,18 +196,17 @@ __device__ __forceinline__ void stage_tile(uint8_t* lds, const InT* __restrict__
 }
 
 // ---------------------------------------------------------------- GEMM core
-// acc[mt][ot] += W (o-tile ot) x X^T (M-tile mt) over all K steps. M-tile mt of this
-// wave is global M-tile index wave + NW*mt: OFDM symbol t = idx / (TW/16), subcarrier
-// block cb = idx % (TW/16). Rows t >= T read the zero rows staged for them.
-template <class A, int CIN, int COUT, int TW, int PITCH, int NW>
-struct Gemm {
+// acc[mt][ot] += W (o-tile ot) x X^T (M-tile mt) over all K steps, for MT M-tiles of
+// 16 REs each. The caller gives, per M-tile, the LDS byte offset of this lane's RE for
+// tap (-1, -1); the staged input has ROWP positions per row and PITCH bytes per
+// position, so tap (dt, dc) adds ((dt + 1) ROWP + dc + 1) positions.
+template <class A, int CIN, int COUT, int ROWP, int PITCH, int MT>
+struct GemmCore {
   static constexpr int NOT = COUT / 16;
   static constexpr int CPT = CIN / A::VEC;                       // chunks per tap
   static constexpr int NCH = 9 * CPT;                            // real chunks
   static constexpr int CPS = 4 * A::CPL;                         // chunks per K step
   static constexpr int NS = (NCH + CPS - 1) / CPS;               // K steps
-  static constexpr int MTOT = TMAX * (TW / 16);                  // M-tiles per tile (T = 14)
-  static constexpr int MT = (MTOT + NW - 1) / NW;                // M-tiles per wave
   static_assert(COUT % 16 == 0, "output channels must be a multiple of 16");
   static_assert(CIN % A::VEC == 0, "");
 
@@ -225,7 +226,7 @@ struct Gemm {
     int ch = (s * 4 + g) * A::CPL + c;
     if (ch >= NCH) ch = 4 * CPT;  // padding chunk: any in-tile address (its weights are 0)
     const int tap = ch / CPT, c0 = (ch - tap * CPT) * A::VEC;
-    return ((tap / 3) * (TW + 2) + (tap % 3)) * PITCH + c0 * (int)sizeof(typename A::Op);
+    return ((tap / 3) * ROWP + (tap % 3)) * PITCH + c0 * (int)sizeof(typename A::Op);
   }
 
   // Filter fragments are prefetched ADEPTH K steps ahead (a ring of ADEPTH + 1 buffers)
@@ -241,21 +242,12 @@ struct Gemm {
   // step of MFMAs hides every load. Scheduling barriers keep the compiler from sinking
   // the loads next to their uses.
   __device__ __forceinline__ static void run(AccV (&acc)[MT][NOT], const uint8_t* lds, const i32x4* __restrict__ wp,
-                                             int wave, int lane) {
-    const int g = lane >> 4, col = lane & 15;
+                                             const int (&base)[MT], int lane) {
+    const int g = lane >> 4;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int ot = 0; ot < NOT; ++ot) acc[mt][ot] = AccV{};
-    // LDS byte offset of this lane's RE in each M-tile, for tap (-1, -1) (top-left)
-    int base[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      int idx = wave + NW * mt;
-      if (idx >= MTOT) idx = MTOT - 1;  // surplus tile of an uneven split: recompute a real one
-      const int t = idx / (TW / 16), cb = idx - t * (TW / 16);
-      base[mt] = (t * (TW + 2) + cb * 16 + col) * PITCH;
-    }
     constexpr int NA = ADEPTH + 1;
     i32x4 a[NA][NOT][A::CPL];
     i32x4 b[MT][A::CPL];
@@ -294,6 +286,103 @@ struct Gemm {
   }
 };
 
+// The single-conv tile: M-tile mt of this wave is global M-tile index wave + NW*mt:
+// OFDM symbol t = idx / (TW/16), subcarrier block cb = idx % (TW/16). Rows t >= T read
+// the zero rows staged for them.
+template <class A, int CIN, int COUT, int TW, int PITCH, int NW>
+struct Gemm {
+  static constexpr int MTOT = TMAX * (TW / 16);                  // M-tiles per tile (T = 14)
+  static constexpr int MT = (MTOT + NW - 1) / NW;                // M-tiles per wave
+  static constexpr int NOT = COUT / 16;
+  using Core = GemmCore<A, CIN, COUT, TW + 2, PITCH, MT>;
+  using AccV = typename A::AccV;
+
+  __device__ __forceinline__ static void run(AccV (&acc)[MT][NOT], const uint8_t* lds, const i32x4* __restrict__ wp,
+                                             int wave, int lane) {
+    const int col = lane & 15;
+    int base[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      int idx = wave + NW * mt;
+      if (idx >= MTOT) idx = MTOT - 1;  // surplus tile of an uneven split: recompute a real one
+      const int t = idx / (TW / 16), cb = idx - t * (TW / 16);
+      base[mt] = (t * (TW + 2) + cb * 16 + col) * PITCH;
+    }
+    Core::run(acc, lds, wp, base, lane);
+  }
+};
+
+// ---------------------------------------------------------------- block output
+// Epilogue of a block's second conv for one RE: v holds conv + bias for this lane's EPL
+// channels from c0 (lanes g = 0..3 of one column hold the RE's C channels). Adds the
+// residual x (x_fn fills EPL values). On the main branch of a fused block (main_fused),
+// keeps the pre-product output when save_o0 is set, multiplies in the stored support
+// outputs of branches 1..K-1 (sup_fn(kk, values), kk < min(K, NSUP + 1)) and applies the
+// per-RE LayerNorm over C. Then either the 1x1 LLR head (head) or a store of the block
+// output to `out` (nullable). A plain block with the head stores its output to save_o0
+// when that is set (the backward's copy).
+template <class A, int COUT, int EPL, int NSUP, class XFn, class SupFn>
+__device__ __forceinline__ void finish_block(typename A::Acc (&v)[EPL], int64_t re, int c0, int g, bool main_fused,
+                                             XFn x_fn, SupFn sup_fn, void* out, void* save_o0, bool head, int K,
+                                             const float* gamma, const float* beta, float eps, const float* Wh,
+                                             const float* bh, float* llr, int m) {
+  using Acc = typename A::Acc;
+  using Act = typename A::Act;
+  {
+    Acc x[EPL];
+    x_fn(x);
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) v[i] += x[i];
+  }
+  if (!main_fused) {
+    if (head && save_o0) store_vals(reinterpret_cast<Act*>(save_o0) + re * COUT + c0, v, EPL, 1.f);
+    if (!head && out) store_vals(reinterpret_cast<Act*>(out) + re * COUT + c0, v, EPL, 1.f);
+  } else {  // product with the stored support outputs, then LayerNorm over C
+    if (save_o0) store_vals(reinterpret_cast<Act*>(save_o0) + re * COUT + c0, v, EPL, 1.f);
+#pragma unroll
+    for (int kk = 1; kk <= NSUP; ++kk) {
+      if (kk >= K) break;
+      Acc sv[EPL];
+      sup_fn(kk, sv);
+#pragma unroll
+      for (int i = 0; i < EPL; ++i) v[i] *= sv[i];
+    }
+    Acc s = 0;
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) s += v[i];
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    const Acc mu = s * ((Acc)1 / (Acc)COUT);
+    Acc q = 0;
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) { const Acc d = v[i] - mu; q += d * d; }
+    q += __shfl_xor(q, 16);
+    q += __shfl_xor(q, 32);
+    const Acc rs = (Acc)1 / sqrtf((float)(q * ((Acc)1 / (Acc)COUT) + (Acc)eps));
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) v[i] = (Acc)gamma[c0 + i] * (v[i] - mu) * rs + (Acc)beta[c0 + i];
+    if (!head && out) store_vals(reinterpret_cast<Act*>(out) + re * COUT + c0, v, EPL, 1.f);
+  }
+  if (head) {
+    Acc part[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      part[j] = 0;
+      if (j < m)
+#pragma unroll
+        for (int i = 0; i < EPL; ++i) part[j] += (Acc)Wh[j * COUT + c0 + i] * v[i];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      part[j] += __shfl_xor(part[j], 16);
+      part[j] += __shfl_xor(part[j], 32);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < m && (j & 3) == g) llr[re * m + j] = (float)(part[j] + (Acc)bh[j]);
+  }
+}
+
 // ---------------------------------------------------------------- the kernel
 // MODE 0: input layer            out = ReLU(conv(X) + b)
 // MODE 1: first conv of a block  out = ReLU(s1 (conv(prologue(x)) + b1) + o1)   (or its max, calibration)
@@ -331,7 +420,7 @@ __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
 
   int prologue = 0;
   if (MODE == 1) prologue = args.pre_s[k] ? 1 : 2;
-  stage_tile<A, InT, CIN, TW, PITCH, NT>(lds, reinterpret_cast<const InT*>(args.in[k]), td, T, prologue,
+  stage_tile<A, InT, CIN, TW + 2, 1, PITCH, NT>(lds, reinterpret_cast<const InT*>(args.in[k]), td, T, prologue,
                                          args.pre_s[k], args.pre_o[k], args.in_qscale[k]);
   __syncthreads();
   AccV acc[MT][NOT];
@@ -434,58 +523,13 @@ __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
         store_vals(reinterpret_cast<Hid*>(args.out[k]) + re * COUT + c0, v, EPL, args.out_qscale[k]);
       }
     } else {
-      Acc x[EPL];
-      load_vals(reinterpret_cast<const Act*>(args.resid[k]) + re * COUT + c0, x, EPL);
-#pragma unroll
-      for (int i = 0; i < EPL; ++i) v[i] += x[i];
-      bool head = false;
-      if constexpr (MODE == 2) {
-        head = args.llr && k == 0;
-        if (head && args.save_o0) store_vals(reinterpret_cast<Act*>(args.save_o0) + re * COUT + c0, v, EPL, 1.f);
-        if (!head && args.out[k]) store_vals(reinterpret_cast<Act*>(args.out[k]) + re * COUT + c0, v, EPL, 1.f);
-      } else {  // MODE 4: product with the stored support outputs, then LayerNorm over C
-        if (args.save_o0) store_vals(reinterpret_cast<Act*>(args.save_o0) + re * COUT + c0, v, EPL, 1.f);
-        for (int kk = 1; kk < args.K; ++kk) {
-          Acc sv[EPL];
-          load_vals(reinterpret_cast<const Act*>(args.sup[kk]) + re * COUT + c0, sv, EPL);
-#pragma unroll
-          for (int i = 0; i < EPL; ++i) v[i] *= sv[i];
-        }
-        Acc s = 0;
-#pragma unroll
-        for (int i = 0; i < EPL; ++i) s += v[i];
-        s += __shfl_xor(s, 16);
-        s += __shfl_xor(s, 32);
-        const Acc mu = s * ((Acc)1 / (Acc)COUT);
-        Acc q = 0;
-#pragma unroll
-        for (int i = 0; i < EPL; ++i) { const Acc d = v[i] - mu; q += d * d; }
-        q += __shfl_xor(q, 16);
-        q += __shfl_xor(q, 32);
-        const Acc rs = (Acc)1 / sqrtf((float)(q * ((Acc)1 / (Acc)COUT) + (Acc)args.eps));
-#pragma unroll
-        for (int i = 0; i < EPL; ++i) v[i] = (Acc)args.gamma[c0 + i] * (v[i] - mu) * rs + (Acc)args.beta[c0 + i];
-        head = args.llr != nullptr;
-        if (!head && args.out[0]) store_vals(reinterpret_cast<Act*>(args.out[0]) + re * COUT + c0, v, EPL, 1.f);
-      }
-      if (head) {
-        Acc part[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          part[j] = 0;
-          if (j < args.m)
-#pragma unroll
-            for (int i = 0; i < EPL; ++i) part[j] += (Acc)args.Wh[j * COUT + c0 + i] * v[i];
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          part[j] += __shfl_xor(part[j], 16);
-          part[j] += __shfl_xor(part[j], 32);
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          if (j < args.m && (j & 3) == g) args.llr[re * args.m + j] = (float)(part[j] + (Acc)args.bh[j]);
-      }
+      const bool head = MODE == 2 ? (args.llr && k == 0) : args.llr != nullptr;
+      const Act* xr = reinterpret_cast<const Act*>(args.resid[k]) + re * COUT + c0;
+      finish_block<A, COUT, EPL, KMAX_ARGS - 1>(
+          v, re, c0, g, MODE == 4, [&](Acc* x) { load_vals(xr, x, EPL); },
+          [&](int kk, Acc* sv) { load_vals(reinterpret_cast<const Act*>(args.sup[kk]) + re * COUT + c0, sv, EPL); },
+          MODE == 2 ? args.out[k] : args.out[0], args.save_o0, head, args.K, args.gamma, args.beta, args.eps, args.Wh,
+          args.bh, args.llr, args.m);
     }
   }
   if constexpr (MODE == 5 || MODE == 6) {

@@ -49,6 +49,87 @@ hipError_t launch_amax(const void* x, int elem_bytes, int64_t n_re, int C, const
 
 static int scale_index(int K, int L, int k, int l, int which) { (void)K; return 1 + 2 * (k * L + l) + which; }
 
+// ---------------------------------------------------------------- fused blocks
+// One block as fused launches (stage marks as for the two-conv path: conv 1, support
+// conv 2, main conv 2). Without fusion after the block: one launch over nk branches.
+// With fusion: the support branches (outputs stored), then the main branch with the
+// product, LayerNorm and, after the last block, the head. act(0, k) is the block
+// input of branch k, act(1, k) its output buffer.
+template <class ActFn, class MarkFn>
+static conet_status launch_fused_block(conet_model* M, const Geometry& geo, int n_tiles, const TileDesc* tiles, int tw,
+                                       int l, int nk, bool fuse, bool fused_prev, bool last, ActFn act, float* llr,
+                                       hipStream_t s, MarkFn& mark) {
+  const conet_config& c = M->cfg;
+  const Layout& lay = M->lay;
+  const int K = c.branches, L = c.blocks, C = c.channels, dt = c.dtype;
+  uint8_t* ws = M->ws;
+  const float* vec = reinterpret_cast<const float*>(ws + lay.vec);
+  const std::vector<float>& sc = M->act_scales;
+  BlockArgs b = {};
+  b.T = geo.T;
+  b.F = geo.uniform ? geo.F : 0;
+  b.tiles_per_slot = geo.uniform ? (geo.F + tw - 1) / tw : 0;
+  b.tiles = geo.uniform ? nullptr : tiles;
+  for (int k = 0; k < nk; ++k) {
+    const float* vb = vec + lay.v_blk[k][l];
+    const bool mrb = (k == 0 && fused_prev);
+    b.x[k] = act(0, k);
+    b.pre_s[k] = mrb ? nullptr : vb + 0 * C;
+    b.pre_o[k] = mrb ? nullptr : vb + 1 * C;
+    b.b1[k] = vb + 2 * C;
+    b.post_s[k] = vb + 3 * C;
+    b.post_o[k] = vb + 4 * C;
+    b.b2[k] = vb + 5 * C;
+    b.ws1[k] = vb + 6 * C;
+    b.ws2[k] = vb + 7 * C;
+    b.w1[k] = ws + lay.w1[k][l];
+    b.w2[k] = ws + lay.w2[k][l];
+    const float s1 = sc[scale_index(K, L, k, l, 0)], s2 = sc[scale_index(K, L, k, l, 1)];
+    b.q1[k] = 1.0f / s1;
+    b.deq1[k] = s1;
+    b.q2[k] = 1.0f / s2;
+    b.deq2[k] = s2;
+  }
+  b.K = K;
+  b.eps = c.ln_eps;
+  b.gamma = vec + lay.v_gamma[l];
+  b.beta = vec + lay.v_beta[l];
+  b.Wh = vec + lay.v_wh;
+  b.bh = vec + lay.v_bh;
+  b.m = c.bits_per_symbol;
+  hipError_t e = mark();  // conv-1 stage: part of the fused launches
+  if (e != hipSuccess) return hip_fail(e, "event record");
+  if (fuse) {
+    if (K > 1) {
+      BlockArgs bs = b;
+      for (int k = 1; k < K; ++k) bs.out[k] = act(1, k);
+      bs.k_off = 1;
+      e = mark();
+      if (e == hipSuccess) e = launch_block(dt, false, C, bs, n_tiles, K - 1, s);
+      if (e != hipSuccess) return hip_fail(e, "fused support block launch");
+    } else {
+      e = mark();
+      if (e != hipSuccess) return hip_fail(e, "event record");
+    }
+    BlockArgs bm = b;
+    for (int k = 1; k < K; ++k) bm.sup[k] = act(1, k);
+    bm.out[0] = last ? nullptr : act(1, 0);
+    bm.llr = last ? llr : nullptr;
+    bm.k_off = 0;
+    e = mark();
+    if (e == hipSuccess) e = launch_block(dt, true, C, bm, n_tiles, 1, s);
+    if (e != hipSuccess) return hip_fail(e, "fused main block launch");
+  } else {
+    for (int k = 0; k < nk; ++k) b.out[k] = last ? nullptr : act(1, k);
+    b.llr = last ? llr : nullptr;
+    e = mark();
+    if (e == hipSuccess) e = launch_block(dt, false, C, b, n_tiles, nk, s);
+    if (e == hipSuccess) e = mark();
+    if (e != hipSuccess) return hip_fail(e, "fused block launch");
+  }
+  return CONET_OK;
+}
+
 // ---------------------------------------------------------------- forward
 conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const Geometry& geo, float* llr,
                          hipStream_t s, std::vector<float>* calib, hipEvent_t* events, bool save) {
@@ -59,20 +140,26 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
   float* vec = reinterpret_cast<float*>(ws + lay.vec);
   std::vector<float>& sc = M->act_scales;
   const int tw_in = conv_tile_width(dt, Ci, C), tw_blk = conv_tile_width(dt, C, C);
+  // Inference runs each block as one fused launch when a fused kernel exists for
+  // (dtype, C); calibration and the training forward (which stores h) use two convs.
+  const int tw_fb = (calib || save) ? 0 : block_tile_width(dt, C, K);
   hipError_t e;
 
-  // tile geometry for both tile widths
-  int n_tiles_in = 0, n_tiles_blk = 0;
+  // tile geometry for every tile width in use
+  int n_tiles_in = 0, n_tiles_blk = 0, n_tiles_fb = 0;
   const TileDesc* d_in = nullptr;
   const TileDesc* d_blk = nullptr;
+  const TileDesc* d_fb = nullptr;
   int64_t n_re = 0;
   if (geo.uniform) {
     n_tiles_in = geo.B * ((geo.F + tw_in - 1) / tw_in);
     n_tiles_blk = geo.B * ((geo.F + tw_blk - 1) / tw_blk);
+    if (tw_fb) n_tiles_fb = geo.B * ((geo.F + tw_fb - 1) / tw_fb);
     n_re = (int64_t)geo.B * geo.T * geo.F;
   } else {
     std::vector<TileDesc> h;
     auto build = [&](int tw) {
+      const size_t first = h.size();
       int64_t base = 0;
       for (int sl = 0; sl < geo.n_slots; ++sl) {
         const int F = geo.F_host[sl];
@@ -80,18 +167,25 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
         base += (int64_t)geo.T * F;
       }
       n_re = base;
+      return first;
     };
-    build(tw_blk);
-    n_tiles_blk = (int)h.size();
-    if (tw_in != tw_blk) build(tw_in);
-    n_tiles_in = tw_in != tw_blk ? (int)h.size() - n_tiles_blk : n_tiles_blk;
+    const size_t o_blk = build(tw_blk);
+    n_tiles_blk = (int)(h.size() - o_blk);
+    const size_t o_in = tw_in != tw_blk ? build(tw_in) : o_blk;
+    n_tiles_in = (int)(tw_in != tw_blk ? h.size() - o_in : n_tiles_blk);
+    size_t o_fb = 0;
+    if (tw_fb) {
+      o_fb = build(tw_fb);
+      n_tiles_fb = (int)(h.size() - o_fb);
+    }
     if (h.size() > ar.max_tiles) return fail(CONET_ESHAPE, "ragged batch needs %zu tiles, capacity %zu", h.size(), ar.max_tiles);
     if (n_re > ar.max_res) return fail(CONET_ESHAPE, "ragged batch has %lld REs, buffers hold %lld", (long long)n_re, (long long)ar.max_res);
     TileDesc* dt_dev = ar.tiles;
     e = hipMemcpyAsync(dt_dev, h.data(), h.size() * sizeof(TileDesc), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "tile descriptor upload");
-    d_blk = dt_dev;
-    d_in = tw_in != tw_blk ? dt_dev + n_tiles_blk : dt_dev;
+    d_blk = dt_dev + o_blk;
+    d_in = dt_dev + o_in;
+    d_fb = dt_dev + o_fb;
   }
   if (n_tiles_in == 0 || n_tiles_blk == 0) return CONET_OK;
 
@@ -162,6 +256,14 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
     const bool last = (l == L - 1);
     const bool fuse = (c.fuse_mask >> l) & 1u;
     const int nk = (last && !fuse) ? 1 : K;
+    if (tw_fb) {
+      conet_status st = launch_fused_block(M, geo, n_tiles_fb, d_fb, tw_fb, l, nk, fuse, fused_prev, last,
+                                           [&](int p, int k) { return actp(p == 0 ? cur : 1 - cur, k); }, llr, s, mark);
+      if (st != CONET_OK) return st;
+      cur = 1 - cur;
+      fused_prev = fuse;
+      continue;
+    }
     ConvArgs a1 = {};
     geom(a1, false);
     for (int k = 0; k < nk; ++k) {

@@ -60,6 +60,41 @@ bool conv_supported(int dtype, int cin, int cout);
 // through its first conv (-> d of the block input). Branch: blockIdx.y + k_off.
 hipError_t launch_conv(int dtype, int mode, int cin, int cout, ConvArgs& a, int n_tiles, int grid_y, hipStream_t s);
 
+// ---------------------------------------------------------------- fused residual block
+// Both convs of one block (per branch blockIdx.y + k_off) in one launch, h kept in LDS:
+// out = x + conv2(ReLU(s1 (conv1(pre(x)) + b1) + o1)) + b2; with `main`, the main branch
+// of a fused block (product with sup[1..K-1], LayerNorm, head when llr is set).
+struct BlockArgs {
+  const void* x[KMAX_ARGS];        // block input (residual stream), [RE][C] Act
+  void* out[KMAX_ARGS];            // block output (nullable); main: out[0]
+  const void* sup[KMAX_ARGS];      // main: this block's stored support-branch outputs
+  const void* w1[KMAX_ARGS];       // fragment-packed filters of conv 1 and conv 2
+  const void* w2[KMAX_ARGS];
+  const float* b1[KMAX_ARGS];
+  const float* b2[KMAX_ARGS];
+  const float* pre_s[KMAX_ARGS];   // pre-activation affine; null => ReLU only (MRB)
+  const float* pre_o[KMAX_ARGS];
+  const float* post_s[KMAX_ARGS];  // affine after conv 1
+  const float* post_o[KMAX_ARGS];
+  const float* ws1[KMAX_ARGS];     // FP8: per-output-channel filter scales
+  const float* ws2[KMAX_ARGS];
+  float q1[KMAX_ARGS], deq1[KMAX_ARGS];  // FP8: 1 / s and s of conv 1's operand pre(x)
+  float q2[KMAX_ARGS], deq2[KMAX_ARGS];  // FP8: 1 / s and s of conv 2's operand h
+  const float* gamma;
+  const float* beta;
+  const float* Wh;
+  const float* bh;
+  float* llr;                      // [RE][m] FP32, or null
+  int m, K, k_off;
+  float eps;
+  int T, F, tiles_per_slot, tw;    // tw: set by the launcher
+  const TileDesc* tiles;           // ragged batches, else null
+};
+// Output subcarriers per fused tile; 0 when (dtype, C, K) runs as two conv launches.
+constexpr int BLOCK_KMAX = 4;  // fused main-branch kernels exist for K <= 4
+int block_tile_width(int dtype, int C, int K);
+hipError_t launch_block(int dtype, bool main, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
+
 // ---------------------------------------------------------------- training kernels
 // Filter gradient of a 3x3 conv over a batch: dW[o][tap*CIN + ch] = sum_re dOut[re][o] *
 // In[re shifted by tap][ch] (In optionally through the block's pre-activation), and
