@@ -313,21 +313,38 @@ def main():
 
     # ---- roofline of the dominant kernel. Stages: input layer, then per block
     # [conv 1 of all branches, conv 2 of the supports (or of all branches without
-    # fusion), conv 2 of the main branch with product fusion + LayerNorm (+ head)].
+    # fusion), conv 2 of the main branch with product fusion + LayerNorm (+ head)];
+    # with fused residual-block launches: [block without fusion after it (all branches),
+    # the support branches' blocks, the main branch's block with the fusion epilogue].
+    # FLOPs are algorithmic: 2 * 9 * C * C per RE per conv (the fused kernel's halo
+    # recompute of conv 1 and padded M-tiles are not counted).
     mask = mc.mask
     blk_fl = res * 2 * 9 * mc.C * mc.C                   # MFMA FLOPs of one block conv over one branch
-    kinds = {"block_conv1": [], "block_conv2_supports": [], "block_conv2_main_fused": []}
-    for l in range(mc.L):
-        fused = (mask >> l) & 1
-        last = l == mc.L - 1
-        c1 = stage_ms[:, 1 + 3 * l]
-        kinds["block_conv1"].append((c1, (mc.K if (fused or not last) else 1) * blk_fl))
-        if fused:
-            if mc.K > 1:
-                kinds["block_conv2_supports"].append((stage_ms[:, 2 + 3 * l], (mc.K - 1) * blk_fl))
-            kinds["block_conv2_main_fused"].append((stage_ms[:, 3 + 3 * l], blk_fl))
-        else:
-            kinds["block_conv2_supports"].append((stage_ms[:, 2 + 3 * l], (1 if last else mc.K) * blk_fl))
+    fused_tw = model.block_tile_width
+    if fused_tw:
+        kinds = {"block_fused_all": [], "block_fused_supports": [], "block_fused_main": []}
+        for l in range(mc.L):
+            fused = (mask >> l) & 1
+            last = l == mc.L - 1
+            if fused:
+                if mc.K > 1:
+                    kinds["block_fused_supports"].append((stage_ms[:, 2 + 3 * l], (mc.K - 1) * 2 * blk_fl))
+                kinds["block_fused_main"].append((stage_ms[:, 3 + 3 * l], 2 * blk_fl))
+            else:
+                kinds["block_fused_all"].append((stage_ms[:, 1 + 3 * l], (1 if last else mc.K) * 2 * blk_fl))
+    else:
+        kinds = {"block_conv1": [], "block_conv2_supports": [], "block_conv2_main_fused": []}
+        for l in range(mc.L):
+            fused = (mask >> l) & 1
+            last = l == mc.L - 1
+            c1 = stage_ms[:, 1 + 3 * l]
+            kinds["block_conv1"].append((c1, (mc.K if (fused or not last) else 1) * blk_fl))
+            if fused:
+                if mc.K > 1:
+                    kinds["block_conv2_supports"].append((stage_ms[:, 2 + 3 * l], (mc.K - 1) * blk_fl))
+                kinds["block_conv2_main_fused"].append((stage_ms[:, 3 + 3 * l], blk_fl))
+            else:
+                kinds["block_conv2_supports"].append((stage_ms[:, 2 + 3 * l], (1 if last else mc.K) * blk_fl))
     tot = {k: sum(float(ms.sum()) for ms, _ in v) for k, v in kinds.items() if v}
     dom = max(tot, key=tot.get)
     launches = kinds[dom]
@@ -339,6 +356,7 @@ def main():
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
                 "flops_per_launch": fl_launch, "mean_launch_ms": round(dom_ms, 4),
+                "fused_block_tile_width": fused_tw,
                 "stage_mean_ms": [round(float(v), 4) for v in stage_ms.mean(axis=0)],
                 "whole_step_tflops": round(flops_per_re(mc.K, mc.L, mc.C, mc.C_in, mc.m) * res / (ms_per_step * 1e-3) / 1e12, 2)}
 

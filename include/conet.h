@@ -131,9 +131,19 @@ conet_status conet_forward_ragged(conet_model* model, const float* x, int32_t n_
  * all branches, (b) the second conv of the support branches (with fusion) or of all
  * branches (without), (c) the second conv of the main branch with the product fusion,
  * LayerNorm and, after the last block, the LLR head (0 without fusion).
+ * When the model runs blocks as fused launches (conet_block_tile_width > 0), stage (a)
+ * holds a block without fusion after it (both convs of every branch), (b) the support
+ * branches' fused launch and (c) the main branch's; the other entries are ~0.
  * Synchronises on the last event. Errors as conet_forward. */
 conet_status conet_forward_profiled(conet_model* model, const float* x, int32_t B, int32_t T, int32_t F, float* llr,
                                     float* stage_ms_host, int32_t n_stages, void* stream);
+
+/* Subcarriers per tile of the fused residual-block kernel that inference forwards of
+ * this model use (both convs of a block in one launch, the hidden activation kept on
+ * chip; BF16 with C in {16, 32, 64} and K <= 4), or 0 when every block runs as two conv
+ * launches (FP32, FP8, other widths; calibration and save_for_backward forwards always
+ * do). Returns 0 for a null model. */
+int32_t conet_block_tile_width(const conet_model* model);
 
 /* ---------------------------------------------------------------- training
  * Reverse mode of the forward above (hand-written): the head, the per-RE LayerNorm,

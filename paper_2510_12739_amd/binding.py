@@ -22,6 +22,7 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "ENOMEM", 4: "EDEVICE", 5: "EBUS
 # Every symbol include/conet.h declares.
 EXPORTS = ("conet_weight_count", "conet_workspace_bytes", "conet_create", "conet_set_act_scales",
            "conet_calibrate", "conet_get_act_scales", "conet_forward", "conet_forward_ragged", "conet_forward_profiled",
+           "conet_block_tile_width",
            "conet_serve_create", "conet_serve_submit", "conet_serve_wait", "conet_serve_get_stats",
            "conet_serve_reset_stats", "conet_serve_pause", "conet_serve_destroy", "conet_backward", "conet_grads",
            "conet_master_weights", "conet_adam_step", "conet_get_weights", "conet_bce", "conet_destroy",
@@ -79,6 +80,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.conet_forward_ragged.restype = i32
     lib.conet_forward_profiled.argtypes = [vp, vp, i32, i32, i32, vp, fp, i32, vp]
     lib.conet_forward_profiled.restype = i32
+    lib.conet_block_tile_width.argtypes = [vp]; lib.conet_block_tile_width.restype = i32
     lib.conet_serve_create.argtypes = [vp, sz, i32, i32, i32, ctypes.POINTER(vp)]
     lib.conet_serve_create.restype = i32
     lib.conet_serve_submit.argtypes = [vp, ctypes.POINTER(conet_request), ctypes.POINTER(ctypes.c_uint64)]
@@ -238,6 +240,11 @@ class Conet:
         return loss, dllr
 
     __call__ = forward
+
+    @property
+    def block_tile_width(self) -> int:
+        """Subcarriers per fused residual-block tile of inference forwards (0: two conv launches per block)."""
+        return int(self.lib.conet_block_tile_width(self.handle))
 
     def forward_profiled(self, x, out=None, stream=None):
         """forward() with per-stage HIP event timing: returns (llr, stage_ms[1 + 3L])."""

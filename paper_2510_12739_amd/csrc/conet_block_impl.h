@@ -34,6 +34,14 @@ constexpr int block_tw() {
   return 0;
 }
 
+// Work-groups per CU the fused kernel is built for (LDS tile and register budget). Three
+// (18-subcarrier tiles, 168 VGPRs) measured slower than two on the C = 64 workload: more
+// halo recompute and padded M-tiles, and no room left to prefetch the epilogue inputs.
+template <class A, int C>
+constexpr int block_occ() {
+  return 2;
+}
+
 // Raw 16-byte (or 8-byte) vectors holding one lane's EPL activation values of one RE.
 template <class Act, int EPL>
 using RawOf = typename std::conditional<(EPL * sizeof(Act)) % 16 == 0, i32x4, uint2>::type;
@@ -45,9 +53,15 @@ __device__ __forceinline__ void unpack_raw(const RawT* r, Acc* v) {
   for (int i = 0; i < EPL; ++i) v[i] = (Acc)(float)a[i];
 }
 
+// Per-channel parameters of a block, staged once per work-group into LDS behind the
+// tile (FP32, C each): conv-1 bias, the affine after conv 1, the dequantisation factors
+// of both convs (FP8; ones otherwise), conv-2 bias and the LayerNorm affine.
+enum { P_B1, P_S1, P_O1, P_Q1, P_B2, P_Q2, P_GAM, P_BET, NPAR };
+
 // NSUP: support branches multiplied in by the main branch (K - 1; 0 otherwise).
-template <class A, int C, int TWO, bool MAIN, int NSUP>
-__global__ void __launch_bounds__(CONV_NW * 64, 2) block_kernel(BlockArgs args) {
+// HEAD: the launch feeds the LLR head (after the last block).
+template <class A, int C, int TWO, bool MAIN, bool HEAD, int NSUP>
+__global__ void __launch_bounds__(CONV_NW * 64, (block_occ<A, C>())) block_kernel(BlockArgs args) {
   using Acc = typename A::Acc;
   using AccV = typename A::AccV;
   using Act = typename A::Act;
@@ -59,11 +73,15 @@ __global__ void __launch_bounds__(CONV_NW * 64, 2) block_kernel(BlockArgs args) 
   constexpr int M1 = (Q1 + 15) / 16, M2 = (Q2 + 15) / 16;
   constexpr int MT1 = (M1 + NW - 1) / NW, MT2 = (M2 + NW - 1) / NW;
   constexpr int NOT = C / 16, EPL = 4 * NOT;
-  using G1 = GemmCore<A, C, C, XW, PITCH, MT1>;
-  using G2 = GemmCore<A, C, C, HW, PITCH, MT2>;
-  static_assert(TROWS * XW * PITCH <= 80 * 1024, "x tile must leave room for two work-groups per CU");
+  constexpr int TILE = TROWS * XW * PITCH;
+  constexpr int OCC = block_occ<A, C>();
+  constexpr int VB = OCC >= 3 ? 120 : 200;  // accumulator + operand VGPRs of the GEMM loops
+  using G1 = GemmCore<A, C, C, XW, PITCH, MT1, VB>;
+  using G2 = GemmCore<A, C, C, HW, PITCH, MT2, VB>;
+  static_assert(OCC * (TILE + NPAR * C * 4) <= 160 * 1024, "LDS must leave room for OCC work-groups per CU");
   static_assert((C * (int)sizeof(Op)) % 16 == 0, "h rows are written in 16-byte chunks");
-  __shared__ __attribute__((aligned(16))) uint8_t lds[TROWS * XW * PITCH];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[TILE + NPAR * C * 4];
+  float* par = reinterpret_cast<float*>(lds + TILE);
 
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const TileDesc td = tile_of(args, bid);
@@ -73,9 +91,34 @@ __global__ void __launch_bounds__(CONV_NW * 64, 2) block_kernel(BlockArgs args) 
   const int c0 = g * EPL;  // first channel owned by this lane
   const int k = blockIdx.y + args.k_off;
 
+  // 0. per-channel parameters: loads issued now, written to LDS after the tile's loads
+  constexpr int NPV = (NPAR * C + NT - 1) / NT;
+  float pv[NPV];
+#pragma unroll
+  for (int u = 0; u < NPV; ++u) {
+    const int i = threadIdx.x + u * NT;
+    const int pi = i / C, c = i - pi * C;
+    float val = 0.f;
+    switch (pi) {
+      case P_B1: val = args.b1[k][c]; break;
+      case P_S1: val = args.post_s[k][c]; break;
+      case P_O1: val = args.post_o[k][c]; break;
+      case P_Q1: val = A::QUANT ? args.deq1[k] * args.ws1[k][c] : 1.f; break;
+      case P_B2: val = args.b2[k][c]; break;
+      case P_Q2: val = A::QUANT ? args.deq2[k] * args.ws2[k][c] : 1.f; break;
+      case P_GAM: val = MAIN ? args.gamma[c] : 0.f; break;
+      case P_BET: val = MAIN ? args.beta[c] : 0.f; break;
+      default: break;
+    }
+    pv[u] = val;
+  }
+
   // 1. pre(x) with a two-RE halo; LDS row r = symbol r - 1, column c = subcarrier f0 + c - 2
   stage_tile<A, Act, C, XW, 2, PITCH, NT>(lds, reinterpret_cast<const Act*>(args.x[k]), td, T,
                                           args.pre_s[k] ? 1 : 2, args.pre_s[k], args.pre_o[k], args.q1[k]);
+#pragma unroll
+  for (int u = 0; u < NPV; ++u)
+    if (threadIdx.x + u * NT < NPAR * C) par[threadIdx.x + u * NT] = pv[u];
   __syncthreads();
 
   // 2. conv 1 on RE q = t * HW + j of the region (symbol t, subcarrier f0 - 1 + j)
@@ -94,10 +137,10 @@ __global__ void __launch_bounds__(CONV_NW * 64, 2) block_kernel(BlockArgs args) 
   float pb[EPL], ps[EPL], po[EPL], pq[EPL];
 #pragma unroll
   for (int i = 0; i < EPL; ++i) {
-    pb[i] = args.b1[k][c0 + i];
-    ps[i] = args.post_s[k][c0 + i];
-    po[i] = args.post_o[k][c0 + i];
-    pq[i] = A::QUANT ? args.deq1[k] * args.ws1[k][c0 + i] : 1.0f;
+    pb[i] = par[P_B1 * C + c0 + i];
+    ps[i] = par[P_S1 * C + c0 + i];
+    po[i] = par[P_O1 * C + c0 + i];
+    pq[i] = par[P_Q1 * C + c0 + i];
   }
   __syncthreads();  // every wave has read its last x operand: h may overwrite the tile
 
@@ -119,7 +162,7 @@ __global__ void __launch_bounds__(CONV_NW * 64, 2) block_kernel(BlockArgs args) 
         Acc a = acc1[mt][ot][i];
         if constexpr (A::QUANT) a = a * (Acc)pq[e];
         const float z = ps[e] * (float)(a + (Acc)pb[e]) + po[e];
-        v[e] = valid ? fmaxf(z, 0.f) : 0.f;
+        v[e] = fmaxf(valid ? z : -1.f, 0.f);  // a select, not a branch: z is computed anyway
       }
     uint8_t* dst = lds + ((t + 1) * HW + j) * PITCH + c0 * (int)sizeof(Op);
     if constexpr (sizeof(Op) == 2) {
@@ -163,7 +206,7 @@ __global__ void __launch_bounds__(CONV_NW * 64, 2) block_kernel(BlockArgs args) 
   using RawT = RawOf<Act, EPL>;
   constexpr int NR = EPL * (int)sizeof(Act) / (int)sizeof(RawT);
   constexpr int NTEN = 1 + NSUP;
-  constexpr int PD = MAIN ? (MT2 < 2 ? MT2 : 2) : MT2;
+  constexpr int PD = (MAIN || OCC >= 3) ? (MT2 < 2 ? MT2 : 2) : (MT2 < 4 ? MT2 : 4);
   RawT raw[PD][NTEN][NR];
   auto re_of = [&](int mt, bool& ok) -> int64_t {
     const int q = (wave + NW * mt) * 16 + col;
@@ -186,7 +229,7 @@ __global__ void __launch_bounds__(CONV_NW * 64, 2) block_kernel(BlockArgs args) 
       for (int r = 0; r < NR; ++r) raw[mt % PD][sidx][r] = ps_[r];
     }
   };
-  constexpr int PRE = MAIN ? 1 : (PD < 3 ? PD : 3);  // as many as the GEMM's registers leave room for
+  constexpr int PRE = OCC >= 3 ? 0 : MAIN ? 1 : (PD < 2 ? PD : 2);  // as the GEMM's registers allow
 #pragma unroll
   for (int d = 0; d < PRE; ++d) issue(d);
   AccV acc2[MT2][NOT];
@@ -205,34 +248,20 @@ __global__ void __launch_bounds__(CONV_NW * 64, 2) block_kernel(BlockArgs args) 
   for (int d = PRE; d < PD; ++d) issue(d);
 #pragma unroll
   for (int i = 0; i < EPL; ++i) {
-    pb[i] = args.b2[k][c0 + i];
-    pq[i] = A::QUANT ? args.deq2[k] * args.ws2[k][c0 + i] : 1.0f;
+    pb[i] = par[P_B2 * C + c0 + i];
+    pq[i] = par[P_Q2 * C + c0 + i];
   }
-  const bool head = MAIN ? args.llr != nullptr : (args.llr != nullptr && k == 0);
+  const bool head = HEAD && (MAIN || k == 0);
 
-  // 5. block output. The LayerNorm affine and the head (read by every M-tile) are
-  //    copied into the now free LDS tile once, instead of one global load per use.
-  const float* gam = args.gamma;
-  const float* bet = args.beta;
-  const float* wh = args.Wh;
-  const float* bhh = args.bh;
-  if (MAIN || head) {  // uniform over the work-group
-    __syncthreads();   // every wave has read its last h operand
-    float* pl = reinterpret_cast<float*>(lds);
+  // 5. block output. The head weights (read by every M-tile) are copied into the now
+  //    free LDS tile once.
+  float* whl = reinterpret_cast<float*>(lds);
+  if constexpr (HEAD) {
+    __syncthreads();  // every wave has read its last h operand
     const int nwh = args.m * C;
-    for (int i = threadIdx.x; i < 2 * C + nwh + 8; i += NT) {
-      float val;
-      if (i < C) val = MAIN ? args.gamma[i] : 0.f;
-      else if (i < 2 * C) val = MAIN ? args.beta[i - C] : 0.f;
-      else if (i < 2 * C + nwh) val = head ? args.Wh[i - 2 * C] : 0.f;
-      else val = (head && i - 2 * C - nwh < args.m) ? args.bh[i - 2 * C - nwh] : 0.f;
-      pl[i] = val;
-    }
+    for (int i = threadIdx.x; i < nwh + 8; i += NT)
+      whl[i] = i < nwh ? args.Wh[i] : (i - nwh < args.m ? args.bh[i - nwh] : 0.f);
     __syncthreads();
-    gam = pl;
-    bet = pl + C;
-    wh = pl + 2 * C;
-    bhh = pl + 2 * C + nwh;
   }
 #pragma unroll
   for (int mt = 0; mt < MT2; ++mt) {
@@ -251,10 +280,29 @@ __global__ void __launch_bounds__(CONV_NW * 64, 2) block_kernel(BlockArgs args) 
       finish_block<A, C, EPL, NSUP>(
           v, re, c0, g, MAIN, [&](Acc* x) { unpack_raw<Act, RawT, EPL>(raw[mt % PD][0], x); },
           [&](int kk, Acc* sv) { unpack_raw<Act, RawT, EPL>(raw[mt % PD][kk], sv); }, MAIN ? args.out[0] : args.out[k],
-          nullptr, head, NSUP + 1, gam, bet, args.eps, wh, bhh, args.llr, args.m);
+          nullptr, head, NSUP + 1, par + P_GAM * C, par + P_BET * C, args.eps, whl, whl + args.m * C, args.llr,
+          args.m);
     }
     if (mt + PD < MT2) issue(mt + PD);
   }
+}
+
+template <class A, int C, bool HEAD>
+static hipError_t launch_block_h(bool main, BlockArgs& a, dim3 grid, hipStream_t s) {
+  constexpr int TWO = block_tw<A, C>();
+  const dim3 blk(CONV_NW * 64);
+  if (!main) {
+    hipLaunchKernelGGL((block_kernel<A, C, TWO, false, HEAD, 0>), grid, blk, 0, s, a);
+  } else {
+    switch (a.K) {
+      case 1: hipLaunchKernelGGL((block_kernel<A, C, TWO, true, HEAD, 0>), grid, blk, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((block_kernel<A, C, TWO, true, HEAD, 1>), grid, blk, 0, s, a); break;
+      case 3: hipLaunchKernelGGL((block_kernel<A, C, TWO, true, HEAD, 2>), grid, blk, 0, s, a); break;
+      case 4: hipLaunchKernelGGL((block_kernel<A, C, TWO, true, HEAD, 3>), grid, blk, 0, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
 }
 
 template <class A, int C>
@@ -264,19 +312,9 @@ static hipError_t launch_block_c(bool main, BlockArgs& a, int n_tiles, int grid_
     return hipErrorInvalidValue;
   } else {
     a.tw = TWO;
-    const dim3 grid(n_tiles, grid_y), blk(CONV_NW * 64);
-    if (!main) {
-      hipLaunchKernelGGL((block_kernel<A, C, TWO, false, 0>), grid, blk, 0, s, a);
-    } else {
-      switch (a.K) {
-        case 1: hipLaunchKernelGGL((block_kernel<A, C, TWO, true, 0>), grid, blk, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((block_kernel<A, C, TWO, true, 1>), grid, blk, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((block_kernel<A, C, TWO, true, 2>), grid, blk, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((block_kernel<A, C, TWO, true, 3>), grid, blk, 0, s, a); break;
-        default: return hipErrorInvalidValue;
-      }
-    }
-    return hipGetLastError();
+    if (a.llr && (a.m < 1 || a.m > 8)) return hipErrorInvalidValue;
+    const dim3 grid(n_tiles, grid_y);
+    return a.llr ? launch_block_h<A, C, true>(main, a, grid, s) : launch_block_h<A, C, false>(main, a, grid, s);
   }
 }
 

@@ -200,7 +200,7 @@ __device__ __forceinline__ void stage_tile(uint8_t* lds, const InT* __restrict__
 // 16 REs each. The caller gives, per M-tile, the LDS byte offset of this lane's RE for
 // tap (-1, -1); the staged input has ROWP positions per row and PITCH bytes per
 // position, so tap (dt, dc) adds ((dt + 1) ROWP + dc + 1) positions.
-template <class A, int CIN, int COUT, int ROWP, int PITCH, int MT>
+template <class A, int CIN, int COUT, int ROWP, int PITCH, int MT, int VBUDGET = 200>
 struct GemmCore {
   static constexpr int NOT = COUT / 16;
   static constexpr int CPT = CIN / A::VEC;                       // chunks per tap
@@ -230,8 +230,9 @@ struct GemmCore {
   }
 
   // Filter fragments are prefetched ADEPTH K steps ahead (a ring of ADEPTH + 1 buffers)
-  // when the registers allow it, else one step ahead.
-  static constexpr int ADEPTH = (MT * NOT * 4 + 3 * NOT * A::CPL * 4 + MT * A::CPL * 4 <= 200) ? 2 : 1;
+  // when the registers allow it (VBUDGET VGPRs for accumulators and operands), else one
+  // step ahead.
+  static constexpr int ADEPTH = (MT * NOT * 4 + 3 * NOT * A::CPL * 4 + MT * A::CPL * 4 <= VBUDGET) ? 2 : 1;
   // B fragments of the next step are prefetched (rolling) unless two chunks per MFMA
   // (FP8) leave no registers for it; then each step issues its own B reads first.
   static constexpr bool BROLL = A::CPL == 1;
