@@ -93,6 +93,72 @@ def load_traffic(kernel: str, workload: str, dtype: str):
     return rec.get("bytes_per_launch")
 
 
+def kernel_kind(name: str):
+    """Roofline kind of a kernel dispatch, from the demangled name rocprofv3 reports."""
+    if "block_kernel<" in name:
+        args = name.split("block_kernel<", 1)[1].split(">", 1)[0].split(",")
+        return "block_fused_main" if args[3].strip() == "true" else "block_fused_supports"
+    if "conv3x3_kernel<" in name:
+        mode = name.split("conv3x3_kernel<", 1)[1].split(",")[1].strip()
+        return {"0": "input_layer", "1": "block_conv1", "2": "block_conv2_supports",
+                "4": "block_conv2_main_fused"}.get(mode)
+    return None
+
+
+def pmc_summary(dirs, copy_bytes, workload_name, dtype, out_md=None):
+    """HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this bench
+    and of --copy-probe (calibration), written to profiles/traffic.json for the current
+    kernel sources. dirs: (bench FETCH, bench WRITE, copy FETCH, copy WRITE) output dirs."""
+    import csv
+    import glob
+
+    def rows(d):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not f:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        return list(csv.DictReader(open(f[0])))
+
+    def per_kind(rs, counter):
+        acc = {}
+        for r in rs:
+            if r["Counter_Name"] != counter:
+                continue
+            k = kernel_kind(r["Kernel_Name"])
+            if k:
+                acc.setdefault(k, []).append(float(r["Counter_Value"]) * 1024.0)
+        return {k: (float(np.mean(v)), len(v)) for k, v in acc.items()}
+
+    def copy_bytes_read(rs, counter):
+        v = [float(r["Counter_Value"]) * 1024.0 for r in rs if r["Counter_Name"] == counter and "opy" in r["Kernel_Name"]]
+        if not v:
+            raise SystemExit("no copy kernel in the calibration run")
+        return float(np.median(v))
+
+    fetch, write = per_kind(rows(dirs[0]), "FETCH_SIZE"), per_kind(rows(dirs[1]), "WRITE_SIZE")
+    fscale = copy_bytes / copy_bytes_read(rows(dirs[2]), "FETCH_SIZE")
+    wscale = copy_bytes / copy_bytes_read(rows(dirs[3]), "WRITE_SIZE")
+    h = kernel_source_hash()
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    db = json.load(open(path)) if os.path.exists(path) else {}
+    db = {k: v for k, v in db.items() if v.get("source_hash") == h}
+    lines = ["| Kernel | Dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | Scaled read GB | Scaled write GB | Total GB/launch |",
+             "|---|---|---|---|---|---|---|"]
+    for k in sorted(set(fetch) & set(write)):
+        rd, wr = fetch[k][0] * fscale, write[k][0] * wscale
+        db[f"{workload_name}/{dtype}/{k}"] = {"bytes_per_launch": int(rd + wr), "read_bytes": int(rd), "write_bytes": int(wr),
+                                             "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4),
+                                             "source_hash": h}
+        lines.append(f"| {k} | {fetch[k][1]} | {fetch[k][0] / 1024:.0f} | {write[k][0] / 1024:.0f} | {rd / 1e9:.3f} | "
+                     f"{wr / 1e9:.3f} | {(rd + wr) / 1e9:.3f} |")
+    json.dump(db, open(path, "w"), indent=1)
+    table = "\n".join(lines)
+    print(f"FETCH_SIZE scale {fscale:.4f}, WRITE_SIZE scale {wscale:.4f}, source hash {h}")
+    print(table)
+    if out_md:
+        with open(out_md, "w") as f:
+            f.write(table + "\n")
+
+
 def serve_measure(loads=(0.5,), duration_s=1.5, n_streams=3, seed=13):
     """Serving on the continuous-batching server: first a saturating burst gives the
     capacity (requests/s); then, for each load fraction, Poisson arrivals at that
@@ -241,7 +307,16 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving point of the default run")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device 3 times (HBM counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="no GPU work: turn rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this bench and of "
+                         "--copy-probe into profiles/traffic.json (needs --copy-bytes)")
+    ap.add_argument("--copy-bytes", type=int, default=268435456)
+    ap.add_argument("--pmc-md", default=None, help="with --pmc-summary: also write the table here")
     args = ap.parse_args()
+
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary, args.copy_bytes, args.workload, args.dtype or "bf16", args.pmc_md)
+        return
 
     if args.copy_probe:
         import torch
@@ -287,6 +362,11 @@ def main():
     if dtype == "fp8":
         model.calibrate(x[:min(4, B)])
     out = torch.empty((B, T, F, mc.m), dtype=torch.float32, device="cuda")
+
+    # attainable dense-MFMA peak and shader clock on this device (context for `frac`)
+    from paper_2510_12739_amd import mfma_peak
+    peak_meas, clock_ghz = mfma_peak(dtype)
+    print(f"[bench] measured MFMA peak {peak_meas:.1f} TFLOP/s at {clock_ghz:.3f} GHz", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         model.forward(x, out=out)
@@ -357,6 +437,8 @@ def main():
                 "frac": round(achieved / peak, 4), "traffic": traffic,
                 "flops_per_launch": fl_launch, "mean_launch_ms": round(dom_ms, 4),
                 "fused_block_tile_width": fused_tw,
+                "measured_peak": round(peak_meas, 1), "measured_clock_ghz": round(clock_ghz, 3),
+                "frac_of_measured_peak": round(achieved / peak_meas, 4) if peak_meas > 0 else None,
                 "stage_mean_ms": [round(float(v), 4) for v in stage_ms.mean(axis=0)],
                 "whole_step_tflops": round(flops_per_re(mc.K, mc.L, mc.C, mc.C_in, mc.m) * res / (ms_per_step * 1e-3) / 1e12, 2)}
 

@@ -145,6 +145,16 @@ conet_status conet_forward_profiled(conet_model* model, const float* x, int32_t 
  * do). Returns 0 for a null model. */
 int32_t conet_block_tile_width(const conet_model* model);
 
+/* Dense-MFMA throughput on the current device, for reading roofline fractions against an
+ * attainable peak: every wave of a full-chip grid (16 waves per CU) issues `iters` rounds
+ * of 8 independent 16x16 MFMAs with register operands (dtype CONET_BF16: 16x16x32 bf16,
+ * CONET_FP8E4M3: 16x16x128 f8, CONET_FP32: 16x16x4 f32), once to warm up and once timed.
+ * *tflops_host gets the dense TFLOP/s of the timed run and *clock_ghz_host the shader
+ * clock measured over one wave's loop (0 if the device does not report its wall-clock
+ * rate). Allocates and frees a small device buffer: not for use under graph capture.
+ * Errors: EINVAL (dtype, iters outside 1..2^24, null outputs), EDEVICE. */
+conet_status conet_mfma_peak(int32_t dtype, int32_t iters, double* tflops_host, double* clock_ghz_host, void* stream);
+
 /* ---------------------------------------------------------------- training
  * Reverse mode of the forward above (hand-written): the head, the per-RE LayerNorm,
  * the product fusion (d O[k] = dP * prod_{j != k} O[j]), and per block the input

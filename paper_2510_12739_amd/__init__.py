@@ -2,4 +2,5 @@
 
 The Python layer only marshals arguments; see binding.Conet.
 """
-from .binding import Conet, ConetError, Server, conet_function, load, make_config, weight_count, workspace_bytes, EXPORTS
+from .binding import (Conet, ConetError, Server, conet_function, load, make_config, mfma_peak, weight_count,
+                      workspace_bytes, EXPORTS)

@@ -22,7 +22,7 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "ENOMEM", 4: "EDEVICE", 5: "EBUS
 # Every symbol include/conet.h declares.
 EXPORTS = ("conet_weight_count", "conet_workspace_bytes", "conet_create", "conet_set_act_scales",
            "conet_calibrate", "conet_get_act_scales", "conet_forward", "conet_forward_ragged", "conet_forward_profiled",
-           "conet_block_tile_width",
+           "conet_block_tile_width", "conet_mfma_peak",
            "conet_serve_create", "conet_serve_submit", "conet_serve_wait", "conet_serve_get_stats",
            "conet_serve_reset_stats", "conet_serve_pause", "conet_serve_destroy", "conet_backward", "conet_grads",
            "conet_master_weights", "conet_adam_step", "conet_get_weights", "conet_bce", "conet_destroy",
@@ -81,6 +81,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.conet_forward_profiled.argtypes = [vp, vp, i32, i32, i32, vp, fp, i32, vp]
     lib.conet_forward_profiled.restype = i32
     lib.conet_block_tile_width.argtypes = [vp]; lib.conet_block_tile_width.restype = i32
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.conet_mfma_peak.argtypes = [i32, i32, dp, dp, vp]; lib.conet_mfma_peak.restype = i32
     lib.conet_serve_create.argtypes = [vp, sz, i32, i32, i32, ctypes.POINTER(vp)]
     lib.conet_serve_create.restype = i32
     lib.conet_serve_submit.argtypes = [vp, ctypes.POINTER(conet_request), ctypes.POINTER(ctypes.c_uint64)]
@@ -363,3 +365,14 @@ def conet_function():
             return None, g.clone(), None
 
     return ConetFunction
+
+
+def mfma_peak(dtype: str = "bf16", iters: int = 0, stream=None):
+    """Measured dense MFMA TFLOP/s and shader clock (GHz) on the current device (conet_mfma_peak)."""
+    lib = load()
+    code = DTYPES[dtype]
+    if iters <= 0:
+        iters = 50_000 if dtype == "f32" else 100_000
+    tf, ghz = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib.conet_mfma_peak(code, iters, ctypes.byref(tf), ctypes.byref(ghz), _stream_ptr(stream)))
+    return tf.value, ghz.value
