@@ -227,6 +227,74 @@ def serve_measure(loads=(0.5,), duration_s=1.5, n_streams=3, seed=13):
     return out
 
 
+def depth_latency(args):
+    """Depth vs latency on this GPU (the paper's claim that inference time follows the number
+    of sequentially dependent layers): CoNet with K = 2 branches of L = 6 blocks (2L + 2 = 14
+    sequential conv layers) against a single pre-activation ResNet of L = 11 blocks (24
+    layers), both fed the same synthetic slots with random He-normal weights and near-equal
+    parameter counts. Reports the latency of one slot (median of `--steps` forwards, each
+    timed by HIP events with the GPU otherwise idle) and the throughput at a 32-slot batch."""
+    import torch
+    from paper_2510_12739_amd import Conet
+    from synth import features_fast, make_blob, workload
+    from synth.weights import ModelConfig
+
+    w = workload("bf16_b64_f3276")
+    F, T, Ci, m = w.sim.F, w.sim.T, w.model.C_in, w.model.m
+    X = torch.from_numpy(features_fast(w.sim, 32, n_distinct=8)).cuda()
+    stream = torch.cuda.current_stream()
+    out_rows = []
+    for C in (64, 96):
+        for name, K, L, mask in (("conet_K2_L6", 2, 6, -1), ("resnet_K1_L11", 1, 11, 0)):
+            mc = ModelConfig(K, L, C, Ci, m, mask)
+            model = Conet(K, L, C, Ci, m, make_blob(mc, seed=11), dtype="bf16", fuse_mask=mc.mask, max_res=32 * T * F)
+            block_params = K * L * 2 * 9 * C * C
+            seq_layers = 2 * L + 2
+            x1 = X[:1].contiguous()
+            o1 = torch.empty((1, T, F, m), dtype=torch.float32, device="cuda")
+            for _ in range(5):
+                model.forward(x1, out=o1)
+            torch.cuda.synchronize()
+            lat = []
+            for _ in range(args.steps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                model.forward(x1, out=o1)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                lat.append(e0.elapsed_time(e1) * 1e3)
+            ob = torch.empty((32, T, F, m), dtype=torch.float32, device="cuda")
+            for _ in range(2):
+                model.forward(X, out=ob)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(5):
+                model.forward(X, out=ob)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 5
+            row = {"model": name, "C": C, "K": K, "L": L, "sequential_conv_layers": seq_layers,
+                   "block_params": block_params, "fused_block_tile_width": model.block_tile_width,
+                   "latency_1slot_us": {"p50": round(float(np.median(lat)), 1),
+                                        "p10": round(float(np.percentile(lat, 10)), 1),
+                                        "p90": round(float(np.percentile(lat, 90)), 1)},
+                   "batch32_ms": round(ms, 3), "batch32_res_per_s": round(32 * T * F / (ms * 1e-3), 1)}
+            out_rows.append(row)
+            print(f"[depth] {name} C={C}: 1-slot p50 {row['latency_1slot_us']['p50']} us, "
+                  f"32 slots {ms:.3f} ms", file=sys.stderr, flush=True)
+            model.close()
+    res = {"experiment": "depth_vs_latency", "slot": f"{T}x{F} REs, C_in={Ci}, m={m}, BF16", "rows": out_rows}
+    for C in (64, 96):
+        a = [r for r in out_rows if r["C"] == C]
+        res[f"C{C}_latency_ratio_conet_over_resnet"] = round(a[0]["latency_1slot_us"]["p50"] / a[1]["latency_1slot_us"]["p50"], 3)
+        res[f"C{C}_throughput_ratio_conet_over_resnet"] = round(a[0]["batch32_res_per_s"] / a[1]["batch32_res_per_s"], 3)
+    print(json.dumps(res), flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(json.dumps(res) + "\n")
+
+
 def train_bench(args):
     """One training step = forward with saved activations + bitwise BCE + backward + Adam,
     on a batch resident in HBM (the simulator's slots tiled to the batch size)."""
@@ -305,6 +373,8 @@ def main():
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--serve", action="store_true", help="only the serving load sweep (10 %% .. 120 %% of capacity)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving point of the default run")
+    ap.add_argument("--depth-latency", action="store_true",
+                    help="only the depth-vs-latency experiment (CoNet K=2 L=6 vs ResNet K=1 L=11)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device 3 times (HBM counter calibration)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
@@ -332,6 +402,10 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path (slots shard across GPUs "
               "with no exchange; see the design notes). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.depth_latency:
+        depth_latency(args)
+        return
 
     if args.serve:
         out = serve_measure(loads=(0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2), duration_s=2.0)
