@@ -63,13 +63,20 @@ typedef struct {
   int32_t channels;        /* C: 16, 32, 64 or 96                                          */
   int32_t in_channels;     /* C_in = 4 N_rx: 8, 16 or 32                                   */
   int32_t bits_per_symbol; /* m, head width, 1..8                                          */
-  uint32_t fuse_mask;      /* bit l-1 => product fusion + LayerNorm after block l          */
+  uint32_t fuse_mask;      /* bit l-1 => fusion + LayerNorm after block l                  */
   float ln_eps;            /* LayerNorm epsilon (1e-5)                                     */
   int32_t dtype;           /* conet_dtype                                                  */
   int32_t train;           /* 1 => FP32 master weights, gradients, Adam state, per-block saved
                               activations (FP32 or BF16; C in {16,32,64}, C_in in {16,32}, K <= 4) */
   int64_t max_res;         /* largest B*T*F one call may pass                              */
+  int32_t fusion_op;       /* CONET_FUSE_PRODUCT (0): P = prod_k O[k] (Sec. III, Example I);
+                              CONET_FUSE_SUM (1): P = sum_k O[k] (fusion by addition, Sec. III) */
+  int32_t feedback;        /* 1 => Example II (Sec. III): after each fusion, support branch k
+                              continues from O[k] + the main branch's fused activation. The
+                              training calls support fusion_op = 0, feedback = 0 only          */
 } conet_config;
+
+enum { CONET_FUSE_PRODUCT = 0, CONET_FUSE_SUM = 1 };
 
 typedef struct conet_model conet_model;
 

@@ -4,8 +4,8 @@ Plain, slow and meant to be read against the paper. Nothing in the product path 
 import it: only tests, the smoke check and the bench's CPU-baseline leg do.
 
 What it computes (paper Sec. II-A and Sec. III):
-  * input layer of every branch: 3x3 conv + ReLU (Sec. III: "input layers are
-    convolutional followed by ReLU");
+  * input layer of every branch: 3x3 conv + ReLU (Sec. III describes the input layers
+    as convolutions with ReLU activations);
   * residual blocks in the pre-activation form of He et al. (Sec. II-A, Fig. 1):
     affine -> ReLU -> conv -> affine -> ReLU -> conv, plus the identity shortcut;
     the affine stands in for inference-form BN;
@@ -16,6 +16,11 @@ What it computes (paper Sec. II-A and Sec. III):
     with M support nets the product runs over all K = M+1 outputs (Sec. III, the
     generalisation to more than two nets);
   * 1x1 output conv with one filter per bit of the symbol (Sec. III) -> LLRs.
+
+Variants the paper also describes (Sec. III): fusion by addition instead of the
+product (``fusion="sum"``: P = sum_k O[k], then the same LayerNorm), and Example II's
+feedback from the main net to the support nets (``feedback=True``: after a fusion, each
+support net continues from its own block output plus the main net's fused activation).
 
 Readings of what the paper leaves open (all listed in the design notes): conv
 biases everywhere; "same" zero padding inside each slot; LN over the C channels of
@@ -233,13 +238,18 @@ def _weights(q: Quant, W: np.ndarray) -> np.ndarray:
 
 
 def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Optional[Quant] = None,
-            keep: bool = False, calib: Optional[np.ndarray] = None):
+            keep: bool = False, calib: Optional[np.ndarray] = None, fusion: str = "product",
+            feedback: bool = False):
     """CoNet forward for a batch X (B, T, F, C_in) -> LLR (B, T, F, m).
 
     keep=True also returns the intermediate tensors the backward needs.
     calib, if given, receives the running max |.| of every conv input operand
     (indexing of act_scale_index), which is how static activation scales are set.
+    fusion: "product" (Example I) or "sum" (fusion by addition); feedback: Example II's
+    main -> support feedback after every fusion. The backward covers the defaults only.
     """
+    if fusion not in ("product", "sum"):
+        raise ValueError(f"unknown fusion {fusion!r}")
     K, L = p["K"], p["L"]
     mask = ((1 << L) - 1) if fuse_mask is None else int(fuse_mask)
     q = quant or Quant()
@@ -282,16 +292,19 @@ def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Opti
                 lev["h"].append(h); lev["mrb"].append(mrb)
         last = (l == L)
         if fused_after(mask, l):
-            # the support outputs enter the product as stored (rounded under emulation)
+            # the support outputs enter the fusion as stored (rounded under emulation)
             P = O[0].copy()
             for k in range(1, K):
-                P = P * q.store(O[k])
+                P = P + q.store(O[k]) if fusion == "sum" else P * q.store(O[k])
             mu = P.mean(axis=-1, keepdims=True)
             var = ((P - mu) ** 2).mean(axis=-1, keepdims=True)
             sig = np.sqrt(var + LN_EPS)
             ahat = (P - mu) / sig
             A0 = p["gamma"][l - 1] * ahat + p["beta"][l - 1]
-            new = [A0 if last else q.store(A0)] + [q.store(O[k]) for k in range(1, K)]
+            if feedback:  # Example II: each support continues from O[k] + the main net's A
+                new = [A0 if last else q.store(A0)] + [q.store(q.store(O[k]) + A0) for k in range(1, K)]
+            else:
+                new = [A0 if last else q.store(A0)] + [q.store(O[k]) for k in range(1, K)]
             if keep:
                 lev["P"] = P; lev["ahat"] = ahat; lev["sig"] = sig
         else:
@@ -305,6 +318,7 @@ def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Opti
     llr = a[0] @ p["W_h"].T + p["b_h"]
     if keep:
         cache["aL"] = a[0]
+        cache["variant"] = (fusion, feedback)
         return llr, cache
     return llr
 
@@ -344,6 +358,8 @@ def backward(p: Dict, cache: Dict, dllr: np.ndarray) -> Dict:
     """
     K, L = p["K"], p["L"]
     mask = cache["mask"]
+    if cache.get("variant", ("product", False)) != ("product", False):
+        raise NotImplementedError("the backward covers product fusion without feedback")
     g = {"branch": [], "gamma": [None] * L, "beta": [None] * L}
     for _k in range(K):
         g["branch"].append({"W_in": None, "b_in": None, "blocks": [dict() for _ in range(L)]})

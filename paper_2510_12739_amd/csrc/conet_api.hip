@@ -138,6 +138,9 @@ conet_status check_config(const conet_config* c) {
   if (!conv_supported(c->dtype, c->channels, c->channels))
     return fail(CONET_EINVAL, "no kernel for C=%d -> C=%d at dtype %d", c->channels, c->channels, c->dtype);
   if (c->train != 0 && c->train != 1) return fail(CONET_EINVAL, "train must be 0 or 1");
+  if (c->fusion_op != CONET_FUSE_PRODUCT && c->fusion_op != CONET_FUSE_SUM)
+    return fail(CONET_EINVAL, "fusion_op must be CONET_FUSE_PRODUCT or CONET_FUSE_SUM");
+  if (c->feedback != 0 && c->feedback != 1) return fail(CONET_EINVAL, "feedback must be 0 or 1");
   if (c->train) {
     if (c->dtype != DT_F32 && c->dtype != DT_BF16) return fail(CONET_EINVAL, "training runs in FP32 or BF16");
     if (c->channels != 16 && c->channels != 32 && c->channels != 64)
@@ -145,6 +148,8 @@ conet_status check_config(const conet_config* c) {
     if (c->in_channels != 16 && c->in_channels != 32) return fail(CONET_EINVAL, "training supports C_in = 16, 32");
     if (c->branches > 4) return fail(CONET_EINVAL, "training supports K <= 4");
     if (c->blocks > 16) return fail(CONET_EINVAL, "training supports L <= 16");
+    if (c->fusion_op != CONET_FUSE_PRODUCT || c->feedback)
+      return fail(CONET_EINVAL, "training supports product fusion without feedback");
   }
   if (c->max_res < 1) return fail(CONET_EINVAL, "max_res must be positive");
   if (!(c->ln_eps > 0.f)) return fail(CONET_EINVAL, "ln_eps must be positive");

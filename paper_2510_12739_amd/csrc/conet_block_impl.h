@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(CONV_NW * 64, (block_occ<A, C>())) block_kerne
           v, re, c0, g, MAIN, [&](Acc* x) { unpack_raw<Act, RawT, EPL>(raw[mt % PD][0], x); },
           [&](int kk, Acc* sv) { unpack_raw<Act, RawT, EPL>(raw[mt % PD][kk], sv); }, MAIN ? args.out[0] : args.out[k],
           nullptr, head, NSUP + 1, par + P_GAM * C, par + P_BET * C, args.eps, whl, whl + args.m * C, args.llr,
-          args.m);
+          args.m, args.fusion_sum != 0, (MAIN && args.feedback) ? const_cast<void* const*>(args.sup) : nullptr);
     }
     if (mt + PD < MT2) issue(mt + PD);
   }

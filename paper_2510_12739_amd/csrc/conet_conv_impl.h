@@ -317,16 +317,18 @@ struct Gemm {
 // Epilogue of a block's second conv for one RE: v holds conv + bias for this lane's EPL
 // channels from c0 (lanes g = 0..3 of one column hold the RE's C channels). Adds the
 // residual x (x_fn fills EPL values). On the main branch of a fused block (main_fused),
-// keeps the pre-product output when save_o0 is set, multiplies in the stored support
-// outputs of branches 1..K-1 (sup_fn(kk, values), kk < min(K, NSUP + 1)) and applies the
-// per-RE LayerNorm over C. Then either the 1x1 LLR head (head) or a store of the block
-// output to `out` (nullable). A plain block with the head stores its output to save_o0
-// when that is set (the backward's copy).
+// keeps the pre-fusion output when save_o0 is set, multiplies (or with fuse_sum adds) in
+// the stored support outputs of branches 1..K-1 (sup_fn(kk, values), kk < min(K, NSUP+1))
+// and applies the per-RE LayerNorm over C; with sup_dst (Example II feedback) it also
+// stores support output + fused activation to sup_dst[kk]. Then either the 1x1 LLR head
+// (head) or a store of the block output to `out` (nullable). A plain block with the head
+// stores its output to save_o0 when that is set (the backward's copy).
 template <class A, int COUT, int EPL, int NSUP, class XFn, class SupFn>
 __device__ __forceinline__ void finish_block(typename A::Acc (&v)[EPL], int64_t re, int c0, int g, bool main_fused,
                                              XFn x_fn, SupFn sup_fn, void* out, void* save_o0, bool head, int K,
                                              const float* gamma, const float* beta, float eps, const float* Wh,
-                                             const float* bh, float* llr, int m) {
+                                             const float* bh, float* llr, int m, bool fuse_sum = false,
+                                             void* const* sup_dst = nullptr) {
   using Acc = typename A::Acc;
   using Act = typename A::Act;
   {
@@ -345,8 +347,13 @@ __device__ __forceinline__ void finish_block(typename A::Acc (&v)[EPL], int64_t 
       if (kk >= K) break;
       Acc sv[EPL];
       sup_fn(kk, sv);
+      if (fuse_sum) {
 #pragma unroll
-      for (int i = 0; i < EPL; ++i) v[i] *= sv[i];
+        for (int i = 0; i < EPL; ++i) v[i] += sv[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < EPL; ++i) v[i] *= sv[i];
+      }
     }
     Acc s = 0;
 #pragma unroll
@@ -362,6 +369,17 @@ __device__ __forceinline__ void finish_block(typename A::Acc (&v)[EPL], int64_t 
     const Acc rs = (Acc)1 / sqrtf((float)(q * ((Acc)1 / (Acc)COUT) + (Acc)eps));
 #pragma unroll
     for (int i = 0; i < EPL; ++i) v[i] = (Acc)gamma[c0 + i] * (v[i] - mu) * rs + (Acc)beta[c0 + i];
+    if (sup_dst) {  // Example II: each support continues from its output plus the fused activation
+#pragma unroll
+      for (int kk = 1; kk <= NSUP; ++kk) {
+        if (kk >= K) break;
+        Acc sv[EPL];
+        sup_fn(kk, sv);
+#pragma unroll
+        for (int i = 0; i < EPL; ++i) sv[i] += v[i];
+        store_vals(reinterpret_cast<Act*>(sup_dst[kk]) + re * COUT + c0, sv, EPL, 1.f);
+      }
+    }
     if (!head && out) store_vals(reinterpret_cast<Act*>(out) + re * COUT + c0, v, EPL, 1.f);
   }
   if (head) {
@@ -530,7 +548,8 @@ __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
           v, re, c0, g, MODE == 4, [&](Acc* x) { load_vals(xr, x, EPL); },
           [&](int kk, Acc* sv) { load_vals(reinterpret_cast<const Act*>(args.sup[kk]) + re * COUT + c0, sv, EPL); },
           MODE == 2 ? args.out[k] : args.out[0], args.save_o0, head, args.K, args.gamma, args.beta, args.eps, args.Wh,
-          args.bh, args.llr, args.m);
+          args.bh, args.llr, args.m, args.fusion_sum != 0,
+          (MODE == 4 && args.feedback) ? const_cast<void* const*>(args.sup) : nullptr);
     }
   }
   if constexpr (MODE == 5 || MODE == 6) {

@@ -116,6 +116,8 @@ static conet_status launch_fused_block(conet_model* M, const Geometry& geo, int 
     bm.out[0] = last ? nullptr : act(1, 0);
     bm.llr = last ? llr : nullptr;
     bm.k_off = 0;
+    bm.fusion_sum = c.fusion_op == CONET_FUSE_SUM;
+    bm.feedback = c.feedback && !last;  // the supports' outputs are not read after the last block
     e = mark();
     if (e == hipSuccess) e = launch_block(dt, true, C, bm, n_tiles, 1, s);
     if (e != hipSuccess) return hip_fail(e, "fused main block launch");
@@ -350,6 +352,8 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
       am.llr = (last && !calib) ? llr : nullptr;
       am.save_o0 = save ? ar.lvl_o0[l] : nullptr;
       am.k_off = 0;
+      am.fusion_sum = c.fusion_op == CONET_FUSE_SUM;
+      am.feedback = c.feedback && !last;
       e = mark();
       if (e == hipSuccess) e = launch_conv(dt, 4, C, C, am, n_tiles_blk, 1, s);
       if (e != hipSuccess) return hip_fail(e, "fused conv 2 launch");

@@ -48,6 +48,8 @@ struct ConvArgs {
   float* part[KMAX_ARGS];          // per-wave per-channel partial sums [gridDim.x * waves][NPART][C]
   int mask_out;                    // mode 6: store dx * (x > 0) (input-layer ReLU adjoint)
   void* save_o0;                   // mode 4 (training): also store the main output before fusion
+  int fusion_sum;                  // mode 4: fuse by addition instead of the product
+  int feedback;                    // mode 4: also rewrite sup[k] <- sup[k] + fused output (Example II)
 };
 
 // Subcarriers per tile used for a (dtype, C_in, C_out) conv.
@@ -89,6 +91,8 @@ struct BlockArgs {
   float eps;
   int T, F, tiles_per_slot, tw;    // tw: set by the launcher
   const TileDesc* tiles;           // ragged batches, else null
+  int fusion_sum;                  // main: fuse by addition instead of the product
+  int feedback;                    // main: also rewrite sup[k] <- sup[k] + fused output (Example II)
 };
 // Output subcarriers per fused tile; 0 when (dtype, C, K) runs as two conv launches.
 constexpr int BLOCK_KMAX = 4;  // fused main-branch kernels exist for K <= 4

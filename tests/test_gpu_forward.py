@@ -196,3 +196,48 @@ def test_fp8_calibration_matches_oracle_scales():
     np.testing.assert_allclose(got, ref, rtol=0.1)
     y = _run(model, X)
     assert np.all(np.isfinite(y))
+
+
+# ----------------------------------------------------------------------------- fusion variants
+
+@pytest.mark.parametrize("dtype,K,L,C,mask,fusion,feedback", [
+    ("f32", 2, 3, 32, -1, "sum", False),
+    ("f32", 3, 2, 32, 0b11, "product", True),
+    ("f32", 3, 3, 32, 0b101, "sum", True),
+    ("bf16", 3, 3, 64, -1, "sum", False),       # fused block kernel
+    ("bf16", 3, 3, 64, 0b011, "product", True),
+    ("bf16", 2, 2, 32, -1, "sum", True),
+])
+def test_fusion_variants_vs_oracle(dtype, K, L, C, mask, fusion, feedback):
+    """Fusion by addition and Example II feedback (Sec. III), through both the fused block
+    kernel (BF16, C = 32/64) and the two-conv path (FP32), on a 2-slot grid with a ragged
+    tile tail (F = 70): FP32 vs FP64 at the FP32 bounds, BF16 vs the BF16-emulating oracle
+    at 5e-3 and vs FP64 at the stated LLR tolerance."""
+    from paper_2510_12739_amd import Conet
+    Ci, m = 16, 4
+    sim = SimConfig(F=70, n_rx=4, bits_per_symbol=m, seed=41)
+    mc = ModelConfig(K, L, C, Ci, m, mask)
+    blob = make_blob(mc, seed=42, perturb=True)
+    X = features(sim, 2)
+    say(f"fusion variant {dtype} K={K} L={L} C={C} mask={mc.mask:b} {fusion} feedback={feedback}")
+    model = Conet(K, L, C, Ci, m, blob, dtype=dtype, fuse_mask=mc.mask, fusion=fusion, feedback=feedback)
+    got = _run(model, X)
+    p = o.unpack(blob, K, L, C, Ci, m)
+    ref = o.forward_slots(p, X.astype(np.float64), fuse_mask=mc.mask, fusion=fusion, feedback=feedback)
+    if dtype == "f32":
+        assert rel_l2(got, ref) <= 1e-5, rel_l2(got, ref)
+        assert max_over_rms(got, ref) <= 1e-4
+    else:
+        emu = o.forward_slots(p, X.astype(np.float64), fuse_mask=mc.mask, fusion=fusion, feedback=feedback,
+                              quant=o.Quant("bf16"))
+        assert rel_l2(got, emu) <= 5e-3, rel_l2(got, emu)
+        assert rel_l2(got, ref) <= 3e-2 and sign_agree(got, ref) >= 0.99
+    model.close()
+
+
+def test_fusion_variant_training_is_refused():
+    from paper_2510_12739_amd import Conet, ConetError
+    mc = ModelConfig(2, 1, 16, 16, 2)
+    blob = make_blob(mc, seed=1)
+    with pytest.raises(ConetError, match="EINVAL"):
+        Conet(2, 1, 16, 16, 2, blob, dtype="bf16", train=True, fusion="sum")
