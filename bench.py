@@ -525,6 +525,29 @@ def main():
               "llr_tolerance": LLR_TOL[dtype],
               "roofline": roofline}
 
+    # input featuriser (LS + interpolation, conet_featurise) on the same grid: reported beside
+    # the forward, not part of `value` (the forward's boundary takes features)
+    from paper_2510_12739_amd import featurise
+    from synth import simulate_slot
+    ys = np.stack([simulate_slot(w.sim, s).y for s in range(min(8, B))])
+    ys = np.concatenate([ys] * (-(-B // ys.shape[0])), axis=0)[:B]
+    y_dev = torch.from_numpy(np.ascontiguousarray(np.stack([ys.real, ys.imag], axis=-1).astype(np.float32))).cuda()
+    del ys
+    xf = torch.empty_like(x)
+    for _ in range(3):
+        featurise(y_dev, mc.C_in, out=xf)
+    fe0, fe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fe0.record(stream)
+    for _ in range(10):
+        featurise(y_dev, mc.C_in, out=xf)
+    fe1.record(stream)
+    torch.cuda.synchronize()
+    f_ms = fe0.elapsed_time(fe1) / 10
+    f_bytes = y_dev.numel() * 4 + xf.numel() * 4
+    result["featuriser"] = {"ms": round(f_ms, 4), "bytes": f_bytes, "GB_per_s": round(f_bytes / (f_ms * 1e-3) / 1e9, 1),
+                            "frac_of_hbm_peak": round(f_bytes / (f_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del y_dev, xf
+
     if not args.no_cpu:
         n_s = min(8, B)
         llr_s = out[:n_s].cpu().numpy()

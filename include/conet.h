@@ -145,6 +145,19 @@ conet_status conet_forward_ragged(conet_model* model, const float* x, int32_t n_
 conet_status conet_forward_profiled(conet_model* model, const float* x, int32_t B, int32_t T, int32_t F, float* llr,
                                     float* stage_ms_host, int32_t n_stages, void* stream);
 
+/* The network's input from the received grid (Sec. II, Eq. (1); Sec. II-A): least-squares
+ * channel estimates at the fixed pilots (symbols 2 and 11, even subcarriers, value
+ * (1+j)/sqrt(2)), interpolated linearly — odd subcarriers of a pilot symbol take the mean of
+ * their even neighbours (a last odd one copies its left neighbour), and every symbol lies on
+ * the line through symbols 2 and 11 — then laid out as the features conet_forward reads.
+ * y: device FP32 [B][T][F][n_rx][2] (Re, Im); x_out: device FP32 [B][T][F][C_in] with
+ * channels 4n..4n+3 = (Re y_n, Im y_n, Re H_n, Im H_n) for n < n_rx and zeros for the
+ * remaining C_in/4 - n_rx antennas. FP32 arithmetic; enqueued on `stream`, no allocation.
+ * Errors: EINVAL (null buffers), ESHAPE (T outside 12..14, B or F < 1, 4 n_rx > C_in, C_in not
+ * a multiple of 4). */
+conet_status conet_featurise(const float* y, int32_t B, int32_t T, int32_t F, int32_t n_rx, int32_t C_in,
+                             float* x_out, void* stream);
+
 /* Subcarriers per tile of the fused residual-block kernel that inference forwards of
  * this model use (both convs of a block in one launch, the hidden activation kept on
  * chip; BF16 with C in {16, 32, 64} and K <= 4), or 0 when every block runs as two conv

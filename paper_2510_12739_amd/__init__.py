@@ -2,5 +2,6 @@
 
 The Python layer only marshals arguments; see binding.Conet.
 """
-from .binding import (Conet, ConetError, Server, conet_function, load, make_config, mfma_peak, weight_count,
+from .binding import (Conet, ConetError, Server, conet_function, featurise, load, make_config, mfma_peak,
+                      weight_count,
                       workspace_bytes, EXPORTS)

@@ -22,7 +22,7 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "ENOMEM", 4: "EDEVICE", 5: "EBUS
 # Every symbol include/conet.h declares.
 EXPORTS = ("conet_weight_count", "conet_workspace_bytes", "conet_create", "conet_set_act_scales",
            "conet_calibrate", "conet_get_act_scales", "conet_forward", "conet_forward_ragged", "conet_forward_profiled",
-           "conet_block_tile_width", "conet_mfma_peak",
+           "conet_block_tile_width", "conet_mfma_peak", "conet_featurise",
            "conet_serve_create", "conet_serve_submit", "conet_serve_wait", "conet_serve_get_stats",
            "conet_serve_reset_stats", "conet_serve_pause", "conet_serve_destroy", "conet_backward", "conet_grads",
            "conet_master_weights", "conet_adam_step", "conet_get_weights", "conet_bce", "conet_destroy",
@@ -84,6 +84,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.conet_block_tile_width.argtypes = [vp]; lib.conet_block_tile_width.restype = i32
     dp = ctypes.POINTER(ctypes.c_double)
     lib.conet_mfma_peak.argtypes = [i32, i32, dp, dp, vp]; lib.conet_mfma_peak.restype = i32
+    lib.conet_featurise.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]; lib.conet_featurise.restype = i32
     lib.conet_serve_create.argtypes = [vp, sz, i32, i32, i32, ctypes.POINTER(vp)]
     lib.conet_serve_create.restype = i32
     lib.conet_serve_submit.argtypes = [vp, ctypes.POINTER(conet_request), ctypes.POINTER(ctypes.c_uint64)]
@@ -384,3 +385,17 @@ def mfma_peak(dtype: str = "bf16", iters: int = 0, stream=None):
     tf, ghz = ctypes.c_double(0.0), ctypes.c_double(0.0)
     _check(lib.conet_mfma_peak(code, iters, ctypes.byref(tf), ctypes.byref(ghz), _stream_ptr(stream)))
     return tf.value, ghz.value
+
+
+def featurise(y, C_in: int, out=None, stream=None):
+    """conet_featurise: y is a contiguous float32 CUDA tensor [B][T][F][n_rx][2]; returns the
+    float32 features [B][T][F][C_in] (LS at the pilots + linear interpolation)."""
+    import torch
+    if not (y.is_cuda and y.dtype == torch.float32 and y.is_contiguous() and y.dim() == 5 and y.shape[-1] == 2):
+        raise ValueError("y must be a contiguous float32 CUDA tensor [B][T][F][n_rx][2]")
+    B, T, F, n_rx, _ = y.shape
+    if out is None:
+        out = torch.empty((B, T, F, C_in), dtype=torch.float32, device=y.device)
+    _check(load().conet_featurise(ctypes.c_void_p(y.data_ptr()), B, T, F, n_rx, C_in,
+                                  ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out

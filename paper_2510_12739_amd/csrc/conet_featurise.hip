@@ -1,0 +1,90 @@
+// Input featuriser of CoNet-Rx on the GPU: least-squares channel estimation at the
+// pilots, linear interpolation over the resource grid, and the network's input layout.
+//
+// The receiver's input is the received grid of one TTI (Sec. II, Eq. (1)); the network
+// reads, per RE and antenna, the received sample and a channel estimate (Sec. II-A:
+// real and imaginary parts as separate channels). Pilots are fixed: symbols 2 and 11,
+// even subcarriers, value p = (1 + j)/sqrt(2). Per antenna:
+//   * on each pilot symbol s, H_s(f) = y(s, f) / p on even f; an odd f takes the mean of
+//     its two even neighbours, and a last odd subcarrier copies its left neighbour;
+//   * every symbol t lies on the line through symbols 2 and 11:
+//     H(t, f) = H_2(f) + (t - 2) / 9 * (H_11(f) - H_2(f)).
+// One thread per (slot, subcarrier, antenna) forms the two pilot-symbol estimates once
+// and walks the slot's symbols, writing the antenna's four channels (Re y, Im y, Re H,
+// Im H) as one 16-byte store per RE; neighbouring threads cover neighbouring subcarriers,
+// so every symbol's loads and stores are contiguous. Memory-bound: 8 B read and 16 B
+// written per RE and antenna.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "conet.h"
+#include "conet_model.h"
+
+namespace conet {
+
+constexpr int PILOT_T0 = 2, PILOT_T1 = 11;
+
+// y / p for p = (1 + j)/sqrt(2): y * conj(p) / |p|^2 = ((a + b) + j (b - a)) / sqrt(2)
+__device__ __forceinline__ float2 div_pilot(float2 y) {
+  const float r = 0.70710678118654752f;
+  return make_float2((y.x + y.y) * r, (y.y - y.x) * r);
+}
+
+// LS estimate on pilot symbol row `row` (pointer to y[b][s][0][n], stride per subcarrier)
+__device__ __forceinline__ float2 pilot_row_estimate(const float2* __restrict__ row, int64_t stride, int f, int F) {
+  if ((f & 1) == 0) return div_pilot(row[(int64_t)f * stride]);
+  const float2 l = div_pilot(row[(int64_t)(f - 1) * stride]);
+  if (f + 1 >= F) return l;
+  const float2 r = div_pilot(row[(int64_t)(f + 1) * stride]);
+  return make_float2(0.5f * (l.x + r.x), 0.5f * (l.y + r.y));
+}
+
+__global__ void __launch_bounds__(256) featurise_kernel(const float2* __restrict__ y, int64_t n_items, int T, int F,
+                                                        int n_rx, int n_ant_out, float4* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_items) return;
+  // item = (b * F + f) * n_ant_out + n; the thread walks the slot's T symbols
+  const int n = (int)(i % n_ant_out);
+  const int64_t bf = i / n_ant_out;
+  const int f = (int)(bf % F);
+  const int64_t b = bf / F;
+  const int64_t slot0 = b * T * F;  // RE index of (b, 0, 0)
+  const int64_t sym = (int64_t)F * n_ant_out;  // stride of one symbol in items
+  if (n >= n_rx) {  // antennas the model has but the grid does not: zero channels
+    for (int t = 0; t < T; ++t) x[(slot0 + f) * n_ant_out + n + t * sym] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  const float2 h0 = pilot_row_estimate(y + (slot0 + (int64_t)PILOT_T0 * F) * n_rx + n, n_rx, f, F);
+  const float2 h1 = pilot_row_estimate(y + (slot0 + (int64_t)PILOT_T1 * F) * n_rx + n, n_rx, f, F);
+  const float2 dh = make_float2(h1.x - h0.x, h1.y - h0.y);
+  const float2* yp = y + (slot0 + f) * n_rx + n;
+  float4* xp = x + (slot0 + f) * n_ant_out + n;
+  for (int t = 0; t < T; ++t) {
+    const float w = (float)(t - PILOT_T0) / (float)(PILOT_T1 - PILOT_T0);
+    const float2 yv = yp[(int64_t)t * F * n_rx];
+    xp[(int64_t)t * sym] = make_float4(yv.x, yv.y, h0.x + w * dh.x, h0.y + w * dh.y);
+  }
+}
+
+}  // namespace conet
+
+using namespace conet;
+
+extern "C" conet_status conet_featurise(const float* y, int32_t B, int32_t T, int32_t F, int32_t n_rx, int32_t C_in,
+                                        float* x_out, void* stream) {
+  if (!y || !x_out) return fail(CONET_EINVAL, "null buffer");
+  if (B < 1 || F < 1 || T <= PILOT_T1 || T > TMAX) return fail(CONET_ESHAPE, "need B >= 1, F >= 1, 12 <= T <= 14");
+  if (n_rx < 1 || C_in < 4 || C_in % 4 != 0 || 4 * n_rx > C_in)
+    return fail(CONET_ESHAPE, "need 1 <= n_rx and 4 * n_rx <= C_in, C_in a multiple of 4");
+  const int n_ant_out = C_in / 4;
+  const int64_t n_items = (int64_t)B * F * n_ant_out;  // one thread per (slot, subcarrier, antenna)
+  const int64_t blocks = (n_items + 255) / 256;
+  if (blocks > 0x7fffffff) return fail(CONET_ESHAPE, "grid too large");
+  hipLaunchKernelGGL(featurise_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                     reinterpret_cast<const float2*>(y), n_items, (int)T, (int)F, (int)n_rx, n_ant_out,
+                     reinterpret_cast<float4*>(x_out));
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "featurise launch");
+  return CONET_OK;
+}
