@@ -95,6 +95,8 @@ def load_traffic(kernel: str, workload: str, dtype: str):
 
 def kernel_kind(name: str):
     """Roofline kind of a kernel dispatch, from the demangled name rocprofv3 reports."""
+    if "block_pair_kernel<" in name:
+        return "block_fused_pair"
     if "block_kernel<" in name:
         args = name.split("block_kernel<", 1)[1].split(">", 1)[0].split(",")
         return "block_fused_main" if args[3].strip() == "true" else "block_fused_supports"
@@ -454,8 +456,9 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
+    stage_units = None
     for _ in range(args.steps):
-        _, ms = model.forward_profiled(x, out=out)
+        _, ms, stage_units = model.forward_profiled(x, out=out, units=True)
         stage_ms.append(ms)
     ev1.record(stream)
     torch.cuda.synchronize()
@@ -465,40 +468,26 @@ def main():
     stage_ms = np.array(stage_ms)                          # [steps, 1 + 2L]
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall:.2f} s)", file=sys.stderr, flush=True)
 
-    # ---- roofline of the dominant kernel. Stages: input layer, then per block
-    # [conv 1 of all branches, conv 2 of the supports (or of all branches without
-    # fusion), conv 2 of the main branch with product fusion + LayerNorm (+ head)];
-    # with fused residual-block launches: [block without fusion after it (all branches),
-    # the support branches' blocks, the main branch's block with the fusion epilogue].
-    # FLOPs are algorithmic: 2 * 9 * C * C per RE per conv (the fused kernel's halo
-    # recompute of conv 1 and padded M-tiles are not counted).
-    mask = mc.mask
+    # ---- roofline of the dominant kernel. Stages: input layer, then per block (a) conv 1 of
+    # all branches / a fused block without fusion after it, (b) support branches (their conv 2,
+    # or with fused residual blocks both convs, paired with the previous block's main branch
+    # when it was deferred to this launch), (c) a main branch launched alone. The library
+    # reports each stage's conv-branch units (one conv of one branch over the batch), so the
+    # FLOPs are algorithmic: units x REs x 2*9*C*C (the fused kernel's halo recompute of conv 1
+    # and padded M-tiles are not counted).
     blk_fl = res * 2 * 9 * mc.C * mc.C                   # MFMA FLOPs of one block conv over one branch
     fused_tw = model.block_tile_width
-    if fused_tw:
-        kinds = {"block_fused_all": [], "block_fused_supports": [], "block_fused_main": []}
-        for l in range(mc.L):
-            fused = (mask >> l) & 1
-            last = l == mc.L - 1
-            if fused:
-                if mc.K > 1:
-                    kinds["block_fused_supports"].append((stage_ms[:, 2 + 3 * l], (mc.K - 1) * 2 * blk_fl))
-                kinds["block_fused_main"].append((stage_ms[:, 3 + 3 * l], 2 * blk_fl))
-            else:
-                kinds["block_fused_all"].append((stage_ms[:, 1 + 3 * l], (1 if last else mc.K) * 2 * blk_fl))
-    else:
-        kinds = {"block_conv1": [], "block_conv2_supports": [], "block_conv2_main_fused": []}
-        for l in range(mc.L):
-            fused = (mask >> l) & 1
-            last = l == mc.L - 1
-            c1 = stage_ms[:, 1 + 3 * l]
-            kinds["block_conv1"].append((c1, (mc.K if (fused or not last) else 1) * blk_fl))
-            if fused:
-                if mc.K > 1:
-                    kinds["block_conv2_supports"].append((stage_ms[:, 2 + 3 * l], (mc.K - 1) * blk_fl))
-                kinds["block_conv2_main_fused"].append((stage_ms[:, 3 + 3 * l], blk_fl))
-            else:
-                kinds["block_conv2_supports"].append((stage_ms[:, 2 + 3 * l], (1 if last else mc.K) * blk_fl))
+    names = (("block_fused_all", "block_fused_supports", "block_fused_main") if fused_tw else
+             ("block_conv1", "block_conv2_supports", "block_conv2_main_fused"))
+    kinds = {}
+    for i in range(1, stage_ms.shape[1]):
+        u = int(stage_units[i])
+        if u == 0:
+            continue
+        name = names[(i - 1) % 3]
+        if fused_tw and (i - 1) % 3 == 1 and u == 2 * mc.K:
+            name = "block_fused_pair"
+        kinds.setdefault(name, []).append((stage_ms[:, i], u * blk_fl))
     tot = {k: sum(float(ms.sum()) for ms, _ in v) for k, v in kinds.items() if v}
     dom = max(tot, key=tot.get)
     launches = kinds[dom]
@@ -514,6 +503,7 @@ def main():
                 "measured_peak": round(peak_meas, 1), "measured_clock_ghz": round(clock_ghz, 3),
                 "frac_of_measured_peak": round(achieved / peak_meas, 4) if peak_meas > 0 else None,
                 "stage_mean_ms": [round(float(v), 4) for v in stage_ms.mean(axis=0)],
+                "stage_conv_units": [int(u) for u in stage_units],
                 "whole_step_tflops": round(flops_per_re(mc.K, mc.L, mc.C, mc.C_in, mc.m) * res / (ms_per_step * 1e-3) / 1e12, 2)}
 
     result = {"metric": METRIC, "value": round(res / (ms_per_step * 1e-3), 1), "unit": "REs/s",

@@ -133,17 +133,22 @@ conet_status conet_forward_ragged(conet_model* model, const float* x, int32_t n_
                                   const int32_t* F_host, float* llr, void* stream);
 
 /* conet_forward on a uniform batch with a HIP event recorded on `stream` before every
- * kernel launch and after the last: stage_ms_host[i] (n_stages = 1 + 3L entries) gets
- * the elapsed time of stage i: the input layer, then per block (a) its first conv over
- * all branches, (b) the second conv of the support branches (with fusion) or of all
- * branches (without), (c) the second conv of the main branch with the product fusion,
- * LayerNorm and, after the last block, the LLR head (0 without fusion).
+ * stage and after the last: stage_ms_host[i] (n_stages = 1 + 3L entries) gets the elapsed
+ * time of stage i: the input layer, then per block (a) its first conv over all branches,
+ * (b) the second conv of the support branches (with fusion) or of all branches (without),
+ * (c) the second conv of the main branch with the fusion epilogue, LayerNorm and, after
+ * the last block, the LLR head (0 without fusion).
  * When the model runs blocks as fused launches (conet_block_tile_width > 0), stage (a)
- * holds a block without fusion after it (both convs of every branch), (b) the support
- * branches' fused launch and (c) the main branch's; the other entries are ~0.
+ * holds a block without fusion after it (both convs of every branch); (b) the support
+ * branches of a fused block, in one launch with the previous block's main branch when that
+ * is deferred to it (no Example II feedback); (c) a main branch launched alone (the last
+ * block's, or one that could not be paired); unused entries are ~0.
+ * stage_units_host (nullable, n_stages entries) receives per stage the conv-branch units it
+ * ran: one conv of one branch over the whole batch (a fused block of one branch counts 2;
+ * stage 0 counts the input conv of each branch), for per-stage FLOP accounting.
  * Synchronises on the last event. Errors as conet_forward. */
 conet_status conet_forward_profiled(conet_model* model, const float* x, int32_t B, int32_t T, int32_t F, float* llr,
-                                    float* stage_ms_host, int32_t n_stages, void* stream);
+                                    float* stage_ms_host, int32_t* stage_units_host, int32_t n_stages, void* stream);
 
 /* The network's input from the received grid (Sec. II, Eq. (1); Sec. II-A): least-squares
  * channel estimates at the fixed pilots (symbols 2 and 11, even subcarriers, value

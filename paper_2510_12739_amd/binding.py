@@ -79,7 +79,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.conet_forward.argtypes = [vp, vp, i32, i32, i32, vp, i32, vp]; lib.conet_forward.restype = i32
     lib.conet_forward_ragged.argtypes = [vp, vp, i32, i32, ctypes.POINTER(i32), vp, vp]
     lib.conet_forward_ragged.restype = i32
-    lib.conet_forward_profiled.argtypes = [vp, vp, i32, i32, i32, vp, fp, i32, vp]
+    lib.conet_forward_profiled.argtypes = [vp, vp, i32, i32, i32, vp, fp, ctypes.POINTER(i32), i32, vp]
     lib.conet_forward_profiled.restype = i32
     lib.conet_block_tile_width.argtypes = [vp]; lib.conet_block_tile_width.restype = i32
     dp = ctypes.POINTER(ctypes.c_double)
@@ -257,19 +257,22 @@ class Conet:
         """Subcarriers per fused residual-block tile of inference forwards (0: two conv launches per block)."""
         return int(self.lib.conet_block_tile_width(self.handle))
 
-    def forward_profiled(self, x, out=None, stream=None):
-        """forward() with per-stage HIP event timing: returns (llr, stage_ms[1 + 3L])."""
+    def forward_profiled(self, x, out=None, stream=None, units: bool = False):
+        """forward() with per-stage HIP event timing: returns (llr, stage_ms[1 + 3L]), plus the
+        per-stage conv-branch units when units=True."""
         import torch
         self._check_x(x)
         B, T, F, _ = x.shape
         if out is None:
             out = torch.empty((B, T, F, self.m), dtype=torch.float32, device=x.device)
         ms = np.zeros(1 + 3 * self.L, dtype=np.float32)
+        un = np.zeros(1 + 3 * self.L, dtype=np.int32)
         _check(self.lib.conet_forward_profiled(self.handle, ctypes.c_void_p(x.data_ptr()), B, T, F,
                                                ctypes.c_void_p(out.data_ptr()),
-                                               ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ms.size,
+                                               ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                               un.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ms.size,
                                                _stream_ptr(stream)))
-        return out, ms
+        return (out, ms, un) if units else (out, ms)
 
     def forward_ragged(self, x_packed, T: int, F_list: Sequence[int], out=None, stream=None):
         """Slots of different widths packed back to back: x_packed [sum T*F_s, C_in]."""

@@ -58,10 +58,17 @@ __device__ __forceinline__ void unpack_raw(const RawT* r, Acc* v) {
 // of both convs (FP8; ones otherwise), conv-2 bias and the LayerNorm affine.
 enum { P_B1, P_S1, P_O1, P_Q1, P_B2, P_Q2, P_GAM, P_BET, NPAR };
 
-// NSUP: support branches multiplied in by the main branch (K - 1; 0 otherwise).
-// HEAD: the launch feeds the LLR head (after the last block).
+// LDS bytes of one work-group of the fused kernel: the x / h tile, then the parameters.
+template <class A, int C, int TWO>
+constexpr int block_lds_bytes() {
+  return TROWS * (TWO + 4) * lds_pitch<A, C>() + NPAR * C * 4;
+}
+
+// One fused residual block of branch k on tile `bid` (before the XCD remap).
+// MAIN: the main branch of a fused block (fusion epilogue); NSUP: the support branches it
+// fuses (K - 1; 0 otherwise). HEAD: this block feeds the LLR head (after the last block).
 template <class A, int C, int TWO, bool MAIN, bool HEAD, int NSUP>
-__global__ void __launch_bounds__(CONV_NW * 64, (block_occ<A, C>())) block_kernel(BlockArgs args) {
+__device__ __forceinline__ void block_body(const BlockArgs& args, int k, uint8_t* lds) {
   using Acc = typename A::Acc;
   using AccV = typename A::AccV;
   using Act = typename A::Act;
@@ -80,7 +87,6 @@ __global__ void __launch_bounds__(CONV_NW * 64, (block_occ<A, C>())) block_kerne
   using G2 = GemmCore<A, C, C, HW, PITCH, MT2, VB>;
   static_assert(OCC * (TILE + NPAR * C * 4) <= 160 * 1024, "LDS must leave room for OCC work-groups per CU");
   static_assert((C * (int)sizeof(Op)) % 16 == 0, "h rows are written in 16-byte chunks");
-  __shared__ __attribute__((aligned(16))) uint8_t lds[TILE + NPAR * C * 4];
   float* par = reinterpret_cast<float*>(lds + TILE);
 
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -89,7 +95,6 @@ __global__ void __launch_bounds__(CONV_NW * 64, (block_occ<A, C>())) block_kerne
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, col = lane & 15;
   const int c0 = g * EPL;  // first channel owned by this lane
-  const int k = blockIdx.y + args.k_off;
 
   // 0. per-channel parameters: loads issued now, written to LDS after the tile's loads
   constexpr int NPV = (NPAR * C + NT - 1) / NT;
@@ -287,13 +292,33 @@ __global__ void __launch_bounds__(CONV_NW * 64, (block_occ<A, C>())) block_kerne
   }
 }
 
+// One fused block per work-group: branch blockIdx.y + k_off.
+template <class A, int C, int TWO, bool MAIN, bool HEAD, int NSUP>
+__global__ void __launch_bounds__(CONV_NW * 64, (block_occ<A, C>())) block_kernel(BlockArgs args) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[block_lds_bytes<A, C, TWO>()];
+  block_body<A, C, TWO, MAIN, HEAD, NSUP>(args, blockIdx.y + args.k_off, lds);
+}
+
+// The main branch of block l (blockIdx.y == 0, fusion epilogue over the supports' stored
+// outputs of block l) together with the support branches of block l + 1 (blockIdx.y >= 1,
+// which read only the supports' outputs of block l): independent work in one launch. The
+// per-branch argument arrays carry block l for branch 0 and block l + 1 for the others.
+template <class A, int C, int TWO, int NSUP>
+__global__ void __launch_bounds__(CONV_NW * 64, (block_occ<A, C>())) block_pair_kernel(BlockArgs args) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[block_lds_bytes<A, C, TWO>()];
+  if (blockIdx.y == 0)
+    block_body<A, C, TWO, true, false, NSUP>(args, 0, lds);
+  else
+    block_body<A, C, TWO, false, false, 0>(args, blockIdx.y, lds);
+}
+
 template <class A, int C, bool HEAD>
-static hipError_t launch_block_h(bool main, BlockArgs& a, dim3 grid, hipStream_t s) {
+static hipError_t launch_block_h(int kind, BlockArgs& a, dim3 grid, hipStream_t s) {
   constexpr int TWO = block_tw<A, C>();
   const dim3 blk(CONV_NW * 64);
-  if (!main) {
+  if (kind == BLOCK_PLAIN) {
     hipLaunchKernelGGL((block_kernel<A, C, TWO, false, HEAD, 0>), grid, blk, 0, s, a);
-  } else {
+  } else if (kind == BLOCK_MAIN) {
     switch (a.K) {
       case 1: hipLaunchKernelGGL((block_kernel<A, C, TWO, true, HEAD, 0>), grid, blk, 0, s, a); break;
       case 2: hipLaunchKernelGGL((block_kernel<A, C, TWO, true, HEAD, 1>), grid, blk, 0, s, a); break;
@@ -301,12 +326,20 @@ static hipError_t launch_block_h(bool main, BlockArgs& a, dim3 grid, hipStream_t
       case 4: hipLaunchKernelGGL((block_kernel<A, C, TWO, true, HEAD, 3>), grid, blk, 0, s, a); break;
       default: return hipErrorInvalidValue;
     }
+  } else {  // BLOCK_PAIR: no head (the last block's main branch runs alone)
+    if constexpr (HEAD) return hipErrorInvalidValue;
+    switch (a.K) {
+      case 2: hipLaunchKernelGGL((block_pair_kernel<A, C, TWO, 1>), grid, blk, 0, s, a); break;
+      case 3: hipLaunchKernelGGL((block_pair_kernel<A, C, TWO, 2>), grid, blk, 0, s, a); break;
+      case 4: hipLaunchKernelGGL((block_pair_kernel<A, C, TWO, 3>), grid, blk, 0, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }
 
 template <class A, int C>
-static hipError_t launch_block_c(bool main, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+static hipError_t launch_block_c(int kind, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
   constexpr int TWO = block_tw<A, C>();
   if constexpr (TWO == 0) {
     return hipErrorInvalidValue;
@@ -314,16 +347,16 @@ static hipError_t launch_block_c(bool main, BlockArgs& a, int n_tiles, int grid_
     a.tw = TWO;
     if (a.llr && (a.m < 1 || a.m > 8)) return hipErrorInvalidValue;
     const dim3 grid(n_tiles, grid_y);
-    return a.llr ? launch_block_h<A, C, true>(main, a, grid, s) : launch_block_h<A, C, false>(main, a, grid, s);
+    return a.llr ? launch_block_h<A, C, true>(kind, a, grid, s) : launch_block_h<A, C, false>(kind, a, grid, s);
   }
 }
 
 template <class A>
-hipError_t launch_block_dtype(bool main, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+hipError_t launch_block_dtype(int kind, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
   switch (C) {
-    case 16: return launch_block_c<A, 16>(main, a, n_tiles, grid_y, s);
-    case 32: return launch_block_c<A, 32>(main, a, n_tiles, grid_y, s);
-    case 64: return launch_block_c<A, 64>(main, a, n_tiles, grid_y, s);
+    case 16: return launch_block_c<A, 16>(kind, a, n_tiles, grid_y, s);
+    case 32: return launch_block_c<A, 32>(kind, a, n_tiles, grid_y, s);
+    case 64: return launch_block_c<A, 64>(kind, a, n_tiles, grid_y, s);
   }
   return hipErrorInvalidValue;
 }

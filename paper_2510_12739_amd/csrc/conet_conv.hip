@@ -10,7 +10,7 @@ hipError_t launch_conv_fp8(int mode, int cin, int cout, ConvArgs& a, int n_tiles
 int conv_tile_width_f32(int cin, int cout);
 int conv_tile_width_bf16(int cin, int cout);
 int conv_tile_width_fp8(int cin, int cout);
-hipError_t launch_block_bf16(bool main, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
+hipError_t launch_block_bf16(int kind, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
 int block_tile_width_bf16(int C);
 
 hipError_t launch_conv(int dtype, int mode, int cin, int cout, ConvArgs& a, int n_tiles, int grid_y, hipStream_t s) {
@@ -38,8 +38,8 @@ int block_tile_width(int dtype, int C, int K) {
   return dtype == DT_BF16 ? block_tile_width_bf16(C) : 0;
 }
 
-hipError_t launch_block(int dtype, bool main, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
-  if (dtype == DT_BF16) return launch_block_bf16(main, C, a, n_tiles, grid_y, s);
+hipError_t launch_block(int dtype, int kind, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+  if (dtype == DT_BF16) return launch_block_bf16(kind, C, a, n_tiles, grid_y, s);
   return hipErrorInvalidValue;
 }
 

@@ -50,30 +50,50 @@ hipError_t launch_amax(const void* x, int elem_bytes, int64_t n_re, int C, const
 static int scale_index(int K, int L, int k, int l, int which) { (void)K; return 1 + 2 * (k * L + l) + which; }
 
 // ---------------------------------------------------------------- fused blocks
-// One block as fused launches (stage marks as for the two-conv path: conv 1, support
-// conv 2, main conv 2). Without fusion after the block: one launch over nk branches.
-// With fusion: the support branches (outputs stored), then the main branch with the
-// product, LayerNorm and, after the last block, the head. act(0, k) is the block
-// input of branch k, act(1, k) its output buffer.
-template <class ActFn, class MarkFn>
-static conet_status launch_fused_block(conet_model* M, const Geometry& geo, int n_tiles, const TileDesc* tiles, int tw,
-                                       int l, int nk, bool fuse, bool fused_prev, bool last, ActFn act, float* llr,
-                                       hipStream_t s, MarkFn& mark) {
-  const conet_config& c = M->cfg;
-  const Layout& lay = M->lay;
-  const int K = c.branches, L = c.blocks, C = c.channels, dt = c.dtype;
-  uint8_t* ws = M->ws;
-  const float* vec = reinterpret_cast<const float*>(ws + lay.vec);
-  const std::vector<float>& sc = M->act_scales;
-  BlockArgs b = {};
-  b.T = geo.T;
-  b.F = geo.uniform ? geo.F : 0;
-  b.tiles_per_slot = geo.uniform ? (geo.F + tw - 1) / tw : 0;
-  b.tiles = geo.uniform ? nullptr : tiles;
-  for (int k = 0; k < nk; ++k) {
+// Schedules the blocks as fused launches (both convs of a block per work-group). Per block
+// l: without fusion after it, one launch over the branches; with fusion, the support
+// branches, then the main branch with the fusion epilogue (product or sum, LayerNorm and,
+// after the last block, the head). The main branch of block l and the support branches of
+// block l + 1 read disjoint inputs (the supports' outputs of block l, and those only), so
+// unless Example II feedback makes supports depend on the main branch they share one
+// launch (BLOCK_PAIR): 2 launches per fused block become one, which halves the dependent
+// launches of a forward. Stage marks stay three per block: (a) a block without fusion,
+// (b) support branches (paired with the previous block's main branch when paired),
+// (c) a main branch launched alone (the last block's, or one that could not be paired).
+struct FusedScheduler {
+  conet_model* M;
+  const Geometry& geo;
+  int n_tiles;
+  const TileDesc* tiles;
+  int tw;
+  float* llr;
+  hipStream_t s;
+  int32_t* units;  // per-stage conv-branch units (two per fused branch block), or null
+  bool pending = false;  // a main-branch launch of the previous block not issued yet
+  BlockArgs main_args = {};
+
+  // geometry + shared fields
+  void base(BlockArgs& b) const {
+    const conet_config& c = M->cfg;
+    b.T = geo.T;
+    b.F = geo.uniform ? geo.F : 0;
+    b.tiles_per_slot = geo.uniform ? (geo.F + tw - 1) / tw : 0;
+    b.tiles = geo.uniform ? nullptr : tiles;
+    b.K = c.branches;
+    b.eps = c.ln_eps;
+    b.m = c.bits_per_symbol;
+  }
+  // branch k's block-l parameters, input x and output out into slot k of b
+  void branch(BlockArgs& b, int k, int l, bool mrb, const void* x, void* out) const {
+    const conet_config& c = M->cfg;
+    const Layout& lay = M->lay;
+    const int K = c.branches, L = c.blocks, C = c.channels;
+    uint8_t* ws = M->ws;
+    const float* vec = reinterpret_cast<const float*>(ws + lay.vec);
+    const std::vector<float>& sc = M->act_scales;
     const float* vb = vec + lay.v_blk[k][l];
-    const bool mrb = (k == 0 && fused_prev);
-    b.x[k] = act(0, k);
+    b.x[k] = x;
+    b.out[k] = out;
     b.pre_s[k] = mrb ? nullptr : vb + 0 * C;
     b.pre_o[k] = mrb ? nullptr : vb + 1 * C;
     b.b1[k] = vb + 2 * C;
@@ -90,51 +110,90 @@ static conet_status launch_fused_block(conet_model* M, const Geometry& geo, int 
     b.q2[k] = 1.0f / s2;
     b.deq2[k] = s2;
   }
-  b.K = K;
-  b.eps = c.ln_eps;
-  b.gamma = vec + lay.v_gamma[l];
-  b.beta = vec + lay.v_beta[l];
-  b.Wh = vec + lay.v_wh;
-  b.bh = vec + lay.v_bh;
-  b.m = c.bits_per_symbol;
-  hipError_t e = mark();  // conv-1 stage: part of the fused launches
-  if (e != hipSuccess) return hip_fail(e, "event record");
-  if (fuse) {
-    if (K > 1) {
-      BlockArgs bs = b;
-      for (int k = 1; k < K; ++k) bs.out[k] = act(1, k);
-      bs.k_off = 1;
-      e = mark();
-      if (e == hipSuccess) e = launch_block(dt, false, C, bs, n_tiles, K - 1, s);
-      if (e != hipSuccess) return hip_fail(e, "fused support block launch");
-    } else {
-      e = mark();
-      if (e != hipSuccess) return hip_fail(e, "event record");
-    }
-    BlockArgs bm = b;
-    for (int k = 1; k < K; ++k) bm.sup[k] = act(1, k);
-    bm.out[0] = last ? nullptr : act(1, 0);
-    bm.llr = last ? llr : nullptr;
-    bm.k_off = 0;
-    bm.fusion_sum = c.fusion_op == CONET_FUSE_SUM;
-    bm.feedback = c.feedback && !last;  // the supports' outputs are not read after the last block
-    e = mark();
-    if (e == hipSuccess) e = launch_block(dt, true, C, bm, n_tiles, 1, s);
-    if (e != hipSuccess) return hip_fail(e, "fused main block launch");
-  } else {
-    for (int k = 0; k < nk; ++k) b.out[k] = last ? nullptr : act(1, k);
-    b.llr = last ? llr : nullptr;
-    e = mark();
-    if (e == hipSuccess) e = launch_block(dt, false, C, b, n_tiles, nk, s);
-    if (e == hipSuccess) e = mark();
-    if (e != hipSuccess) return hip_fail(e, "fused block launch");
+  conet_status launch(int kind, BlockArgs& b, int grid_y, int stage, int n_blocks, const char* what) {
+    const hipError_t e = launch_block(M->cfg.dtype, kind, M->cfg.channels, b, n_tiles, grid_y, s);
+    if (e != hipSuccess) return hip_fail(e, what);
+    if (units) units[stage] += 2 * n_blocks;
+    return CONET_OK;
   }
-  return CONET_OK;
-}
+  conet_status flush(int stage) {
+    if (!pending) return CONET_OK;
+    pending = false;
+    return launch(BLOCK_MAIN, main_args, 1, stage, 1, "fused main block launch");
+  }
+
+  // Block l of every branch: in(k) / out(k) are the block's input and output buffers.
+  template <class InFn, class OutFn, class MarkFn>
+  conet_status block(int l, bool fuse, bool fused_prev, bool last, InFn in, OutFn out, MarkFn& mark) {
+    const conet_config& c = M->cfg;
+    const Layout& lay = M->lay;
+    const int K = c.branches;
+    const float* vec = reinterpret_cast<const float*>(M->ws + lay.vec);
+    const int sa = 1 + 3 * l, sb = 2 + 3 * l, sc_ = 3 + 3 * l;
+    conet_status st = CONET_OK;
+    hipError_t e = mark();  // (a)
+    if (e != hipSuccess) return hip_fail(e, "event record");
+    if (!fuse) {
+      st = flush(sa);
+      if (st != CONET_OK) return st;
+      const int nk = last ? 1 : K;  // after the last block only branch 0 feeds the head
+      BlockArgs b = {};
+      base(b);
+      for (int k = 0; k < nk; ++k) branch(b, k, l, k == 0 && fused_prev, in(k), last ? nullptr : out(k));
+      b.llr = last ? llr : nullptr;
+      b.Wh = vec + lay.v_wh;
+      b.bh = vec + lay.v_bh;
+      st = launch(BLOCK_PLAIN, b, nk, sa, nk, "fused block launch");
+      if (st != CONET_OK) return st;
+      e = mark();  // (b)
+      if (e == hipSuccess) e = mark();  // (c)
+      return e == hipSuccess ? CONET_OK : hip_fail(e, "event record");
+    }
+    e = mark();  // (b)
+    if (e != hipSuccess) return hip_fail(e, "event record");
+    if (K > 1) {
+      if (pending && !c.feedback) {  // previous main branch + these supports in one launch
+        BlockArgs b = main_args;
+        for (int k = 1; k < K; ++k) branch(b, k, l, false, in(k), out(k));
+        pending = false;
+        st = launch(BLOCK_PAIR, b, K, sb, K, "paired block launch");
+      } else {
+        st = flush(sb);
+        if (st != CONET_OK) return st;
+        BlockArgs b = {};
+        base(b);
+        for (int k = 1; k < K; ++k) branch(b, k, l, false, in(k), out(k));
+        b.k_off = 1;
+        st = launch(BLOCK_PLAIN, b, K - 1, sb, K - 1, "fused support block launch");
+      }
+    } else {
+      st = flush(sb);
+    }
+    if (st != CONET_OK) return st;
+    // the main branch of this block: run now after the last block, else deferred
+    BlockArgs m = {};
+    base(m);
+    branch(m, 0, l, fused_prev, in(0), last ? nullptr : out(0));
+    for (int k = 1; k < K; ++k) m.sup[k] = out(k);
+    m.gamma = vec + lay.v_gamma[l];
+    m.beta = vec + lay.v_beta[l];
+    m.Wh = vec + lay.v_wh;
+    m.bh = vec + lay.v_bh;
+    m.llr = last ? llr : nullptr;
+    m.fusion_sum = c.fusion_op == CONET_FUSE_SUM;
+    m.feedback = c.feedback && !last;  // the supports' outputs are not read after the last block
+    e = mark();  // (c)
+    if (e != hipSuccess) return hip_fail(e, "event record");
+    if (last) return launch(BLOCK_MAIN, m, 1, sc_, 1, "fused main block launch");
+    main_args = m;
+    pending = true;
+    return CONET_OK;
+  }
+};
 
 // ---------------------------------------------------------------- forward
 conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const Geometry& geo, float* llr,
-                         hipStream_t s, std::vector<float>* calib, hipEvent_t* events, bool save) {
+                         hipStream_t s, std::vector<float>* calib, hipEvent_t* events, bool save, int32_t* units) {
   const conet_config& c = M->cfg;
   const Layout& lay = M->lay;
   const int K = c.branches, L = c.blocks, C = c.channels, Ci = c.in_channels, dt = c.dtype;
@@ -221,7 +280,11 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
   if (calib && !geo.uniform) return fail(CONET_EINVAL, "calibration takes a uniform batch");
 
   int stage = 0;
-  auto mark = [&]() -> hipError_t { return events ? hipEventRecord(events[stage++], s) : hipSuccess; };
+  auto mark = [&]() -> hipError_t {
+    const int i = stage++;
+    return events ? hipEventRecord(events[i], s) : hipSuccess;
+  };
+  auto add_units = [&](int n) { if (units && stage > 0) units[stage - 1] += n; };
 
   // ---- input layer
   if (calib) {
@@ -249,18 +312,21 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
     e = mark();
     if (e == hipSuccess) e = launch_conv(dt, 0, Ci, C, a, n_tiles_in, K, s);
     if (e != hipSuccess) return hip_fail(e, "input layer launch");
+    add_units(K);
   }
 
   int cur = 0;
   bool fused_prev = false;
+  FusedScheduler fsched{M, geo, n_tiles_fb, d_fb, tw_fb, llr, s, units};
   for (int l = 0; l < L; ++l) {
     lvl = l;
     const bool last = (l == L - 1);
     const bool fuse = (c.fuse_mask >> l) & 1u;
     const int nk = (last && !fuse) ? 1 : K;
     if (tw_fb) {
-      conet_status st = launch_fused_block(M, geo, n_tiles_fb, d_fb, tw_fb, l, nk, fuse, fused_prev, last,
-                                           [&](int p, int k) { return actp(p == 0 ? cur : 1 - cur, k); }, llr, s, mark);
+      const int in_p = cur, out_p = 1 - cur;
+      conet_status st = fsched.block(l, fuse, fused_prev, last, [&](int k) { return actp(in_p, k); },
+                                     [&](int k) { return actp(out_p, k); }, mark);
       if (st != CONET_OK) return st;
       cur = 1 - cur;
       fused_prev = fuse;
@@ -313,6 +379,7 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
     e = mark();
     if (e == hipSuccess) e = launch_conv(dt, 1, C, C, a1, n_tiles_blk, nk, s);
     if (e != hipSuccess) return hip_fail(e, "block conv 1 launch");
+    add_units(nk);
 
     ConvArgs a2 = {};
     geom(a2, false);
@@ -343,6 +410,7 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
         e = mark();
         if (e == hipSuccess) e = launch_conv(dt, 2, C, C, as, n_tiles_blk, K - 1, s);
         if (e != hipSuccess) return hip_fail(e, "support conv 2 launch");
+        add_units(K - 1);
       } else {
         e = mark();
       }
@@ -357,12 +425,14 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
       e = mark();
       if (e == hipSuccess) e = launch_conv(dt, 4, C, C, am, n_tiles_blk, 1, s);
       if (e != hipSuccess) return hip_fail(e, "fused conv 2 launch");
+      add_units(1);
     } else {
       for (int k = 0; k < nk; ++k) a2.out[k] = last ? nullptr : actp(1 - cur, k);
       a2.llr = (last && !calib) ? llr : nullptr;
       a2.save_o0 = (save && last) ? ar.lvl_o0[l] : nullptr;
       e = mark();
       if (e == hipSuccess) e = launch_conv(dt, 2, C, C, a2, n_tiles_blk, nk, s);
+      if (e == hipSuccess) add_units(nk);
       if (e == hipSuccess) e = mark();  // no third launch in an unfused block
       if (e != hipSuccess) return hip_fail(e, "block conv 2 launch");
     }
@@ -395,7 +465,8 @@ extern "C" conet_status conet_calibrate(conet_model* M, const float* x, int32_t 
 }
 
 extern "C" conet_status conet_forward_profiled(conet_model* M, const float* x, int32_t B, int32_t T, int32_t F,
-                                               float* llr, float* stage_ms_host, int32_t n_stages, void* stream) {
+                                               float* llr, float* stage_ms_host, int32_t* stage_units_host,
+                                               int32_t n_stages, void* stream) {
   if (!M || !x || !llr || !stage_ms_host) return fail(CONET_EINVAL, "null argument");
   const int ns = 1 + 3 * M->cfg.blocks;
   if (n_stages != ns) return fail(CONET_EINVAL, "expected %d stages, got %d", ns, n_stages);
@@ -410,7 +481,9 @@ extern "C" conet_status conet_forward_profiled(conet_model* M, const float* x, i
   if (st == CONET_OK) {
     Geometry geo;
     geo.uniform = true; geo.B = B; geo.T = T; geo.F = F;
-    st = run_forward(M, M->arena, x, geo, llr, (hipStream_t)stream, nullptr, ev.data());
+    if (stage_units_host)
+      for (int i = 0; i < ns; ++i) stage_units_host[i] = 0;
+    st = run_forward(M, M->arena, x, geo, llr, (hipStream_t)stream, nullptr, ev.data(), false, stage_units_host);
   }
   if (st == CONET_OK) {
     e = hipEventSynchronize(ev[ns]);

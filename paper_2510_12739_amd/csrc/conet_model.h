@@ -94,10 +94,13 @@ conet_status hip_fail(hipError_t e, const char* what);
 
 // Calibration hooks: when `amax` is non-null, run_forward stops after recording the
 // max |operand| of every conv input, in network order, into amax_host (FP8 models).
-// events (optional, 2L+2 entries): recorded on the stream before every launch and after
-// the last one, so stage i took elapsed(events[i], events[i+1]).
+// events (optional, 3L+2 entries): recorded on the stream before every stage and after
+// the last one, so stage i took elapsed(events[i], events[i+1]). units (optional, 3L+1
+// zero-initialised entries) receives per stage the conv-branch executions it ran (one
+// conv of one branch over the batch; a fused block counts two).
 conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const Geometry& geo, float* llr,
-                         hipStream_t s, std::vector<float>* calib, hipEvent_t* events = nullptr, bool save = false);
+                         hipStream_t s, std::vector<float>* calib, hipEvent_t* events = nullptr, bool save = false,
+                         int32_t* units = nullptr);
 
 size_t align256(size_t x);
 size_t n_params(const conet_config& c);
