@@ -255,6 +255,7 @@ conet_status conet_create(const conet_config* cfg, const float* w, size_t n_weig
   M->ws = (uint8_t*)workspace;
   arena_carve(*cfg, cfg->max_res, M->ws + M->lay.arena, M->arena);
   hipError_t e = hipGetDevice(&M->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&M->n_cu, hipDeviceAttributeMultiprocessorCount, M->device);
   if (e != hipSuccess) { delete M; return hip_fail(e, "hipGetDevice"); }
 
   const int K = cfg->branches, L = cfg->blocks, C = cfg->channels, Ci = cfg->in_channels, m = cfg->bits_per_symbol;
@@ -365,5 +366,5 @@ conet_status conet_forward_ragged(conet_model* M, const float* x, int32_t n_slot
 }  // extern "C"
 
 extern "C" int32_t conet_block_tile_width(const conet_model* M) {
-  return M ? block_tile_width(M->cfg.dtype, M->cfg.channels, M->cfg.branches) : 0;
+  return M ? block_tile_width(M->cfg.dtype, M->cfg.channels, M->cfg.branches, false) : 0;
 }

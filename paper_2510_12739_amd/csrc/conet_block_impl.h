@@ -28,9 +28,16 @@ namespace conet {
 // x tile of TROWS x (TWO+4) positions must leave room for two work-groups per CU, and
 // conv 1's accumulators (ceil(14 (TWO+2) / 64) M-tiles per wave) must fit the
 // per-lane register budget.
-template <class A, int C>
+// NARROW: the tile width for batches whose wide tiles cannot fill the GPU (one slot, a
+// serving batch): more, shorter work-groups cut the latency of each launch at the cost of
+// halo recompute. The arithmetic per RE is the same at every width, so results are
+// bit-identical whichever width a batch runs at.
+template <class A, int C, bool NARROW = false>
 constexpr int block_tw() {
-  if constexpr (std::is_same<A, ArithBF16>::value) return C == 64 ? 30 : C == 32 ? 44 : C == 16 ? 60 : 0;
+  if constexpr (std::is_same<A, ArithBF16>::value) {
+    if (C == 64) return NARROW ? 14 : 30;
+    return C == 32 ? 44 : C == 16 ? 60 : 0;
+  }
   return 0;
 }
 
@@ -312,9 +319,8 @@ __global__ void __launch_bounds__(CONV_NW * 64, (block_occ<A, C>())) block_pair_
     block_body<A, C, TWO, false, false, 0>(args, blockIdx.y, lds);
 }
 
-template <class A, int C, bool HEAD>
+template <class A, int C, int TWO, bool HEAD>
 static hipError_t launch_block_h(int kind, BlockArgs& a, dim3 grid, hipStream_t s) {
-  constexpr int TWO = block_tw<A, C>();
   const dim3 blk(CONV_NW * 64);
   if (kind == BLOCK_PLAIN) {
     hipLaunchKernelGGL((block_kernel<A, C, TWO, false, HEAD, 0>), grid, blk, 0, s, a);
@@ -338,35 +344,43 @@ static hipError_t launch_block_h(int kind, BlockArgs& a, dim3 grid, hipStream_t 
   return hipGetLastError();
 }
 
+template <class A, int C, int TWO>
+static hipError_t launch_block_w(int kind, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+  a.tw = TWO;
+  if (a.llr && (a.m < 1 || a.m > 8)) return hipErrorInvalidValue;
+  const dim3 grid(n_tiles, grid_y);
+  return a.llr ? launch_block_h<A, C, TWO, true>(kind, a, grid, s) : launch_block_h<A, C, TWO, false>(kind, a, grid, s);
+}
+
 template <class A, int C>
-static hipError_t launch_block_c(int kind, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
-  constexpr int TWO = block_tw<A, C>();
-  if constexpr (TWO == 0) {
+static hipError_t launch_block_c(int kind, bool narrow, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+  constexpr int TW = block_tw<A, C, false>(), TN = block_tw<A, C, true>();
+  if constexpr (TW == 0) {
     return hipErrorInvalidValue;
+  } else if constexpr (TN != TW) {
+    return narrow ? launch_block_w<A, C, TN>(kind, a, n_tiles, grid_y, s)
+                  : launch_block_w<A, C, TW>(kind, a, n_tiles, grid_y, s);
   } else {
-    a.tw = TWO;
-    if (a.llr && (a.m < 1 || a.m > 8)) return hipErrorInvalidValue;
-    const dim3 grid(n_tiles, grid_y);
-    return a.llr ? launch_block_h<A, C, true>(kind, a, grid, s) : launch_block_h<A, C, false>(kind, a, grid, s);
+    return launch_block_w<A, C, TW>(kind, a, n_tiles, grid_y, s);
   }
 }
 
 template <class A>
-hipError_t launch_block_dtype(int kind, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+hipError_t launch_block_dtype(int kind, bool narrow, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
   switch (C) {
-    case 16: return launch_block_c<A, 16>(kind, a, n_tiles, grid_y, s);
-    case 32: return launch_block_c<A, 32>(kind, a, n_tiles, grid_y, s);
-    case 64: return launch_block_c<A, 64>(kind, a, n_tiles, grid_y, s);
+    case 16: return launch_block_c<A, 16>(kind, narrow, a, n_tiles, grid_y, s);
+    case 32: return launch_block_c<A, 32>(kind, narrow, a, n_tiles, grid_y, s);
+    case 64: return launch_block_c<A, 64>(kind, narrow, a, n_tiles, grid_y, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <class A>
-int block_tile_width_dtype(int C) {
+int block_tile_width_dtype(int C, bool narrow) {
   switch (C) {
-    case 16: return block_tw<A, 16>();
-    case 32: return block_tw<A, 32>();
-    case 64: return block_tw<A, 64>();
+    case 16: return narrow ? block_tw<A, 16, true>() : block_tw<A, 16, false>();
+    case 32: return narrow ? block_tw<A, 32, true>() : block_tw<A, 32, false>();
+    case 64: return narrow ? block_tw<A, 64, true>() : block_tw<A, 64, false>();
   }
   return 0;
 }

@@ -10,8 +10,8 @@ hipError_t launch_conv_fp8(int mode, int cin, int cout, ConvArgs& a, int n_tiles
 int conv_tile_width_f32(int cin, int cout);
 int conv_tile_width_bf16(int cin, int cout);
 int conv_tile_width_fp8(int cin, int cout);
-hipError_t launch_block_bf16(int kind, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
-int block_tile_width_bf16(int C);
+hipError_t launch_block_bf16(int kind, bool narrow, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
+int block_tile_width_bf16(int C, bool narrow);
 
 hipError_t launch_conv(int dtype, int mode, int cin, int cout, ConvArgs& a, int n_tiles, int grid_y, hipStream_t s) {
   switch (dtype) {
@@ -33,13 +33,13 @@ int conv_tile_width(int dtype, int cin, int cout) {
 
 bool conv_supported(int dtype, int cin, int cout) { return conv_tile_width(dtype, cin, cout) > 0; }
 
-int block_tile_width(int dtype, int C, int K) {
+int block_tile_width(int dtype, int C, int K, bool narrow) {
   if (K < 1 || K > BLOCK_KMAX) return 0;
-  return dtype == DT_BF16 ? block_tile_width_bf16(C) : 0;
+  return dtype == DT_BF16 ? block_tile_width_bf16(C, narrow) : 0;
 }
 
-hipError_t launch_block(int dtype, int kind, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
-  if (dtype == DT_BF16) return launch_block_bf16(kind, C, a, n_tiles, grid_y, s);
+hipError_t launch_block(int dtype, int kind, bool narrow, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+  if (dtype == DT_BF16) return launch_block_bf16(kind, narrow, C, a, n_tiles, grid_y, s);
   return hipErrorInvalidValue;
 }
 

@@ -95,14 +95,15 @@ struct BlockArgs {
   int feedback;                    // main: also rewrite sup[k] <- sup[k] + fused output (Example II)
 };
 // Output subcarriers per fused tile; 0 when (dtype, C, K) runs as two conv launches.
+// narrow: the width used when a batch's wide tiles cannot fill the GPU.
 constexpr int BLOCK_KMAX = 4;  // fused main-branch kernels exist for K <= 4
-int block_tile_width(int dtype, int C, int K);
+int block_tile_width(int dtype, int C, int K, bool narrow);
 // kind BLOCK_PLAIN: branches blockIdx.y + k_off, no fusion epilogue (support branches, or
 // every branch of a block without fusion; head on branch 0 when llr is set); BLOCK_MAIN: the
 // main branch of a fused block (k_off = 0, grid.y = 1); BLOCK_PAIR: grid.y = K, blockIdx.y 0
 // is the main branch of block l and 1..K-1 the support branches of block l + 1 (no head).
 enum { BLOCK_PLAIN = 0, BLOCK_MAIN = 1, BLOCK_PAIR = 2 };
-hipError_t launch_block(int dtype, int kind, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
+hipError_t launch_block(int dtype, int kind, bool narrow, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
 
 // ---------------------------------------------------------------- training kernels
 // Filter gradient of a 3x3 conv over a batch: dW[o][tap*CIN + ch] = sum_re dOut[re][o] *

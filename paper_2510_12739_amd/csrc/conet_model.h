@@ -74,6 +74,7 @@ struct conet_model {
   conet::Layout lay;
   uint8_t* ws = nullptr;
   int device = 0;
+  int n_cu = 256;                    // compute units of `device`
   std::vector<float> blob;           // FP32 parameters as given
   std::vector<float> act_scales;     // FP8 static activation scales
   bool scales_set = false;

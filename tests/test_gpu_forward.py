@@ -241,3 +241,21 @@ def test_fusion_variant_training_is_refused():
     blob = make_blob(mc, seed=1)
     with pytest.raises(ConetError, match="EINVAL"):
         Conet(2, 1, 16, 16, 2, blob, dtype="bf16", train=True, fusion="sum")
+
+
+def test_narrow_and_wide_fused_tiles_agree_bitwise():
+    """A batch too small to fill the GPU runs on narrow fused tiles; the per-RE arithmetic is
+    the same at either width, so a slot's LLRs must be bit-identical alone (narrow) and inside
+    a batch large enough for wide tiles."""
+    from paper_2510_12739_amd import Conet
+    K, L, C, Ci, m = 3, 2, 64, 16, 4
+    blob = make_blob(ModelConfig(K, L, C, Ci, m), seed=61, perturb=True)
+    sim = SimConfig(F=3276, n_rx=4, bits_per_symbol=4, seed=62)
+    X = features(sim, 2)
+    Xb = np.concatenate([X] * 4, axis=0)  # 8 slots: 8 x 110 wide tiles x 3 branches fill the GPU
+    model = Conet(K, L, C, Ci, m, blob, dtype="bf16", max_res=8 * 14 * 3276)
+    say("narrow (1 slot) vs wide (8 slots) fused tiles")
+    alone = _run(model, X[1:2])
+    batch = _run(model, Xb)
+    np.testing.assert_array_equal(alone[0], batch[5])
+    model.close()
