@@ -176,6 +176,10 @@ __device__ __forceinline__ void block_body(const BlockArgs& args, int k, uint8_t
         const float z = ps[e] * (float)(a + (Acc)pb[e]) + po[e];
         v[e] = fmaxf(valid ? z : -1.f, 0.f);  // a select, not a branch: z is computed anyway
       }
+    if (args.hid_out[k] && valid && j >= 1 && j <= TWO) {  // training: h of this tile's own REs
+      const int64_t re = td.re_base + (int64_t)t * td.F + f;
+      store_vals(reinterpret_cast<typename A::Hid*>(args.hid_out[k]) + re * C + c0, v, EPL, args.q2[k]);
+    }
     uint8_t* dst = lds + ((t + 1) * HW + j) * PITCH + c0 * (int)sizeof(Op);
     if constexpr (sizeof(Op) == 2) {
 #pragma unroll
@@ -292,7 +296,7 @@ __device__ __forceinline__ void block_body(const BlockArgs& args, int k, uint8_t
       finish_block<A, C, EPL, NSUP>(
           v, re, c0, g, MAIN, [&](Acc* x) { unpack_raw<Act, RawT, EPL>(raw[mt % PD][0], x); },
           [&](int kk, Acc* sv) { unpack_raw<Act, RawT, EPL>(raw[mt % PD][kk], sv); }, MAIN ? args.out[0] : args.out[k],
-          nullptr, head, NSUP + 1, par + P_GAM * C, par + P_BET * C, args.eps, whl, whl + args.m * C, args.llr,
+          (MAIN || k == 0) ? args.save_o0 : nullptr, head, NSUP + 1, par + P_GAM * C, par + P_BET * C, args.eps, whl, whl + args.m * C, args.llr,
           args.m, args.fusion_sum != 0, (MAIN && args.feedback) ? const_cast<void* const*>(args.sup) : nullptr);
     }
     if (mt + PD < MT2) issue(mt + PD);

@@ -124,8 +124,11 @@ struct FusedScheduler {
   }
 
   // Block l of every branch: in(k) / out(k) are the block's input and output buffers.
-  template <class InFn, class OutFn, class MarkFn>
-  conet_status block(int l, bool fuse, bool fused_prev, bool last, InFn in, OutFn out, MarkFn& mark) {
+  // Training forwards also pass hid(k) (where h is saved) and o0 (the main branch's output
+  // before the fusion, or branch 0's before the head); both null otherwise.
+  template <class InFn, class OutFn, class HidFn, class MarkFn>
+  conet_status block(int l, bool fuse, bool fused_prev, bool last, InFn in, OutFn out, HidFn hid, void* o0,
+                     MarkFn& mark) {
     const conet_config& c = M->cfg;
     const Layout& lay = M->lay;
     const int K = c.branches;
@@ -140,8 +143,12 @@ struct FusedScheduler {
       const int nk = last ? 1 : K;  // after the last block only branch 0 feeds the head
       BlockArgs b = {};
       base(b);
-      for (int k = 0; k < nk; ++k) branch(b, k, l, k == 0 && fused_prev, in(k), last ? nullptr : out(k));
+      for (int k = 0; k < nk; ++k) {
+        branch(b, k, l, k == 0 && fused_prev, in(k), last ? nullptr : out(k));
+        b.hid_out[k] = hid(k);
+      }
       b.llr = last ? llr : nullptr;
+      b.save_o0 = last ? o0 : nullptr;  // kept where the head reads branch 0's output
       b.Wh = vec + lay.v_wh;
       b.bh = vec + lay.v_bh;
       st = launch(BLOCK_PLAIN, b, nk, sa, nk, "fused block launch");
@@ -155,7 +162,10 @@ struct FusedScheduler {
     if (K > 1) {
       if (pending && !c.feedback) {  // previous main branch + these supports in one launch
         BlockArgs b = main_args;
-        for (int k = 1; k < K; ++k) branch(b, k, l, false, in(k), out(k));
+        for (int k = 1; k < K; ++k) {
+          branch(b, k, l, false, in(k), out(k));
+          b.hid_out[k] = hid(k);
+        }
         pending = false;
         st = launch(BLOCK_PAIR, b, K, sb, K, "paired block launch");
       } else {
@@ -163,7 +173,10 @@ struct FusedScheduler {
         if (st != CONET_OK) return st;
         BlockArgs b = {};
         base(b);
-        for (int k = 1; k < K; ++k) branch(b, k, l, false, in(k), out(k));
+        for (int k = 1; k < K; ++k) {
+          branch(b, k, l, false, in(k), out(k));
+          b.hid_out[k] = hid(k);
+        }
         b.k_off = 1;
         st = launch(BLOCK_PLAIN, b, K - 1, sb, K - 1, "fused support block launch");
       }
@@ -175,6 +188,8 @@ struct FusedScheduler {
     BlockArgs m = {};
     base(m);
     branch(m, 0, l, fused_prev, in(0), last ? nullptr : out(0));
+    m.hid_out[0] = hid(0);
+    m.save_o0 = o0;
     for (int k = 1; k < K; ++k) m.sup[k] = out(k);
     m.gamma = vec + lay.v_gamma[l];
     m.beta = vec + lay.v_beta[l];
@@ -204,7 +219,7 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
   const int tw_in = conv_tile_width(dt, Ci, C), tw_blk = conv_tile_width(dt, C, C);
   // Inference runs each block as one fused launch when a fused kernel exists for
   // (dtype, C); calibration and the training forward (which stores h) use two convs.
-  int tw_fb = (calib || save) ? 0 : block_tile_width(dt, C, K, false);
+  int tw_fb = calib ? 0 : block_tile_width(dt, C, K, false);
   // a batch whose wide tiles cannot fill the GPU once (a slot, a serving batch) runs on
   // narrow tiles: more, shorter work-groups per launch
   bool narrow = false;
@@ -342,7 +357,9 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
     if (tw_fb) {
       const int in_p = cur, out_p = 1 - cur;
       conet_status st = fsched.block(l, fuse, fused_prev, last, [&](int k) { return actp(in_p, k); },
-                                     [&](int k) { return actp(out_p, k); }, mark);
+                                     [&](int k) { return actp(out_p, k); },
+                                     [&](int k) -> void* { return save ? hidp(k) : nullptr; },
+                                     save ? ar.lvl_o0[l] : nullptr, mark);
       if (st != CONET_OK) return st;
       cur = 1 - cur;
       fused_prev = fuse;

@@ -93,6 +93,10 @@ struct BlockArgs {
   const TileDesc* tiles;           // ragged batches, else null
   int fusion_sum;                  // main: fuse by addition instead of the product
   int feedback;                    // main: also rewrite sup[k] <- sup[k] + fused output (Example II)
+  // training forward (nullable): h of branch k as stored by the two-conv path, and the
+  // main branch's output before the fusion (or branch 0's output before the head)
+  void* hid_out[KMAX_ARGS];
+  void* save_o0;
 };
 // Output subcarriers per fused tile; 0 when (dtype, C, K) runs as two conv launches.
 // narrow: the width used when a batch's wide tiles cannot fill the GPU.
