@@ -435,13 +435,17 @@ __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, col = lane & 15;
   const int c0 = g * EPL;  // first channel owned by this lane
-  const int k = blockIdx.y + args.k_off;
+  const int k0 = blockIdx.y + args.k_off;
 
   int prologue = 0;
-  if (MODE == 1) prologue = args.pre_s[k] ? 1 : 2;
-  stage_tile<A, InT, CIN, TW + 2, 1, PITCH, NT>(lds, reinterpret_cast<const InT*>(args.in[k]), td, T, prologue,
-                                         args.pre_s[k], args.pre_o[k], args.in_qscale[k]);
+  if (MODE == 1) prologue = args.pre_s[k0] ? 1 : 2;
+  stage_tile<A, InT, CIN, TW + 2, 1, PITCH, NT>(lds, reinterpret_cast<const InT*>(args.in[k0]), td, T, prologue,
+                                         args.pre_s[k0], args.pre_o[k0], args.in_qscale[k0]);
   __syncthreads();
+  // the input layer can run every branch from one staged tile (the features are shared)
+  const int nb = (MODE == 0 && args.inner_branches > 1) ? args.inner_branches : 1;
+  for (int kb = 0; kb < nb; ++kb) {
+  const int k = k0 + kb;
   AccV acc[MT][NOT];
   G::run(acc, lds, reinterpret_cast<const i32x4*>(args.wpack[k]), wave, lane);
 
@@ -580,6 +584,7 @@ __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
       if (lane == 0) atomicMax(args.amax + k, amax_bits);
     }
   }
+  }  // branches
 }
 
 // ---------------------------------------------------------------- launch

@@ -341,7 +341,8 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
       a.deq[k] = sc[0];
     }
     e = mark();
-    if (e == hipSuccess) e = launch_conv(dt, 0, Ci, C, a, n_tiles_in, K, s);
+    a.inner_branches = K;  // the features are staged once per tile for all branches
+    if (e == hipSuccess) e = launch_conv(dt, 0, Ci, C, a, n_tiles_in, 1, s);
     if (e != hipSuccess) return hip_fail(e, "input layer launch");
     add_units(K);
   }

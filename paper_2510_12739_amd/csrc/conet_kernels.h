@@ -48,6 +48,8 @@ struct ConvArgs {
   float* part[KMAX_ARGS];          // per-wave per-channel partial sums [gridDim.x * waves][NPART][C]
   int mask_out;                    // mode 6: store dx * (x > 0) (input-layer ReLU adjoint)
   void* save_o0;                   // mode 4 (training): also store the main output before fusion
+  int inner_branches;              // mode 0: run branches k_off .. k_off + n - 1 in every work-group
+                                   // (one staged feature tile; launch with grid.y = 1)
   int fusion_sum;                  // mode 4: fuse by addition instead of the product
   int feedback;                    // mode 4: also rewrite sup[k] <- sup[k] + fused output (Example II)
 };
