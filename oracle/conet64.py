@@ -438,10 +438,11 @@ def grad_blob(p: Dict, X: np.ndarray, dllr: np.ndarray, fuse_mask: Optional[int]
     return pack(g)
 
 
-def calibrate(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None) -> np.ndarray:
-    """Static FP8 activation scales: max |operand| over a calibration batch / 448."""
+def calibrate(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, **variant) -> np.ndarray:
+    """Static FP8 activation scales: max |operand| over a calibration batch / 448.
+    variant: forward()'s fusion / feedback options of the network being calibrated."""
     K, L = p["K"], p["L"]
     amax = np.zeros(1 + 2 * K * L)
     for b in range(X.shape[0]):
-        forward(p, X[b:b + 1], fuse_mask=fuse_mask, calib=amax)
+        forward(p, X[b:b + 1], fuse_mask=fuse_mask, calib=amax, **variant)
     return np.where(amax > 0, amax / E4M3_MAX, 1.0)

@@ -115,6 +115,38 @@ void pack_filter(int dtype, int cin, int cout, const float* W, uint8_t* dst, flo
         }
 }
 
+// FP8 fragments of the 32x32x64 MFMA: [s][ot][lane][32 B] for K step s and output tile ot
+// (32 filter rows). Lane half h = l/32 walks the chunks 3h .. 3h+2 of every tap (16 input
+// channels each) in the sequence u = 0 .. 9*cin/32 - 1 (tap u / (cin/32), chunk
+// cin/32 * h + u % (cin/32)); lane l supplies row r = l%32 with the taps of u = 2s and
+// 2s + 1 (past the end: zero). Row r of tile ot
+// is filter o = ((r/4)%2) (cout/2) + 16 ot + 4 (r/8) + r%4, so that the accumulator rows a
+// lane holds (8j + 4(l/32) + q) are the cout/2 contiguous channels from (l/32) (cout/2).
+// wscale: the per-output-channel scales pack_filter chose.
+size_t packed_bytes32(int cin, int cout) {
+  const int nu = 9 * (cin / 32), ns = (nu + 1) / 2;
+  return (size_t)ns * (cout / 32) * 64 * 32;
+}
+
+void pack_filter32(int cin, int cout, const float* W, const float* wscale, uint8_t* dst) {
+  const int hc = cin / 32, nu = 9 * hc, ns = (nu + 1) / 2, NOT = cout / 32;
+  for (int s = 0; s < ns; ++s)
+    for (int ot = 0; ot < NOT; ++ot)
+      for (int lane = 0; lane < 64; ++lane) {
+        uint8_t* out = dst + (((size_t)s * NOT + ot) * 64 + lane) * 32;
+        memset(out, 0, 32);
+        const int r = lane & 31, h = lane >> 5;
+        const int o = ((r >> 2) & 1) * (cout / 2) + 16 * ot + 4 * (r >> 3) + (r & 3);
+        for (int cc = 0; cc < 2; ++cc) {
+          const int u = 2 * s + cc;
+          if (u >= nu) continue;  // padding taps: weight 0
+          const int tap = u / hc, c0 = (hc * h + u % hc) * 16;
+          for (int e = 0; e < 16; ++e)
+            out[16 * cc + e] = e4m3_bits(W[(((size_t)o * cin + c0 + e) * 3 + tap / 3) * 3 + tap % 3] / wscale[o]);
+        }
+      }
+}
+
 // ---------------------------------------------------------------- layout
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -190,6 +222,13 @@ void plan_layout(const conet_config& c, Layout& lay) {
     for (int l = 0; l < L; ++l) {
       lay.w1[k][l] = off; off = align256(off + packed_bytes(c.dtype, C, C));
       lay.w2[k][l] = off; off = align256(off + packed_bytes(c.dtype, C, C));
+      if (block_uses_mfma32(c.dtype, C)) {
+        lay.w1f[k][l] = off; off = align256(off + packed_bytes32(C, C));
+        lay.w2f[k][l] = off; off = align256(off + packed_bytes32(C, C));
+      } else {
+        lay.w1f[k][l] = lay.w1[k][l];
+        lay.w2f[k][l] = lay.w2[k][l];
+      }
     }
   }
   // FP32 vectors: per branch b_in, wscale_in; per (k,l): s0 o0 b1 s1 o1 b2 ws1 ws2; per l gamma beta; Wh bh
@@ -273,11 +312,15 @@ conet_status conet_create(const conet_config* cfg, const float* w, size_t n_weig
       float* vb = vec + lay.v_blk[k][l];  // s0 o0 b1 s1 o1 b2 ws1 ws2
       memcpy(vb + 0 * C, p, C * 4); p += C;                 // s0
       memcpy(vb + 1 * C, p, C * 4); p += C;                 // o0
-      pack_filter(cfg->dtype, C, C, p, img.data() + lay.w1[k][l], vb + 6 * C); p += (size_t)C * C * 9;
+      pack_filter(cfg->dtype, C, C, p, img.data() + lay.w1[k][l], vb + 6 * C);
+      if (lay.w1f[k][l] != lay.w1[k][l]) pack_filter32(C, C, p, vb + 6 * C, img.data() + lay.w1f[k][l]);
+      p += (size_t)C * C * 9;
       memcpy(vb + 2 * C, p, C * 4); p += C;                 // b1
       memcpy(vb + 3 * C, p, C * 4); p += C;                 // s1
       memcpy(vb + 4 * C, p, C * 4); p += C;                 // o1
-      pack_filter(cfg->dtype, C, C, p, img.data() + lay.w2[k][l], vb + 7 * C); p += (size_t)C * C * 9;
+      pack_filter(cfg->dtype, C, C, p, img.data() + lay.w2[k][l], vb + 7 * C);
+      if (lay.w2f[k][l] != lay.w2[k][l]) pack_filter32(C, C, p, vb + 7 * C, img.data() + lay.w2f[k][l]);
+      p += (size_t)C * C * 9;
       memcpy(vb + 5 * C, p, C * 4); p += C;                 // b2
     }
   }

@@ -1,5 +1,6 @@
-// FP8 instantiations of the 3x3 conv kernels (one translation unit per dtype).
-#include "conet_conv_impl.h"
+// FP8 instantiations of the 3x3 conv kernels and the fused block kernel (one
+// translation unit per dtype).
+#include "conet_block32_impl.h"
 
 namespace conet {
 
@@ -8,5 +9,13 @@ hipError_t launch_conv_fp8(int mode, int cin, int cout, ConvArgs& a, int n_tiles
 }
 
 int conv_tile_width_fp8(int cin, int cout) { return tile_width_dtype<ArithFP8>(cin, cout); }
+
+// 96 channels: the 32x32x64 kernel (its own filter packing); no other width is fused in FP8.
+hipError_t launch_block_fp8(int kind, bool narrow, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+  if (C != B32_C) return hipErrorInvalidValue;
+  return launch_block32(kind, a, n_tiles, grid_y, s);
+}
+
+int block_tile_width_fp8(int C, bool narrow) { return C == B32_C ? B32_TWO : 0; }
 
 }  // namespace conet

@@ -322,8 +322,9 @@ struct Gemm {
 // and applies the per-RE LayerNorm over C; with sup_dst (Example II feedback) it also
 // stores support output + fused activation to sup_dst[kk]. Then either the 1x1 LLR head
 // (head) or a store of the block output to `out` (nullable). A plain block with the head
-// stores its output to save_o0 when that is set (the backward's copy).
-template <class A, int COUT, int EPL, int NSUP, class XFn, class SupFn>
+// stores its output to save_o0 when that is set (the backward's copy). LPR lanes (g =
+// 0..LPR-1, 16 or 32 lanes apart) hold the C channels of one RE.
+template <class A, int COUT, int EPL, int NSUP, class XFn, class SupFn, int LPR = 4>
 __device__ __forceinline__ void finish_block(typename A::Acc (&v)[EPL], int64_t re, int c0, int g, bool main_fused,
                                              XFn x_fn, SupFn sup_fn, void* out, void* save_o0, bool head, int K,
                                              const float* gamma, const float* beta, float eps, const float* Wh,
@@ -358,13 +359,13 @@ __device__ __forceinline__ void finish_block(typename A::Acc (&v)[EPL], int64_t 
     Acc s = 0;
 #pragma unroll
     for (int i = 0; i < EPL; ++i) s += v[i];
-    s += __shfl_xor(s, 16);
+    if (LPR == 4) s += __shfl_xor(s, 16);
     s += __shfl_xor(s, 32);
     const Acc mu = s * ((Acc)1 / (Acc)COUT);
     Acc q = 0;
 #pragma unroll
     for (int i = 0; i < EPL; ++i) { const Acc d = v[i] - mu; q += d * d; }
-    q += __shfl_xor(q, 16);
+    if (LPR == 4) q += __shfl_xor(q, 16);
     q += __shfl_xor(q, 32);
     const Acc rs = (Acc)1 / sqrtf((float)(q * ((Acc)1 / (Acc)COUT) + (Acc)eps));
 #pragma unroll
@@ -393,12 +394,12 @@ __device__ __forceinline__ void finish_block(typename A::Acc (&v)[EPL], int64_t 
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      part[j] += __shfl_xor(part[j], 16);
+      if (LPR == 4) part[j] += __shfl_xor(part[j], 16);
       part[j] += __shfl_xor(part[j], 32);
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-      if (j < m && (j & 3) == g) llr[re * m + j] = (float)(part[j] + (Acc)bh[j]);
+      if (j < m && (j % LPR) == g) llr[re * m + j] = (float)(part[j] + (Acc)bh[j]);
   }
 }
 

@@ -103,8 +103,8 @@ struct FusedScheduler {
     b.b2[k] = vb + 5 * C;
     b.ws1[k] = vb + 6 * C;
     b.ws2[k] = vb + 7 * C;
-    b.w1[k] = ws + lay.w1[k][l];
-    b.w2[k] = ws + lay.w2[k][l];
+    b.w1[k] = ws + lay.w1f[k][l];
+    b.w2[k] = ws + lay.w2f[k][l];
     const float s1 = sc[scale_index(K, L, k, l, 0)], s2 = sc[scale_index(K, L, k, l, 1)];
     b.q1[k] = 1.0f / s1;
     b.deq1[k] = s1;

@@ -103,6 +103,9 @@ struct BlockArgs {
 // Output subcarriers per fused tile; 0 when (dtype, C, K) runs as two conv launches.
 // narrow: the width used when a batch's wide tiles cannot fill the GPU.
 constexpr int BLOCK_KMAX = 4;  // fused main-branch kernels exist for K <= 4
+// FP8 at 96 channels runs the fused block on the 32x32x64 MFMA, which reads filters in
+// its own fragment packing (pack_filter32).
+inline bool block_uses_mfma32(int dtype, int C) { return dtype == DT_FP8 && C == 96; }
 int block_tile_width(int dtype, int C, int K, bool narrow);
 // kind BLOCK_PLAIN: branches blockIdx.y + k_off, no fusion epilogue (support branches, or
 // every branch of a block without fusion; head on branch 0 when llr is set); BLOCK_MAIN: the

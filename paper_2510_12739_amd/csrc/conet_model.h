@@ -17,6 +17,7 @@ constexpr int LMAX = 32;
 struct Layout {
   size_t w_in[KMAX_ARGS];
   size_t w1[KMAX_ARGS][LMAX], w2[KMAX_ARGS][LMAX];
+  size_t w1f[KMAX_ARGS][LMAX], w2f[KMAX_ARGS][LMAX];  // packs the fused block kernel reads
   size_t vec;                      // FP32 vectors
   size_t n_vec;
   size_t v_bin[KMAX_ARGS], v_wsin[KMAX_ARGS];
@@ -111,6 +112,8 @@ size_t train_bytes(const conet_config& c, Layout& lay, size_t base);
 conet_status train_init(conet_model* M);
 void pack_filter(int dtype, int cin, int cout, const float* W, uint8_t* dst, float* wscale);
 size_t packed_bytes(int dtype, int cin, int cout);
+void pack_filter32(int cin, int cout, const float* W, const float* wscale, uint8_t* dst);
+size_t packed_bytes32(int cin, int cout);
 
 // Bytes of activation buffers (plus descriptor capacity) for `max_res` REs.
 size_t arena_bytes(const conet_config& c, int64_t max_res);
