@@ -26,7 +26,7 @@
 
 namespace conet {
 
-constexpr int B32_C = 96, B32_TWO = 14;
+constexpr int B32_C = 96, B32_TWO = 22;
 
 __device__ __forceinline__ i32x8 cat8(const i32x4 (&x)[2]) {
   return __builtin_shufflevector(x[0], x[1], 0, 1, 2, 3, 4, 5, 6, 7);
@@ -37,7 +37,7 @@ __device__ __forceinline__ i32x8 cat8(const i32x4 (&x)[2]) {
 template <int ROWP, int PITCH, int MT>
 struct GemmCore32 {
   static constexpr int C = B32_C, NOT = C / 32, HC = C / 32, NU = 9 * HC, NS = (NU + 1) / 2;
-  static constexpr int ADEPTH = 2, NA = ADEPTH + 1;
+  static constexpr int ADEPTH = 1, NA = ADEPTH + 1;
 
   // LDS byte offset of chunk c (0, 1) of lane half 0 in K step s (half 1: + 16 HC)
   __device__ __forceinline__ static constexpr int b_off(int s, int c) {

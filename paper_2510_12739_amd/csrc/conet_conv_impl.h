@@ -346,6 +346,9 @@ __device__ __forceinline__ void finish_block(typename A::Acc (&v)[EPL], int64_t 
 #pragma unroll
     for (int kk = 1; kk <= NSUP; ++kk) {
       if (kk >= K) break;
+      // two lanes per RE: one support tensor in registers at a time (the compiler would
+      // otherwise issue every support's loads up front)
+      if constexpr (LPR == 2) __builtin_amdgcn_sched_barrier(0);
       Acc sv[EPL];
       sup_fn(kk, sv);
       if (fuse_sum) {

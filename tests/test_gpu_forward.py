@@ -219,7 +219,7 @@ def test_fp8_fused_block_kernel_vs_emulated(K, L, mask, fusion, feedback, T, F, 
     """FP8 at 96 channels runs each block as one fused kernel on the 32x32x64 MFMA (its own
     filter packing and chunk order). Every launch kind (plain, main with and without the
     head, paired main + supports), both fusion operators, feedback and a short slot, on two
-    slots with a ragged tile tail (14-subcarrier tiles), against the FP8-emulating oracle
+    slots with a ragged tile tail, against the FP8-emulating oracle
     (per-case bound, see the module notes) and plain FP64 at the FP8 bounds."""
     from paper_2510_12739_amd import Conet
     C, Ci, m = 96, 32, 8
@@ -232,7 +232,7 @@ def test_fp8_fused_block_kernel_vs_emulated(K, L, mask, fusion, feedback, T, F, 
     scales = o.calibrate(p, X64, **kw)
     say(f"fp8 fused block K={K} L={L} mask={mc.mask:b} {fusion} feedback={feedback} T={T} F={F}")
     model = Conet(K, L, C, Ci, m, blob, dtype="fp8", fuse_mask=mc.mask, fusion=fusion, feedback=feedback)
-    assert model.block_tile_width == 14
+    assert 0 < model.block_tile_width < F  # fused kernel, several tiles per slot
     model.set_act_scales(scales)
     got = _run(model, X)
     emu = o.forward_slots(p, X64, quant=o.Quant("fp8", scales), **kw)
