@@ -221,9 +221,12 @@ def serve_measure(loads=(0.5,), duration_s=1.5, n_streams=3, seed=13):
         out["points"].append({"load": f, "offered_req_s": round(rate, 1), "p50_us": round(st["p50_us"], 1),
                               "p99_us": round(st["p99_us"], 1), "max_us": round(st["max_us"], 1),
                               "res_per_s": round(st["res_per_s"], 1), "requests": int(st["completed"]),
-                              "mean_batch_requests": round(st["mean_batch_requests"], 2)})
-        print(f"[bench] serving load {f:.2f}: {rate:.0f} req/s, p50 {st['p50_us']:.0f} us, p99 {st['p99_us']:.0f} us",
-              file=sys.stderr, flush=True)
+                              "mean_batch_requests": round(st["mean_batch_requests"], 2),
+                              "mean_us": round(st["mean_us"], 1),
+                              "mean_phase_us": {k: round(st["mean_" + k + "_us"], 1)
+                                                for k in ("queue", "prep", "device", "scatter", "h2d", "forward", "d2h")}})
+        print(f"[bench] serving load {f:.2f}: {rate:.0f} req/s, p50 {st['p50_us']:.0f} us, p99 {st['p99_us']:.0f} us, "
+              f"phases {out['points'][-1]['mean_phase_us']}", file=sys.stderr, flush=True)
     srv.close()
     model.close()
     return out

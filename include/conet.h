@@ -237,6 +237,14 @@ typedef struct {
   double mean_batch_requests;
   uint64_t completed, rejected, batches;
   int64_t lane_res;                        /* REs one lane admits                          */
+  /* where the mean latency goes, per completed request: waiting in the queue; forming its
+   * batch (feature packing, enqueueing copies and kernels); enqueued -> the batch's
+   * completion seen on the host (H2D, forward, D2H, plus the wait's wake-up); scattering
+   * the LLRs to the callers' buffers */
+  double mean_queue_us, mean_prep_us, mean_device_us, mean_scatter_us;
+  /* GPU-timed parts of the device phase (stream events): the feature copy, the forward,
+   * the LLR copy of the request's batch */
+  double mean_h2d_us, mean_forward_us, mean_d2h_us;
 } conet_serve_stats;
 
 /* Start a server on `model` (which must outlive it): n_streams lanes of up to

@@ -53,7 +53,9 @@ class conet_serve_stats(ctypes.Structure):
     _fields_ = [("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double), ("mean_us", ctypes.c_double),
                 ("max_us", ctypes.c_double), ("res_per_s", ctypes.c_double), ("mean_batch_requests", ctypes.c_double),
                 ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64), ("batches", ctypes.c_uint64),
-                ("lane_res", ctypes.c_int64)]
+                ("lane_res", ctypes.c_int64), ("mean_queue_us", ctypes.c_double), ("mean_prep_us", ctypes.c_double),
+                ("mean_device_us", ctypes.c_double), ("mean_scatter_us", ctypes.c_double),
+                ("mean_h2d_us", ctypes.c_double), ("mean_forward_us", ctypes.c_double), ("mean_d2h_us", ctypes.c_double)]
 
 
 _lib = None

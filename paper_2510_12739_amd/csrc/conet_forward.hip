@@ -273,7 +273,12 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
     if (h.size() > ar.max_tiles) return fail(CONET_ESHAPE, "ragged batch needs %zu tiles, capacity %zu", h.size(), ar.max_tiles);
     if (n_re > ar.max_res) return fail(CONET_ESHAPE, "ragged batch has %lld REs, buffers hold %lld", (long long)n_re, (long long)ar.max_res);
     TileDesc* dt_dev = ar.tiles;
-    e = hipMemcpyAsync(dt_dev, h.data(), h.size() * sizeof(TileDesc), hipMemcpyHostToDevice, s);
+    const TileDesc* src = h.data();
+    if (geo.tiles_pin && h.size() <= geo.tiles_pin_cap) {
+      std::memcpy(geo.tiles_pin, h.data(), h.size() * sizeof(TileDesc));
+      src = geo.tiles_pin;
+    }
+    e = hipMemcpyAsync(dt_dev, src, h.size() * sizeof(TileDesc), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "tile descriptor upload");
     d_blk = dt_dev + o_blk;
     d_in = dt_dev + o_in;

@@ -66,6 +66,10 @@ struct Geometry {
   int B = 0, T = 0, F = 0;                 // uniform
   int n_slots = 0;                         // ragged
   const int32_t* F_host = nullptr;
+  // ragged: pinned host staging for the tile list (capacity in descriptors), so that its
+  // upload is an asynchronous copy; null: a pageable copy
+  TileDesc* tiles_pin = nullptr;
+  size_t tiles_pin_cap = 0;
 };
 
 }  // namespace conet

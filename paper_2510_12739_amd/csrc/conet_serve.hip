@@ -9,7 +9,9 @@
 // D2H copy on the lane's stream. Lanes run on separate streams, so a batch formed
 // while others are on the GPU overlaps with them on the device. Each lane has a
 // completion thread that waits for its batch, scatters the LLRs to the callers'
-// buffers and releases the waiters.
+// buffers and releases the waiters. Packing and scattering are host memory copies on
+// the critical path of every request; a small pool of helper threads splits each over
+// the batch's REs.
 //
 // Every slot is computed in tiles that never cross slot boundaries and each kernel's
 // arithmetic per RE does not depend on the other slots, so a request's LLRs are
@@ -22,6 +24,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -33,6 +36,82 @@
 namespace conet {
 
 using clk = std::chrono::steady_clock;
+
+constexpr int SERVE_COPY_HELPERS = 3;  // host copies run on the calling thread + 3 helpers
+
+// The first mq of every m LLRs of n REs (a request's modulation below the head width).
+template <int MQ>
+static void copy_llr_fixed(float* dst, const float* src, int64_t n, int m) {
+  for (int64_t r = 0; r < n; ++r)
+    for (int j = 0; j < MQ; ++j) dst[r * MQ + j] = src[r * m + j];
+}
+static void copy_llr(float* dst, const float* src, int64_t n, int m, int mq) {
+  switch (mq) {
+    case 2: copy_llr_fixed<2>(dst, src, n, m); return;
+    case 4: copy_llr_fixed<4>(dst, src, n, m); return;
+    default:
+      for (int64_t r = 0; r < n; ++r)
+        for (int j = 0; j < mq; ++j) dst[r * mq + j] = src[r * m + j];
+  }
+}
+
+// Fixed helper threads for the batch's host copies: run(fn) calls fn(part, parts) for
+// part 0 on the calling thread and parts 1.. on the helpers, and returns when all are
+// done. One job at a time (callers from different threads take turns).
+class CopyPool {
+ public:
+  explicit CopyPool(int helpers) {
+    for (int i = 0; i < helpers; ++i) th_.emplace_back([this, i] { loop(i + 1); });
+  }
+  ~CopyPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+  int parts() const { return (int)th_.size() + 1; }
+  void run(const std::function<void(int, int)>& fn) {
+    std::lock_guard<std::mutex> job(job_mu_);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      job_ = &fn;
+      pending_ = (int)th_.size();
+      ++gen_;
+    }
+    cv_.notify_all();
+    fn(0, parts());
+    std::unique_lock<std::mutex> lk(mu_);
+    cv_done_.wait(lk, [&] { return pending_ == 0; });
+    job_ = nullptr;
+  }
+
+ private:
+  void loop(int part) {
+    uint64_t seen = 0;
+    for (;;) {
+      const std::function<void(int, int)>* f;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+        f = job_;
+      }
+      (*f)(part, parts());
+      std::lock_guard<std::mutex> lk(mu_);
+      if (--pending_ == 0) cv_done_.notify_one();
+    }
+  }
+  std::vector<std::thread> th_;
+  std::mutex mu_, job_mu_;
+  std::condition_variable cv_, cv_done_;
+  const std::function<void(int, int)>* job_ = nullptr;
+  int pending_ = 0;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
 
 struct Pending {
   conet_request req;
@@ -49,15 +128,18 @@ struct Done {
 
 struct Lane {
   hipStream_t stream = nullptr;
-  hipEvent_t ev = nullptr;
+  hipEvent_t ev = nullptr;         // end of the batch (after the D2H copy)
+  hipEvent_t ev_h2d = nullptr, ev_fwd = nullptr, ev_d2h = nullptr;  // starts of the three steps
   uint8_t* dev = nullptr;          // arena + x + llr
   Arena arena;
   float* x_dev = nullptr;          // [max_res][C_in]
   float* llr_dev = nullptr;        // [max_res][m]
   float* x_pin = nullptr;          // pinned staging
   float* llr_pin = nullptr;
+  TileDesc* tiles_pin = nullptr;   // pinned staging of the batch's tile list
   std::vector<Pending> batch;      // requests of the batch in flight
   std::vector<int32_t> F;          // widths of the batch's slots
+  clk::time_point t_formed, t_enqueued;  // batch taken from the queue; all its GPU work enqueued
   bool busy = false;               // a batch is assigned to the lane
   bool launched = false;           // ... and its completion event is recorded
   std::thread waiter;
@@ -76,6 +158,7 @@ struct conet_server {
   std::condition_variable cv_lane;    // a lane got work
   std::condition_variable cv_done;    // a request completed
   std::deque<conet::Pending> queue;
+  conet::CopyPool* pool = nullptr;    // helpers for packing and scattering
   std::unordered_map<uint64_t, conet::Done> results;
   uint64_t next_ticket = 1;
   bool stop = false;
@@ -85,6 +168,8 @@ struct conet_server {
   std::vector<double> lat_us;
   uint64_t completed = 0, rejected = 0, batches = 0, batched_requests = 0;
   int64_t res_done = 0;
+  double sum_queue_us = 0, sum_prep_us = 0, sum_device_us = 0, sum_scatter_us = 0;
+  double sum_h2d_us = 0, sum_fwd_us = 0, sum_d2h_us = 0;
   bool have_first = false;
   conet::clk::time_point t_first, t_last;
   conet_status async_error = CONET_OK;
@@ -94,7 +179,7 @@ namespace conet {
 
 static void lane_wait_loop(conet_server* S, int li) {
   Lane& ln = S->lanes[li];
-  hipSetDevice(S->device);
+  (void)hipSetDevice(S->device);
   const int m = S->M->cfg.bits_per_symbol;
   for (;;) {
     {
@@ -104,24 +189,36 @@ static void lane_wait_loop(conet_server* S, int li) {
     }
     hipError_t e = hipEventSynchronize(ln.ev);
     const auto t_done_gpu = clk::now();
-    // scatter LLRs: slot s's REs start at its offset; the head has m outputs per RE
-    int64_t off = 0;
-    for (auto& p : ln.batch) {
-      const int mq = p.req.bits_per_symbol;
-      if (e == hipSuccess) {
-        const float* src = ln.llr_pin + off * m;
-        float* dst = p.req.llr_host;
-        if (mq == m) {
-          memcpy(dst, src, sizeof(float) * p.n_re * m);
-        } else {
-          for (int64_t r = 0; r < p.n_re; ++r)
-            for (int j = 0; j < mq; ++j) dst[r * mq + j] = src[r * m + j];
+    float ms_h2d = 0.f, ms_fwd = 0.f, ms_d2h = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms_h2d, ln.ev_h2d, ln.ev_fwd);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms_fwd, ln.ev_fwd, ln.ev_d2h);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms_d2h, ln.ev_d2h, ln.ev);
+    auto us = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double, std::micro>(b - a).count(); };
+    // scatter LLRs: slot s's REs start at its offset; the head has m outputs per RE. Each
+    // part copies its share [r0, r1) of the batch's REs.
+    if (e == hipSuccess) {
+      int64_t total = 0;
+      for (auto& p : ln.batch) total += p.n_re;
+      S->pool->run([&](int part, int parts) {
+        const int64_t r0 = total * part / parts, r1 = total * (part + 1) / parts;
+        int64_t off = 0;
+        for (auto& p : ln.batch) {
+          const int64_t a = std::max(r0, off), b = std::min(r1, off + p.n_re);
+          if (a < b) {
+            const int mq = p.req.bits_per_symbol;
+            const float* src = ln.llr_pin + a * m;
+            float* dst = p.req.llr_host + (a - off) * mq;
+            if (mq == m) {
+              memcpy(dst, src, sizeof(float) * (b - a) * m);
+            } else {
+              copy_llr(dst, src, b - a, m, mq);
+            }
+          }
+          off += p.n_re;
         }
-      }
-      off += p.n_re;
+      });
     }
     const auto t_done = clk::now();
-    (void)t_done_gpu;
     {
       std::lock_guard<std::mutex> lk(S->mu);
       for (auto& p : ln.batch) {
@@ -133,6 +230,13 @@ static void lane_wait_loop(conet_server* S, int li) {
           S->lat_us.push_back(d.latency_us);
           ++S->completed;
           S->res_done += p.n_re;
+          S->sum_queue_us += us(p.t_submit, ln.t_formed);
+          S->sum_prep_us += us(ln.t_formed, ln.t_enqueued);
+          S->sum_device_us += us(ln.t_enqueued, t_done_gpu);
+          S->sum_scatter_us += us(t_done_gpu, t_done);
+          S->sum_h2d_us += 1e3 * ms_h2d;
+          S->sum_fwd_us += 1e3 * ms_fwd;
+          S->sum_d2h_us += 1e3 * ms_d2h;
         }
       }
       if (e != hipSuccess) S->async_error = CONET_EDEVICE;
@@ -159,29 +263,39 @@ static void launch_batch(conet_server* S, int li, std::unique_lock<std::mutex>& 
     S->queue.pop_front();
   }
   if (ln.batch.empty()) return;
+  ln.t_formed = clk::now();
   ln.busy = true;
   ++S->batches;
   S->batched_requests += ln.batch.size();
   lk.unlock();
-  // pack features (zero-pad antennas beyond the request's) into pinned staging
+  // pack features (zero-pad antennas beyond the request's) into pinned staging, each part
+  // its share [r0, r1) of the batch's REs
   const int Ci = c.in_channels, T = ln.batch[0].req.T;
-  int64_t off = 0;
-  for (auto& p : ln.batch) {
-    const int F = 12 * p.req.n_prb, ci = 4 * p.req.n_rx;
-    ln.F.push_back(F);
-    float* dst = ln.x_pin + off * Ci;
-    const float* src = p.req.x_host;
-    if (ci == Ci) {
-      memcpy(dst, src, sizeof(float) * p.n_re * Ci);
-    } else {
-      for (int64_t r = 0; r < p.n_re; ++r) {
-        memcpy(dst + r * Ci, src + r * ci, sizeof(float) * ci);
-        memset(dst + r * Ci + ci, 0, sizeof(float) * (Ci - ci));
+  for (auto& p : ln.batch) ln.F.push_back(12 * p.req.n_prb);
+  S->pool->run([&](int part, int parts) {
+    const int64_t r0 = res * part / parts, r1 = res * (part + 1) / parts;
+    int64_t off = 0;
+    for (auto& p : ln.batch) {
+      const int64_t a = std::max(r0, off), b = std::min(r1, off + p.n_re);
+      if (a < b) {
+        const int ci = 4 * p.req.n_rx;
+        float* dst = ln.x_pin + a * Ci;
+        const float* src = p.req.x_host + (a - off) * ci;
+        if (ci == Ci) {
+          memcpy(dst, src, sizeof(float) * (b - a) * Ci);
+        } else {
+          for (int64_t r = 0; r < b - a; ++r) {
+            memcpy(dst + r * Ci, src + r * ci, sizeof(float) * ci);
+            memset(dst + r * Ci + ci, 0, sizeof(float) * (Ci - ci));
+          }
+        }
       }
+      off += p.n_re;
     }
-    off += p.n_re;
-  }
-  hipError_t e = hipMemcpyAsync(ln.x_dev, ln.x_pin, sizeof(float) * res * Ci, hipMemcpyHostToDevice, ln.stream);
+  });
+  hipError_t e = hipEventRecord(ln.ev_h2d, ln.stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(ln.x_dev, ln.x_pin, sizeof(float) * res * Ci, hipMemcpyHostToDevice, ln.stream);
+  if (e == hipSuccess) e = hipEventRecord(ln.ev_fwd, ln.stream);
   conet_status st = e == hipSuccess ? CONET_OK : hip_fail(e, "serving H2D");
   if (st == CONET_OK) {
     Geometry geo;
@@ -189,14 +303,18 @@ static void launch_batch(conet_server* S, int li, std::unique_lock<std::mutex>& 
     geo.T = T;
     geo.n_slots = (int)ln.F.size();
     geo.F_host = ln.F.data();
+    geo.tiles_pin = ln.tiles_pin;
+    geo.tiles_pin_cap = ln.arena.max_tiles;
     st = run_forward(S->M, ln.arena, ln.x_dev, geo, ln.llr_dev, ln.stream, nullptr);
   }
   if (st == CONET_OK) {
-    e = hipMemcpyAsync(ln.llr_pin, ln.llr_dev, sizeof(float) * res * c.bits_per_symbol, hipMemcpyDeviceToHost,
+    e = hipEventRecord(ln.ev_d2h, ln.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ln.llr_pin, ln.llr_dev, sizeof(float) * res * c.bits_per_symbol, hipMemcpyDeviceToHost,
                        ln.stream);
     if (e == hipSuccess) e = hipEventRecord(ln.ev, ln.stream);
     if (e != hipSuccess) st = hip_fail(e, "serving D2H");
   }
+  ln.t_enqueued = clk::now();
   lk.lock();
   if (st != CONET_OK) {  // fail the whole batch; the lane stays usable
     for (auto& p : ln.batch) {
@@ -214,7 +332,7 @@ static void launch_batch(conet_server* S, int li, std::unique_lock<std::mutex>& 
 }
 
 static void scheduler_loop(conet_server* S) {
-  hipSetDevice(S->device);
+  (void)hipSetDevice(S->device);
   std::unique_lock<std::mutex> lk(S->mu);
   for (;;) {
     S->cv_sched.wait(lk, [&] {
@@ -264,28 +382,36 @@ conet_status conet_serve_create(conet_model* M, size_t mem_budget_bytes, int32_t
   hipError_t e = hipSetDevice(M->device);
   for (auto& ln : S->lanes) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&ln.ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&ln.ev);
+    if (e == hipSuccess) e = hipEventCreate(&ln.ev_h2d);
+    if (e == hipSuccess) e = hipEventCreate(&ln.ev_fwd);
+    if (e == hipSuccess) e = hipEventCreate(&ln.ev_d2h);
     if (e == hipSuccess) e = hipMalloc(&ln.dev, lane_bytes(c, lane_res));
     if (e == hipSuccess) e = hipHostMalloc(&ln.x_pin, sizeof(float) * lane_res * c.in_channels, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(&ln.llr_pin, sizeof(float) * lane_res * c.bits_per_symbol, hipHostMallocDefault);
     if (e != hipSuccess) break;
     auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
     arena_carve(c, lane_res, ln.dev, ln.arena);
+    e = hipHostMalloc(&ln.tiles_pin, sizeof(TileDesc) * ln.arena.max_tiles, hipHostMallocDefault);
+    if (e != hipSuccess) break;
     ln.x_dev = reinterpret_cast<float*>(ln.dev + a256(arena_bytes(c, lane_res)));
     ln.llr_dev = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(ln.x_dev) + a256(sizeof(float) * lane_res * c.in_channels));
   }
   if (e != hipSuccess) {
     conet_status st = hip_fail(e, "serving lane set-up");
     for (auto& ln : S->lanes) {
-      if (ln.stream) hipStreamDestroy(ln.stream);
-      if (ln.ev) hipEventDestroy(ln.ev);
-      if (ln.dev) hipFree(ln.dev);
-      if (ln.x_pin) hipHostFree(ln.x_pin);
-      if (ln.llr_pin) hipHostFree(ln.llr_pin);
+      if (ln.stream) (void)hipStreamDestroy(ln.stream);
+      for (hipEvent_t v : {ln.ev, ln.ev_h2d, ln.ev_fwd, ln.ev_d2h})
+        if (v) (void)hipEventDestroy(v);
+      if (ln.dev) (void)hipFree(ln.dev);
+      if (ln.x_pin) (void)hipHostFree(ln.x_pin);
+      if (ln.llr_pin) (void)hipHostFree(ln.llr_pin);
+      if (ln.tiles_pin) (void)hipHostFree(ln.tiles_pin);
     }
     delete S;
     return st;
   }
+  S->pool = new CopyPool(SERVE_COPY_HELPERS);
   for (int i = 0; i < n_streams; ++i) S->lanes[i].waiter = std::thread(lane_wait_loop, S, i);
   S->scheduler = std::thread(scheduler_loop, S);
   *out = S;
@@ -364,6 +490,14 @@ conet_status conet_serve_get_stats(conet_server* S, conet_serve_stats* st) {
     st->mean_us = s / v.size();
     const double span = std::chrono::duration<double>(S->t_last - S->t_first).count();
     st->res_per_s = span > 0 ? S->res_done / span : 0.0;
+    const double n = (double)S->completed;
+    st->mean_queue_us = S->sum_queue_us / n;
+    st->mean_prep_us = S->sum_prep_us / n;
+    st->mean_device_us = S->sum_device_us / n;
+    st->mean_scatter_us = S->sum_scatter_us / n;
+    st->mean_h2d_us = S->sum_h2d_us / n;
+    st->mean_forward_us = S->sum_fwd_us / n;
+    st->mean_d2h_us = S->sum_d2h_us / n;
   }
   return S->async_error;
 }
@@ -374,6 +508,8 @@ conet_status conet_serve_reset_stats(conet_server* S) {
   S->lat_us.clear();
   S->completed = S->rejected = S->batches = S->batched_requests = 0;
   S->res_done = 0;
+  S->sum_queue_us = S->sum_prep_us = S->sum_device_us = S->sum_scatter_us = 0;
+  S->sum_h2d_us = S->sum_fwd_us = S->sum_d2h_us = 0;
   S->have_first = false;
   return CONET_OK;
 }
@@ -407,13 +543,15 @@ conet_status conet_serve_destroy(conet_server* S) {
   if (S->scheduler.joinable()) S->scheduler.join();
   for (auto& ln : S->lanes) if (ln.waiter.joinable()) ln.waiter.join();
   for (auto& ln : S->lanes) {
-    hipStreamSynchronize(ln.stream);
-    hipStreamDestroy(ln.stream);
-    hipEventDestroy(ln.ev);
-    hipFree(ln.dev);
-    hipHostFree(ln.x_pin);
-    hipHostFree(ln.llr_pin);
+    (void)hipStreamSynchronize(ln.stream);
+    (void)hipStreamDestroy(ln.stream);
+    for (hipEvent_t v : {ln.ev, ln.ev_h2d, ln.ev_fwd, ln.ev_d2h}) (void)hipEventDestroy(v);
+    (void)hipFree(ln.dev);
+    (void)hipHostFree(ln.x_pin);
+    (void)hipHostFree(ln.llr_pin);
+    (void)hipHostFree(ln.tiles_pin);
   }
+  delete S->pool;
   delete S;
   return CONET_OK;
 }
