@@ -95,11 +95,14 @@ def load_traffic(kernel: str, workload: str, dtype: str):
 
 def kernel_kind(name: str):
     """Roofline kind of a kernel dispatch, from the demangled name rocprofv3 reports."""
-    if "block_pair_kernel<" in name:
+    if "block_pair_kernel<" in name or "block32_pair_kernel<" in name:
         return "block_fused_pair"
-    if "block_kernel<" in name:
+    if "block_kernel<" in name:  # <Arith, C, TWO, MAIN, HEAD, NSUP>
         args = name.split("block_kernel<", 1)[1].split(">", 1)[0].split(",")
         return "block_fused_main" if args[3].strip() == "true" else "block_fused_supports"
+    if "block32_kernel<" in name:  # FP8, 96 channels: <TWO, MAIN, HEAD, NSUP>
+        args = name.split("block32_kernel<", 1)[1].split(">", 1)[0].split(",")
+        return "block_fused_main" if args[1].strip() == "true" else "block_fused_supports"
     if "conv3x3_kernel<" in name:
         mode = name.split("conv3x3_kernel<", 1)[1].split(",")[1].strip()
         return {"0": "input_layer", "1": "block_conv1", "2": "block_conv2_supports",
