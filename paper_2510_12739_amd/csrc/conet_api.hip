@@ -115,34 +115,48 @@ void pack_filter(int dtype, int cin, int cout, const float* W, uint8_t* dst, flo
         }
 }
 
-// FP8 fragments of the 32x32x64 MFMA: [s][ot][lane][32 B] for K step s and output tile ot
-// (32 filter rows). Lane half h = l/32 walks the chunks 3h .. 3h+2 of every tap (16 input
-// channels each) in the sequence u = 0 .. 9*cin/32 - 1 (tap u / (cin/32), chunk
-// cin/32 * h + u % (cin/32)); lane l supplies row r = l%32 with the taps of u = 2s and
-// 2s + 1 (past the end: zero). Row r of tile ot
-// is filter o = ((r/4)%2) (cout/2) + 16 ot + 4 (r/8) + r%4, so that the accumulator rows a
-// lane holds (8j + 4(l/32) + q) are the cout/2 contiguous channels from (l/32) (cout/2).
-// wscale: the per-output-channel scales pack_filter chose.
-size_t packed_bytes32(int cin, int cout) {
-  const int nu = 9 * (cin / 32), ns = (nu + 1) / 2;
-  return (size_t)ns * (cout / 32) * 64 * 32;
+// Fragments of the 32x32 MFMAs: [s][ot][lane][CPL x 16 B] for K step s and output tile ot
+// (32 filter rows), with CPL = 2 chunks of 16 channels per lane per step (FP8, 32x32x64) or
+// 1 chunk of 8 channels (BF16, 32x32x16). Lane half h = l/32 walks the hc = cin/2 / (channels
+// per chunk) chunks of channels h*cin/2 .. (h+1)*cin/2 - 1 of every tap in the sequence
+// u = 0 .. 9 hc - 1 (tap u / hc, chunk hc h + u % hc); lane l supplies row r = l%32 with the
+// chunks u = CPL s .. CPL s + CPL - 1 (past the end: zero). Row r of tile ot is filter
+// o = ((r/4)%2) (cout/2) + 16 ot + 4 (r/8) + r%4, so that the accumulator rows a lane holds
+// (8j + 4(l/32) + q) are the cout/2 contiguous channels from (l/32) (cout/2).
+// wscale: the per-output-channel scales pack_filter chose (FP8; unused for BF16).
+struct Frag32 { int cpl, chc, esize; };
+static Frag32 frag32(int dtype) { return dtype == DT_FP8 ? Frag32{2, 16, 1} : Frag32{1, 8, 2}; }
+
+size_t packed_bytes32(int dtype, int cin, int cout) {
+  const Frag32 f = frag32(dtype);
+  const int nu = 9 * (cin / 2 / f.chc), ns = (nu + f.cpl - 1) / f.cpl;
+  return (size_t)ns * (cout / 32) * 64 * 16 * f.cpl;
 }
 
-void pack_filter32(int cin, int cout, const float* W, const float* wscale, uint8_t* dst) {
-  const int hc = cin / 32, nu = 9 * hc, ns = (nu + 1) / 2, NOT = cout / 32;
+void pack_filter32(int dtype, int cin, int cout, const float* W, const float* wscale, uint8_t* dst) {
+  const Frag32 f = frag32(dtype);
+  const int hc = cin / 2 / f.chc, nu = 9 * hc, ns = (nu + f.cpl - 1) / f.cpl, NOT = cout / 32;
+  const int lane_bytes = 16 * f.cpl;
   for (int s = 0; s < ns; ++s)
     for (int ot = 0; ot < NOT; ++ot)
       for (int lane = 0; lane < 64; ++lane) {
-        uint8_t* out = dst + (((size_t)s * NOT + ot) * 64 + lane) * 32;
-        memset(out, 0, 32);
+        uint8_t* out = dst + (((size_t)s * NOT + ot) * 64 + lane) * lane_bytes;
+        memset(out, 0, lane_bytes);
         const int r = lane & 31, h = lane >> 5;
         const int o = ((r >> 2) & 1) * (cout / 2) + 16 * ot + 4 * (r >> 3) + (r & 3);
-        for (int cc = 0; cc < 2; ++cc) {
-          const int u = 2 * s + cc;
+        for (int cc = 0; cc < f.cpl; ++cc) {
+          const int u = f.cpl * s + cc;
           if (u >= nu) continue;  // padding taps: weight 0
-          const int tap = u / hc, c0 = (hc * h + u % hc) * 16;
-          for (int e = 0; e < 16; ++e)
-            out[16 * cc + e] = e4m3_bits(W[(((size_t)o * cin + c0 + e) * 3 + tap / 3) * 3 + tap % 3] / wscale[o]);
+          const int tap = u / hc, c0 = (hc * h + u % hc) * f.chc;
+          for (int e = 0; e < f.chc; ++e) {
+            const float w = W[(((size_t)o * cin + c0 + e) * 3 + tap / 3) * 3 + tap % 3];
+            if (dtype == DT_FP8) {
+              out[16 * cc + e] = e4m3_bits(w / wscale[o]);
+            } else {
+              const uint16_t bb = bf16_bits(w);
+              memcpy(out + 16 * cc + 2 * e, &bb, 2);
+            }
+          }
         }
       }
 }
@@ -222,9 +236,9 @@ void plan_layout(const conet_config& c, Layout& lay) {
     for (int l = 0; l < L; ++l) {
       lay.w1[k][l] = off; off = align256(off + packed_bytes(c.dtype, C, C));
       lay.w2[k][l] = off; off = align256(off + packed_bytes(c.dtype, C, C));
-      if (block_uses_mfma32(c.dtype, C)) {
-        lay.w1f[k][l] = off; off = align256(off + packed_bytes32(C, C));
-        lay.w2f[k][l] = off; off = align256(off + packed_bytes32(C, C));
+      if (block_uses_mfma32(c.dtype, C) && !c.train) {
+        lay.w1f[k][l] = off; off = align256(off + packed_bytes32(c.dtype, C, C));
+        lay.w2f[k][l] = off; off = align256(off + packed_bytes32(c.dtype, C, C));
       } else {
         lay.w1f[k][l] = lay.w1[k][l];
         lay.w2f[k][l] = lay.w2[k][l];
@@ -313,13 +327,13 @@ conet_status conet_create(const conet_config* cfg, const float* w, size_t n_weig
       memcpy(vb + 0 * C, p, C * 4); p += C;                 // s0
       memcpy(vb + 1 * C, p, C * 4); p += C;                 // o0
       pack_filter(cfg->dtype, C, C, p, img.data() + lay.w1[k][l], vb + 6 * C);
-      if (lay.w1f[k][l] != lay.w1[k][l]) pack_filter32(C, C, p, vb + 6 * C, img.data() + lay.w1f[k][l]);
+      if (lay.w1f[k][l] != lay.w1[k][l]) pack_filter32(cfg->dtype, C, C, p, vb + 6 * C, img.data() + lay.w1f[k][l]);
       p += (size_t)C * C * 9;
       memcpy(vb + 2 * C, p, C * 4); p += C;                 // b1
       memcpy(vb + 3 * C, p, C * 4); p += C;                 // s1
       memcpy(vb + 4 * C, p, C * 4); p += C;                 // o1
       pack_filter(cfg->dtype, C, C, p, img.data() + lay.w2[k][l], vb + 7 * C);
-      if (lay.w2f[k][l] != lay.w2[k][l]) pack_filter32(C, C, p, vb + 7 * C, img.data() + lay.w2f[k][l]);
+      if (lay.w2f[k][l] != lay.w2[k][l]) pack_filter32(cfg->dtype, C, C, p, vb + 7 * C, img.data() + lay.w2f[k][l]);
       p += (size_t)C * C * 9;
       memcpy(vb + 5 * C, p, C * 4); p += C;                 // b2
     }
@@ -409,5 +423,5 @@ conet_status conet_forward_ragged(conet_model* M, const float* x, int32_t n_slot
 }  // extern "C"
 
 extern "C" int32_t conet_block_tile_width(const conet_model* M) {
-  return M ? block_tile_width(M->cfg.dtype, M->cfg.channels, M->cfg.branches, false) : 0;
+  return M ? block_tile_width(M->cfg.dtype, M->cfg.channels, M->cfg.branches, false, M->cfg.train != 0) : 0;
 }

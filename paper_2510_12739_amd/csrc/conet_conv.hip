@@ -35,8 +35,9 @@ int conv_tile_width(int dtype, int cin, int cout) {
 
 bool conv_supported(int dtype, int cin, int cout) { return conv_tile_width(dtype, cin, cout) > 0; }
 
-int block_tile_width(int dtype, int C, int K, bool narrow) {
+int block_tile_width(int dtype, int C, int K, bool narrow, bool train) {
   if (K < 1 || K > BLOCK_KMAX) return 0;
+  if (train && block_uses_mfma32(dtype, C)) return 0;
   switch (dtype) {
     case DT_BF16: return block_tile_width_bf16(C, narrow);
     case DT_FP8: return block_tile_width_fp8(C, narrow);

@@ -13,9 +13,9 @@ int conv_tile_width_fp8(int cin, int cout) { return tile_width_dtype<ArithFP8>(c
 // 96 channels: the 32x32x64 kernel (its own filter packing); no other width is fused in FP8.
 hipError_t launch_block_fp8(int kind, bool narrow, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
   if (C != B32_C) return hipErrorInvalidValue;
-  return launch_block32(kind, a, n_tiles, grid_y, s);
+  return launch_block32<Mfma32FP8>(kind, a, n_tiles, grid_y, s);
 }
 
-int block_tile_width_fp8(int C, bool narrow) { return C == B32_C ? B32_TWO : 0; }
+int block_tile_width_fp8(int C, bool narrow) { return C == B32_C ? Mfma32FP8::TWO : 0; }
 
 }  // namespace conet

@@ -219,7 +219,7 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
   const int tw_in = conv_tile_width(dt, Ci, C), tw_blk = conv_tile_width(dt, C, C);
   // Inference runs each block as one fused launch when a fused kernel exists for
   // (dtype, C); calibration and the training forward (which stores h) use two convs.
-  int tw_fb = calib ? 0 : block_tile_width(dt, C, K, false);
+  int tw_fb = calib ? 0 : block_tile_width(dt, C, K, false, c.train != 0);
   // a batch whose wide tiles cannot fill the GPU once (a slot, a serving batch) runs on
   // narrow tiles: more, shorter work-groups per launch
   bool narrow = false;
@@ -232,7 +232,7 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
     }
     if (wide_tiles * K < 2LL * M->n_cu) {
       narrow = true;
-      tw_fb = block_tile_width(dt, C, K, true);
+      tw_fb = block_tile_width(dt, C, K, true, c.train != 0);
     }
   }
   hipError_t e;

@@ -101,12 +101,14 @@ struct BlockArgs {
   void* save_o0;
 };
 // Output subcarriers per fused tile; 0 when (dtype, C, K) runs as two conv launches.
-// narrow: the width used when a batch's wide tiles cannot fill the GPU.
+// narrow: the width used when a batch's wide tiles cannot fill the GPU. train: the model
+// keeps training state (its forward must read the filter packs the optimiser updates).
 constexpr int BLOCK_KMAX = 4;  // fused main-branch kernels exist for K <= 4
-// FP8 at 96 channels runs the fused block on the 32x32x64 MFMA, which reads filters in
-// its own fragment packing (pack_filter32).
-inline bool block_uses_mfma32(int dtype, int C) { return dtype == DT_FP8 && C == 96; }
-int block_tile_width(int dtype, int C, int K, bool narrow);
+// FP8 and BF16 at 96 channels run the fused block on the 32x32 MFMAs, which read filters in
+// their own fragment packing (pack_filter32). Training models do not use them (the
+// optimiser regenerates only the 16x16 packs).
+inline bool block_uses_mfma32(int dtype, int C) { return C == 96 && (dtype == DT_FP8 || dtype == DT_BF16); }
+int block_tile_width(int dtype, int C, int K, bool narrow, bool train = false);
 // kind BLOCK_PLAIN: branches blockIdx.y + k_off, no fusion epilogue (support branches, or
 // every branch of a block without fusion; head on branch 0 when llr is set); BLOCK_MAIN: the
 // main branch of a fused block (k_off = 0, grid.y = 1); BLOCK_PAIR: grid.y = K, blockIdx.y 0

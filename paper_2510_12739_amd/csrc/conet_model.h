@@ -116,8 +116,8 @@ size_t train_bytes(const conet_config& c, Layout& lay, size_t base);
 conet_status train_init(conet_model* M);
 void pack_filter(int dtype, int cin, int cout, const float* W, uint8_t* dst, float* wscale);
 size_t packed_bytes(int dtype, int cin, int cout);
-void pack_filter32(int cin, int cout, const float* W, const float* wscale, uint8_t* dst);
-size_t packed_bytes32(int cin, int cout);
+void pack_filter32(int dtype, int cin, int cout, const float* W, const float* wscale, uint8_t* dst);
+size_t packed_bytes32(int dtype, int cin, int cout);
 
 // Bytes of activation buffers (plus descriptor capacity) for `max_res` REs.
 size_t arena_bytes(const conet_config& c, int64_t max_res);

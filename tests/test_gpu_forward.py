@@ -191,6 +191,40 @@ def test_fp8_small_grid_vs_emulated_and_fp64():
     assert rel_l2(got, ref) <= 0.25 and sign_agree(got, ref) >= 0.93, (rel_l2(got, ref), sign_agree(got, ref))
 
 
+@pytest.mark.parametrize("K,L,mask,fusion,feedback,T,F", [
+    (1, 1, 0, "product", False, 14, 75),      # plain block with the head
+    (4, 1, -1, "product", False, 14, 75),     # fused main branch with the head, three supports
+    (2, 2, 0b01, "product", False, 14, 75),   # fused main branch (no head), then a plain head block
+    (3, 3, -1, "sum", True, 14, 40),          # feedback: every main branch launched alone
+    (4, 3, 0b101, "product", False, 14, 75),  # main + next supports paired in one launch
+    (4, 2, -1, "product", False, 7, 29),      # short slot
+])
+def test_bf16_96_channel_fused_block_kernel(K, L, mask, fusion, feedback, T, F):
+    """BF16 at 96 channels runs each block as one fused kernel on the 32x32x16 MFMA (its own
+    filter packing and chunk order), for every launch kind, both fusion operators, feedback
+    and a short slot, on two slots with a ragged tile tail: against the BF16-emulating
+    oracle at the BF16 bound (5e-3) and plain FP64 at the stated BF16 LLR tolerance."""
+    from paper_2510_12739_amd import Conet
+    C, Ci, m = 96, 16, 4
+    mc = ModelConfig(K, L, C, Ci, m, mask)
+    blob = make_blob(mc, seed=80 + K + L, perturb=True)
+    X = features(SimConfig(F=F, n_rx=4, bits_per_symbol=m, seed=81), 2)[:, :T]
+    p = o.unpack(blob, K, L, C, Ci, m)
+    X64 = X.astype(np.float64)
+    kw = dict(fuse_mask=mc.mask, fusion=fusion, feedback=feedback)
+    say(f"bf16 96-channel fused block K={K} L={L} mask={mc.mask:b} {fusion} feedback={feedback} T={T} F={F}")
+    model = Conet(K, L, C, Ci, m, blob, dtype="bf16", fuse_mask=mc.mask, fusion=fusion, feedback=feedback)
+    assert 0 < model.block_tile_width < F
+    got = _run(model, X)
+    model.close()
+    emu = o.forward_slots(p, X64, quant=o.Quant("bf16"), **kw)
+    ref = o.forward_slots(p, X64, **kw)
+    say(f'  rel-L2 vs emulated {rel_l2(got, emu):.2e}, vs fp64 {rel_l2(got, ref):.2e}, sign {sign_agree(got, ref):.4f}')
+    assert got.shape == (2, T, F, m)
+    assert rel_l2(got, emu) <= 5e-3, rel_l2(got, emu)
+    assert rel_l2(got, ref) <= 3e-2 and sign_agree(got, ref) >= 0.99, (rel_l2(got, ref), sign_agree(got, ref))
+
+
 def test_fp8_full_size_128x3276_sampled_windows():
     """The FP8 throughput workload at full size (128 slots of 3276 x 14, K=4 L=6 C=96), in
     the launch configuration the benchmark times. A whole slot costs the FP64 oracle about
