@@ -74,9 +74,16 @@ typedef struct {
   int32_t feedback;        /* 1 => Example II (Sec. III): after each fusion, support branch k
                               continues from O[k] + the main branch's fused activation. The
                               training calls support fusion_op = 0, feedback = 0 only          */
+  int32_t norm;            /* normalisation after each fusion (Sec. III allows BN or LN):
+                              CONET_NORM_LN (0): per-RE LayerNorm over C, gamma/beta affine;
+                              CONET_NORM_BN (1): BatchNorm with stored running statistics,
+                              gamma (P - mean) / sqrt(var + ln_eps) + beta per channel; the
+                              blob then ends with mean_l, var_l (C each) for l = 1..L.
+                              Inference only (train = 1 needs CONET_NORM_LN)                   */
 } conet_config;
 
 enum { CONET_FUSE_PRODUCT = 0, CONET_FUSE_SUM = 1 };
+enum { CONET_NORM_LN = 0, CONET_NORM_BN = 1 };
 
 typedef struct conet_model conet_model;
 

@@ -21,6 +21,11 @@ Variants the paper also describes (Sec. III): fusion by addition instead of the
 product (``fusion="sum"``: P = sum_k O[k], then the same LayerNorm), and Example II's
 feedback from the main net to the support nets (``feedback=True``: after a fusion, each
 support net continues from its own block output plus the main net's fused activation).
+The normalisation after the fusion may be BatchNorm instead of LayerNorm (the paper
+allows either): ``norm="bn"`` applies gamma (P - mean) / sqrt(var + eps) + beta per
+channel with running statistics stored in the blob (``unpack(..., norm="bn")``), and
+``norm="bn_batch"`` uses the batch's own per-channel statistics over every RE (biased
+variance, as BN does while training), which is how running statistics are produced.
 
 Readings of what the paper leaves open (all listed in the design notes): conv
 biases everywhere; "same" zero padding inside each slot; LN over the C channels of
@@ -45,8 +50,9 @@ LN_EPS = 1e-5
 
 # ----------------------------------------------------------------------------- params
 
-def unpack(blob: np.ndarray, K: int, L: int, C: int, C_in: int, m: int) -> Dict:
-    """Parse the packed FP32 parameter vector into FP64 arrays (blob order of the C header)."""
+def unpack(blob: np.ndarray, K: int, L: int, C: int, C_in: int, m: int, norm: str = "ln") -> Dict:
+    """Parse the packed FP32 parameter vector into FP64 arrays (blob order of the C header).
+    norm="bn": the blob ends with the BatchNorm running mean and variance of every block."""
     v = np.asarray(blob, dtype=np.float64).ravel()
     pos = [0]
 
@@ -74,6 +80,14 @@ def unpack(blob: np.ndarray, K: int, L: int, C: int, C_in: int, m: int) -> Dict:
         p["beta"].append(take(C))
     p["W_h"] = take(m, C)
     p["b_h"] = take(m)
+    p["norm"] = norm
+    if norm == "bn":
+        p["bn_mean"], p["bn_var"] = [], []
+        for _l in range(L):
+            p["bn_mean"].append(take(C))
+            p["bn_var"].append(take(C))
+    elif norm != "ln":
+        raise ValueError(f"unknown norm {norm!r}")
     if pos[0] != v.size:
         raise ValueError(f"blob has {v.size} values, layout needs {pos[0]}")
     return p
@@ -89,6 +103,9 @@ def pack(p: Dict) -> np.ndarray:
     for g, b in zip(p["gamma"], p["beta"]):
         parts += [g, b]
     parts += [p["W_h"], p["b_h"]]
+    if p.get("norm", "ln") == "bn":
+        for mu, var in zip(p["bn_mean"], p["bn_var"]):
+            parts += [mu, var]
     return np.concatenate([np.asarray(a, dtype=np.float64).ravel() for a in parts])
 
 
@@ -239,17 +256,22 @@ def _weights(q: Quant, W: np.ndarray) -> np.ndarray:
 
 def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Optional[Quant] = None,
             keep: bool = False, calib: Optional[np.ndarray] = None, fusion: str = "product",
-            feedback: bool = False):
+            feedback: bool = False, norm: Optional[str] = None, bn_stats: Optional[Dict] = None):
     """CoNet forward for a batch X (B, T, F, C_in) -> LLR (B, T, F, m).
 
     keep=True also returns the intermediate tensors the backward needs.
     calib, if given, receives the running max |.| of every conv input operand
     (indexing of act_scale_index), which is how static activation scales are set.
     fusion: "product" (Example I) or "sum" (fusion by addition); feedback: Example II's
-    main -> support feedback after every fusion. The backward covers the defaults only.
+    main -> support feedback after every fusion. norm: "ln", "bn" (running statistics of
+    p) or "bn_batch" (this batch's statistics, recorded into bn_stats[l - 1] = (mean, var)
+    if given); default: p's own. The backward covers the defaults only.
     """
     if fusion not in ("product", "sum"):
         raise ValueError(f"unknown fusion {fusion!r}")
+    norm = norm or p.get("norm", "ln")
+    if norm not in ("ln", "bn", "bn_batch"):
+        raise ValueError(f"unknown norm {norm!r}")
     K, L = p["K"], p["L"]
     mask = ((1 << L) - 1) if fuse_mask is None else int(fuse_mask)
     q = quant or Quant()
@@ -296,8 +318,16 @@ def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Opti
             P = O[0].copy()
             for k in range(1, K):
                 P = P + q.store(O[k]) if fusion == "sum" else P * q.store(O[k])
-            mu = P.mean(axis=-1, keepdims=True)
-            var = ((P - mu) ** 2).mean(axis=-1, keepdims=True)
+            if norm == "ln":  # over the C channels of each RE
+                mu = P.mean(axis=-1, keepdims=True)
+                var = ((P - mu) ** 2).mean(axis=-1, keepdims=True)
+            elif norm == "bn":  # per channel, running statistics
+                mu, var = p["bn_mean"][l - 1], p["bn_var"][l - 1]
+            else:  # per channel over every RE of the batch, biased variance
+                mu = P.mean(axis=(0, 1, 2))
+                var = ((P - mu) ** 2).mean(axis=(0, 1, 2))
+                if bn_stats is not None:
+                    bn_stats[l - 1] = (mu.copy(), var.copy())
             sig = np.sqrt(var + LN_EPS)
             ahat = (P - mu) / sig
             A0 = p["gamma"][l - 1] * ahat + p["beta"][l - 1]
@@ -318,7 +348,7 @@ def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Opti
     llr = a[0] @ p["W_h"].T + p["b_h"]
     if keep:
         cache["aL"] = a[0]
-        cache["variant"] = (fusion, feedback)
+        cache["variant"] = (fusion, feedback, norm)
         return llr, cache
     return llr
 
@@ -358,8 +388,8 @@ def backward(p: Dict, cache: Dict, dllr: np.ndarray) -> Dict:
     """
     K, L = p["K"], p["L"]
     mask = cache["mask"]
-    if cache.get("variant", ("product", False)) != ("product", False):
-        raise NotImplementedError("the backward covers product fusion without feedback")
+    if cache.get("variant", ("product", False, "ln")) != ("product", False, "ln"):
+        raise NotImplementedError("the backward covers product fusion without feedback, with LayerNorm")
     g = {"branch": [], "gamma": [None] * L, "beta": [None] * L}
     for _k in range(K):
         g["branch"].append({"W_in": None, "b_in": None, "blocks": [dict() for _ in range(L)]})

@@ -40,7 +40,7 @@ class conet_config(ctypes.Structure):
                 ("in_channels", ctypes.c_int32), ("bits_per_symbol", ctypes.c_int32),
                 ("fuse_mask", ctypes.c_uint32), ("ln_eps", ctypes.c_float), ("dtype", ctypes.c_int32),
                 ("train", ctypes.c_int32), ("max_res", ctypes.c_int64), ("fusion_op", ctypes.c_int32),
-                ("feedback", ctypes.c_int32)]
+                ("feedback", ctypes.c_int32), ("norm", ctypes.c_int32)]
 
 
 class conet_request(ctypes.Structure):
@@ -118,14 +118,15 @@ def _check(st: int):
 
 
 FUSIONS = {"product": 0, "sum": 1}
+NORMS = {"ln": 0, "bn": 1}
 
 
 def make_config(K: int, L: int, C: int, C_in: int, m: int, dtype: str = "bf16", fuse_mask: int = -1,
                 max_res: int = 1 << 20, ln_eps: float = 1e-5, train: bool = False, fusion: str = "product",
-                feedback: bool = False) -> conet_config:
+                feedback: bool = False, norm: str = "ln") -> conet_config:
     mask = ((1 << L) - 1) if fuse_mask < 0 else int(fuse_mask)
     return conet_config(K, L, C, C_in, m, mask, ln_eps, DTYPES[dtype], 1 if train else 0, int(max_res),
-                        FUSIONS[fusion], 1 if feedback else 0)
+                        FUSIONS[fusion], 1 if feedback else 0, NORMS[norm])
 
 
 def weight_count(cfg: conet_config) -> int:
@@ -151,12 +152,12 @@ class Conet:
 
     def __init__(self, K: int, L: int, C: int, C_in: int, m: int, blob: np.ndarray, dtype: str = "bf16",
                  fuse_mask: int = -1, max_res: int = 1 << 20, device=None, train: bool = False,
-                 fusion: str = "product", feedback: bool = False):
+                 fusion: str = "product", feedback: bool = False, norm: str = "ln"):
         import torch
         self.lib = load()
         self.train = train
         self.cfg = make_config(K, L, C, C_in, m, dtype, fuse_mask, max_res, train=train, fusion=fusion,
-                               feedback=feedback)
+                               feedback=feedback, norm=norm)
         self.K, self.L, self.C, self.C_in, self.m, self.dtype = K, L, C, C_in, m, dtype
         n = weight_count(self.cfg)
         if n == 0:

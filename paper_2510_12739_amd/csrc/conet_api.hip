@@ -170,7 +170,8 @@ static int hid_bytes(int dtype) { return dtype == DT_F32 ? 4 : (dtype == DT_BF16
 
 size_t n_params(const conet_config& c) {
   const size_t K = c.branches, L = c.blocks, C = c.channels, Ci = c.in_channels, m = c.bits_per_symbol;
-  return K * (C * Ci * 9 + C + L * (6 * C + 2 * 9 * C * C)) + 2 * L * C + m * C + m;
+  const size_t bn = c.norm == CONET_NORM_BN ? 2 * L * C : 0;  // running mean and variance per block
+  return K * (C * Ci * 9 + C + L * (6 * C + 2 * 9 * C * C)) + 2 * L * C + m * C + m + bn;
 }
 
 conet_status check_config(const conet_config* c) {
@@ -187,6 +188,7 @@ conet_status check_config(const conet_config* c) {
   if (c->fusion_op != CONET_FUSE_PRODUCT && c->fusion_op != CONET_FUSE_SUM)
     return fail(CONET_EINVAL, "fusion_op must be CONET_FUSE_PRODUCT or CONET_FUSE_SUM");
   if (c->feedback != 0 && c->feedback != 1) return fail(CONET_EINVAL, "feedback must be 0 or 1");
+  if (c->norm != CONET_NORM_LN && c->norm != CONET_NORM_BN) return fail(CONET_EINVAL, "norm must be CONET_NORM_LN or CONET_NORM_BN");
   if (c->train) {
     if (c->dtype != DT_F32 && c->dtype != DT_BF16) return fail(CONET_EINVAL, "training runs in FP32 or BF16");
     if (c->channels != 16 && c->channels != 32 && c->channels != 64)
@@ -196,6 +198,7 @@ conet_status check_config(const conet_config* c) {
     if (c->blocks > 16) return fail(CONET_EINVAL, "training supports L <= 16");
     if (c->fusion_op != CONET_FUSE_PRODUCT || c->feedback)
       return fail(CONET_EINVAL, "training supports product fusion without feedback");
+    if (c->norm != CONET_NORM_LN) return fail(CONET_EINVAL, "training supports LayerNorm after the fusion");
   }
   if (c->max_res < 1) return fail(CONET_EINVAL, "max_res must be positive");
   if (!(c->ln_eps > 0.f)) return fail(CONET_EINVAL, "ln_eps must be positive");
@@ -295,6 +298,14 @@ conet_status conet_create(const conet_config* cfg, const float* w, size_t n_weig
   if (st != CONET_OK) return st;
   if (!w || !workspace) return fail(CONET_EINVAL, "null weights or workspace");
   if (n_weights != n_params(*cfg)) return fail(CONET_EINVAL, "blob has %zu values, configuration needs %zu", n_weights, n_params(*cfg));
+  if (cfg->norm == CONET_NORM_BN) {  // running variances must keep var + eps positive
+    const size_t C = cfg->channels, L = cfg->blocks, tail = n_weights - 2 * L * C;
+    for (size_t l = 0; l < L; ++l)
+      for (size_t c = 0; c < C; ++c) {
+        const float v = w[tail + (2 * l + 1) * C + c];
+        if (!(v + cfg->ln_eps > 0.f) || !std::isfinite(v)) return fail(CONET_EINVAL, "BatchNorm variance %g of block %zu", v, l + 1);
+      }
+  }
   if (((uintptr_t)workspace & 255) != 0) return fail(CONET_EINVAL, "workspace must be 256-byte aligned");
   conet_model* M = new (std::nothrow) conet_model();
   if (!M) return fail(CONET_ENOMEM, "host allocation failed");
@@ -344,6 +355,22 @@ conet_status conet_create(const conet_config* cfg, const float* w, size_t n_weig
   }
   memcpy(vec + lay.v_wh, p, (size_t)m * C * 4); p += (size_t)m * C;
   memcpy(vec + lay.v_bh, p, m * 4); p += m;
+  if (cfg->norm == CONET_NORM_BN) {
+    // BatchNorm with running statistics is a per-channel affine: fold it into gamma/beta,
+    // gamma' = gamma / sqrt(var + eps), beta' = beta - mean gamma'
+    for (int l = 0; l < L; ++l) {
+      const float* mean = p + (size_t)l * 2 * C;
+      const float* var = mean + C;
+      float* g = vec + lay.v_gamma[l];
+      float* b = vec + lay.v_beta[l];
+      for (int c = 0; c < C; ++c) {
+        const float gs = (float)((double)g[c] / std::sqrt((double)var[c] + (double)cfg->ln_eps));
+        b[c] = (float)((double)b[c] - (double)mean[c] * (double)gs);
+        g[c] = gs;
+      }
+    }
+    p += (size_t)2 * L * C;
+  }
   e = hipMemcpy(M->ws, img.data(), img.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) { delete M; return hip_fail(e, "upload of packed weights"); }
   M->act_scales.assign(1 + 2 * K * L, 1.0f);

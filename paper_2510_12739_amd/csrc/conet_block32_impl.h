@@ -303,7 +303,8 @@ __device__ __forceinline__ void block32_body(const BlockArgs& args, int k, uint8
     finish_block<A, C, EPL, NSUP, decltype(x_fn), decltype(sup_fn), 2>(
         v, re, c0, h, MAIN, x_fn, sup_fn, MAIN ? args.out[0] : args.out[k], (MAIN || k == 0) ? args.save_o0 : nullptr,
         head, NSUP + 1, par + P_GAM * C, par + P_BET * C, args.eps, whl, whl + args.m * C, args.llr, args.m,
-        args.fusion_sum != 0, (MAIN && args.feedback) ? const_cast<void* const*>(args.sup) : nullptr);
+        args.fusion_sum != 0, (MAIN && args.feedback) ? const_cast<void* const*>(args.sup) : nullptr,
+        args.norm_affine != 0);
   }
 }
 

@@ -297,7 +297,8 @@ __device__ __forceinline__ void block_body(const BlockArgs& args, int k, uint8_t
           v, re, c0, g, MAIN, [&](Acc* x) { unpack_raw<Act, RawT, EPL>(raw[mt % PD][0], x); },
           [&](int kk, Acc* sv) { unpack_raw<Act, RawT, EPL>(raw[mt % PD][kk], sv); }, MAIN ? args.out[0] : args.out[k],
           (MAIN || k == 0) ? args.save_o0 : nullptr, head, NSUP + 1, par + P_GAM * C, par + P_BET * C, args.eps, whl, whl + args.m * C, args.llr,
-          args.m, args.fusion_sum != 0, (MAIN && args.feedback) ? const_cast<void* const*>(args.sup) : nullptr);
+          args.m, args.fusion_sum != 0, (MAIN && args.feedback) ? const_cast<void* const*>(args.sup) : nullptr,
+          args.norm_affine != 0);
     }
     if (mt + PD < MT2) issue(mt + PD);
   }

@@ -319,7 +319,8 @@ struct Gemm {
 // residual x (x_fn fills EPL values). On the main branch of a fused block (main_fused),
 // keeps the pre-fusion output when save_o0 is set, multiplies (or with fuse_sum adds) in
 // the stored support outputs of branches 1..K-1 (sup_fn(kk, values), kk < min(K, NSUP+1))
-// and applies the per-RE LayerNorm over C; with sup_dst (Example II feedback) it also
+// and applies the per-RE LayerNorm over C (with norm_affine, BatchNorm with running statistics
+// folded into gamma/beta: a per-channel affine); with sup_dst (Example II feedback) it also
 // stores support output + fused activation to sup_dst[kk]. Then either the 1x1 LLR head
 // (head) or a store of the block output to `out` (nullable). A plain block with the head
 // stores its output to save_o0 when that is set (the backward's copy). LPR lanes (g =
@@ -329,7 +330,7 @@ __device__ __forceinline__ void finish_block(typename A::Acc (&v)[EPL], int64_t 
                                              XFn x_fn, SupFn sup_fn, void* out, void* save_o0, bool head, int K,
                                              const float* gamma, const float* beta, float eps, const float* Wh,
                                              const float* bh, float* llr, int m, bool fuse_sum = false,
-                                             void* const* sup_dst = nullptr) {
+                                             void* const* sup_dst = nullptr, bool norm_affine = false) {
   using Acc = typename A::Acc;
   using Act = typename A::Act;
   {
@@ -359,20 +360,25 @@ __device__ __forceinline__ void finish_block(typename A::Acc (&v)[EPL], int64_t 
         for (int i = 0; i < EPL; ++i) v[i] *= sv[i];
       }
     }
-    Acc s = 0;
+    if (norm_affine) {
 #pragma unroll
-    for (int i = 0; i < EPL; ++i) s += v[i];
-    if (LPR == 4) s += __shfl_xor(s, 16);
-    s += __shfl_xor(s, 32);
-    const Acc mu = s * ((Acc)1 / (Acc)COUT);
-    Acc q = 0;
+      for (int i = 0; i < EPL; ++i) v[i] = (Acc)gamma[c0 + i] * v[i] + (Acc)beta[c0 + i];
+    } else {
+      Acc s = 0;
 #pragma unroll
-    for (int i = 0; i < EPL; ++i) { const Acc d = v[i] - mu; q += d * d; }
-    if (LPR == 4) q += __shfl_xor(q, 16);
-    q += __shfl_xor(q, 32);
-    const Acc rs = (Acc)1 / sqrtf((float)(q * ((Acc)1 / (Acc)COUT) + (Acc)eps));
+      for (int i = 0; i < EPL; ++i) s += v[i];
+      if (LPR == 4) s += __shfl_xor(s, 16);
+      s += __shfl_xor(s, 32);
+      const Acc mu = s * ((Acc)1 / (Acc)COUT);
+      Acc q = 0;
 #pragma unroll
-    for (int i = 0; i < EPL; ++i) v[i] = (Acc)gamma[c0 + i] * (v[i] - mu) * rs + (Acc)beta[c0 + i];
+      for (int i = 0; i < EPL; ++i) { const Acc d = v[i] - mu; q += d * d; }
+      if (LPR == 4) q += __shfl_xor(q, 16);
+      q += __shfl_xor(q, 32);
+      const Acc rs = (Acc)1 / sqrtf((float)(q * ((Acc)1 / (Acc)COUT) + (Acc)eps));
+#pragma unroll
+      for (int i = 0; i < EPL; ++i) v[i] = (Acc)gamma[c0 + i] * (v[i] - mu) * rs + (Acc)beta[c0 + i];
+    }
     if (sup_dst) {  // Example II: each support continues from its output plus the fused activation
 #pragma unroll
       for (int kk = 1; kk <= NSUP; ++kk) {
@@ -557,7 +563,7 @@ __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
           [&](int kk, Acc* sv) { load_vals(reinterpret_cast<const Act*>(args.sup[kk]) + re * COUT + c0, sv, EPL); },
           MODE == 2 ? args.out[k] : args.out[0], args.save_o0, head, args.K, args.gamma, args.beta, args.eps, args.Wh,
           args.bh, args.llr, args.m, args.fusion_sum != 0,
-          (MODE == 4 && args.feedback) ? const_cast<void* const*>(args.sup) : nullptr);
+          (MODE == 4 && args.feedback) ? const_cast<void* const*>(args.sup) : nullptr, args.norm_affine != 0);
     }
   }
   if constexpr (MODE == 5 || MODE == 6) {

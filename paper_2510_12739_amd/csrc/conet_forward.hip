@@ -197,6 +197,7 @@ struct FusedScheduler {
     m.bh = vec + lay.v_bh;
     m.llr = last ? llr : nullptr;
     m.fusion_sum = c.fusion_op == CONET_FUSE_SUM;
+    m.norm_affine = c.norm == CONET_NORM_BN;
     m.feedback = c.feedback && !last;  // the supports' outputs are not read after the last block
     e = mark();  // (c)
     if (e != hipSuccess) return hip_fail(e, "event record");
@@ -460,6 +461,7 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
       am.save_o0 = save ? ar.lvl_o0[l] : nullptr;
       am.k_off = 0;
       am.fusion_sum = c.fusion_op == CONET_FUSE_SUM;
+      am.norm_affine = c.norm == CONET_NORM_BN;
       am.feedback = c.feedback && !last;
       e = mark();
       if (e == hipSuccess) e = launch_conv(dt, 4, C, C, am, n_tiles_blk, 1, s);

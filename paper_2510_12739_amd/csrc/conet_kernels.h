@@ -51,6 +51,8 @@ struct ConvArgs {
   int inner_branches;              // mode 0: run branches k_off .. k_off + n - 1 in every work-group
                                    // (one staged feature tile; launch with grid.y = 1)
   int fusion_sum;                  // mode 4: fuse by addition instead of the product
+  int norm_affine;                 // mode 4: gamma/beta are a per-channel affine (BatchNorm with
+                                   // running statistics folded in) instead of LayerNorm's
   int feedback;                    // mode 4: also rewrite sup[k] <- sup[k] + fused output (Example II)
 };
 
@@ -94,6 +96,7 @@ struct BlockArgs {
   int T, F, tiles_per_slot, tw;    // tw: set by the launcher
   const TileDesc* tiles;           // ragged batches, else null
   int fusion_sum;                  // main: fuse by addition instead of the product
+  int norm_affine;                 // main: per-channel affine (folded BatchNorm) instead of LayerNorm
   int feedback;                    // main: also rewrite sup[k] <- sup[k] + fused output (Example II)
   // training forward (nullable): h of branch k as stored by the two-conv path, and the
   // main branch's output before the fusion (or branch 0's output before the head)

@@ -34,6 +34,9 @@ def test_weight_count_matches_blob_layout(K, L, C, Ci, m):
         cfg = b.make_config(K, L, C, Ci, m, dt)
         assert b.weight_count(cfg) == blob_size(ModelConfig(K, L, C, Ci, m))
         assert b.workspace_bytes(cfg) > 0
+        # BatchNorm after the fusion: the blob ends with a running mean and variance per block
+        bn = b.make_config(K, L, C, Ci, m, dt, norm="bn")
+        assert b.weight_count(bn) == blob_size(ModelConfig(K, L, C, Ci, m)) + 2 * L * C
 
 
 def test_workspace_grows_with_max_res():
@@ -47,6 +50,7 @@ def test_workspace_grows_with_max_res():
     (dict(K=2, L=2, C=48, C_in=8, m=2), "no kernel"),
     (dict(K=2, L=2, C=32, C_in=8, m=9), "bits_per_symbol"),
     (dict(K=2, L=2, C=32, C_in=8, m=2, fuse_mask=0b100), "fuse_mask"),
+    (dict(K=2, L=2, C=32, C_in=16, m=2, norm="bn", train=True), "LayerNorm"),
 ])
 def test_invalid_configs_are_rejected_with_a_message(kw, msg):
     lib = b.load()

@@ -360,6 +360,71 @@ def test_fusion_variants_vs_oracle(dtype, K, L, C, mask, fusion, feedback):
     model.close()
 
 
+@pytest.mark.parametrize("dtype,K,L,C,Ci,mask", [
+    ("f32", 2, 2, 32, 16, -1),       # two-conv path (fusion epilogue of the second conv)
+    ("bf16", 3, 3, 64, 16, -1),      # fused 16x16 kernels: paired launches, main branch with the head
+    ("bf16", 3, 2, 96, 16, 0b01),    # fused 32x32x16 kernel, fused main without the head
+    ("fp8", 4, 2, 96, 32, -1),       # fused 32x32x64 kernel
+])
+def test_batchnorm_fusion_vs_oracle(dtype, K, L, C, Ci, mask):
+    """BatchNorm after the fusion (Sec. III allows BN or LN) with running statistics: the
+    library folds them into a per-channel affine. The statistics are the oracle's own batch
+    statistics of the same slots (BN's training-time estimate), appended to the blob.
+    Bounds as for the LayerNorm network of the same dtype."""
+    from paper_2510_12739_amd import Conet
+    m = 4
+    sim = SimConfig(F=70, n_rx=Ci // 4, bits_per_symbol=m, seed=51)
+    mc = ModelConfig(K, L, C, Ci, m, mask)
+    base = make_blob(mc, seed=52, perturb=True)
+    X = features(sim, 2)
+    X64 = X.astype(np.float64)
+    p = o.unpack(np.concatenate([base, np.tile(np.concatenate([np.zeros(C), np.ones(C)]), L).astype(np.float32)]),
+                 K, L, C, Ci, m, norm="bn")
+    stats = {}
+    o.forward(p, X64, fuse_mask=mc.mask, norm="bn_batch", bn_stats=stats)
+    for l, (mu, var) in stats.items():
+        p["bn_mean"][l], p["bn_var"][l] = mu, var
+    blob = o.pack(p).astype(np.float32)
+    p = o.unpack(blob, K, L, C, Ci, m, norm="bn")          # the FP32 statistics both sides see
+    say(f"batchnorm fusion {dtype} K={K} L={L} C={C} mask={mc.mask:b}")
+    model = Conet(K, L, C, Ci, m, blob, dtype=dtype, fuse_mask=mc.mask, norm="bn")
+    quant = None
+    if dtype == "fp8":
+        scales = o.calibrate(p, X64, fuse_mask=mc.mask)
+        model.set_act_scales(scales)
+        quant = o.Quant("fp8", scales)
+    elif dtype == "bf16":
+        quant = o.Quant("bf16")
+    got = _run(model, X)
+    model.close()
+    ref = o.forward_slots(p, X64, fuse_mask=mc.mask)
+    if dtype == "f32":
+        assert rel_l2(got, ref) <= 1e-5, rel_l2(got, ref)
+        assert max_over_rms(got, ref) <= 1e-4
+        return
+    emu = o.forward_slots(p, X64, fuse_mask=mc.mask, quant=quant)
+    say(f'  rel-L2 vs emulated {rel_l2(got, emu):.2e}, vs fp64 {rel_l2(got, ref):.2e}, sign {sign_agree(got, ref):.4f}')
+    if dtype == "bf16":
+        assert rel_l2(got, emu) <= 5e-3, rel_l2(got, emu)
+        assert rel_l2(got, ref) <= 3e-2 and sign_agree(got, ref) >= 0.99
+    else:
+        assert rel_l2(got, emu) <= 6e-2, rel_l2(got, emu)
+        assert rel_l2(got, ref) <= 0.25 and sign_agree(got, ref) >= 0.93
+
+
+def test_batchnorm_training_and_bad_variance_are_refused():
+    from paper_2510_12739_amd import Conet, ConetError
+    K, L, C, Ci, m = 2, 1, 16, 16, 2
+    base = make_blob(ModelConfig(K, L, C, Ci, m), seed=1)
+    ok = np.concatenate([base, np.zeros(C, np.float32), np.ones(C, np.float32)])
+    with pytest.raises(ConetError, match="EINVAL"):
+        Conet(K, L, C, Ci, m, ok, dtype="bf16", train=True, norm="bn")
+    bad = ok.copy()
+    bad[-1] = -1.0
+    with pytest.raises(ConetError, match="EINVAL"):
+        Conet(K, L, C, Ci, m, bad, dtype="bf16", norm="bn")
+
+
 def test_fusion_variant_training_is_refused():
     from paper_2510_12739_amd import Conet, ConetError
     mc = ModelConfig(2, 1, 16, 16, 2)

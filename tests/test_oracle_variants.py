@@ -1,7 +1,7 @@
-"""Pins of the oracle's fusion variants (CPU): fusion by addition and Example II's
-main -> support feedback (paper Sec. III), against an independent FP64 implementation
-built from torch's conv2d and layer_norm, and against special cases that reduce to the
-already pinned product fusion."""
+"""Pins of the oracle's fusion variants (CPU): fusion by addition, Example II's
+main -> support feedback and BatchNorm after the fusion (paper Sec. III), against an
+independent FP64 implementation built from torch's conv2d, layer_norm and batch_norm, and
+against special cases that reduce to the already pinned product fusion."""
 import numpy as np
 import pytest
 import torch
@@ -19,8 +19,9 @@ def _x(B=2, T=5, F=7, Ci=4, seed=1):
     return np.random.default_rng(seed).standard_normal((B, T, F, Ci))
 
 
-def _torch_conet(p, X, mask, fusion, feedback):
-    """CoNet from library primitives: NCHW conv2d with padding 1, layer_norm over C."""
+def _torch_conet(p, X, mask, fusion, feedback, norm="ln"):
+    """CoNet from library primitives: NCHW conv2d with padding 1, layer_norm over C, or
+    batch_norm over (N, H, W) with running statistics ("bn") or the batch's ("bn_batch")."""
     K, L = p["K"], p["L"]
     tt = lambda a: torch.from_numpy(np.ascontiguousarray(a))
     ch = lambda v: tt(v)[None, :, None, None]
@@ -41,8 +42,13 @@ def _torch_conet(p, X, mask, fusion, feedback):
             for k in range(1, K):
                 P = P + outs[k] if fusion == "sum" else P * outs[k]
             C = P.shape[1]
-            A = torch.nn.functional.layer_norm(P.permute(0, 2, 3, 1), (C,), tt(p["gamma"][l]), tt(p["beta"][l]),
-                                               eps=o.LN_EPS).permute(0, 3, 1, 2)
+            if norm == "ln":
+                A = torch.nn.functional.layer_norm(P.permute(0, 2, 3, 1), (C,), tt(p["gamma"][l]), tt(p["beta"][l]),
+                                                   eps=o.LN_EPS).permute(0, 3, 1, 2)
+            else:
+                rm, rv = (tt(p["bn_mean"][l]), tt(p["bn_var"][l])) if norm == "bn" else (None, None)
+                A = torch.nn.functional.batch_norm(P, rm, rv, tt(p["gamma"][l]), tt(p["beta"][l]),
+                                                   training=norm == "bn_batch", eps=o.LN_EPS)
             a = [A] + [outs[k] + A if feedback else outs[k] for k in range(1, K)]
         else:
             a = outs
@@ -110,5 +116,67 @@ def test_backward_refuses_variants():
     K, L, C, Ci, m = 2, 1, 4, 4, 2
     p = _params(K, L, C, Ci, m, seed=35)
     llr, cache = o.forward(p, _x(seed=36), fusion="sum", keep=True)
+    with pytest.raises(NotImplementedError):
+        o.backward(p, cache, np.ones_like(llr))
+
+
+def _bn_params(K, L, C, Ci, m, seed):
+    """Parameters with BatchNorm running statistics appended to the blob (mean ~ N(0, 0.3^2),
+    variance ~ U(0.5, 2))."""
+    cfg = ModelConfig(K=K, L=L, C=C, C_in=Ci, m=m)
+    rng = np.random.default_rng(seed + 1000)
+    tail = np.concatenate([np.concatenate([0.3 * rng.standard_normal(C), rng.uniform(0.5, 2.0, C)]) for _ in range(L)])
+    blob = np.concatenate([make_blob(cfg, seed=seed, perturb=True), tail.astype(np.float32)])
+    return o.unpack(blob, K, L, C, Ci, m, norm="bn"), blob
+
+
+@pytest.mark.parametrize("K,L,mask,norm", [(2, 3, 0b111, "bn"), (3, 2, 0b10, "bn"), (3, 3, 0b101, "bn_batch"),
+                                           (2, 2, 0b11, "bn_batch")])
+def test_batchnorm_matches_torch_reference(K, L, mask, norm):
+    C, Ci, m = 4, 4, 3
+    p, _ = _bn_params(K, L, C, Ci, m, seed=40 + K + L)
+    X = _x(seed=41)
+    got = o.forward(p, X, fuse_mask=mask, norm=norm)
+    ref = _torch_conet(p, X, mask, "product", False, norm=norm)
+    np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-10)
+
+
+def test_batch_statistics_as_running_statistics_reproduce_batch_mode():
+    """Running statistics recorded from a batch, stored in the blob and applied in inference
+    mode give exactly the batch-statistics forward on that batch; pack() round-trips them."""
+    K, L, C, Ci, m = 3, 3, 4, 4, 2
+    p, blob = _bn_params(K, L, C, Ci, m, seed=42)
+    np.testing.assert_array_equal(o.pack(p), blob.astype(np.float64))
+    X = _x(B=3, seed=43)
+    stats = {}
+    batch = o.forward(p, X, norm="bn_batch", bn_stats=stats)
+    assert sorted(stats) == [0, 1, 2]
+    for l, (mu, var) in stats.items():
+        p["bn_mean"][l], p["bn_var"][l] = mu, var
+    np.testing.assert_allclose(o.forward(p, X, norm="bn"), batch, rtol=1e-12, atol=1e-12)
+
+
+def test_batchnorm_with_unit_statistics_is_the_affine():
+    """mean 0, var 1 - eps: BN reduces to gamma P + beta, which a LayerNorm network cannot
+    produce; checked against the fusion written out by hand for one block."""
+    K, L, C, Ci, m = 2, 1, 4, 4, 2
+    p, _ = _bn_params(K, L, C, Ci, m, seed=44)
+    p["bn_mean"][0] = np.zeros(C)
+    p["bn_var"][0] = np.full(C, 1.0 - o.LN_EPS)
+    X = _x(seed=45)
+    got = o.forward(p, X, norm="bn")
+    a = [o.relu(o.conv3x3(X, p["branch"][k]["W_in"], p["branch"][k]["b_in"])) for k in range(K)]
+    outs = []
+    for k in range(K):
+        blk = p["branch"][k]["blocks"][0]
+        h = o.relu(blk["s1"] * o.conv3x3(o.relu(blk["s0"] * a[k] + blk["o0"]), blk["W1"], blk["b1"]) + blk["o1"])
+        outs.append(a[k] + o.conv3x3(h, blk["W2"], blk["b2"]))
+    A = p["gamma"][0] * (outs[0] * outs[1]) + p["beta"][0]
+    np.testing.assert_allclose(got, A @ p["W_h"].T + p["b_h"], rtol=1e-12, atol=1e-12)
+
+
+def test_backward_refuses_batchnorm():
+    p, _ = _bn_params(2, 1, 4, 4, 2, seed=46)
+    llr, cache = o.forward(p, _x(seed=47), keep=True)
     with pytest.raises(NotImplementedError):
         o.backward(p, cache, np.ones_like(llr))
