@@ -32,19 +32,21 @@ __device__ __forceinline__ i32x8 cat8(const i32x4* x) {
   return __builtin_shufflevector(x[0], x[1], 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
-// The two operand formats. CPL: 16-byte chunks per lane per instruction; CHC: channels per
-// chunk; TWO: output subcarriers per tile (the x tile of 16 x (TWO + 4) positions leaves room
-// for two work-groups per CU); ADEPTH: filter prefetch distance in K steps (registers).
+// The two operand formats. C: channels (a multiple of 32); CPL: 16-byte chunks per lane per
+// instruction; CHC: channels per chunk; TWO: output subcarriers per tile (the x tile of
+// 16 x (TWO + 4) positions leaves room for two work-groups per CU); ADEPTH: filter prefetch
+// distance in K steps (registers).
 struct Mfma32FP8 {
   using A = ArithFP8;
-  static constexpr int CPL = 2, CHC = 16, TWO = 22, ADEPTH = 1;
+  static constexpr int C = B32_C, CPL = 2, CHC = 16, TWO = 22, ADEPTH = 2;
   __device__ __forceinline__ static f32x16 mma(const i32x4* a, const i32x4* b, f32x16 c) {
     return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(cat8(a), cat8(b), c, 0, 0, 0, 0, 0, 0);
   }
 };
+template <int C_ = B32_C>
 struct Mfma32BF16 {
   using A = ArithBF16;
-  static constexpr int CPL = 1, CHC = 8, TWO = 18, ADEPTH = 2;
+  static constexpr int C = C_, CPL = 1, CHC = 8, TWO = C_ == 96 ? 18 : 30, ADEPTH = 2;
   __device__ __forceinline__ static f32x16 mma(const i32x4* a, const i32x4* b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[0]), __builtin_bit_cast(bf16x8, b[0]), c,
                                                    0, 0, 0);
@@ -55,7 +57,7 @@ struct Mfma32BF16 {
 // tap (-1, -1) operand of each lane's RE) and all 96 output channels.
 template <class M, int ROWP, int PITCH, int MT>
 struct GemmCore32 {
-  static constexpr int C = B32_C, NOT = C / 32, CPL = M::CPL, HC = C / 2 / M::CHC, NU = 9 * HC;
+  static constexpr int C = M::C, NOT = C / 32, CPL = M::CPL, HC = C / 2 / M::CHC, NU = 9 * HC;
   static constexpr int NS = (NU + CPL - 1) / CPL, ADEPTH = M::ADEPTH, NA = ADEPTH + 1;
   static constexpr int HALF = 16 * HC;  // byte offset of lane half 1's chunks
 
@@ -80,8 +82,9 @@ struct GemmCore32 {
     for (int c = 0; c < CPL; ++c) b[c] = *reinterpret_cast<const i32x4*>(lds + base + b_off(s, c));
   }
 
-  // Filter fragments are prefetched ADEPTH steps ahead; the B fragment of M-tile mt for
-  // step s + 1 is read right after step s's last MFMA on it, into the same registers.
+  // Filter fragments are prefetched ADEPTH steps ahead; activation fragments alternate
+  // between two buffers, the next (step, M-tile)'s read issued before this one's MFMAs (its
+  // LDS latency hides behind three MFMAs), which leaves the registers for the filter ring.
   // base[mt]: LDS byte offset of the lane's RE at tap (-1, -1), lane half included.
   __device__ __forceinline__ static void run(f32x16 (&acc)[MT][NOT], const uint8_t* lds, const i32x4* __restrict__ wp,
                                              const int (&base)[MT], int lane) {
@@ -90,20 +93,21 @@ struct GemmCore32 {
 #pragma unroll
       for (int ot = 0; ot < NOT; ++ot) acc[mt][ot] = f32x16{};
     i32x4 a[NA][NOT][CPL];
-    i32x4 b[MT][CPL];
+    i32x4 b[2][CPL];  // ping-pong: the fragment of the next (step, M-tile) is read before this one's MFMAs
 #pragma unroll
     for (int d = 0; d < ADEPTH; ++d) load_a(a[d], wp, d, lane);
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) load_b(b[mt], lds, base[mt], 0);
+    load_b(b[0], lds, base[0], 0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       if (s + ADEPTH < NS) load_a(a[(s + ADEPTH) % NA], wp, s + ADEPTH, lane);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
+        const int i = s * MT + mt;
+        if (mt + 1 < MT) load_b(b[(i + 1) & 1], lds, base[mt + 1], s);
+        else if (s + 1 < NS) load_b(b[(i + 1) & 1], lds, base[0], s + 1);
 #pragma unroll
-        for (int ot = 0; ot < NOT; ++ot) acc[mt][ot] = M::mma(a[s % NA][ot], b[mt], acc[mt][ot]);
-        if (s + 1 < NS) load_b(b[mt], lds, base[mt], s + 1);
+        for (int ot = 0; ot < NOT; ++ot) acc[mt][ot] = M::mma(a[s % NA][ot], b[i & 1], acc[mt][ot]);
         __builtin_amdgcn_sched_barrier(0);
       }
     }
@@ -112,7 +116,7 @@ struct GemmCore32 {
 
 template <class M>
 constexpr int block32_lds_bytes() {
-  return TROWS * (M::TWO + 4) * lds_pitch<typename M::A, B32_C>() + NPAR * B32_C * 4;
+  return TROWS * (M::TWO + 4) * lds_pitch<typename M::A, M::C>() + NPAR * M::C * 4;
 }
 
 // One fused residual block of branch k on tile `bid` (before the XCD remap); MAIN, HEAD and
@@ -122,7 +126,7 @@ __device__ __forceinline__ void block32_body(const BlockArgs& args, int k, uint8
   using A = typename M::A;
   using Act = typename A::Act;
   constexpr int TWO = M::TWO;
-  constexpr int C = B32_C, NW = CONV_NW, NT = NW * 64;
+  constexpr int C = M::C, NW = CONV_NW, NT = NW * 64;
   constexpr int XW = TWO + 4, HW = TWO + 2;  // LDS positions per row: x tile, h tile
   constexpr int PITCH = lds_pitch<A, C>();
   constexpr int Q1 = TMAX * HW, Q2 = TMAX * TWO;  // REs of the conv-1 and conv-2 regions

@@ -12,12 +12,12 @@ int conv_tile_width_bf16(int cin, int cout) { return tile_width_dtype<ArithBF16>
 
 // 96 channels: the 32x32x16 kernel (its own filter packing); 16, 32, 64: the 16x16x32 one.
 hipError_t launch_block_bf16(int kind, bool narrow, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
-  if (C == B32_C) return launch_block32<Mfma32BF16>(kind, a, n_tiles, grid_y, s);
+  if (C == B32_C) return launch_block32<Mfma32BF16<>>(kind, a, n_tiles, grid_y, s);
   return launch_block_dtype<ArithBF16>(kind, narrow, C, a, n_tiles, grid_y, s);
 }
 
 int block_tile_width_bf16(int C, bool narrow) {
-  return C == B32_C ? Mfma32BF16::TWO : block_tile_width_dtype<ArithBF16>(C, narrow);
+  return C == B32_C ? Mfma32BF16<>::TWO : block_tile_width_dtype<ArithBF16>(C, narrow);
 }
 
 }  // namespace conet
