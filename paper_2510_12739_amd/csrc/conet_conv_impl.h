@@ -233,15 +233,16 @@ struct GemmCore {
   // when the registers allow it (VBUDGET VGPRs for accumulators and operands), else one
   // step ahead.
   static constexpr int ADEPTH = (MT * NOT * 4 + 3 * NOT * A::CPL * 4 + MT * A::CPL * 4 <= VBUDGET) ? 2 : 1;
-  // B fragments of the next step are prefetched (rolling) unless two chunks per MFMA
-  // (FP8) leave no registers for it; then each step issues its own B reads first.
+  // B fragments are prefetched through a ring unless two chunks per MFMA (FP8) leave no
+  // registers for it; then each step issues its own B reads first.
   static constexpr bool BROLL = A::CPL == 1;
 
   // Software pipeline of one wave. The filter fragments of step s + ADEPTH are issued
-  // before step s's MFMAs; the B fragment of M-tile mt for step s + 1 is issued right
-  // after the last MFMA of step s that reads it, into the same registers, so about one
-  // step of MFMAs hides every load. Scheduling barriers keep the compiler from sinking
-  // the loads next to their uses.
+  // before step s's MFMAs; the B fragment of (step, M-tile) pair i + 2 is issued before
+  // pair i's MFMAs into a ring of three buffers, so two M-tiles of MFMAs hide each LDS
+  // read (a ring instead of one buffer per M-tile measured 1.6 % faster on the BF16
+  // forward). Scheduling barriers keep the compiler from sinking the loads next to their
+  // uses.
   __device__ __forceinline__ static void run(AccV (&acc)[MT][NOT], const uint8_t* lds, const i32x4* __restrict__ wp,
                                              const int (&base)[MT], int lane) {
     const int g = lane >> 4;
@@ -251,37 +252,48 @@ struct GemmCore {
       for (int ot = 0; ot < NOT; ++ot) acc[mt][ot] = AccV{};
     constexpr int NA = ADEPTH + 1;
     i32x4 a[NA][NOT][A::CPL];
-    i32x4 b[MT][A::CPL];
 #pragma unroll
-    for (int d = 0; d < ADEPTH; ++d)
-      if (d < NS) load_a(a[d], wp, d, lane);
+    for (int dd = 0; dd < ADEPTH; ++dd)
+      if (dd < NS) load_a(a[dd], wp, dd, lane);
     if constexpr (BROLL) {
+      // ring of three activation fragments: pair i = (step i / MT, M-tile i % MT) is read two
+      // pairs ahead of its MFMAs
+      constexpr int NP = NS * MT;
+      i32x4 b[3][A::CPL];
+      auto ld = [&](int i) {
+        const int s = i / MT, mt = i - s * MT;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+        for (int c = 0; c < A::CPL; ++c) b[i % 3][c] = *reinterpret_cast<const i32x4*>(lds + base[mt] + b_off(s, c, g));
+      };
+      ld(0);
+      if (1 < NP) ld(1);
 #pragma unroll
-        for (int c = 0; c < A::CPL; ++c) b[mt][c] = *reinterpret_cast<const i32x4*>(lds + base[mt] + b_off(0, c, g));
-    }
+      for (int s = 0; s < NS; ++s) {
+        if (s + ADEPTH < NS) load_a(a[(s + ADEPTH) % NA], wp, s + ADEPTH, lane);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      if (s + ADEPTH < NS) load_a(a[(s + ADEPTH) % NA], wp, s + ADEPTH, lane);
-      if constexpr (!BROLL) {
+        for (int mt = 0; mt < MT; ++mt) {
+          const int i = s * MT + mt;
+          if (i + 2 < NP) ld(i + 2);
+#pragma unroll
+          for (int ot = 0; ot < NOT; ++ot) acc[mt][ot] = A::mma(a[s % NA][ot], b[i % 3], acc[mt][ot]);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    } else {
+      i32x4 b[MT][A::CPL];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        if (s + ADEPTH < NS) load_a(a[(s + ADEPTH) % NA], wp, s + ADEPTH, lane);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
           for (int c = 0; c < A::CPL; ++c)
             b[mt][c] = *reinterpret_cast<const i32x4*>(lds + base[mt] + b_off(s, c, g));
-      }
-      if constexpr (BROLL) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int ot = 0; ot < NOT; ++ot) acc[mt][ot] = A::mma(a[s % NA][ot], b[mt], acc[mt][ot]);
-        if (BROLL && s + 1 < NS) {
-#pragma unroll
-          for (int c = 0; c < A::CPL; ++c)
-            b[mt][c] = *reinterpret_cast<const i32x4*>(lds + base[mt] + b_off(s + 1, c, g));
-        }
-        if constexpr (BROLL) __builtin_amdgcn_sched_barrier(0);
+          for (int ot = 0; ot < NOT; ++ot) acc[mt][ot] = A::mma(a[s % NA][ot], b[mt], acc[mt][ot]);
       }
     }
   }
