@@ -90,16 +90,24 @@ def test_fp32_variants_perturbed(K, L, C, Ci, m, mask, B, T, F):
     assert rel_l2(got, ref) <= 1e-5 and max_over_rms(got, ref) <= 1e-4, (rel_l2(got, ref), max_over_rms(got, ref))
 
 
-def test_ragged_equals_uniform_slots_bitwise():
-    """Each slot of a ragged batch gives exactly what it gives alone (tiles never span slots)."""
-    K, L, C, Ci, m = 2, 2, 32, 8, 2
+@pytest.mark.parametrize("dtype,K,L,C,Ci,m", [
+    ("bf16", 2, 2, 32, 8, 2),     # 16x16 fused kernel, 44-subcarrier tiles
+    ("bf16", 3, 2, 96, 16, 4),    # 32x32x16 fused kernel, 18-subcarrier tiles
+    ("fp8", 4, 2, 96, 32, 8),     # 32x32x64 fused kernel, 22-subcarrier tiles
+    ("f32", 2, 1, 96, 16, 4),     # two-conv path, 16-subcarrier tiles
+])
+def test_ragged_equals_uniform_slots_bitwise(dtype, K, L, C, Ci, m):
+    """Each slot of a ragged batch gives exactly what it gives alone (tiles never span slots),
+    for every fused tile width: slot widths below, at and across tile boundaries."""
     blob = make_blob(ModelConfig(K, L, C, Ci, m), seed=5, perturb=True)
-    model = _model(K, L, C, Ci, m, "bf16", blob)
+    model = _model(K, L, C, Ci, m, dtype, blob)
+    if dtype == "fp8":
+        model.set_act_scales(np.full(1 + 2 * K * L, 0.05))
     rng = np.random.default_rng(3)
-    Fs = [48, 7, 100, 33, 1]
+    Fs = [48, 7, 100, 33, 1, 22, 18, 44]
     slots = [rng.standard_normal((14, F, Ci)).astype(np.float32) for F in Fs]
     packed = torch.from_numpy(np.concatenate([s.reshape(-1, Ci) for s in slots])).cuda()
-    say("ragged vs alone, F =", Fs)
+    say(f"ragged vs alone ({dtype}, C={C}), F =", Fs)
     mix = model.forward_ragged(packed, 14, Fs).cpu().numpy()
     off = 0
     for s in slots:
