@@ -233,10 +233,18 @@ typedef struct {
                                missing antennas are zero-padded                               */
   int32_t bits_per_symbol;  /* m of the request (<= the model's head width): LLR channels 0..m-1 */
   int32_t T;                /* OFDM symbols (1..14; all requests of a server share T)        */
-  const float* x_host;      /* host [T][F][4*n_rx] FP32 features; read when the request is batched */
+  const float* x_host;      /* host FP32 input, read when the request is batched: features
+                               [T][F][4*n_rx] (input = CONET_INPUT_FEATURES), or the received
+                               grid [T][F][n_rx][2] (Re, Im; input = CONET_INPUT_GRID)       */
   float* llr_host;          /* host [T][F][m] FP32 output; written before conet_serve_wait returns */
   uint64_t tag;             /* caller's value, unused by the library                        */
+  int32_t input;            /* CONET_INPUT_FEATURES (0) or CONET_INPUT_GRID (1): the server forms
+                               the features on the GPU with conet_featurise (pilots on symbols
+                               2 and 11, so T >= 12); half (4 rx) or a quarter (2 rx) of the
+                               bytes to pack and copy                                         */
 } conet_request;
+
+enum { CONET_INPUT_FEATURES = 0, CONET_INPUT_GRID = 1 };
 
 typedef struct {
   double p50_us, p99_us, mean_us, max_us;  /* latency: submit -> LLRs in llr_host           */

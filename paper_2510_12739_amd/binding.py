@@ -46,7 +46,7 @@ class conet_config(ctypes.Structure):
 class conet_request(ctypes.Structure):
     _fields_ = [("n_prb", ctypes.c_int32), ("n_rx", ctypes.c_int32), ("bits_per_symbol", ctypes.c_int32),
                 ("T", ctypes.c_int32), ("x_host", ctypes.c_void_p), ("llr_host", ctypes.c_void_p),
-                ("tag", ctypes.c_uint64)]
+                ("tag", ctypes.c_uint64), ("input", ctypes.c_int32)]
 
 
 class conet_serve_stats(ctypes.Structure):
@@ -317,15 +317,18 @@ class Server:
         self.handle = h
         self._held = {}
 
-    def submit(self, x: np.ndarray, n_prb: int, n_rx: int, m: int, out: Optional[np.ndarray] = None, T: int = 14):
-        """x: float32 [T, 12*n_prb, 4*n_rx] (C-contiguous). Returns (ticket, llr array [T, F, m])."""
+    def submit(self, x: np.ndarray, n_prb: int, n_rx: int, m: int, out: Optional[np.ndarray] = None, T: int = 14,
+               grid: bool = False):
+        """x: float32 features [T, 12*n_prb, 4*n_rx], or with grid=True the received grid
+        [T, 12*n_prb, n_rx, 2] (Re, Im; featurised on the GPU). Returns (ticket, llr array [T, F, m])."""
         x = np.ascontiguousarray(x, dtype=np.float32)
         F = 12 * n_prb
-        if x.shape != (T, F, 4 * n_rx):
-            raise ValueError(f"x has shape {x.shape}, expected {(T, F, 4 * n_rx)}")
+        want = (T, F, n_rx, 2) if grid else (T, F, 4 * n_rx)
+        if x.shape != want:
+            raise ValueError(f"x has shape {x.shape}, expected {want}")
         if out is None:
             out = np.empty((T, F, m), dtype=np.float32)
-        req = conet_request(n_prb, n_rx, m, T, x.ctypes.data, out.ctypes.data, 0)
+        req = conet_request(n_prb, n_rx, m, T, x.ctypes.data, out.ctypes.data, 0, 1 if grid else 0)
         t = ctypes.c_uint64()
         _check(self.lib.conet_serve_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
         self._held[t.value] = (x, out)

@@ -233,16 +233,24 @@ struct GemmCore {
   // when the registers allow it (VBUDGET VGPRs for accumulators and operands), else one
   // step ahead.
   static constexpr int ADEPTH = (MT * NOT * 4 + 3 * NOT * A::CPL * 4 + MT * A::CPL * 4 <= VBUDGET) ? 2 : 1;
-  // B fragments are prefetched through a ring unless two chunks per MFMA (FP8) leave no
-  // registers for it; then each step issues its own B reads first.
-  static constexpr bool BROLL = A::CPL == 1;
+  // B fragments are prefetched unless two chunks per MFMA (FP8) leave no registers for it;
+  // then each step issues its own B reads first. BF16 prefetches through a ring of three
+  // buffers, FP32 one step ahead in one buffer per M-tile (the ring measured 1.6 % faster
+  // on the BF16 forward and 60 % slower on the FP32 one at 96 channels).
+  enum { B_PLAIN, B_ROLL, B_RING };
+  static constexpr int BMODE = A::CPL != 1 ? B_PLAIN : sizeof(typename A::Op) == 2 ? B_RING : B_ROLL;
+
+  __device__ __forceinline__ static void load_b(i32x4 (&b)[A::CPL], const uint8_t* lds, int base, int s, int g) {
+#pragma unroll
+    for (int c = 0; c < A::CPL; ++c) b[c] = *reinterpret_cast<const i32x4*>(lds + base + b_off(s, c, g));
+  }
 
   // Software pipeline of one wave. The filter fragments of step s + ADEPTH are issued
-  // before step s's MFMAs; the B fragment of (step, M-tile) pair i + 2 is issued before
-  // pair i's MFMAs into a ring of three buffers, so two M-tiles of MFMAs hide each LDS
-  // read (a ring instead of one buffer per M-tile measured 1.6 % faster on the BF16
-  // forward). Scheduling barriers keep the compiler from sinking the loads next to their
-  // uses.
+  // before step s's MFMAs. B_RING: the B fragment of (step, M-tile) pair i + 2 is issued
+  // before pair i's MFMAs, so two M-tiles of MFMAs hide each LDS read. B_ROLL: the B
+  // fragment of M-tile mt for step s + 1 is issued right after the last MFMA of step s
+  // that reads it, into the same registers. Scheduling barriers keep the compiler from
+  // sinking the loads next to their uses.
   __device__ __forceinline__ static void run(AccV (&acc)[MT][NOT], const uint8_t* lds, const i32x4* __restrict__ wp,
                                              const int (&base)[MT], int lane) {
     const int g = lane >> 4;
@@ -253,20 +261,13 @@ struct GemmCore {
     constexpr int NA = ADEPTH + 1;
     i32x4 a[NA][NOT][A::CPL];
 #pragma unroll
-    for (int dd = 0; dd < ADEPTH; ++dd)
-      if (dd < NS) load_a(a[dd], wp, dd, lane);
-    if constexpr (BROLL) {
-      // ring of three activation fragments: pair i = (step i / MT, M-tile i % MT) is read two
-      // pairs ahead of its MFMAs
-      constexpr int NP = NS * MT;
+    for (int d = 0; d < ADEPTH; ++d)
+      if (d < NS) load_a(a[d], wp, d, lane);
+    if constexpr (BMODE == B_RING) {
+      constexpr int NP = NS * MT;  // pair i = (step i / MT, M-tile i % MT)
       i32x4 b[3][A::CPL];
-      auto ld = [&](int i) {
-        const int s = i / MT, mt = i - s * MT;
-#pragma unroll
-        for (int c = 0; c < A::CPL; ++c) b[i % 3][c] = *reinterpret_cast<const i32x4*>(lds + base[mt] + b_off(s, c, g));
-      };
-      ld(0);
-      if (1 < NP) ld(1);
+      load_b(b[0], lds, base[0], 0, g);
+      if (1 < NP) load_b(b[1], lds, base[1 % MT], 1 / MT, g);
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         if (s + ADEPTH < NS) load_a(a[(s + ADEPTH) % NA], wp, s + ADEPTH, lane);
@@ -274,9 +275,25 @@ struct GemmCore {
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
           const int i = s * MT + mt;
-          if (i + 2 < NP) ld(i + 2);
+          if (i + 2 < NP) load_b(b[(i + 2) % 3], lds, base[(i + 2) % MT], (i + 2) / MT, g);
 #pragma unroll
           for (int ot = 0; ot < NOT; ++ot) acc[mt][ot] = A::mma(a[s % NA][ot], b[i % 3], acc[mt][ot]);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    } else if constexpr (BMODE == B_ROLL) {
+      i32x4 b[MT][A::CPL];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) load_b(b[mt], lds, base[mt], 0, g);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        if (s + ADEPTH < NS) load_a(a[(s + ADEPTH) % NA], wp, s + ADEPTH, lane);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+          for (int ot = 0; ot < NOT; ++ot) acc[mt][ot] = A::mma(a[s % NA][ot], b[mt], acc[mt][ot]);
+          if (s + 1 < NS) load_b(b[mt], lds, base[mt], s + 1, g);
           __builtin_amdgcn_sched_barrier(0);
         }
       }
@@ -286,10 +303,7 @@ struct GemmCore {
       for (int s = 0; s < NS; ++s) {
         if (s + ADEPTH < NS) load_a(a[(s + ADEPTH) % NA], wp, s + ADEPTH, lane);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-          for (int c = 0; c < A::CPL; ++c)
-            b[mt][c] = *reinterpret_cast<const i32x4*>(lds + base[mt] + b_off(s, c, g));
+        for (int mt = 0; mt < MT; ++mt) load_b(b[mt], lds, base[mt], s, g);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll

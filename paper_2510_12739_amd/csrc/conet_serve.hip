@@ -11,7 +11,9 @@
 // completion thread that waits for its batch, scatters the LLRs to the callers'
 // buffers and releases the waiters. Packing and scattering are host memory copies on
 // the critical path of every request; a small pool of helper threads splits each over
-// the batch's REs.
+// the batch's REs. A request may carry the received grid instead of the features: the
+// grid (8 bytes per RE and antenna instead of 16) is packed and copied, and the lane forms
+// the features on the GPU (conet_featurise) before the forward.
 //
 // Every slot is computed in tiles that never cross slot boundaries and each kernel's
 // arithmetic per RE does not depend on the other slots, so a request's LLRs are
@@ -135,6 +137,9 @@ struct Lane {
   float* x_dev = nullptr;          // [max_res][C_in]
   float* llr_dev = nullptr;        // [max_res][m]
   float* x_pin = nullptr;          // pinned staging
+  float* y_dev = nullptr;          // received grids of the batch's grid requests, packed
+  float* y_pin = nullptr;
+  std::vector<int64_t> y_off;      // per request of the batch: offset (floats) of its grid in y_pin, or -1
   float* llr_pin = nullptr;
   TileDesc* tiles_pin = nullptr;   // pinned staging of the batch's tile list
   std::vector<Pending> batch;      // requests of the batch in flight
@@ -268,16 +273,33 @@ static void launch_batch(conet_server* S, int li, std::unique_lock<std::mutex>& 
   ++S->batches;
   S->batched_requests += ln.batch.size();
   lk.unlock();
-  // pack features (zero-pad antennas beyond the request's) into pinned staging, each part
-  // its share [r0, r1) of the batch's REs
+  // pack features (zero-pad antennas beyond the request's) into pinned staging, and the
+  // grids of grid requests back to back into their own staging; each part copies its
+  // share [r0, r1) of the batch's REs
   const int Ci = c.in_channels, T = ln.batch[0].req.T;
-  for (auto& p : ln.batch) ln.F.push_back(12 * p.req.n_prb);
+  int64_t y_total = 0;
+  bool any_features = false;
+  ln.y_off.clear();
+  for (auto& p : ln.batch) {
+    ln.F.push_back(12 * p.req.n_prb);
+    if (p.req.input == CONET_INPUT_GRID) {
+      ln.y_off.push_back(y_total);
+      y_total += p.n_re * 2 * p.req.n_rx;
+    } else {
+      ln.y_off.push_back(-1);
+      any_features = true;
+    }
+  }
   S->pool->run([&](int part, int parts) {
     const int64_t r0 = res * part / parts, r1 = res * (part + 1) / parts;
     int64_t off = 0;
-    for (auto& p : ln.batch) {
+    for (size_t q = 0; q < ln.batch.size(); ++q) {
+      const Pending& p = ln.batch[q];
       const int64_t a = std::max(r0, off), b = std::min(r1, off + p.n_re);
-      if (a < b) {
+      if (a < b && ln.y_off[q] >= 0) {
+        const int yc = 2 * p.req.n_rx;
+        memcpy(ln.y_pin + ln.y_off[q] + (a - off) * yc, p.req.x_host + (a - off) * yc, sizeof(float) * (b - a) * yc);
+      } else if (a < b) {
         const int ci = 4 * p.req.n_rx;
         float* dst = ln.x_pin + a * Ci;
         const float* src = p.req.x_host + (a - off) * ci;
@@ -294,9 +316,22 @@ static void launch_batch(conet_server* S, int li, std::unique_lock<std::mutex>& 
     }
   });
   hipError_t e = hipEventRecord(ln.ev_h2d, ln.stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(ln.x_dev, ln.x_pin, sizeof(float) * res * Ci, hipMemcpyHostToDevice, ln.stream);
+  if (e == hipSuccess && any_features)
+    e = hipMemcpyAsync(ln.x_dev, ln.x_pin, sizeof(float) * res * Ci, hipMemcpyHostToDevice, ln.stream);
+  if (e == hipSuccess && y_total > 0)
+    e = hipMemcpyAsync(ln.y_dev, ln.y_pin, sizeof(float) * y_total, hipMemcpyHostToDevice, ln.stream);
   if (e == hipSuccess) e = hipEventRecord(ln.ev_fwd, ln.stream);
   conet_status st = e == hipSuccess ? CONET_OK : hip_fail(e, "serving H2D");
+  {  // features of the grid requests, written where the forward reads them
+    int64_t off = 0;
+    for (size_t q = 0; q < ln.batch.size() && st == CONET_OK; ++q) {
+      const Pending& p = ln.batch[q];
+      if (ln.y_off[q] >= 0)
+        st = conet_featurise(ln.y_dev + ln.y_off[q], 1, T, 12 * p.req.n_prb, p.req.n_rx, Ci, ln.x_dev + off * Ci,
+                             ln.stream);
+      off += p.n_re;
+    }
+  }
   if (st == CONET_OK) {
     Geometry geo;
     geo.uniform = false;
@@ -347,10 +382,13 @@ static void scheduler_loop(conet_server* S) {
   }
 }
 
+// grid staging: at most C_in / 4 antennas of (Re, Im) per RE
+static size_t grid_floats(const conet_config& c, int64_t res) { return (size_t)res * (c.in_channels / 4) * 2; }
+
 static size_t lane_bytes(const conet_config& c, int64_t res) {
   auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
   return a256(arena_bytes(c, res)) + a256(sizeof(float) * res * c.in_channels) +
-         a256(sizeof(float) * res * c.bits_per_symbol);
+         a256(sizeof(float) * res * c.bits_per_symbol) + a256(sizeof(float) * grid_floats(c, res));
 }
 
 }  // namespace conet
@@ -396,6 +434,9 @@ conet_status conet_serve_create(conet_model* M, size_t mem_budget_bytes, int32_t
     if (e != hipSuccess) break;
     ln.x_dev = reinterpret_cast<float*>(ln.dev + a256(arena_bytes(c, lane_res)));
     ln.llr_dev = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(ln.x_dev) + a256(sizeof(float) * lane_res * c.in_channels));
+    ln.y_dev = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(ln.llr_dev) + a256(sizeof(float) * lane_res * c.bits_per_symbol));
+    e = hipHostMalloc(&ln.y_pin, sizeof(float) * grid_floats(c, lane_res), hipHostMallocDefault);
+    if (e != hipSuccess) break;
   }
   if (e != hipSuccess) {
     conet_status st = hip_fail(e, "serving lane set-up");
@@ -407,6 +448,7 @@ conet_status conet_serve_create(conet_model* M, size_t mem_budget_bytes, int32_t
       if (ln.x_pin) (void)hipHostFree(ln.x_pin);
       if (ln.llr_pin) (void)hipHostFree(ln.llr_pin);
       if (ln.tiles_pin) (void)hipHostFree(ln.tiles_pin);
+      if (ln.y_pin) (void)hipHostFree(ln.y_pin);
     }
     delete S;
     return st;
@@ -426,6 +468,10 @@ conet_status conet_serve_submit(conet_server* S, const conet_request* r, uint64_
       r->bits_per_symbol < 1 || r->bits_per_symbol > c.bits_per_symbol)
     return fail(CONET_ESHAPE, "request does not fit the model (T=%d n_prb=%d n_rx=%d m=%d)", r->T, r->n_prb, r->n_rx,
                 r->bits_per_symbol);
+  if (r->input != CONET_INPUT_FEATURES && r->input != CONET_INPUT_GRID)
+    return fail(CONET_EINVAL, "input must be CONET_INPUT_FEATURES or CONET_INPUT_GRID");
+  if (r->input == CONET_INPUT_GRID && r->T < 12)
+    return fail(CONET_ESHAPE, "a grid request needs T >= 12 (pilots on symbols 2 and 11)");
   const int64_t n_re = (int64_t)r->T * 12 * r->n_prb;
   std::lock_guard<std::mutex> lk(S->mu);
   if (n_re > S->lane_res) {
@@ -550,6 +596,7 @@ conet_status conet_serve_destroy(conet_server* S) {
     (void)hipHostFree(ln.x_pin);
     (void)hipHostFree(ln.llr_pin);
     (void)hipHostFree(ln.tiles_pin);
+    (void)hipHostFree(ln.y_pin);
   }
   delete S->pool;
   delete S;

@@ -18,9 +18,10 @@ class Request:
     n_prb: int
     n_rx: int
     m: int
-    x: np.ndarray           # [14, 12 n_prb, 4 n_rx] float32
+    x: np.ndarray           # [14, 12 n_prb, 4 n_rx] float32 features
     bits: np.ndarray        # [14, 12 n_prb, m] uint8
     seed: int
+    y: np.ndarray = None    # [14, 12 n_prb, n_rx, 2] float32 received grid (Re, Im)
 
 
 def make_requests(n: int, seed: int = 5, prb_range=(4, 273)) -> List[Request]:
@@ -34,7 +35,8 @@ def make_requests(n: int, seed: int = 5, prb_range=(4, 273)) -> List[Request]:
         m = int(BITS[rng.integers(0, 3)])
         sim = SimConfig(F=12 * n_prb, n_rx=n_rx, bits_per_symbol=m, n_taps=8, max_doppler_hz=400.0, seed=seed)
         sl = simulate_slot(sim, i)
-        out.append(Request(n_prb, n_rx, m, sl.features, sl.bits, i))
+        y = np.stack([sl.y.real, sl.y.imag], axis=-1).astype(np.float32)
+        out.append(Request(n_prb, n_rx, m, sl.features, sl.bits, i, y))
     return out
 
 

@@ -75,6 +75,40 @@ def test_served_llrs_match_oracle(served):
         assert rel_l2(llr, ref) <= 3e-2 and sign_agree(llr, ref) >= 0.99
 
 
+def test_grid_requests_featurised_on_the_gpu(served):
+    """Requests carrying the received grid instead of the features: the server forms the
+    features with the library's featuriser. Each request's LLRs equal, bitwise, the model's
+    forward on conet_featurise of the same grid, alone and in a batch mixed with feature
+    requests; and they match the oracle (its own featuriser and the BF16-emulating forward)."""
+    from paper_2510_12739_amd import Server, featurise
+    from oracle import featurise as of
+    model, blob, mc = served
+    reqs = make_requests(8, seed=9, prb_range=(4, 40))
+    srv = Server(model, mem_budget=2 << 30, n_streams=2, max_batch_res=200_000)
+    say("serving: 8 grid requests mixed with 8 feature requests")
+    outs = []
+    for r in reqs:
+        outs.append(srv.submit(r.y, r.n_prb, r.n_rx, r.m, grid=True))
+        outs.append(srv.submit(r.x, r.n_prb, r.n_rx, r.m))
+    for t, _ in outs:
+        srv.wait(t)
+    with pytest.raises(Exception, match="T >= 12"):
+        srv.submit(np.ascontiguousarray(reqs[0].y[:10]), reqs[0].n_prb, reqs[0].n_rx, reqs[0].m, T=10, grid=True)
+    srv.close()
+    p = o.unpack(blob, mc.K, mc.L, mc.C, mc.C_in, mc.m)
+    for i, r in enumerate(reqs):
+        grid_llr, feat_llr = outs[2 * i][1], outs[2 * i + 1][1]
+        X = featurise(torch.from_numpy(r.y[None]).cuda(), mc.C_in)
+        alone = model(X)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(grid_llr, alone.cpu().numpy()[0, ..., :r.m])
+        Xo = of.features((r.y[..., 0].astype(np.float64) + 1j * r.y[..., 1].astype(np.float64))[None], mc.C_in)
+        emu = o.forward(p, Xo, quant=o.Quant("bf16"))[0, ..., :r.m]
+        assert rel_l2(grid_llr, emu) <= 5e-3, rel_l2(grid_llr, emu)
+        # the simulator's own features (FP64 LS, rounded to FP32) give nearly the same LLRs
+        assert rel_l2(grid_llr, feat_llr) <= 5e-3, rel_l2(grid_llr, feat_llr)
+
+
 def test_backpressure_timeout_and_rejection(served):
     """Conditions forced from the host: a paused server queues, refuses beyond max_queue
     (EBUSY), and a wait on a queued request times out (ETIMEOUT); resuming drains it."""
