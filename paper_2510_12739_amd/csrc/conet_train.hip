@@ -4,9 +4,11 @@
 //    dOut[re][o] * In[re + tap][ch]. The reduction runs over REs, so both operands are
 //    staged into LDS transposed (channel-major, RE-contiguous): an MFMA lane then reads
 //    VEC consecutive REs of one channel with one 16-byte load. Taps shifted along the
-//    subcarrier axis read two aligned 16-byte words and funnel-shift them. Each
-//    work-group loops over a share of the tiles and writes one partial row; the rows
-//    are summed in a fixed order by reduce_kernel (deterministic, no atomics).
+//    subcarrier axis read two aligned 16-byte words and funnel-shift them. A thread
+//    issues all of its staging loads of a tile before consuming any (one load in flight
+//    at a time made the staging three times longer than the MFMAs). Each work-group
+//    loops over a share of the tiles and writes one partial row; the rows are summed in
+//    a fixed order by reduce_kernel (deterministic, no atomics).
 //  * fuse_bwd_kernel: adjoint of the head, the per-RE LayerNorm and the K-way product,
 //    dO[k] = dP * prod_{j != k} O[j] (no division, so exact zeros are handled).
 //  * bce_kernel, adam_kernel, repack_kernel, gather_kernel, reduce_kernel.
@@ -104,52 +106,76 @@ __global__ void __launch_bounds__(256, 1) wgrad_kernel(WgradArgs args) {
     const int f0 = (tile - b * args.tiles_per_slot) * TW;
     const int64_t re_base = (int64_t)b * T * args.F;
     __syncthreads();  // the previous tile's LDS reads are done
-    // dOut tile [TMAX][TW] transposed to [o][t][c]
-    for (int idx = tid; idx < TMAX * TW * CPD; idx += NT) {
-      const int pos = idx / CPD;
-      const int t = pos / TW, c = pos - t * TW, f = f0 + c;
-      float v[EPD];
-      if (t < T && f < args.F) {
-        const i32x4 raw = *reinterpret_cast<const i32x4*>(dout + (re_base + (int64_t)t * args.F + f) * COUT + ccD * EPD);
-        to_elems(raw, v, (const Act*)nullptr);
+    // dOut tile [TMAX][TW] transposed to [o][t][c]. All of a thread's 16-byte loads are
+    // issued before any is consumed, so their latencies overlap.
+    {
+      constexpr int ND = (TMAX * TW * CPD + NT - 1) / NT;
+      i32x4 raw[ND];
 #pragma unroll
-        for (int i = 0; i < EPD; ++i) bsum[i] += v[i];
-      } else {
-#pragma unroll
-        for (int i = 0; i < EPD; ++i) v[i] = 0.f;
+      for (int u = 0; u < ND; ++u) {
+        const int idx = tid + u * NT;
+        const int pos = idx / CPD;
+        const int t = pos / TW, c = pos - t * TW, f = f0 + c;
+        raw[u] = i32x4{0, 0, 0, 0};
+        if (idx < TMAX * TW * CPD && t < T && f < args.F)
+          raw[u] = *reinterpret_cast<const i32x4*>(dout + (re_base + (int64_t)t * args.F + f) * COUT + ccD * EPD);
       }
 #pragma unroll
-      for (int i = 0; i < EPD; ++i) st_elem<E>(ldsD + (ccD * EPD + i) * DS + (t * TW + c) * (int)sizeof(E), v[i]);
+      for (int u = 0; u < ND; ++u) {
+        const int idx = tid + u * NT;
+        if (idx >= TMAX * TW * CPD) break;
+        const int pos = idx / CPD;
+        const int t = pos / TW, c = pos - t * TW;
+        float v[EPD];
+        to_elems(raw[u], v, (const Act*)nullptr);  // zero outside the slot
+#pragma unroll
+        for (int i = 0; i < EPD; ++i) {
+          bsum[i] += v[i];
+          st_elem<E>(ldsD + (ccD * EPD + i) * DS + (t * TW + c) * (int)sizeof(E), v[i]);
+        }
+      }
     }
     // In halo tile [TROWS][TW+2] (prologue, then zero padding) transposed to [ch][r][c]
-    for (int idx = tid; idx < TROWS * (TW + 2) * CPI; idx += NT) {
-      const int pos = idx / CPI;
-      const int r = pos / (TW + 2), c = pos - r * (TW + 2);
-      const int t = r - 1, f = f0 + c - 1;
-      float v[EPI];
-      if (t >= 0 && t < T && f >= 0 && f < args.F) {
-        const InT* src = in + (re_base + (int64_t)t * args.F + f) * CIN + ccI * EPI;
-        if constexpr (sizeof(InT) == 4) {
-          const float4 q = *reinterpret_cast<const float4*>(src);
-          v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    {
+      constexpr int NI = (TROWS * (TW + 2) * CPI + NT - 1) / NT;
+      i32x4 raw[NI];
+      bool ok[NI];
 #pragma unroll
-          for (int i = 4; i < EPI; ++i) v[i] = 0.f;
-        } else {
-          to_elems(*reinterpret_cast<const i32x4*>(src), v, (const InT*)nullptr);
-        }
-        if (pro == 1) {
-#pragma unroll
-          for (int i = 0; i < EPI; ++i) v[i] = fmaxf(sv[i] * v[i] + ov[i], 0.f);
-        } else if (pro == 2) {
-#pragma unroll
-          for (int i = 0; i < EPI; ++i) v[i] = fmaxf(v[i], 0.f);
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < EPI; ++i) v[i] = 0.f;
+      for (int u = 0; u < NI; ++u) {
+        const int idx = tid + u * NT;
+        const int pos = idx / CPI;
+        const int r = pos / (TW + 2), c = pos - r * (TW + 2);
+        const int t = r - 1, f = f0 + c - 1;
+        ok[u] = idx < TROWS * (TW + 2) * CPI && t >= 0 && t < T && f >= 0 && f < args.F;
+        raw[u] = i32x4{0, 0, 0, 0};
+        if (ok[u]) raw[u] = *reinterpret_cast<const i32x4*>(in + (re_base + (int64_t)t * args.F + f) * CIN + ccI * EPI);
       }
 #pragma unroll
-      for (int i = 0; i < EPI; ++i) st_elem<E>(ldsI + (ccI * EPI + i) * IS + (r * ICOLS + c) * (int)sizeof(E), v[i]);
+      for (int u = 0; u < NI; ++u) {
+        const int idx = tid + u * NT;
+        if (idx >= TROWS * (TW + 2) * CPI) break;
+        const int pos = idx / CPI;
+        const int r = pos / (TW + 2), c = pos - r * (TW + 2);
+        float v[EPI];
+        if constexpr (sizeof(InT) == 4) {
+          const float* q = reinterpret_cast<const float*>(&raw[u]);
+#pragma unroll
+          for (int i = 0; i < EPI; ++i) v[i] = i < 4 ? q[i] : 0.f;
+        } else {
+          to_elems(raw[u], v, (const InT*)nullptr);
+        }
+        if (ok[u]) {
+          if (pro == 1) {
+#pragma unroll
+            for (int i = 0; i < EPI; ++i) v[i] = fmaxf(sv[i] * v[i] + ov[i], 0.f);
+          } else if (pro == 2) {
+#pragma unroll
+            for (int i = 0; i < EPI; ++i) v[i] = fmaxf(v[i], 0.f);
+          }
+        }  // else: zero padding (the raw value is zero)
+#pragma unroll
+        for (int i = 0; i < EPI; ++i) st_elem<E>(ldsI + (ccI * EPI + i) * IS + (r * ICOLS + c) * (int)sizeof(E), v[i]);
+      }
     }
     __syncthreads();
     for (int t = 0; t < T; ++t) {  // one MFMA K step per OFDM symbol: TW REs = 4 lane groups x VEC
