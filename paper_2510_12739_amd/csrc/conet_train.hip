@@ -255,13 +255,17 @@ hipError_t launch_wgrad(int dtype, bool in_f32, int cin, int cout, WgradArgs& a,
 }
 
 // ---------------------------------------------------------------- head / LN / product adjoint
-template <class Act, int C, int KB>
+// HEAD: this launch also back-propagates through the LLR head (the last block) and
+// accumulates the head's gradients; the other launches leave those registers out, which
+// lets two waves share a SIMD.
+template <class Act, int C, int KB, bool HEAD>
 __global__ void __launch_bounds__(256) fuse_bwd_kernel(FuseBwdArgs a) {
   constexpr int QC = C / 4;
   const int tid = threadIdx.x, q = tid & 3, wave = tid >> 6;
   const int c0 = q * QC;
   const int m = a.m;
-  float gam[QC], bet[QC], bet_acc[QC], gam_acc[QC], wh_acc[8][QC], bh_acc[8];
+  constexpr int NH = HEAD ? 8 : 1;  // head outputs accumulated by this launch
+  float gam[QC], bet[QC], bet_acc[QC], gam_acc[QC], wh_acc[NH][QC], bh_acc[NH];
 #pragma unroll
   for (int i = 0; i < QC; ++i) {
     gam[i] = a.fused ? a.gamma[c0 + i] : 1.f;
@@ -270,7 +274,7 @@ __global__ void __launch_bounds__(256) fuse_bwd_kernel(FuseBwdArgs a) {
     gam_acc[i] = 0.f;
   }
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
+  for (int j = 0; j < NH; ++j) {
     bh_acc[j] = 0.f;
 #pragma unroll
     for (int i = 0; i < QC; ++i) wh_acc[j][i] = 0.f;
@@ -311,7 +315,7 @@ __global__ void __launch_bounds__(256) fuse_bwd_kernel(FuseBwdArgs a) {
     }
     // gradient of the block's main activation
     float dA[QC];
-    if (a.head) {
+    if constexpr (HEAD) {
       float dl[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) dl[j] = j < m ? a.dllr[re * m + j] : 0.f;
@@ -325,7 +329,7 @@ __global__ void __launch_bounds__(256) fuse_bwd_kernel(FuseBwdArgs a) {
       }
       // head parameters: A = gamma ahat + beta (fused) or O[0] (unfused)
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < NH; ++j) {
         if (j >= m) continue;
         if (q == 0) bh_acc[j] += dl[j];
 #pragma unroll
@@ -405,13 +409,13 @@ __global__ void __launch_bounds__(256) fuse_bwd_kernel(FuseBwdArgs a) {
     if ((tid & 63) < 4) { red[wave][c0 + i] = ga; red[wave][C + c0 + i] = ba; }
   }
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
+  for (int j = 0; j < 8; ++j) {  // head gradients (zero rows for the other launches)
 #pragma unroll
     for (int i = 0; i < QC; ++i) {
-      const float w = wsum(wh_acc[j][i]);
+      const float w = j < NH ? wsum(wh_acc[j < NH ? j : 0][i]) : 0.f;
       if ((tid & 63) < 4) red[wave][2 * C + j * C + c0 + i] = w;
     }
-    const float bsum = wsum(bh_acc[j]);
+    const float bsum = j < NH ? wsum(bh_acc[j < NH ? j : 0]) : 0.f;
     if ((tid & 63) == 0) red[wave][10 * C + j] = bsum;
   }
   __syncthreads();
@@ -421,7 +425,11 @@ __global__ void __launch_bounds__(256) fuse_bwd_kernel(FuseBwdArgs a) {
 
 hipError_t launch_fuse_bwd(int dtype, FuseBwdArgs& a, int grid, hipStream_t s) {
 #define CONET_FB(E, C_, K_) \
-  if (a.C == C_ && a.K == K_) { hipLaunchKernelGGL((fuse_bwd_kernel<E, C_, K_>), dim3(grid), dim3(256), 0, s, a); return hipGetLastError(); }
+  if (a.C == C_ && a.K == K_) {                                                                          \
+    if (a.head) hipLaunchKernelGGL((fuse_bwd_kernel<E, C_, K_, true>), dim3(grid), dim3(256), 0, s, a);     \
+    else hipLaunchKernelGGL((fuse_bwd_kernel<E, C_, K_, false>), dim3(grid), dim3(256), 0, s, a);           \
+    return hipGetLastError();                                                                            \
+  }
 #define CONET_FBC(E, C_) CONET_FB(E, C_, 1) CONET_FB(E, C_, 2) CONET_FB(E, C_, 3) CONET_FB(E, C_, 4)
   if (dtype == DT_BF16) { CONET_FBC(__bf16, 16) CONET_FBC(__bf16, 32) CONET_FBC(__bf16, 64) }
   if (dtype == DT_F32) { CONET_FBC(float, 16) CONET_FBC(float, 32) CONET_FBC(float, 64) }
