@@ -235,8 +235,13 @@ typedef struct {
   int32_t T;                /* OFDM symbols (1..14; all requests of a server share T)        */
   const float* x_host;      /* host FP32 input, read when the request is batched: features
                                [T][F][4*n_rx] (input = CONET_INPUT_FEATURES), or the received
-                               grid [T][F][n_rx][2] (Re, Im; input = CONET_INPUT_GRID)       */
-  float* llr_host;          /* host [T][F][m] FP32 output; written before conet_serve_wait returns */
+                               grid [T][F][n_rx][2] (Re, Im; input = CONET_INPUT_GRID).
+                               Page-locked memory (hipHostMalloc) is read by DMA with no host
+                               copy, for grids and for features with all C_in channels; other
+                               inputs are packed into the server's pinned staging first     */
+  float* llr_host;          /* host [T][F][m] FP32 output; written before conet_serve_wait
+                               returns. Page-locked memory is written by DMA; other buffers
+                               receive a host copy from the server's pinned staging         */
   uint64_t tag;             /* caller's value, unused by the library                        */
   int32_t input;            /* CONET_INPUT_FEATURES (0) or CONET_INPUT_GRID (1): the server forms
                                the features on the GPU with conet_featurise (pilots on symbols
@@ -254,12 +259,15 @@ typedef struct {
   int64_t lane_res;                        /* REs one lane admits                          */
   /* where the mean latency goes, per completed request: waiting in the queue; forming its
    * batch (feature packing, enqueueing copies and kernels); enqueued -> the batch's
-   * completion seen on the host (H2D, forward, D2H, plus the wait's wake-up); scattering
-   * the LLRs to the callers' buffers */
+   * completion seen on the host (H2D, forward, D2H, plus the wait's wake-up); copying
+   * the LLRs from pinned staging to the callers' buffers that are not page-locked */
   double mean_queue_us, mean_prep_us, mean_device_us, mean_scatter_us;
-  /* GPU-timed parts of the device phase (stream events): the feature copy, the forward,
-   * the LLR copy of the request's batch */
+  /* GPU-timed parts of the device phase (stream events): the input copies, the forward
+   * (with featurisation and the packing of narrower LLRs), the LLR copies of the batch */
   double mean_h2d_us, mean_forward_us, mean_d2h_us;
+  /* completed requests whose input / LLRs went by DMA straight from / to the caller's
+   * page-locked buffer */
+  uint64_t direct_inputs, direct_outputs;
 } conet_serve_stats;
 
 /* Start a server on `model` (which must outlive it): n_streams lanes of up to

@@ -55,7 +55,8 @@ class conet_serve_stats(ctypes.Structure):
                 ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64), ("batches", ctypes.c_uint64),
                 ("lane_res", ctypes.c_int64), ("mean_queue_us", ctypes.c_double), ("mean_prep_us", ctypes.c_double),
                 ("mean_device_us", ctypes.c_double), ("mean_scatter_us", ctypes.c_double),
-                ("mean_h2d_us", ctypes.c_double), ("mean_forward_us", ctypes.c_double), ("mean_d2h_us", ctypes.c_double)]
+                ("mean_h2d_us", ctypes.c_double), ("mean_forward_us", ctypes.c_double), ("mean_d2h_us", ctypes.c_double),
+                ("direct_inputs", ctypes.c_uint64), ("direct_outputs", ctypes.c_uint64)]
 
 
 _lib = None
@@ -301,10 +302,21 @@ class Conet:
             pass
 
 
+def pinned_array(shape, dtype=np.float32) -> np.ndarray:
+    """A zeroed numpy array in page-locked host memory (torch's pinned allocator); the array
+    keeps that memory alive."""
+    import torch
+    tdt = {np.dtype(np.float32): torch.float32, np.dtype(np.uint8): torch.uint8}[np.dtype(dtype)]
+    n = int(np.prod(shape))
+    return torch.zeros(n, dtype=tdt, pin_memory=True).numpy().reshape(shape)
+
+
 class Server:
     """Continuous-batching server over a Conet model (lanes = HIP streams with own buffers).
 
-    submit() copies nothing: the feature and LLR arrays are held until wait() returns.
+    submit() copies nothing: the feature and LLR arrays are held until wait() returns. Arrays
+    from pinned_array() are page-locked: the server reads and writes them by DMA, with no host
+    copy (inputs: grids, and features with all C_in channels).
     """
 
     def __init__(self, model: Conet, mem_budget: int = 8 << 30, n_streams: int = 2, max_batch_res: int = 1 << 20,
@@ -328,6 +340,8 @@ class Server:
             raise ValueError(f"x has shape {x.shape}, expected {want}")
         if out is None:
             out = np.empty((T, F, m), dtype=np.float32)
+        elif out.dtype != np.float32 or not out.flags.c_contiguous or out.shape != (T, F, m):
+            raise ValueError(f"out must be a C-contiguous float32 array of shape {(T, F, m)}")
         req = conet_request(n_prb, n_rx, m, T, x.ctypes.data, out.ctypes.data, 0, 1 if grid else 0)
         t = ctypes.c_uint64()
         _check(self.lib.conet_serve_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))

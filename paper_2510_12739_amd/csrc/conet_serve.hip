@@ -4,16 +4,22 @@
 // model's head width) are queued by conet_serve_submit. A scheduler thread forms a
 // ragged batch whenever one of the server's lanes is free: it takes queued requests in
 // arrival order while their REs fit the lane's buffers (admission by memory; a request
-// never waits for a batch to fill), packs their features into the lane's pinned staging
-// buffer (zero-padding missing antennas), and enqueues H2D copy -> ragged forward ->
-// D2H copy on the lane's stream. Lanes run on separate streams, so a batch formed
-// while others are on the GPU overlaps with them on the device. Each lane has a
-// completion thread that waits for its batch, scatters the LLRs to the callers'
-// buffers and releases the waiters. Packing and scattering are host memory copies on
-// the critical path of every request; a small pool of helper threads splits each over
-// the batch's REs. A request may carry the received grid instead of the features: the
-// grid (8 bytes per RE and antenna instead of 16) is packed and copied, and the lane forms
-// the features on the GPU (conet_featurise) before the forward.
+// never waits for a batch to fill), and enqueues H2D copies -> ragged forward -> D2H
+// copies on the lane's stream. Lanes run on separate streams, so a batch formed while
+// others are on the GPU overlaps with them on the device. Each lane has a completion
+// thread that waits for its batch, moves the LLRs to the callers' buffers where the
+// copy engines could not, and releases the waiters.
+//
+// A request may carry the received grid instead of the features: the grid (8 bytes per RE
+// and antenna instead of 16) is copied, and the lane forms the features on the GPU
+// (conet_featurise) before the forward. Inputs in page-locked caller memory that need no
+// reshaping (grids, and features with all C_in channels) are copied by DMA straight from
+// the caller's buffer; the rest are first packed into the lane's pinned staging buffer
+// (zero-padding missing antennas). On the way out, a request whose modulation uses fewer
+// bits than the head's width has its LLR channels packed on the GPU, and the LLRs go by
+// DMA to the caller's buffer when it is page-locked, else to pinned staging followed by a
+// host copy. Host copies are on the critical path of every request that needs them; a
+// small pool of helper threads splits each over the batch.
 //
 // Every slot is computed in tiles that never cross slot boundaries and each kernel's
 // arithmetic per RE does not depend on the other slots, so a request's LLRs are
@@ -41,20 +47,42 @@ using clk = std::chrono::steady_clock;
 
 constexpr int SERVE_COPY_HELPERS = 3;  // host copies run on the calling thread + 3 helpers
 
-// The first mq of every m LLRs of n REs (a request's modulation below the head width).
-template <int MQ>
-static void copy_llr_fixed(float* dst, const float* src, int64_t n, int m) {
-  for (int64_t r = 0; r < n; ++r)
-    for (int j = 0; j < MQ; ++j) dst[r * MQ + j] = src[r * m + j];
+// LLR channels 0..mq-1 of each of n REs whose LLRs are m apart, written back to back
+// (a request whose modulation uses fewer bits than the head's width).
+__global__ void __launch_bounds__(256) compact_llr_kernel(const float* __restrict__ src, float* __restrict__ dst,
+                                                          int64_t n, int m, int mq) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n * mq) return;
+  const int64_t r = i / mq;
+  dst[i] = src[r * m + (i - r * mq)];
 }
-static void copy_llr(float* dst, const float* src, int64_t n, int m, int mq) {
-  switch (mq) {
-    case 2: copy_llr_fixed<2>(dst, src, n, m); return;
-    case 4: copy_llr_fixed<4>(dst, src, n, m); return;
-    default:
-      for (int64_t r = 0; r < n; ++r)
-        for (int j = 0; j < mq; ++j) dst[r * mq + j] = src[r * m + j];
+
+// Whether [p, p + bytes) lies in one page-locked host allocation (hipHostMalloc), which the
+// copy engines read and write directly. A pageable pointer makes the query fail on some
+// runtimes; that error is taken back so that it is not reported by a later call.
+static bool host_pinned(const void* p, size_t bytes) {
+  const char* q = static_cast<const char*>(p);
+  hipPointerAttribute_t a0{}, a1{};
+  hipError_t e0 = hipPointerGetAttributes(&a0, q);
+  hipError_t e1 = e0 == hipSuccess ? hipPointerGetAttributes(&a1, q + bytes - 1) : e0;
+  if (e0 != hipSuccess || e1 != hipSuccess) (void)hipGetLastError();
+  return e0 == hipSuccess && e1 == hipSuccess && a0.type == hipMemoryTypeHost && a1.type == hipMemoryTypeHost &&
+         static_cast<const char*>(a1.devicePointer) - static_cast<const char*>(a0.devicePointer) == (ptrdiff_t)(bytes - 1);
+}
+
+// One DMA copy; consecutive pieces that continue each other on both sides merge.
+struct CopyRun {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+static void add_copy(std::vector<CopyRun>& v, void* dst, const void* src, size_t bytes) {
+  if (!v.empty() && static_cast<char*>(v.back().dst) + v.back().bytes == dst &&
+      static_cast<const char*>(v.back().src) + v.back().bytes == src) {
+    v.back().bytes += bytes;
+    return;
   }
+  v.push_back({dst, src, bytes});
 }
 
 // Fixed helper threads for the batch's host copies: run(fn) calls fn(part, parts) for
@@ -120,6 +148,9 @@ struct Pending {
   uint64_t ticket;
   clk::time_point t_submit;
   int64_t n_re;
+  // the input is copied by DMA from the caller's buffer (page-locked, and a grid or features
+  // with all C_in channels); the LLRs are copied by DMA to the caller's buffer (page-locked)
+  bool x_direct = false, llr_direct = false;
 };
 
 struct Done {
@@ -136,10 +167,13 @@ struct Lane {
   Arena arena;
   float* x_dev = nullptr;          // [max_res][C_in]
   float* llr_dev = nullptr;        // [max_res][m]
+  float* llr_c = nullptr;          // LLRs of requests with fewer than m bits, packed at c_off
   float* x_pin = nullptr;          // pinned staging
   float* y_dev = nullptr;          // received grids of the batch's grid requests, packed
   float* y_pin = nullptr;
   std::vector<int64_t> y_off;      // per request of the batch: offset (floats) of its grid in y_pin, or -1
+  std::vector<int64_t> c_off;      // per request: offset (floats) of its mq-wide LLRs in llr_c and llr_pin
+  std::vector<CopyRun> h2d, d2h;   // the batch's DMA copies
   float* llr_pin = nullptr;
   TileDesc* tiles_pin = nullptr;   // pinned staging of the batch's tile list
   std::vector<Pending> batch;      // requests of the batch in flight
@@ -171,7 +205,7 @@ struct conet_server {
   std::thread scheduler;
   // statistics
   std::vector<double> lat_us;
-  uint64_t completed = 0, rejected = 0, batches = 0, batched_requests = 0;
+  uint64_t completed = 0, rejected = 0, batches = 0, batched_requests = 0, direct_inputs = 0, direct_outputs = 0;
   int64_t res_done = 0;
   double sum_queue_us = 0, sum_prep_us = 0, sum_device_us = 0, sum_scatter_us = 0;
   double sum_h2d_us = 0, sum_fwd_us = 0, sum_d2h_us = 0;
@@ -185,7 +219,6 @@ namespace conet {
 static void lane_wait_loop(conet_server* S, int li) {
   Lane& ln = S->lanes[li];
   (void)hipSetDevice(S->device);
-  const int m = S->M->cfg.bits_per_symbol;
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
@@ -199,29 +232,25 @@ static void lane_wait_loop(conet_server* S, int li) {
     if (e == hipSuccess) e = hipEventElapsedTime(&ms_fwd, ln.ev_fwd, ln.ev_d2h);
     if (e == hipSuccess) e = hipEventElapsedTime(&ms_d2h, ln.ev_d2h, ln.ev);
     auto us = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double, std::micro>(b - a).count(); };
-    // scatter LLRs: slot s's REs start at its offset; the head has m outputs per RE. Each
-    // part copies its share [r0, r1) of the batch's REs.
+    // LLRs that went to pinned staging: request q's n_re * mq floats sit at c_off[q]. Each
+    // part copies its share [r0, r1) of those floats, counted over the batch's requests.
     if (e == hipSuccess) {
       int64_t total = 0;
-      for (auto& p : ln.batch) total += p.n_re;
-      S->pool->run([&](int part, int parts) {
-        const int64_t r0 = total * part / parts, r1 = total * (part + 1) / parts;
-        int64_t off = 0;
-        for (auto& p : ln.batch) {
-          const int64_t a = std::max(r0, off), b = std::min(r1, off + p.n_re);
-          if (a < b) {
-            const int mq = p.req.bits_per_symbol;
-            const float* src = ln.llr_pin + a * m;
-            float* dst = p.req.llr_host + (a - off) * mq;
-            if (mq == m) {
-              memcpy(dst, src, sizeof(float) * (b - a) * m);
-            } else {
-              copy_llr(dst, src, b - a, m, mq);
-            }
+      for (auto& p : ln.batch)
+        if (!p.llr_direct) total += p.n_re * p.req.bits_per_symbol;
+      if (total > 0)
+        S->pool->run([&](int part, int parts) {
+          const int64_t r0 = total * part / parts, r1 = total * (part + 1) / parts;
+          int64_t off = 0;
+          for (size_t q = 0; q < ln.batch.size(); ++q) {
+            const Pending& p = ln.batch[q];
+            if (p.llr_direct) continue;
+            const int64_t n = p.n_re * p.req.bits_per_symbol;
+            const int64_t a = std::max(r0, off), b = std::min(r1, off + n);
+            if (a < b) memcpy(p.req.llr_host + (a - off), ln.llr_pin + ln.c_off[q] + (a - off), sizeof(float) * (b - a));
+            off += n;
           }
-          off += p.n_re;
-        }
-      });
+        });
     }
     const auto t_done = clk::now();
     {
@@ -234,6 +263,8 @@ static void lane_wait_loop(conet_server* S, int li) {
         if (e == hipSuccess) {
           S->lat_us.push_back(d.latency_us);
           ++S->completed;
+          S->direct_inputs += p.x_direct;
+          S->direct_outputs += p.llr_direct;
           S->res_done += p.n_re;
           S->sum_queue_us += us(p.t_submit, ln.t_formed);
           S->sum_prep_us += us(ln.t_formed, ln.t_enqueued);
@@ -273,36 +304,40 @@ static void launch_batch(conet_server* S, int li, std::unique_lock<std::mutex>& 
   ++S->batches;
   S->batched_requests += ln.batch.size();
   lk.unlock();
-  // pack features (zero-pad antennas beyond the request's) into pinned staging, and the
-  // grids of grid requests back to back into their own staging; each part copies its
-  // share [r0, r1) of the batch's REs
-  const int Ci = c.in_channels, T = ln.batch[0].req.T;
+  // Inputs: a grid goes to its packed place in y (featurised below), features to their REs'
+  // rows of x. A page-locked caller buffer that needs no reshaping is the DMA source itself;
+  // the others are packed into pinned staging first, each part of the pool copying its share
+  // [r0, r1) of the batch's REs (zero-padding antennas beyond the request's).
+  const int Ci = c.in_channels, m = c.bits_per_symbol, T = ln.batch[0].req.T;
+  const size_t nb = ln.batch.size();
   int64_t y_total = 0;
-  bool any_features = false;
+  bool any_pack = false;
   ln.y_off.clear();
   for (auto& p : ln.batch) {
     ln.F.push_back(12 * p.req.n_prb);
-    if (p.req.input == CONET_INPUT_GRID) {
-      ln.y_off.push_back(y_total);
-      y_total += p.n_re * 2 * p.req.n_rx;
-    } else {
-      ln.y_off.push_back(-1);
-      any_features = true;
-    }
+    const bool grid = p.req.input == CONET_INPUT_GRID;
+    ln.y_off.push_back(grid ? y_total : -1);
+    if (grid) y_total += p.n_re * 2 * p.req.n_rx;
+    any_pack |= !p.x_direct;
   }
-  S->pool->run([&](int part, int parts) {
-    const int64_t r0 = res * part / parts, r1 = res * (part + 1) / parts;
-    int64_t off = 0;
-    for (size_t q = 0; q < ln.batch.size(); ++q) {
-      const Pending& p = ln.batch[q];
-      const int64_t a = std::max(r0, off), b = std::min(r1, off + p.n_re);
-      if (a < b && ln.y_off[q] >= 0) {
-        const int yc = 2 * p.req.n_rx;
-        memcpy(ln.y_pin + ln.y_off[q] + (a - off) * yc, p.req.x_host + (a - off) * yc, sizeof(float) * (b - a) * yc);
-      } else if (a < b) {
+  if (any_pack)
+    S->pool->run([&](int part, int parts) {
+      const int64_t r0 = res * part / parts, r1 = res * (part + 1) / parts;
+      int64_t off = 0;
+      for (size_t q = 0; q < nb; ++q) {
+        const Pending& p = ln.batch[q];
+        const int64_t a = std::max(r0, off), b = std::min(r1, off + p.n_re);
+        off += p.n_re;
+        if (a >= b || p.x_direct) continue;
+        const int64_t o = off - p.n_re;
+        if (ln.y_off[q] >= 0) {
+          const int yc = 2 * p.req.n_rx;
+          memcpy(ln.y_pin + ln.y_off[q] + (a - o) * yc, p.req.x_host + (a - o) * yc, sizeof(float) * (b - a) * yc);
+          continue;
+        }
         const int ci = 4 * p.req.n_rx;
         float* dst = ln.x_pin + a * Ci;
-        const float* src = p.req.x_host + (a - off) * ci;
+        const float* src = p.req.x_host + (a - o) * ci;
         if (ci == Ci) {
           memcpy(dst, src, sizeof(float) * (b - a) * Ci);
         } else {
@@ -312,19 +347,29 @@ static void launch_batch(conet_server* S, int li, std::unique_lock<std::mutex>& 
           }
         }
       }
+    });
+  ln.h2d.clear();
+  {
+    int64_t off = 0;
+    for (size_t q = 0; q < nb; ++q) {
+      const Pending& p = ln.batch[q];
+      const bool direct = p.x_direct;
+      if (ln.y_off[q] >= 0)
+        add_copy(ln.h2d, ln.y_dev + ln.y_off[q], direct ? p.req.x_host : ln.y_pin + ln.y_off[q],
+                 sizeof(float) * p.n_re * 2 * p.req.n_rx);
+      else
+        add_copy(ln.h2d, ln.x_dev + off * Ci, direct ? p.req.x_host : ln.x_pin + off * Ci, sizeof(float) * p.n_re * Ci);
       off += p.n_re;
     }
-  });
+  }
   hipError_t e = hipEventRecord(ln.ev_h2d, ln.stream);
-  if (e == hipSuccess && any_features)
-    e = hipMemcpyAsync(ln.x_dev, ln.x_pin, sizeof(float) * res * Ci, hipMemcpyHostToDevice, ln.stream);
-  if (e == hipSuccess && y_total > 0)
-    e = hipMemcpyAsync(ln.y_dev, ln.y_pin, sizeof(float) * y_total, hipMemcpyHostToDevice, ln.stream);
+  for (const CopyRun& r : ln.h2d)
+    if (e == hipSuccess) e = hipMemcpyAsync(r.dst, r.src, r.bytes, hipMemcpyHostToDevice, ln.stream);
   if (e == hipSuccess) e = hipEventRecord(ln.ev_fwd, ln.stream);
   conet_status st = e == hipSuccess ? CONET_OK : hip_fail(e, "serving H2D");
   {  // features of the grid requests, written where the forward reads them
     int64_t off = 0;
-    for (size_t q = 0; q < ln.batch.size() && st == CONET_OK; ++q) {
+    for (size_t q = 0; q < nb && st == CONET_OK; ++q) {
       const Pending& p = ln.batch[q];
       if (ln.y_off[q] >= 0)
         st = conet_featurise(ln.y_dev + ln.y_off[q], 1, T, 12 * p.req.n_prb, p.req.n_rx, Ci, ln.x_dev + off * Ci,
@@ -342,10 +387,32 @@ static void launch_batch(conet_server* S, int li, std::unique_lock<std::mutex>& 
     geo.tiles_pin_cap = ln.arena.max_tiles;
     st = run_forward(S->M, ln.arena, ln.x_dev, geo, ln.llr_dev, ln.stream, nullptr);
   }
+  // Outputs: request q's LLRs, mq = its bits per symbol of the head's m per RE, packed on
+  // the GPU when mq < m, then copied to its buffer (page-locked) or to pinned staging at
+  // the same packed offset c_off[q].
   if (st == CONET_OK) {
-    e = hipEventRecord(ln.ev_d2h, ln.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(ln.llr_pin, ln.llr_dev, sizeof(float) * res * c.bits_per_symbol, hipMemcpyDeviceToHost,
-                       ln.stream);
+    ln.c_off.clear();
+    ln.d2h.clear();
+    int64_t off = 0, coff = 0;
+    for (size_t q = 0; q < nb && e == hipSuccess; ++q) {
+      const Pending& p = ln.batch[q];
+      const int mq = p.req.bits_per_symbol;
+      const float* src = ln.llr_dev + off * m;
+      if (mq != m) {
+        const int64_t n = p.n_re * mq;
+        hipLaunchKernelGGL(compact_llr_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ln.stream, src,
+                           ln.llr_c + coff, p.n_re, m, mq);
+        e = hipGetLastError();
+        src = ln.llr_c + coff;
+      }
+      add_copy(ln.d2h, p.llr_direct ? p.req.llr_host : ln.llr_pin + coff, src, sizeof(float) * p.n_re * mq);
+      ln.c_off.push_back(coff);
+      off += p.n_re;
+      coff += p.n_re * mq;
+    }
+    if (e == hipSuccess) e = hipEventRecord(ln.ev_d2h, ln.stream);
+    for (const CopyRun& r : ln.d2h)
+      if (e == hipSuccess) e = hipMemcpyAsync(r.dst, r.src, r.bytes, hipMemcpyDeviceToHost, ln.stream);
     if (e == hipSuccess) e = hipEventRecord(ln.ev, ln.stream);
     if (e != hipSuccess) st = hip_fail(e, "serving D2H");
   }
@@ -388,7 +455,7 @@ static size_t grid_floats(const conet_config& c, int64_t res) { return (size_t)r
 static size_t lane_bytes(const conet_config& c, int64_t res) {
   auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
   return a256(arena_bytes(c, res)) + a256(sizeof(float) * res * c.in_channels) +
-         a256(sizeof(float) * res * c.bits_per_symbol) + a256(sizeof(float) * grid_floats(c, res));
+         2 * a256(sizeof(float) * res * c.bits_per_symbol) + a256(sizeof(float) * grid_floats(c, res));
 }
 
 }  // namespace conet
@@ -434,7 +501,8 @@ conet_status conet_serve_create(conet_model* M, size_t mem_budget_bytes, int32_t
     if (e != hipSuccess) break;
     ln.x_dev = reinterpret_cast<float*>(ln.dev + a256(arena_bytes(c, lane_res)));
     ln.llr_dev = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(ln.x_dev) + a256(sizeof(float) * lane_res * c.in_channels));
-    ln.y_dev = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(ln.llr_dev) + a256(sizeof(float) * lane_res * c.bits_per_symbol));
+    ln.llr_c = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(ln.llr_dev) + a256(sizeof(float) * lane_res * c.bits_per_symbol));
+    ln.y_dev = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(ln.llr_c) + a256(sizeof(float) * lane_res * c.bits_per_symbol));
     e = hipHostMalloc(&ln.y_pin, sizeof(float) * grid_floats(c, lane_res), hipHostMallocDefault);
     if (e != hipSuccess) break;
   }
@@ -473,6 +541,10 @@ conet_status conet_serve_submit(conet_server* S, const conet_request* r, uint64_
   if (r->input == CONET_INPUT_GRID && r->T < 12)
     return fail(CONET_ESHAPE, "a grid request needs T >= 12 (pilots on symbols 2 and 11)");
   const int64_t n_re = (int64_t)r->T * 12 * r->n_prb;
+  const size_t in_floats = (size_t)n_re * (r->input == CONET_INPUT_GRID ? 2 : 4) * r->n_rx;
+  const bool x_direct = (r->input == CONET_INPUT_GRID || 4 * r->n_rx == c.in_channels) &&
+                        host_pinned(r->x_host, sizeof(float) * in_floats);
+  const bool llr_direct = host_pinned(r->llr_host, sizeof(float) * n_re * r->bits_per_symbol);
   std::lock_guard<std::mutex> lk(S->mu);
   if (n_re > S->lane_res) {
     ++S->rejected;
@@ -489,6 +561,8 @@ conet_status conet_serve_submit(conet_server* S, const conet_request* r, uint64_
   p.ticket = S->next_ticket++;
   p.t_submit = clk::now();
   p.n_re = n_re;
+  p.x_direct = x_direct;
+  p.llr_direct = llr_direct;
   if (!S->have_first) { S->have_first = true; S->t_first = p.t_submit; }
   S->results[p.ticket] = Done();
   S->queue.push_back(p);
@@ -525,6 +599,8 @@ conet_status conet_serve_get_stats(conet_server* S, conet_serve_stats* st) {
   st->batches = S->batches;
   st->mean_batch_requests = S->batches ? (double)S->batched_requests / S->batches : 0.0;
   st->lane_res = S->lane_res;
+  st->direct_inputs = S->direct_inputs;
+  st->direct_outputs = S->direct_outputs;
   if (!v.empty()) {
     std::sort(v.begin(), v.end());
     auto q = [&](double f) { return v[std::min(v.size() - 1, (size_t)(f * (v.size() - 1) + 0.5))]; };
@@ -553,6 +629,7 @@ conet_status conet_serve_reset_stats(conet_server* S) {
   std::lock_guard<std::mutex> lk(S->mu);
   S->lat_us.clear();
   S->completed = S->rejected = S->batches = S->batched_requests = 0;
+  S->direct_inputs = S->direct_outputs = 0;
   S->res_done = 0;
   S->sum_queue_us = S->sum_prep_us = S->sum_device_us = S->sum_scatter_us = 0;
   S->sum_h2d_us = S->sum_fwd_us = S->sum_d2h_us = 0;

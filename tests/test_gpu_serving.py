@@ -109,6 +109,44 @@ def test_grid_requests_featurised_on_the_gpu(served):
         assert rel_l2(grid_llr, feat_llr) <= 5e-3, rel_l2(grid_llr, feat_llr)
 
 
+def test_page_locked_buffers_go_by_dma_and_match(served):
+    """Requests whose buffers are page-locked are copied by DMA from and to the caller's
+    memory (grids, features with all C_in channels; any LLR buffer), the rest go through the
+    server's pinned staging. Every mix of the two, in one burst with all three modulations and
+    both antenna counts, gives bitwise the LLRs of the all-pageable path, and the server's
+    counters show which requests went directly."""
+    from paper_2510_12739_amd import Server, pinned_array
+    model, blob, mc = served
+    reqs = make_requests(10, seed=21, prb_range=(4, 60))
+    assert {r.m for r in reqs} == {2, 4, 6} and {r.n_rx for r in reqs} == {2, 4}
+
+    def pinned_copy(a):
+        b = pinned_array(a.shape)
+        b[...] = a
+        return b
+
+    srv = Server(model, mem_budget=2 << 30, n_streams=2, max_batch_res=200_000)
+    say("serving: 10 requests x {features, grid} x {pageable, pinned in, pinned out, both}")
+    runs = {}
+    for i, r in enumerate(reqs):
+        for grid in (False, True):
+            x = r.y if grid else r.x
+            for pin_in in (False, True):
+                for pin_out in (False, True):
+                    out = pinned_array((14, 12 * r.n_prb, r.m)) if pin_out else None
+                    runs[i, grid, pin_in, pin_out] = srv.submit(pinned_copy(x) if pin_in else x, r.n_prb, r.n_rx,
+                                                                r.m, out=out, grid=grid)
+    for t, _ in runs.values():
+        srv.wait(t)
+    st = srv.stats()
+    srv.close()
+    n_direct_in = sum(1 for (i, grid, pin_in, _) in runs if pin_in and (grid or 4 * reqs[i].n_rx == mc.C_in))
+    assert st["direct_inputs"] == n_direct_in and n_direct_in > 0
+    assert st["direct_outputs"] == len(runs) // 2
+    for (i, grid, pin_in, pin_out), (_, llr) in runs.items():
+        np.testing.assert_array_equal(llr, runs[i, grid, False, False][1], err_msg=f"{i} {grid} {pin_in} {pin_out}")
+
+
 def test_backpressure_timeout_and_rejection(served):
     """Conditions forced from the host: a paused server queues, refuses beyond max_queue
     (EBUSY), and a wait on a queued request times out (ETIMEOUT); resuming drains it."""
