@@ -450,5 +450,5 @@ conet_status conet_forward_ragged(conet_model* M, const float* x, int32_t n_slot
 }  // extern "C"
 
 extern "C" int32_t conet_block_tile_width(const conet_model* M) {
-  return M ? block_tile_width(M->cfg.dtype, M->cfg.channels, M->cfg.branches, false, M->cfg.train != 0) : 0;
+  return M ? block_tile_width(M->cfg.dtype, M->cfg.channels, M->cfg.branches, TW_WIDE, M->cfg.train != 0) : 0;
 }

@@ -28,14 +28,17 @@ namespace conet {
 // x tile of TROWS x (TWO+4) positions must leave room for two work-groups per CU, and
 // conv 1's accumulators (ceil(14 (TWO+2) / 64) M-tiles per wave) must fit the
 // per-lane register budget.
-// NARROW: the tile width for batches whose wide tiles cannot fill the GPU (one slot, a
-// serving batch): more, shorter work-groups cut the latency of each launch at the cost of
-// halo recompute. The arithmetic per RE is the same at every width, so results are
-// bit-identical whichever width a batch runs at.
-template <class A, int C, bool NARROW = false>
+// W = TW_NARROW: the tile width for batches whose wide tiles cannot fill the GPU (one slot,
+// a serving batch): more, shorter work-groups cut the latency of each launch at the cost of
+// halo recompute. W = TW_NARROW3 (64 channels only, 0 elsewhere): such a batch whose paired
+// launches hold more narrow work-groups than two per CU; built for three per CU. The
+// arithmetic per RE is the same at every width, so results are bit-identical whichever
+// width a batch runs at.
+template <class A, int C, int W = TW_WIDE>
 constexpr int block_tw() {
   if constexpr (std::is_same<A, ArithBF16>::value) {
-    if (C == 64) return NARROW ? 14 : 30;
+    if (C == 64) return W == TW_NARROW3 ? 13 : W == TW_NARROW ? 14 : 30;
+    if (W == TW_NARROW3) return 0;
     return C == 32 ? 44 : C == 16 ? 60 : 0;
   }
   return 0;
@@ -44,9 +47,13 @@ constexpr int block_tw() {
 // Work-groups per CU the fused kernel is built for (LDS tile and register budget). Three
 // (18-subcarrier tiles, 168 VGPRs) measured slower than two on the C = 64 workload: more
 // halo recompute and padded M-tiles, and no room left to prefetch the epilogue inputs.
-template <class A, int C>
+// The TW_NARROW3 width is built for three: on a batch too small to fill the GPU a
+// work-group's time is set by latency rather than by the CU's throughput, and three per CU
+// let the paired launch of one full-band slot (3 x 252 work-groups at K = 3) run in one
+// round instead of two.
+template <class A, int C, int TWO>
 constexpr int block_occ() {
-  return 2;
+  return TWO == block_tw<A, C, TW_NARROW3>() ? 3 : 2;
 }
 
 // Raw 16-byte (or 8-byte) vectors holding one lane's EPL activation values of one RE.
@@ -88,7 +95,7 @@ __device__ __forceinline__ void block_body(const BlockArgs& args, int k, uint8_t
   constexpr int MT1 = (M1 + NW - 1) / NW, MT2 = (M2 + NW - 1) / NW;
   constexpr int NOT = C / 16, EPL = 4 * NOT;
   constexpr int TILE = TROWS * XW * PITCH;
-  constexpr int OCC = block_occ<A, C>();
+  constexpr int OCC = block_occ<A, C, TWO>();
   constexpr int VB = OCC >= 3 ? 120 : 200;  // accumulator + operand VGPRs of the GEMM loops
   using G1 = GemmCore<A, C, C, XW, PITCH, MT1, VB>;
   using G2 = GemmCore<A, C, C, HW, PITCH, MT2, VB>;
@@ -222,7 +229,8 @@ __device__ __forceinline__ void block_body(const BlockArgs& args, int k, uint8_t
   using RawT = RawOf<Act, EPL>;
   constexpr int NR = EPL * (int)sizeof(Act) / (int)sizeof(RawT);
   constexpr int NTEN = 1 + NSUP;
-  constexpr int PD = (MAIN || OCC >= 3) ? (MT2 < 2 ? MT2 : 2) : (MT2 < 4 ? MT2 : 4);
+  constexpr int PDM = (OCC >= 3 && NSUP >= 2) ? 1 : 2;  // at three per CU the registers hold one M-tile
+  constexpr int PD = (MAIN || OCC >= 3) ? (MT2 < PDM ? MT2 : PDM) : (MT2 < 4 ? MT2 : 4);
   RawT raw[PD][NTEN][NR];
   auto re_of = [&](int mt, bool& ok) -> int64_t {
     const int q = (wave + NW * mt) * 16 + col;
@@ -306,7 +314,7 @@ __device__ __forceinline__ void block_body(const BlockArgs& args, int k, uint8_t
 
 // One fused block per work-group: branch blockIdx.y + k_off.
 template <class A, int C, int TWO, bool MAIN, bool HEAD, int NSUP>
-__global__ void __launch_bounds__(CONV_NW * 64, (block_occ<A, C>())) block_kernel(BlockArgs args) {
+__global__ void __launch_bounds__(CONV_NW * 64, (block_occ<A, C, TWO>())) block_kernel(BlockArgs args) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[block_lds_bytes<A, C, TWO>()];
   block_body<A, C, TWO, MAIN, HEAD, NSUP>(args, blockIdx.y + args.k_off, lds);
 }
@@ -316,7 +324,7 @@ __global__ void __launch_bounds__(CONV_NW * 64, (block_occ<A, C>())) block_kerne
 // which read only the supports' outputs of block l): independent work in one launch. The
 // per-branch argument arrays carry block l for branch 0 and block l + 1 for the others.
 template <class A, int C, int TWO, int NSUP>
-__global__ void __launch_bounds__(CONV_NW * 64, (block_occ<A, C>())) block_pair_kernel(BlockArgs args) {
+__global__ void __launch_bounds__(CONV_NW * 64, (block_occ<A, C, TWO>())) block_pair_kernel(BlockArgs args) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[block_lds_bytes<A, C, TWO>()];
   if (blockIdx.y == 0)
     block_body<A, C, TWO, true, false, NSUP>(args, 0, lds);
@@ -358,34 +366,39 @@ static hipError_t launch_block_w(int kind, BlockArgs& a, int n_tiles, int grid_y
 }
 
 template <class A, int C>
-static hipError_t launch_block_c(int kind, bool narrow, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
-  constexpr int TW = block_tw<A, C, false>(), TN = block_tw<A, C, true>();
+static hipError_t launch_block_c(int kind, int wclass, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+  constexpr int TW = block_tw<A, C, TW_WIDE>(), TN = block_tw<A, C, TW_NARROW>(), T3 = block_tw<A, C, TW_NARROW3>();
   if constexpr (TW == 0) {
     return hipErrorInvalidValue;
-  } else if constexpr (TN != TW) {
-    return narrow ? launch_block_w<A, C, TN>(kind, a, n_tiles, grid_y, s)
-                  : launch_block_w<A, C, TW>(kind, a, n_tiles, grid_y, s);
   } else {
+    if (wclass == TW_NARROW3) {
+      if constexpr (T3 != 0) return launch_block_w<A, C, T3>(kind, a, n_tiles, grid_y, s);
+      return hipErrorInvalidValue;
+    }
+    if constexpr (TN != TW) {
+      if (wclass == TW_NARROW) return launch_block_w<A, C, TN>(kind, a, n_tiles, grid_y, s);
+    }
     return launch_block_w<A, C, TW>(kind, a, n_tiles, grid_y, s);
   }
 }
 
 template <class A>
-hipError_t launch_block_dtype(int kind, bool narrow, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+hipError_t launch_block_dtype(int kind, int wclass, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
   switch (C) {
-    case 16: return launch_block_c<A, 16>(kind, narrow, a, n_tiles, grid_y, s);
-    case 32: return launch_block_c<A, 32>(kind, narrow, a, n_tiles, grid_y, s);
-    case 64: return launch_block_c<A, 64>(kind, narrow, a, n_tiles, grid_y, s);
+    case 16: return launch_block_c<A, 16>(kind, wclass, a, n_tiles, grid_y, s);
+    case 32: return launch_block_c<A, 32>(kind, wclass, a, n_tiles, grid_y, s);
+    case 64: return launch_block_c<A, 64>(kind, wclass, a, n_tiles, grid_y, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <class A>
-int block_tile_width_dtype(int C, bool narrow) {
+int block_tile_width_dtype(int C, int wclass) {
+  auto pick = [wclass](int w, int n, int n3) { return wclass == TW_NARROW3 ? n3 : wclass == TW_NARROW ? n : w; };
   switch (C) {
-    case 16: return narrow ? block_tw<A, 16, true>() : block_tw<A, 16, false>();
-    case 32: return narrow ? block_tw<A, 32, true>() : block_tw<A, 32, false>();
-    case 64: return narrow ? block_tw<A, 64, true>() : block_tw<A, 64, false>();
+    case 16: return pick(block_tw<A, 16>(), block_tw<A, 16, TW_NARROW>(), block_tw<A, 16, TW_NARROW3>());
+    case 32: return pick(block_tw<A, 32>(), block_tw<A, 32, TW_NARROW>(), block_tw<A, 32, TW_NARROW3>());
+    case 64: return pick(block_tw<A, 64>(), block_tw<A, 64, TW_NARROW>(), block_tw<A, 64, TW_NARROW3>());
   }
   return 0;
 }

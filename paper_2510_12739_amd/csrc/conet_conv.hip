@@ -10,10 +10,10 @@ hipError_t launch_conv_fp8(int mode, int cin, int cout, ConvArgs& a, int n_tiles
 int conv_tile_width_f32(int cin, int cout);
 int conv_tile_width_bf16(int cin, int cout);
 int conv_tile_width_fp8(int cin, int cout);
-hipError_t launch_block_bf16(int kind, bool narrow, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
-int block_tile_width_bf16(int C, bool narrow);
-hipError_t launch_block_fp8(int kind, bool narrow, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
-int block_tile_width_fp8(int C, bool narrow);
+hipError_t launch_block_bf16(int kind, int wclass, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
+int block_tile_width_bf16(int C, int wclass);
+hipError_t launch_block_fp8(int kind, int wclass, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
+int block_tile_width_fp8(int C, int wclass);
 
 hipError_t launch_conv(int dtype, int mode, int cin, int cout, ConvArgs& a, int n_tiles, int grid_y, hipStream_t s) {
   switch (dtype) {
@@ -35,20 +35,20 @@ int conv_tile_width(int dtype, int cin, int cout) {
 
 bool conv_supported(int dtype, int cin, int cout) { return conv_tile_width(dtype, cin, cout) > 0; }
 
-int block_tile_width(int dtype, int C, int K, bool narrow, bool train) {
+int block_tile_width(int dtype, int C, int K, int wclass, bool train) {
   if (K < 1 || K > BLOCK_KMAX) return 0;
   if (train && block_uses_mfma32(dtype, C)) return 0;
   switch (dtype) {
-    case DT_BF16: return block_tile_width_bf16(C, narrow);
-    case DT_FP8: return block_tile_width_fp8(C, narrow);
+    case DT_BF16: return block_tile_width_bf16(C, wclass);
+    case DT_FP8: return block_tile_width_fp8(C, wclass);
   }
   return 0;
 }
 
-hipError_t launch_block(int dtype, int kind, bool narrow, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+hipError_t launch_block(int dtype, int kind, int wclass, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {
   switch (dtype) {
-    case DT_BF16: return launch_block_bf16(kind, narrow, C, a, n_tiles, grid_y, s);
-    case DT_FP8: return launch_block_fp8(kind, narrow, C, a, n_tiles, grid_y, s);
+    case DT_BF16: return launch_block_bf16(kind, wclass, C, a, n_tiles, grid_y, s);
+    case DT_FP8: return launch_block_fp8(kind, wclass, C, a, n_tiles, grid_y, s);
   }
   return hipErrorInvalidValue;
 }

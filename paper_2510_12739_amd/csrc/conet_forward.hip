@@ -66,7 +66,7 @@ struct FusedScheduler {
   int n_tiles;
   const TileDesc* tiles;
   int tw;
-  bool narrow;  // tw is the narrow-tile width
+  int wclass;  // the width class of tw (TW_WIDE, TW_NARROW, TW_NARROW3)
   float* llr;
   hipStream_t s;
   int32_t* units;  // per-stage conv-branch units (two per fused branch block), or null
@@ -112,7 +112,7 @@ struct FusedScheduler {
     b.deq2[k] = s2;
   }
   conet_status launch(int kind, BlockArgs& b, int grid_y, int stage, int n_blocks, const char* what) {
-    const hipError_t e = launch_block(M->cfg.dtype, kind, narrow, M->cfg.channels, b, n_tiles, grid_y, s);
+    const hipError_t e = launch_block(M->cfg.dtype, kind, wclass, M->cfg.channels, b, n_tiles, grid_y, s);
     if (e != hipSuccess) return hip_fail(e, what);
     if (units) units[stage] += 2 * n_blocks;
     return CONET_OK;
@@ -220,20 +220,29 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
   const int tw_in = conv_tile_width(dt, Ci, C), tw_blk = conv_tile_width(dt, C, C);
   // Inference runs each block as one fused launch when a fused kernel exists for
   // (dtype, C); calibration and the training forward (which stores h) use two convs.
-  int tw_fb = calib ? 0 : block_tile_width(dt, C, K, false, c.train != 0);
+  int tw_fb = calib ? 0 : block_tile_width(dt, C, K, TW_WIDE, c.train != 0);
   // a batch whose wide tiles cannot fill the GPU once (a slot, a serving batch) runs on
-  // narrow tiles: more, shorter work-groups per launch
-  bool narrow = false;
+  // narrow tiles: more, shorter work-groups per launch; if its paired launches (K branches
+  // per tile) would then hold more than two work-groups per CU, on the build for three
+  int wclass = TW_WIDE;
   if (tw_fb) {
-    int64_t wide_tiles = 0;
-    if (geo.uniform) {
-      wide_tiles = (int64_t)geo.B * ((geo.F + tw_fb - 1) / tw_fb);
-    } else {
-      for (int sl = 0; sl < geo.n_slots; ++sl) wide_tiles += (geo.F_host[sl] + tw_fb - 1) / tw_fb;
-    }
-    if (wide_tiles * K < 2LL * M->n_cu) {
-      narrow = true;
-      tw_fb = block_tile_width(dt, C, K, true, c.train != 0);
+    auto tiles_at = [&](int tw) {
+      int64_t n = 0;
+      if (geo.uniform) {
+        n = (int64_t)geo.B * ((geo.F + tw - 1) / tw);
+      } else {
+        for (int sl = 0; sl < geo.n_slots; ++sl) n += (geo.F_host[sl] + tw - 1) / tw;
+      }
+      return n;
+    };
+    if (tiles_at(tw_fb) * K < 2LL * M->n_cu) {
+      wclass = TW_NARROW;
+      tw_fb = block_tile_width(dt, C, K, TW_NARROW, c.train != 0);
+      const int tw3 = block_tile_width(dt, C, K, TW_NARROW3, c.train != 0);
+      if (tw3 && tiles_at(tw_fb) * K > 2LL * M->n_cu) {
+        wclass = TW_NARROW3;
+        tw_fb = tw3;
+      }
     }
   }
   hipError_t e;
@@ -355,7 +364,7 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
 
   int cur = 0;
   bool fused_prev = false;
-  FusedScheduler fsched{M, geo, n_tiles_fb, d_fb, tw_fb, narrow, llr, s, units};
+  FusedScheduler fsched{M, geo, n_tiles_fb, d_fb, tw_fb, wclass, llr, s, units};
   for (int l = 0; l < L; ++l) {
     lvl = l;
     const bool last = (l == L - 1);

@@ -103,21 +103,24 @@ struct BlockArgs {
   void* hid_out[KMAX_ARGS];
   void* save_o0;
 };
-// Output subcarriers per fused tile; 0 when (dtype, C, K) runs as two conv launches.
-// narrow: the width used when a batch's wide tiles cannot fill the GPU. train: the model
-// keeps training state (its forward must read the filter packs the optimiser updates).
+// Output subcarriers per fused tile; 0 when (dtype, C, K) runs as two conv launches, or when
+// there is no kernel of that width class. TW_WIDE: batches that fill the GPU; TW_NARROW: a
+// batch whose wide tiles cannot fill it once; TW_NARROW3: such a batch whose paired launches
+// would need two rounds of narrow work-groups at two per CU (built for three per CU). train:
+// the model keeps training state (its forward must read the filter packs the optimiser updates).
+enum { TW_WIDE = 0, TW_NARROW = 1, TW_NARROW3 = 2 };
 constexpr int BLOCK_KMAX = 4;  // fused main-branch kernels exist for K <= 4
 // FP8 and BF16 at 96 channels run the fused block on the 32x32 MFMAs, which read filters in
 // their own fragment packing (pack_filter32). Training models do not use them (the
 // optimiser regenerates only the 16x16 packs).
 inline bool block_uses_mfma32(int dtype, int C) { return C == 96 && (dtype == DT_FP8 || dtype == DT_BF16); }
-int block_tile_width(int dtype, int C, int K, bool narrow, bool train = false);
+int block_tile_width(int dtype, int C, int K, int wclass, bool train = false);
 // kind BLOCK_PLAIN: branches blockIdx.y + k_off, no fusion epilogue (support branches, or
 // every branch of a block without fusion; head on branch 0 when llr is set); BLOCK_MAIN: the
 // main branch of a fused block (k_off = 0, grid.y = 1); BLOCK_PAIR: grid.y = K, blockIdx.y 0
 // is the main branch of block l and 1..K-1 the support branches of block l + 1 (no head).
 enum { BLOCK_PLAIN = 0, BLOCK_MAIN = 1, BLOCK_PAIR = 2 };
-hipError_t launch_block(int dtype, int kind, bool narrow, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
+hipError_t launch_block(int dtype, int kind, int wclass, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
 
 // ---------------------------------------------------------------- training kernels
 // Filter gradient of a 3x3 conv over a batch: dW[o][tap*CIN + ch] = sum_re dOut[re][o] *

@@ -441,18 +441,21 @@ def test_fusion_variant_training_is_refused():
         Conet(2, 1, 16, 16, 2, blob, dtype="bf16", train=True, fusion="sum")
 
 
-def test_narrow_and_wide_fused_tiles_agree_bitwise():
+@pytest.mark.parametrize("F", [3276, 1656])
+def test_narrow_and_wide_fused_tiles_agree_bitwise(F):
     """A batch too small to fill the GPU runs on narrow fused tiles; the per-RE arithmetic is
-    the same at either width, so a slot's LLRs must be bit-identical alone (narrow) and inside
-    a batch large enough for wide tiles."""
+    the same at every width, so a slot's LLRs must be bit-identical alone (narrow) and inside
+    a batch large enough for wide tiles. One 1656-subcarrier slot runs on 14-subcarrier tiles
+    (3 x 119 work-groups per paired launch); one 3276-subcarrier slot has too many of those for
+    two work-groups per CU and runs on the 13-subcarrier build for three per CU."""
     from paper_2510_12739_amd import Conet
     K, L, C, Ci, m = 3, 2, 64, 16, 4
     blob = make_blob(ModelConfig(K, L, C, Ci, m), seed=61, perturb=True)
-    sim = SimConfig(F=3276, n_rx=4, bits_per_symbol=4, seed=62)
+    sim = SimConfig(F=F, n_rx=4, bits_per_symbol=4, seed=62)
     X = features(sim, 2)
-    Xb = np.concatenate([X] * 4, axis=0)  # 8 slots: 8 x 110 wide tiles x 3 branches fill the GPU
-    model = Conet(K, L, C, Ci, m, blob, dtype="bf16", max_res=8 * 14 * 3276)
-    say("narrow (1 slot) vs wide (8 slots) fused tiles")
+    Xb = np.concatenate([X] * 4, axis=0)  # 8 slots: 8 x (F / 30) wide tiles x 3 branches fill the GPU
+    model = Conet(K, L, C, Ci, m, blob, dtype="bf16", max_res=8 * 14 * F)
+    say(f"narrow (1 slot) vs wide (8 slots) fused tiles, F={F}")
     alone = _run(model, X[1:2])
     batch = _run(model, Xb)
     np.testing.assert_array_equal(alone[0], batch[5])
