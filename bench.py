@@ -248,10 +248,13 @@ def serve_measure(loads=(0.5,), duration_s=1.5, n_streams=3, seed=13, grid=False
                               "mean_batch_requests": round(st["mean_batch_requests"], 2),
                               "mean_us": round(st["mean_us"], 1),
                               "mean_phase_us": {k: round(st["mean_" + k + "_us"], 1)
-                                                for k in ("queue", "prep", "device", "scatter", "h2d", "forward", "d2h")}})
+                                                for k in ("queue", "prep", "device", "scatter", "h2d", "forward", "d2h")},
+                              "slowest_phase_us": {k: round(st["slowest_" + k + "_us"], 1)
+                                                   for k in ("queue", "prep", "device", "scatter")}})
         print(f"[bench] serving ({'grid' if grid else 'features'}{', pinned' if pinned else ''}) load {f:.2f}: {rate:.0f} req/s, "
               f"p50 {st['p50_us']:.0f} us, p99 {st['p99_us']:.0f} us, "
-              f"phases {out['points'][-1]['mean_phase_us']}", file=sys.stderr, flush=True)
+              f"phases {out['points'][-1]['mean_phase_us']}, slowest {round(st['max_us'])} us: "
+              f"{out['points'][-1]['slowest_phase_us']}", file=sys.stderr, flush=True)
     srv.close()
     model.close()
     return out

@@ -220,10 +220,10 @@ conet_status conet_bce(conet_model* model, const float* llr, const uint8_t* bits
                        int32_t T, int32_t F, int64_t n_data_per_slot, float* dllr, float* loss_dev, void* stream);
 
 /* ---------------------------------------------------------------- serving
- * Continuous batching of slot requests (one TTI each). A scheduler thread forms a
- * ragged batch whenever one of the server's lanes (one HIP stream + its own activation
- * buffers each) is free, taking queued requests in arrival order while their REs fit
- * the lane (admission by memory); batches on different lanes overlap on the device.
+ * Continuous batching of slot requests (one TTI each). Each of the server's lanes (one HIP
+ * stream + its own activation buffers) has a thread that forms a ragged batch whenever the
+ * lane is free, taking queued requests in arrival order while their REs fit the lane
+ * (admission by memory); batches on different lanes overlap on the device.
  * A request's LLRs do not depend on the other requests it is batched with. */
 typedef struct conet_server conet_server;
 
@@ -268,6 +268,8 @@ typedef struct {
   /* completed requests whose input / LLRs went by DMA straight from / to the caller's
    * page-locked buffer */
   uint64_t direct_inputs, direct_outputs;
+  /* the same four phases for the slowest completed request (its latency is max_us) */
+  double slowest_queue_us, slowest_prep_us, slowest_device_us, slowest_scatter_us;
 } conet_serve_stats;
 
 /* Start a server on `model` (which must outlive it): n_streams lanes of up to

@@ -56,7 +56,9 @@ class conet_serve_stats(ctypes.Structure):
                 ("lane_res", ctypes.c_int64), ("mean_queue_us", ctypes.c_double), ("mean_prep_us", ctypes.c_double),
                 ("mean_device_us", ctypes.c_double), ("mean_scatter_us", ctypes.c_double),
                 ("mean_h2d_us", ctypes.c_double), ("mean_forward_us", ctypes.c_double), ("mean_d2h_us", ctypes.c_double),
-                ("direct_inputs", ctypes.c_uint64), ("direct_outputs", ctypes.c_uint64)]
+                ("direct_inputs", ctypes.c_uint64), ("direct_outputs", ctypes.c_uint64),
+                ("slowest_queue_us", ctypes.c_double), ("slowest_prep_us", ctypes.c_double),
+                ("slowest_device_us", ctypes.c_double), ("slowest_scatter_us", ctypes.c_double)]
 
 
 _lib = None

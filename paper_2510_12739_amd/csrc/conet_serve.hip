@@ -1,14 +1,14 @@
 // Continuous-batching server for CoNet-Rx slot requests.
 //
 // Requests (one TTI each, any PRB allocation, 2..N_rx antennas, any modulation up to the
-// model's head width) are queued by conet_serve_submit. A scheduler thread forms a
-// ragged batch whenever one of the server's lanes is free: it takes queued requests in
-// arrival order while their REs fit the lane's buffers (admission by memory; a request
-// never waits for a batch to fill), and enqueues H2D copies -> ragged forward -> D2H
-// copies on the lane's stream. Lanes run on separate streams, so a batch formed while
-// others are on the GPU overlaps with them on the device. Each lane has a completion
-// thread that waits for its batch, moves the LLRs to the callers' buffers where the
-// copy engines could not, and releases the waiters.
+// model's head width) are queued by conet_serve_submit. Each lane (a HIP stream with its
+// own buffers) has a thread that forms a ragged batch whenever the lane is free: it takes
+// queued requests in arrival order while their REs fit the lane's buffers (admission by
+// memory; a request never waits for a batch to fill), and enqueues H2D copies -> ragged
+// forward -> D2H copies on the lane's stream. Lanes run on separate streams, so a batch
+// formed while others are on the GPU overlaps with them on the device. The same thread
+// then waits for its batch, moves the LLRs to the callers' buffers where the copy engines
+// could not, and releases the waiters.
 //
 // A request may carry the received grid instead of the features: the grid (8 bytes per RE
 // and antenna instead of 16) is copied, and the lane forms the features on the GPU
@@ -181,7 +181,7 @@ struct Lane {
   clk::time_point t_formed, t_enqueued;  // batch taken from the queue; all its GPU work enqueued
   bool busy = false;               // a batch is assigned to the lane
   bool launched = false;           // ... and its completion event is recorded
-  std::thread waiter;
+  std::thread worker;              // forms, enqueues, waits for and delivers the lane's batches
 };
 
 }  // namespace conet
@@ -193,8 +193,7 @@ struct conet_server {
   size_t max_queue = 0;
   std::vector<conet::Lane> lanes;
   std::mutex mu;
-  std::condition_variable cv_sched;   // queue grew or a lane became free
-  std::condition_variable cv_lane;    // a lane got work
+  std::condition_variable cv_sched;   // the queue grew, or batches may be formed again
   std::condition_variable cv_done;    // a request completed
   std::deque<conet::Pending> queue;
   conet::CopyPool* pool = nullptr;    // helpers for packing and scattering
@@ -202,13 +201,13 @@ struct conet_server {
   uint64_t next_ticket = 1;
   bool stop = false;
   bool paused = false;                // no new batches are formed while set
-  std::thread scheduler;
   // statistics
   std::vector<double> lat_us;
   uint64_t completed = 0, rejected = 0, batches = 0, batched_requests = 0, direct_inputs = 0, direct_outputs = 0;
   int64_t res_done = 0;
   double sum_queue_us = 0, sum_prep_us = 0, sum_device_us = 0, sum_scatter_us = 0;
   double sum_h2d_us = 0, sum_fwd_us = 0, sum_d2h_us = 0;
+  double slowest_us = 0, slowest_phase_us[4] = {0, 0, 0, 0};  // the slowest request: queue, prep, device, scatter
   bool have_first = false;
   conet::clk::time_point t_first, t_last;
   conet_status async_error = CONET_OK;
@@ -216,14 +215,21 @@ struct conet_server {
 
 namespace conet {
 
-static void lane_wait_loop(conet_server* S, int li) {
+static void launch_batch(conet_server* S, int li, std::unique_lock<std::mutex>& lk);
+
+// One thread per lane: when the lane is free, take a batch from the head of the queue, enqueue
+// its work, wait for it and deliver the LLRs. Lanes form their batches independently, so a
+// batch whose host work is held up (a thread not scheduled for a while) delays only its lane.
+static void lane_loop(conet_server* S, int li) {
   Lane& ln = S->lanes[li];
   (void)hipSetDevice(S->device);
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      S->cv_lane.wait(lk, [&] { return S->stop || ln.launched; });
-      if (!ln.launched && S->stop) return;
+      S->cv_sched.wait(lk, [&] { return S->stop || (!S->paused && !S->queue.empty()); });
+      if (S->stop) return;
+      launch_batch(S, li, lk);  // unlocks while packing and enqueueing; returns with the lock held
+      if (!ln.launched) continue;  // the batch failed (its requests are completed with the error)
     }
     hipError_t e = hipEventSynchronize(ln.ev);
     const auto t_done_gpu = clk::now();
@@ -266,10 +272,16 @@ static void lane_wait_loop(conet_server* S, int li) {
           S->direct_inputs += p.x_direct;
           S->direct_outputs += p.llr_direct;
           S->res_done += p.n_re;
-          S->sum_queue_us += us(p.t_submit, ln.t_formed);
-          S->sum_prep_us += us(ln.t_formed, ln.t_enqueued);
-          S->sum_device_us += us(ln.t_enqueued, t_done_gpu);
-          S->sum_scatter_us += us(t_done_gpu, t_done);
+          const double ph[4] = {us(p.t_submit, ln.t_formed), us(ln.t_formed, ln.t_enqueued),
+                                us(ln.t_enqueued, t_done_gpu), us(t_done_gpu, t_done)};
+          S->sum_queue_us += ph[0];
+          S->sum_prep_us += ph[1];
+          S->sum_device_us += ph[2];
+          S->sum_scatter_us += ph[3];
+          if (d.latency_us > S->slowest_us) {
+            S->slowest_us = d.latency_us;
+            for (int i = 0; i < 4; ++i) S->slowest_phase_us[i] = ph[i];
+          }
           S->sum_h2d_us += 1e3 * ms_h2d;
           S->sum_fwd_us += 1e3 * ms_fwd;
           S->sum_d2h_us += 1e3 * ms_d2h;
@@ -282,7 +294,6 @@ static void lane_wait_loop(conet_server* S, int li) {
       ln.busy = false;
     }
     S->cv_done.notify_all();
-    S->cv_sched.notify_all();
   }
 }
 
@@ -430,23 +441,6 @@ static void launch_batch(conet_server* S, int li, std::unique_lock<std::mutex>& 
     return;
   }
   ln.launched = true;
-  S->cv_lane.notify_all();
-}
-
-static void scheduler_loop(conet_server* S) {
-  (void)hipSetDevice(S->device);
-  std::unique_lock<std::mutex> lk(S->mu);
-  for (;;) {
-    S->cv_sched.wait(lk, [&] {
-      if (S->stop) return true;
-      if (S->queue.empty() || S->paused) return false;
-      for (auto& ln : S->lanes) if (!ln.busy) return true;
-      return false;
-    });
-    if (S->stop) return;
-    for (size_t li = 0; li < S->lanes.size() && !S->queue.empty() && !S->paused; ++li)
-      if (!S->lanes[li].busy) launch_batch(S, (int)li, lk);
-  }
 }
 
 // grid staging: at most C_in / 4 antennas of (Re, Im) per RE
@@ -522,8 +516,7 @@ conet_status conet_serve_create(conet_model* M, size_t mem_budget_bytes, int32_t
     return st;
   }
   S->pool = new CopyPool(SERVE_COPY_HELPERS);
-  for (int i = 0; i < n_streams; ++i) S->lanes[i].waiter = std::thread(lane_wait_loop, S, i);
-  S->scheduler = std::thread(scheduler_loop, S);
+  for (int i = 0; i < n_streams; ++i) S->lanes[i].worker = std::thread(lane_loop, S, i);
   *out = S;
   return CONET_OK;
 }
@@ -601,6 +594,10 @@ conet_status conet_serve_get_stats(conet_server* S, conet_serve_stats* st) {
   st->lane_res = S->lane_res;
   st->direct_inputs = S->direct_inputs;
   st->direct_outputs = S->direct_outputs;
+  st->slowest_queue_us = S->slowest_phase_us[0];
+  st->slowest_prep_us = S->slowest_phase_us[1];
+  st->slowest_device_us = S->slowest_phase_us[2];
+  st->slowest_scatter_us = S->slowest_phase_us[3];
   if (!v.empty()) {
     std::sort(v.begin(), v.end());
     auto q = [&](double f) { return v[std::min(v.size() - 1, (size_t)(f * (v.size() - 1) + 0.5))]; };
@@ -630,6 +627,8 @@ conet_status conet_serve_reset_stats(conet_server* S) {
   S->lat_us.clear();
   S->completed = S->rejected = S->batches = S->batched_requests = 0;
   S->direct_inputs = S->direct_outputs = 0;
+  S->slowest_us = 0;
+  for (double& v : S->slowest_phase_us) v = 0;
   S->res_done = 0;
   S->sum_queue_us = S->sum_prep_us = S->sum_device_us = S->sum_scatter_us = 0;
   S->sum_h2d_us = S->sum_fwd_us = S->sum_d2h_us = 0;
@@ -662,9 +661,7 @@ conet_status conet_serve_destroy(conet_server* S) {
     S->stop = true;
   }
   S->cv_sched.notify_all();
-  S->cv_lane.notify_all();
-  if (S->scheduler.joinable()) S->scheduler.join();
-  for (auto& ln : S->lanes) if (ln.waiter.joinable()) ln.waiter.join();
+  for (auto& ln : S->lanes) if (ln.worker.joinable()) ln.worker.join();
   for (auto& ln : S->lanes) {
     (void)hipStreamSynchronize(ln.stream);
     (void)hipStreamDestroy(ln.stream);
