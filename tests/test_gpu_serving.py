@@ -209,4 +209,11 @@ def test_poisson_load_reports_latency(served):
     say(f"  p50 {st['p50_us']:.0f} us, p99 {st['p99_us']:.0f} us, {st['res_per_s'] / 1e6:.1f} M REs/s, "
         f"{st['mean_batch_requests']:.2f} requests/batch")
     assert st["completed"] == 600 and st["p50_us"] > 0 and st["p99_us"] >= st["p50_us"]
+    # the phases split each request's latency exactly: their means add up to the mean latency,
+    # and the slowest request's phases to the largest latency
+    means = sum(st[f"mean_{k}_us"] for k in ("queue", "prep", "device", "scatter"))
+    slowest = sum(st[f"slowest_{k}_us"] for k in ("queue", "prep", "device", "scatter"))
+    assert abs(means - st["mean_us"]) <= 1e-6 * st["mean_us"] + 1e-3, (means, st["mean_us"])
+    assert abs(slowest - st["max_us"]) <= 1e-6 * st["max_us"] + 1e-3, (slowest, st["max_us"])
+    assert st["direct_inputs"] == 0 and st["direct_outputs"] == 0   # pageable numpy buffers
     srv.close()
