@@ -74,3 +74,24 @@ def test_create_rejects_bad_arguments_without_touching_the_gpu():
     assert lib.conet_create(ctypes.byref(cfg), fp, n, ctypes.c_void_p(256), 16, ctypes.byref(h)) == 3
     assert lib.conet_forward(None, None, 1, 14, 8, None, 0, None) == 1
     assert lib.conet_destroy(None) == 1
+
+
+def _header_struct_fields(name):
+    """Field names, in order, of `typedef struct { ... } name;` in include/conet.h."""
+    src = open(os.path.join(os.path.dirname(__file__), "..", "include", "conet.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct\s*\{([^}]*)\}\s*" + name + r"\s*;", src).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        names = decl.split(None, 1)[1] if not decl.startswith("const ") else decl.split(None, 2)[2]
+        fields += [n.strip().lstrip("*") for n in names.split(",")]
+    return fields
+
+
+@pytest.mark.parametrize("struct", ["conet_config", "conet_request", "conet_serve_stats"])
+def test_binding_structs_match_the_header(struct):
+    """The ctypes mirrors of the C structs list the header's fields in the header's order."""
+    assert [f for f, _ in getattr(b, struct)._fields_] == _header_struct_fields(struct)
