@@ -32,11 +32,19 @@ biases everywhere; "same" zero padding inside each slot; LN over the C channels 
 each RE with eps = 1e-5 and affine (gamma, beta); the head is linear with bias and
 reads the last main-net activation; LLR = ln P(b=1)/P(b=0).
 
-Optional precision emulation (``quant``): rounds, with the same rounding rule as the
-GPU, the conv weights, each conv's input operand and every activation tensor that
-crosses between kernels. "bf16" follows the BF16 contract (FP32 everything else);
-"fp8" follows the FP8 contract (e4m3 operands with per-output-channel weight scales
-and per-tensor static activation scales, BF16 inter-kernel tensors).
+Optional precision emulation (``quant``), the reduced-precision contract written from
+what the configurations fix (conv arithmetic in BF16 or FP8 e4m3 with per-output-channel
+scales, FP32 accumulation) plus one rule for what is stored:
+  * every conv operand is rounded: filters and input activations to BF16 ("bf16"), or to
+    e4m3 of value / scale ("fp8": filter scale amax/448 per output channel, a static
+    activation scale per conv input, saturating round-to-nearest-even);
+  * a tensor that leaves a residual block -- the input layer's output, a block output
+    that a net carries on (or that a support net hands to the fusion), the fused
+    activation -- is stored in BF16 on both paths; a main-net output consumed by its own
+    block's fusion, and the last activation feeding the head, are not;
+  * everything else (accumulation, biases, affines, ReLU, residual adds, the fusion, the
+    normalisation, the head) is exact here and FP32 on the GPU.
+The pins construct this contract independently with torch's casts.
 """
 from __future__ import annotations
 
@@ -223,7 +231,7 @@ class Quant:
     act_scales: Optional[np.ndarray] = None
 
     def store(self, a):
-        """Rounding of an activation tensor written between kernels."""
+        """Rounding of an activation tensor that leaves a residual block (BF16 on both paths)."""
         return a if self.kind is None else round_bf16(a)
 
 
@@ -254,9 +262,30 @@ def _weights(q: Quant, W: np.ndarray) -> np.ndarray:
     return round_e4m3(Wf / s[:, None, None, None]) * s[:, None, None, None]
 
 
+FP32_UNIT = 2.0 ** -24
+
+
+def _conv_acc(xq: np.ndarray, Wq: np.ndarray, b: Optional[np.ndarray], noise) -> np.ndarray:
+    """conv3x3 of an operand; with `noise` (a numpy Generator), plus a model of the error an
+    FP32 accumulation of the same sum would make.
+
+    Model: summing N terms in FP32, each partial sum carries a relative rounding error of at
+    most 2^-24; treated as independent, the errors add up to a standard deviation of about
+    2^-24 sqrt(N / 2) sqrt(sum_i term_i^2) (term_i = w_i x_i, N = 9 C_in). Used to bound how far
+    an FP32-accumulating implementation may lie from this FP64 one, never as a result.
+    """
+    c = conv3x3(xq, Wq, b)
+    if noise is not None:
+        n_terms = 9 * xq.shape[-1]
+        sq = conv3x3(xq * xq, Wq * Wq)
+        c = c + FP32_UNIT * np.sqrt(n_terms / 2.0) * np.sqrt(np.maximum(sq, 0.0)) * noise.standard_normal(c.shape)
+    return c
+
+
 def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Optional[Quant] = None,
             keep: bool = False, calib: Optional[np.ndarray] = None, fusion: str = "product",
-            feedback: bool = False, norm: Optional[str] = None, bn_stats: Optional[Dict] = None):
+            feedback: bool = False, norm: Optional[str] = None, bn_stats: Optional[Dict] = None,
+            acc_noise: Optional[np.random.Generator] = None):
     """CoNet forward for a batch X (B, T, F, C_in) -> LLR (B, T, F, m).
 
     keep=True also returns the intermediate tensors the backward needs.
@@ -266,6 +295,8 @@ def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Opti
     main -> support feedback after every fusion. norm: "ln", "bn" (running statistics of
     p) or "bn_batch" (this batch's statistics, recorded into bn_stats[l - 1] = (mean, var)
     if given); default: p's own. The backward covers the defaults only.
+    acc_noise: a numpy Generator; every conv and the head then carry the FP32-accumulation
+    error model of _conv_acc (for deriving tolerances; see there).
     """
     if fusion not in ("product", "sum"):
         raise ValueError(f"unknown fusion {fusion!r}")
@@ -284,7 +315,7 @@ def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Opti
     a = []
     for k in range(K):
         br = p["branch"][k]
-        z = conv3x3(Xq, _weights(q, br["W_in"]), br["b_in"])
+        z = _conv_acc(Xq, _weights(q, br["W_in"]), br["b_in"], acc_noise)
         a.append(q.store(relu(z)))
     cache["a0"] = [t.copy() for t in a] if keep else None
 
@@ -300,13 +331,15 @@ def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Opti
             if calib is not None:
                 i0 = act_scale_index(K, L, k, l, 0)
                 calib[i0] = max(calib[i0], float(np.abs(pre).max()))
-            c1 = conv3x3(_operand(q, pre, act_scale_index(K, L, k, l, 0)), _weights(q, blk["W1"]), blk["b1"])
+            c1 = _conv_acc(_operand(q, pre, act_scale_index(K, L, k, l, 0)), _weights(q, blk["W1"]), blk["b1"],
+                           acc_noise)
             z1 = blk["s1"] * c1 + blk["o1"]
             h = q.store(relu(z1)) if q.kind is None or q.kind == "bf16" else relu(z1)
             if calib is not None:
                 i1 = act_scale_index(K, L, k, l, 1)
                 calib[i1] = max(calib[i1], float(np.abs(h).max()))
-            c2 = conv3x3(_operand(q, h, act_scale_index(K, L, k, l, 1)), _weights(q, blk["W2"]), blk["b2"])
+            c2 = _conv_acc(_operand(q, h, act_scale_index(K, L, k, l, 1)), _weights(q, blk["W2"]), blk["b2"],
+                           acc_noise)
             Ok = x + c2
             O.append(Ok)
             if keep:
@@ -346,6 +379,9 @@ def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Opti
         fused_prev = fused_after(mask, l)
 
     llr = a[0] @ p["W_h"].T + p["b_h"]
+    if acc_noise is not None:  # the head's C-term sums, same error model
+        sq = (a[0] * a[0]) @ (p["W_h"] * p["W_h"]).T
+        llr = llr + FP32_UNIT * np.sqrt(p["C"] / 2.0) * np.sqrt(sq) * acc_noise.standard_normal(llr.shape)
     if keep:
         cache["aL"] = a[0]
         cache["variant"] = (fusion, feedback, norm)
