@@ -51,8 +51,12 @@ def flops_per_re(K, L, C, C_in, m):
     return 2 * 9 * C_in * K * C + K * L * 2 * (2 * 9 * C * C) + 2 * C * m
 
 
-def cpu_baseline(workload, blob, X_sample, llr_gpu_sample, budget_s=15.0, max_slots=8):
-    """Time the FP64 oracle on whole slots until the budget is spent (at least one slot)."""
+def cpu_baseline(workload, blob, X_sample, budget_s=15.0, max_slots=8, extra=None):
+    """The FP64 oracle timed on the host cores: whole slots of the headline workload until the
+    budget is spent (at least one slot). `extra`: (name, workload, blob, [(X_window, keep_slice)])
+    samples of other workloads (sampled subcarrier windows, each with the margin its outputs
+    depend on), timed the same way. Returns the baseline record and the FP64 LLRs of every
+    sample, which the GPU legs' LLR errors are measured against."""
     from oracle import conet64 as o
     try:
         from threadpoolctl import threadpool_info
@@ -70,14 +74,47 @@ def cpu_baseline(workload, blob, X_sample, llr_gpu_sample, budget_s=15.0, max_sl
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    ref = np.concatenate(outs)
-    got = llr_gpu_sample[:n].astype(np.float64)
-    err = {"rel_l2_vs_fp64": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
-           "sign_agreement": float(np.mean((got > 0) == (ref > 0))),
-           "slots": n}
-    return {"value": res / dt, "unit": "REs/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n} whole slot(s) of {X_sample.shape[1]}x{X_sample.shape[2]} REs, FP64 NumPy "
-                      f"(im2col + BLAS), {dt:.1f} s"}, err
+    rec = {"value": res / dt, "unit": "REs/s", "cores": int(threads), "kind": "oracle",
+           "cpu_model": cpu_model_name(), "host_cpus": os.cpu_count(),
+           "sample": f"{n} whole slot(s) of {X_sample.shape[1]}x{X_sample.shape[2]} REs of {workload.name}, "
+                     f"FP64 NumPy (im2col + BLAS), {dt:.1f} s"}
+    refs = {workload.name: np.concatenate(outs)}
+    for name, w2, blob2, wins in (extra or []):
+        m2 = w2.model
+        p2 = o.unpack(blob2, m2.K, m2.L, m2.C, m2.C_in, m2.m)
+        t1 = time.perf_counter()
+        r2, got = 0, []
+        for Xw, keep in wins:
+            got.append(o.forward(p2, Xw.astype(np.float64))[:, :, keep])
+            r2 += Xw.shape[1] * Xw.shape[2]
+        d2 = time.perf_counter() - t1
+        rec.setdefault("other_workloads", {})[name] = {
+            "value": r2 / d2, "unit": "REs/s",
+            "sample": f"{len(wins)} subcarrier windows ({r2} REs incl. margins) of {w2.name}, {d2:.1f} s"}
+        refs[name] = got
+    return rec, refs
+
+
+def cpu_model_name() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def llr_error(got, ref) -> dict:
+    """rel-L2, max |d| / RMS(ref) with the worst element's index, and sign agreement."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    d = np.abs(got - ref)
+    i = np.unravel_index(int(np.argmax(d)), d.shape)
+    rms = float(np.sqrt(np.mean(ref ** 2)))
+    return {"rel_l2_vs_fp64": float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)),
+            "max_abs_over_rms": float(d.max() / max(rms, 1e-300)), "worst_index": [int(v) for v in i],
+            "sign_agreement": float(np.mean((got > 0) == (ref > 0))), "n": int(ref.size)}
 
 
 def load_traffic(kernel: str, workload: str, dtype: str):
@@ -394,18 +431,340 @@ def train_bench(args):
             f.write(line + "\n")
 
 
+# ----------------------------------------------------------------------------- forward legs
+
+def trained_blob(name: str):
+    """Weights trained on simulator data by tests/golden/train_weights.py (CPU), if present."""
+    path = os.path.join(ROOT, "tests", "golden", f"trained_{name}.npy")
+    return np.load(path).astype(np.float32) if os.path.exists(path) else None
+
+
+def leg_inputs(w):
+    """Blob (trained if available, else He-normal) and features of a workload's batch (8 distinct
+    simulated slots tiled to the batch; the cost does not depend on the values)."""
+    from synth import features_fast, make_blob
+    blob = trained_blob(w.name)
+    kind = "trained on simulator data (CPU trainer)" if blob is not None else "He-normal random"
+    if blob is None:
+        blob = make_blob(w.model, seed=w.weight_seed)
+    return blob, kind, features_fast(w.sim, w.batch, n_distinct=min(8, w.batch))
+
+
+def dominant_roofline(stage_ms, stage_units, mc, res, dtype, fused_tw, wl_name):
+    """Roofline of the kernel kind that takes most of the step. Stages: input layer, then per
+    block (a) a block without fusion after it (fused) or conv 1 of all branches, (b) support
+    branches (paired with the previous block's main branch when deferred to this launch),
+    (c) a main branch launched alone. Units are conv-branch executions (one conv of one branch
+    over the batch), so FLOPs are algorithmic: units x REs x 2*9*C*C."""
+    blk_fl = res * 2 * 9 * mc.C * mc.C
+    names = (("block_fused_all", "block_fused_supports", "block_fused_main") if fused_tw else
+             ("block_conv1", "block_conv2_supports", "block_conv2_main_fused"))
+    kinds = {}
+    for i in range(1, stage_ms.shape[1]):
+        u = int(stage_units[i])
+        if u == 0:
+            continue
+        name = names[(i - 1) % 3]
+        if fused_tw and (i - 1) % 3 == 1 and u == 2 * mc.K:
+            name = "block_fused_pair"
+        kinds.setdefault(name, []).append((stage_ms[:, i], u * blk_fl))
+    tot = {k: sum(float(ms.sum()) for ms, _ in v) for k, v in kinds.items() if v}
+    dom = max(tot, key=tot.get)
+    launches = kinds[dom]
+    fl_launch = float(np.mean([fl for _, fl in launches]))
+    dom_ms = float(np.mean([ms.mean() for ms, _ in launches]))
+    achieved = float(np.mean([fl / (ms.mean() * 1e-3) for ms, fl in launches])) / 1e12
+    peak = PEAK_TFLOPS[dtype]
+    return {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": load_traffic(dom, wl_name, dtype),
+            "flops_per_launch": fl_launch, "launches_per_step": len(launches), "mean_launch_ms": round(dom_ms, 4),
+            "fused_block_tile_width": fused_tw,
+            "stage_mean_ms": [round(float(v), 4) for v in stage_ms.mean(axis=0)],
+            "stage_conv_units": [int(u) for u in stage_units]}
+
+
+def forward_leg(w, dtype, blob, X, steps, warmup, label):
+    """W untimed forwards, then exactly `steps` timed ones (a HIP event before every launch, on
+    the stream the kernels run on). Returns the leg's record and the LLRs of the last step."""
+    import torch
+    from paper_2510_12739_amd import Conet
+    mc = w.model
+    B, T, F = X.shape[0], X.shape[1], X.shape[2]
+    res = B * T * F
+    print(f"[bench] {label}: {w.name} {dtype} B={B} T={T} F={F} K={mc.K} L={mc.L} C={mc.C}", file=sys.stderr, flush=True)
+    x = torch.from_numpy(X).cuda()
+    model = Conet(mc.K, mc.L, mc.C, mc.C_in, mc.m, blob, dtype=dtype, max_res=res)
+    if dtype == "fp8":
+        model.calibrate(x[:min(4, B)])
+    out = torch.empty((B, T, F, mc.m), dtype=torch.float32, device="cuda")
+    for _ in range(warmup):
+        model.forward(x, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stage_ms, units = [], None
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        _, ms, units = model.forward_profiled(x, out=out, units=True)
+        stage_ms.append(ms)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = ev0.elapsed_time(ev1) / steps
+    stage_ms = np.array(stage_ms, dtype=np.float64)
+    per_call = stage_ms.sum(axis=1)                    # first to last event of each forward
+    rec = {"workload": w.name, "dtype": dtype, "value": round(res / (ms_per_step * 1e-3), 1), "unit": "REs/s",
+           "steps": steps, "warmup": warmup, "ms_per_step": round(ms_per_step, 4),
+           "call_ms": {"p10": round(float(np.percentile(per_call, 10)), 4), "p50": round(float(np.median(per_call)), 4),
+                       "p90": round(float(np.percentile(per_call, 90)), 4)},
+           "res_per_step": res, "K": mc.K, "L": mc.L, "C": mc.C, "C_in": mc.C_in, "m": mc.m,
+           "whole_step_tflops": round(flops_per_re(mc.K, mc.L, mc.C, mc.C_in, mc.m) * res / (ms_per_step * 1e-3) / 1e12, 2),
+           "roofline": dominant_roofline(stage_ms, units, mc, res, dtype, model.block_tile_width, w.name)}
+    print(f"[bench] {label}: {ms_per_step:.3f} ms/step, median call {rec['call_ms']['p50']:.3f} ms, "
+          f"{rec['roofline']['kernel']} at {rec['roofline']['frac']:.3f} of peak", file=sys.stderr, flush=True)
+    model.close()
+    return rec, out
+
+
+def c1_latency(calls=100, warmup=10):
+    """The single-slot FP32 workload (72 x 14 grid, K=2 L=2 C=32): latency of one forward, each
+    call timed alone by HIP events on its stream with the GPU otherwise idle."""
+    import torch
+    from paper_2510_12739_amd import Conet
+    from synth import make_blob, simulate_slot, workload
+    w = workload("fp32_b1_f72")
+    mc = w.model
+    X = np.stack([simulate_slot(w.sim, s).features for s in range(w.batch)])
+    x = torch.from_numpy(X).cuda()
+    model = Conet(mc.K, mc.L, mc.C, mc.C_in, mc.m, make_blob(mc, seed=w.weight_seed), dtype="f32",
+                  max_res=X.shape[0] * 14 * 72)
+    out = torch.empty((w.batch, 14, 72, mc.m), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        model.forward(x, out=out)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(calls):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        model.forward(x, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        lat.append(e0.elapsed_time(e1) * 1e3)
+    model.close()
+    return {"workload": w.name, "dtype": "f32", "calls": calls,
+            "latency_us": {"p10": round(float(np.percentile(lat, 10)), 1), "p50": round(float(np.median(lat)), 1),
+                           "p90": round(float(np.percentile(lat, 90)), 1)}}
+
+
+def snr_at(snr, ber, target):
+    """SNR where a BER curve crosses `target` (log-linear interpolation), or None."""
+    lt = np.log10(target)
+    lb = np.log10(np.maximum(np.asarray(ber, float), 1e-12))
+    for i in range(len(snr) - 1):
+        if (lb[i] - lt) * (lb[i + 1] - lt) <= 0 and lb[i] != lb[i + 1]:
+            return float(snr[i] + (lt - lb[i]) * (snr[i + 1] - snr[i]) / (lb[i + 1] - lb[i]))
+    return None
+
+
+def ber_leg(wl, dtypes):
+    """BER against SNR of the trained network at each GPU precision on the slots whose FP64 BER
+    tests/golden/ber_<wl>.json holds (common random numbers), and the horizontal gap to the FP64
+    curve at BER 1e-3 (1e-2 if the FP64 curve does not reach 1e-3)."""
+    import torch
+    from paper_2510_12739_amd import Conet
+    from synth import SimConfig, simulate_slot, workload
+    from synth.ofdm import data_mask
+    path = os.path.join(ROOT, "tests", "golden", f"ber_{wl}.json")
+    blob = trained_blob(wl)
+    if blob is None or not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    w = workload(wl)
+    mc, s0 = w.model, w.sim
+    snr = [r["snr_db"] for r in g["points"]]
+    F, n_sl, T = g["F"], g["slots_per_point"], g["T"]
+    X, bits = [], []
+    for i, v in enumerate(snr):
+        sim = SimConfig(F=F, n_rx=s0.n_rx, bits_per_symbol=s0.bits_per_symbol, n_taps=s0.n_taps,
+                        max_doppler_hz=s0.max_doppler_hz, snr_db=float(v), seed=g["sim_seed"])
+        for s in range(n_sl):
+            sl = simulate_slot(sim, i * 1000 + s)
+            X.append(sl.features)
+            bits.append(sl.bits)
+    X = np.stack(X)
+    bits = np.stack(bits).reshape(len(snr), n_sl, T, F, mc.m)
+    mask = np.broadcast_to(data_mask(T, F)[None, None, :, :, None], bits.shape)
+    ber64 = np.array([r["errors_fp64"] / r["bits"] for r in g["points"]])
+    target = 1e-3 if ber64.min() <= 1e-3 else 1e-2
+    s64 = snr_at(snr, ber64, target)
+    out = {"workload": wl, "weights": g["weights"], "slots": f"{len(snr)} SNR points x {n_sl} slots of {T}x{F} REs",
+           "target_ber": target, "snr_db_at_target": {"fp64": s64}, "delta_db": {}, "ber": {"snr_db": snr,
+           "fp64": [float(v) for v in ber64]}}
+    x = torch.from_numpy(X).cuda()
+    for dt in dtypes:
+        model = Conet(mc.K, mc.L, mc.C, mc.C_in, mc.m, blob, dtype=dt, max_res=X.shape[0] * T * F)
+        if dt == "fp8":
+            from synth import features_fast
+            model.calibrate(torch.from_numpy(features_fast(s0.__class__(**{**s0.__dict__, "F": F}), 8)).cuda())
+        llr = model(x)
+        torch.cuda.synchronize()
+        err = ((llr.cpu().numpy() > 0).reshape(bits.shape) != bits) & mask
+        b = err.reshape(len(snr), -1).sum(axis=1) / mask.reshape(len(snr), -1).sum(axis=1)
+        sx = snr_at(snr, b, target)
+        out["ber"][dt] = [float(v) for v in b]
+        out["snr_db_at_target"][dt] = sx
+        out["delta_db"][dt] = None if (sx is None or s64 is None) else round(sx - s64, 4)
+        model.close()
+        print(f"[bench] BER {wl} {dt}: delta {out['delta_db'][dt]} dB at {target:g}", file=sys.stderr, flush=True)
+    return out
+
+
+def window_samples(X, windows, R):
+    """(X window with its R-subcarrier margin, slice of its own outputs) per (slot, f0, f1)."""
+    outs = []
+    for s, f0, f1 in windows:
+        a, b = max(f0 - R, 0), min(f1 + R, X.shape[2])
+        outs.append((X[s:s + 1, :, a:b], slice(f0 - a, f0 - a + (f1 - f0))))
+    return outs
+
+
+def headline(args):
+    """The default run: the BF16 batched-inference workload (the metric's configuration) with its
+    roofline and the FP64 oracle beside it, plus the comparison legs the metric names."""
+    import torch
+    from synth import workload
+
+    dtype = args.dtype or workload(args.workload).dtype
+    w = workload(args.workload)
+    blob, wkind, X = leg_inputs(w)
+    from paper_2510_12739_amd import mfma_peak
+    peak_meas, clock_ghz = mfma_peak(dtype)
+    print(f"[bench] measured MFMA peak {peak_meas:.1f} TFLOP/s at {clock_ghz:.3f} GHz", file=sys.stderr, flush=True)
+    rec, out = forward_leg(w, dtype, blob, X, args.steps, args.warmup, "headline")
+    n_s = min(8, w.batch)
+    llr_head = out[:n_s].cpu().numpy()
+    del out
+    rl = dict(rec["roofline"])
+    rl.update({"measured_peak": round(peak_meas, 1), "measured_clock_ghz": round(clock_ghz, 3),
+               "frac_of_measured_peak": round(rl["achieved"] / peak_meas, 4) if peak_meas > 0 else None,
+               "whole_step_tflops": rec["whole_step_tflops"]})
+    mc = w.model
+    B, T, F = X.shape[:3]
+    result = {"metric": METRIC, "value": rec["value"], "unit": "REs/s", "n_gpus": 1, "steps": args.steps,
+              "warmup": args.warmup, "ms_per_step": rec["ms_per_step"], "call_ms": rec["call_ms"],
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+              "data": f"synthetic (seeded OFDM simulator: Rayleigh + Jakes channel, AWGN, LS features; {wkind} weights)",
+              "config": {"workload": w.name, "slots": B, "T": T, "F": F, "n_rx": w.sim.n_rx, "K": mc.K, "L": mc.L,
+                         "C": mc.C, "C_in": mc.C_in, "m": mc.m, "res_per_step": B * T * F, "parallelism": "single-gpu"},
+              "llr_tolerance": LLR_TOL[dtype], "roofline": rl}
+    legs = {}
+    full = not args.quick and args.workload == "bf16_b64_f3276" and dtype == "bf16"
+    llr_legs = {}
+    if full:
+        # FP32 on the same shape (the metric's comparison point)
+        r32, o32 = forward_leg(w, "f32", blob, X, max(3, args.steps // 10), 1, "fp32 on the BF16 shape")
+        llr_legs[("bf16_b64_f3276", "f32")] = o32[:n_s].cpu().numpy()
+        del o32
+        r32["speedup_of_bf16"] = round(rec["value"] / r32["value"], 3)
+        legs["f32_" + w.name] = r32
+        # the FP8 workload, and BF16 / FP32 on its shape
+        w3 = workload("fp8_b128_f3276")
+        blob3, wkind3, X3 = leg_inputs(w3)
+        R = 2 * w3.model.L + 1
+        wins = [(0, 0, 128), (3, 1600, 1728), (7, 3148, 3276)]
+        for dt3, st in (("fp8", max(5, args.steps // 5)), ("bf16", max(3, args.steps // 10)), ("f32", 2)):
+            r3, o3 = forward_leg(w3, dt3, blob3, X3, st, 1, f"{dt3} on the FP8 shape")
+            llr_legs[("fp8_b128_f3276", dt3)] = [o3[s:s + 1, :, f0:f1].cpu().numpy() for s, f0, f1 in wins]
+            del o3
+            r3["weights"] = wkind3
+            legs[f"{dt3}_{w3.name}"] = r3
+            torch.cuda.empty_cache()
+        v8 = legs["fp8_fp8_b128_f3276"]["value"]
+        legs["fp8_fp8_b128_f3276"]["speedup_over_bf16"] = round(v8 / legs["bf16_fp8_b128_f3276"]["value"], 3)
+        legs["fp8_fp8_b128_f3276"]["speedup_over_f32"] = round(v8 / legs["f32_fp8_b128_f3276"]["value"], 3)
+        legs["c1_latency"] = c1_latency()
+    if not args.no_cpu:
+        extra = []
+        if full:
+            extra = [("fp8_b128_f3276", w3, blob3, window_samples(X3, wins, R))]
+        cb, refs = cpu_baseline(w, blob, X[:n_s], budget_s=args.cpu_budget, extra=extra)
+        result["cpu_baseline"] = cb
+        ref = refs[w.name]
+        result["llr_err"] = llr_error(llr_head[:ref.shape[0]], ref)
+        for (wl, dt), got in llr_legs.items():
+            if wl == w.name:
+                legs[f"{dt}_{wl}"]["llr_err"] = llr_error(got[:ref.shape[0]], ref)
+            else:
+                legs[f"{dt}_{wl}"]["llr_err"] = llr_error(np.concatenate([g.ravel() for g in got]),
+                                                          np.concatenate([r.ravel() for r in refs[wl]]))
+                legs[f"{dt}_{wl}"]["llr_err"]["sample"] = f"{len(wins)} windows of 128 subcarriers"
+    else:
+        result["cpu_baseline"] = None
+    if full:
+        ber = {}
+        for wl, dts in (("bf16_b64_f3276", ("f32", "bf16")), ("fp8_b128_f3276", ("f32", "bf16", "fp8"))):
+            b = ber_leg(wl, dts)
+            if b is not None:
+                ber[wl] = b
+        result["ber_delta"] = ber or None
+    result["legs"] = legs or None
+
+    # input featuriser (LS + interpolation, conet_featurise) on the headline grid: reported
+    # beside the forward, not part of `value` (the forward's boundary takes features)
+    if not args.quick:
+        from paper_2510_12739_amd import featurise
+        from synth import simulate_slot
+        stream = torch.cuda.current_stream()
+        ys = np.stack([simulate_slot(w.sim, s).y for s in range(min(8, B))])
+        ys = np.concatenate([ys] * (-(-B // ys.shape[0])), axis=0)[:B]
+        y_dev = torch.from_numpy(np.ascontiguousarray(np.stack([ys.real, ys.imag], axis=-1).astype(np.float32))).cuda()
+        del ys
+        xf = torch.empty((B, T, F, mc.C_in), dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            featurise(y_dev, mc.C_in, out=xf)
+        fe0, fe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fe0.record(stream)
+        for _ in range(10):
+            featurise(y_dev, mc.C_in, out=xf)
+        fe1.record(stream)
+        torch.cuda.synchronize()
+        f_ms = fe0.elapsed_time(fe1) / 10
+        f_bytes = y_dev.numel() * 4 + xf.numel() * 4
+        result["featuriser"] = {"ms": round(f_ms, 4), "bytes": f_bytes,
+                                "GB_per_s": round(f_bytes / (f_ms * 1e-3) / 1e9, 1),
+                                "frac_of_hbm_peak": round(f_bytes / (f_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del y_dev, xf
+        torch.cuda.empty_cache()
+
+    if full and not args.no_serve:
+        result["serving"] = serve_measure(loads=args.serve_loads, duration_s=args.serve_seconds, grid=True, pinned=True)
+        ok = [p["offered_req_s"] for p in result["serving"]["points"] if p["p99_us"] < 500.0]
+        result["serving"]["max_load_req_s_p99_under_500us"] = max(ok) if ok else None
+
+    line = json.dumps(result)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(line + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="bf16_b64_f3276")
     ap.add_argument("--dtype", default=None, help="override the workload's dtype (f32, bf16, fp8)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--serve", action="store_true", help="only the serving load sweep (10 %% .. 120 %% of capacity)")
-    ap.add_argument("--no-serve", action="store_true", help="skip the serving point of the default run")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep of the default run")
+    ap.add_argument("--quick", action="store_true", help="only the headline workload (no comparison legs, BER, "
+                    "featuriser or serving)")
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.1, 0.25, 0.5, 0.75, 1.0])
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--depth-latency", action="store_true",
                     help="only the depth-vs-latency experiment (CoNet K=2 L=6 vs ResNet K=1 L=11)")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -452,144 +811,7 @@ def main():
         train_bench(args)
         return
 
-    import torch
-    from paper_2510_12739_amd import Conet
-    from synth import features_fast, make_blob, workload
-
-    w = workload(args.workload)
-    dtype = args.dtype or w.dtype
-    mc = w.model
-    B, T, F = w.batch, w.sim.T, w.sim.F
-    res = B * T * F
-    print(f"[bench] workload {w.name} dtype {dtype}: B={B} T={T} F={F} K={mc.K} L={mc.L} C={mc.C} "
-          f"C_in={mc.C_in} m={mc.m}", file=sys.stderr, flush=True)
-    blob = make_blob(mc, seed=w.weight_seed)
-    X = features_fast(w.sim, B, n_distinct=min(8, B))
-    x = torch.from_numpy(X).cuda()
-    model = Conet(mc.K, mc.L, mc.C, mc.C_in, mc.m, blob, dtype=dtype, max_res=res)
-    if dtype == "fp8":
-        model.calibrate(x[:min(4, B)])
-    out = torch.empty((B, T, F, mc.m), dtype=torch.float32, device="cuda")
-
-    # attainable dense-MFMA peak and shader clock on this device (context for `frac`)
-    from paper_2510_12739_amd import mfma_peak
-    peak_meas, clock_ghz = mfma_peak(dtype)
-    print(f"[bench] measured MFMA peak {peak_meas:.1f} TFLOP/s at {clock_ghz:.3f} GHz", file=sys.stderr, flush=True)
-
-    for _ in range(args.warmup):
-        model.forward(x, out=out)
-    torch.cuda.synchronize()
-    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
-
-    # ---- timed region: K steps; each records a HIP event before every kernel launch
-    stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    stage_ms = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    stage_units = None
-    for _ in range(args.steps):
-        _, ms, stage_units = model.forward_profiled(x, out=out, units=True)
-        stage_ms.append(ms)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_total = ev0.elapsed_time(ev1)
-    ms_per_step = ms_total / args.steps
-    stage_ms = np.array(stage_ms)                          # [steps, 1 + 2L]
-    print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall:.2f} s)", file=sys.stderr, flush=True)
-
-    # ---- roofline of the dominant kernel. Stages: input layer, then per block (a) conv 1 of
-    # all branches / a fused block without fusion after it, (b) support branches (their conv 2,
-    # or with fused residual blocks both convs, paired with the previous block's main branch
-    # when it was deferred to this launch), (c) a main branch launched alone. The library
-    # reports each stage's conv-branch units (one conv of one branch over the batch), so the
-    # FLOPs are algorithmic: units x REs x 2*9*C*C (the fused kernel's halo recompute of conv 1
-    # and padded M-tiles are not counted).
-    blk_fl = res * 2 * 9 * mc.C * mc.C                   # MFMA FLOPs of one block conv over one branch
-    fused_tw = model.block_tile_width
-    names = (("block_fused_all", "block_fused_supports", "block_fused_main") if fused_tw else
-             ("block_conv1", "block_conv2_supports", "block_conv2_main_fused"))
-    kinds = {}
-    for i in range(1, stage_ms.shape[1]):
-        u = int(stage_units[i])
-        if u == 0:
-            continue
-        name = names[(i - 1) % 3]
-        if fused_tw and (i - 1) % 3 == 1 and u == 2 * mc.K:
-            name = "block_fused_pair"
-        kinds.setdefault(name, []).append((stage_ms[:, i], u * blk_fl))
-    tot = {k: sum(float(ms.sum()) for ms, _ in v) for k, v in kinds.items() if v}
-    dom = max(tot, key=tot.get)
-    launches = kinds[dom]
-    fl_launch = float(np.mean([fl for _, fl in launches]))
-    dom_ms = float(np.mean([ms.mean() for ms, _ in launches]))
-    achieved = float(np.mean([fl / (ms.mean() * 1e-3) for ms, fl in launches])) / 1e12
-    peak = PEAK_TFLOPS[dtype]
-    traffic = load_traffic(dom, w.name, dtype)
-    roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": traffic,
-                "flops_per_launch": fl_launch, "mean_launch_ms": round(dom_ms, 4),
-                "fused_block_tile_width": fused_tw,
-                "measured_peak": round(peak_meas, 1), "measured_clock_ghz": round(clock_ghz, 3),
-                "frac_of_measured_peak": round(achieved / peak_meas, 4) if peak_meas > 0 else None,
-                "stage_mean_ms": [round(float(v), 4) for v in stage_ms.mean(axis=0)],
-                "stage_conv_units": [int(u) for u in stage_units],
-                "whole_step_tflops": round(flops_per_re(mc.K, mc.L, mc.C, mc.C_in, mc.m) * res / (ms_per_step * 1e-3) / 1e12, 2)}
-
-    result = {"metric": METRIC, "value": round(res / (ms_per_step * 1e-3), 1), "unit": "REs/s",
-              "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
-              "data": "synthetic (seeded OFDM simulator: Rayleigh + Jakes channel, AWGN, LS features; He-normal weights)",
-              "config": {"workload": w.name, "slots": B, "T": T, "F": F, "n_rx": w.sim.n_rx, "K": mc.K, "L": mc.L,
-                         "C": mc.C, "C_in": mc.C_in, "m": mc.m, "res_per_step": res, "parallelism": "single-gpu"},
-              "llr_tolerance": LLR_TOL[dtype],
-              "roofline": roofline}
-
-    # input featuriser (LS + interpolation, conet_featurise) on the same grid: reported beside
-    # the forward, not part of `value` (the forward's boundary takes features)
-    from paper_2510_12739_amd import featurise
-    from synth import simulate_slot
-    ys = np.stack([simulate_slot(w.sim, s).y for s in range(min(8, B))])
-    ys = np.concatenate([ys] * (-(-B // ys.shape[0])), axis=0)[:B]
-    y_dev = torch.from_numpy(np.ascontiguousarray(np.stack([ys.real, ys.imag], axis=-1).astype(np.float32))).cuda()
-    del ys
-    xf = torch.empty_like(x)
-    for _ in range(3):
-        featurise(y_dev, mc.C_in, out=xf)
-    fe0, fe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    fe0.record(stream)
-    for _ in range(10):
-        featurise(y_dev, mc.C_in, out=xf)
-    fe1.record(stream)
-    torch.cuda.synchronize()
-    f_ms = fe0.elapsed_time(fe1) / 10
-    f_bytes = y_dev.numel() * 4 + xf.numel() * 4
-    result["featuriser"] = {"ms": round(f_ms, 4), "bytes": f_bytes, "GB_per_s": round(f_bytes / (f_ms * 1e-3) / 1e9, 1),
-                            "frac_of_hbm_peak": round(f_bytes / (f_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    del y_dev, xf
-
-    if not args.no_cpu:
-        n_s = min(8, B)
-        llr_s = out[:n_s].cpu().numpy()
-        cb, err = cpu_baseline(w, blob, X[:n_s], llr_s, budget_s=args.cpu_budget)
-        result["cpu_baseline"] = cb
-        result["llr_err"] = err
-    else:
-        result["cpu_baseline"] = None
-
-    if not args.no_serve and args.workload == "bf16_b64_f3276" and dtype == "bf16":
-        del model, x, out
-        torch.cuda.empty_cache()
-        # received grids in page-locked buffers (the server's fastest input path); --serve sweeps all four
-        result["serving"] = serve_measure(loads=(0.1, 0.5), duration_s=1.5, grid=True, pinned=True)
-
-    line = json.dumps(result)
-    print(line, flush=True)
-    if args.json_out:
-        with open(args.json_out, "w") as f:
-            f.write(line + "\n")
+    headline(args)
 
 
 if __name__ == "__main__":

@@ -145,14 +145,21 @@ def train(p0: Dict, sim_kwargs: Dict, steps: int, batch: int, out_path: str, lr:
     T = sim_kwargs.get("T", 14)
     dm = torch.from_numpy(dmask(T, sim_kwargs["F"]))
     log = {"sim": sim_kwargs, "steps": steps, "batch": batch, "lr": lr, "lr_final": lr_final, "clip": clip,
-           "loss": []}
+           "first_slot": first_slot, "loss": []}
     t0 = time.time()
     ctx = mp.get_context("fork")
     with ctx.Pool(workers, initializer=_init_worker, initargs=(sim_kwargs,)) as pool:
-        jobs = ((first_slot + s * batch, batch) for s in range(steps))
+        # at most 2 batches per worker in flight: the simulator outruns the optimiser, and an
+        # unbounded imap would queue every step's batch in memory
+        ahead = 2 * workers
+        pending = [pool.apply_async(_make_batch, ((first_slot + s * batch, batch),)) for s in range(min(ahead, steps))]
         run = 0.0
         step = 0
-        for X, bits in pool.imap(_make_batch, jobs, chunksize=1):
+        while pending:
+            X, bits = pending.pop(0).get()
+            nxt = step + len(pending) + 1
+            if nxt < steps:
+                pending.append(pool.apply_async(_make_batch, ((first_slot + nxt * batch, batch),)))
             frac = step / max(1, steps - 1)
             if max_seconds is not None:  # decay over whichever budget runs out first
                 frac = max(frac, (time.time() - t0) / max_seconds)

@@ -35,6 +35,8 @@ def main():
     ap.add_argument("--threads", type=int, default=6)
     ap.add_argument("--workers", type=int, default=2)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--resume", action="store_true",
+                    help="start from the blob already written (fresh Adam state, training slots after those used)")
     args = ap.parse_args()
     w = workload(args.workload)
     mc = w.model
@@ -42,8 +44,15 @@ def main():
     sim = dict(w.sim.__dict__)
     sim.update(F=args.F, seed=1000 + w.sim.seed)
     out = os.path.join(HERE, f"trained_{args.workload}.npy")
+    first = 0
+    if args.resume:
+        import json
+        import numpy as np
+        p0 = o.unpack(np.load(out), mc.K, mc.L, mc.C, mc.C_in, mc.m)
+        prev = json.load(open(os.path.splitext(out)[0] + ".json"))
+        first = prev.get("first_slot", 0) + prev["steps_done"] * prev["batch"]
     trainer.train(p0, sim, steps=args.steps, batch=args.batch, out_path=out, lr=args.lr,
-                  threads=args.threads, workers=args.workers, max_seconds=args.minutes * 60.0)
+                  threads=args.threads, workers=args.workers, max_seconds=args.minutes * 60.0, first_slot=first)
     print("wrote", out)
 
 
