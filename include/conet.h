@@ -139,6 +139,27 @@ conet_status conet_forward(conet_model* model, const float* x, int32_t B, int32_
 conet_status conet_forward_ragged(conet_model* model, const float* x, int32_t n_slots, int32_t T,
                                   const int32_t* F_host, float* llr, void* stream);
 
+/* Bytes of the library's static device scratch array used by conet_forward_noalloc. */
+#define CONET_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (HIP graph capture, serving loops that
+ * forbid hipMalloc): conet_forward on a uniform batch, same arguments, layout and results
+ * (bitwise), except that the forward's activation buffers (residual-stream ping-pong and
+ * middle activations of every branch) come from a file-scope device array of
+ * CONET_NOALLOC_SCRATCH_BYTES per GPU, held from the library's load on that GPU until the
+ * process ends, instead of the model's workspace. The call allocates nothing and enqueues
+ * no memset. Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (any model, any stream) race and must be serialised by the caller. Inference only (no
+ * save_for_backward). Errors: as conet_forward, plus ESHAPE when B*T*F exceeds
+ * conet_forward_noalloc_capacity(model), EDEVICE when the current device is not the
+ * model's. */
+conet_status conet_forward_noalloc(conet_model* model, const float* x, int32_t B, int32_t T, int32_t F, float* llr,
+                                   void* stream);
+
+/* Largest B*T*F conet_forward_noalloc accepts for this model (its activation buffers
+ * must fit the static array: at K = 3, C = 64 in BF16 about 58 K REs). 0 for a null model. */
+int64_t conet_forward_noalloc_capacity(const conet_model* model);
+
 /* conet_forward on a uniform batch with a HIP event recorded on `stream` before every
  * stage and after the last: stage_ms_host[i] (n_stages = 1 + 3L entries) gets the elapsed
  * time of stage i: the input layer, then per block (a) its first conv over all branches,

@@ -22,6 +22,7 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "ENOMEM", 4: "EDEVICE", 5: "EBUS
 # Every symbol include/conet.h declares.
 EXPORTS = ("conet_weight_count", "conet_workspace_bytes", "conet_create", "conet_set_act_scales",
            "conet_calibrate", "conet_get_act_scales", "conet_forward", "conet_forward_ragged", "conet_forward_profiled",
+           "conet_forward_noalloc", "conet_forward_noalloc_capacity",
            "conet_block_tile_width", "conet_mfma_peak", "conet_featurise",
            "conet_serve_create", "conet_serve_submit", "conet_serve_wait", "conet_serve_get_stats",
            "conet_serve_reset_stats", "conet_serve_pause", "conet_serve_destroy", "conet_backward", "conet_grads",
@@ -86,6 +87,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.conet_forward_ragged.restype = i32
     lib.conet_forward_profiled.argtypes = [vp, vp, i32, i32, i32, vp, fp, ctypes.POINTER(i32), i32, vp]
     lib.conet_forward_profiled.restype = i32
+    lib.conet_forward_noalloc.argtypes = [vp, vp, i32, i32, i32, vp, vp]; lib.conet_forward_noalloc.restype = i32
+    lib.conet_forward_noalloc_capacity.argtypes = [vp]; lib.conet_forward_noalloc_capacity.restype = i64
     lib.conet_block_tile_width.argtypes = [vp]; lib.conet_block_tile_width.restype = i32
     dp = ctypes.POINTER(ctypes.c_double)
     lib.conet_mfma_peak.argtypes = [i32, i32, dp, dp, vp]; lib.conet_mfma_peak.restype = i32
@@ -215,6 +218,19 @@ class Conet:
         if save:
             self._saved_x = x
         return out
+
+    def forward_noalloc(self, x, out, stream=None):
+        """conet_forward_noalloc: the forward with its activation buffers in the library's static
+        device array (no allocation; `out` must be given). Calls on one GPU must not overlap."""
+        self._check_x(x)
+        B, T, F, _ = x.shape
+        _check(self.lib.conet_forward_noalloc(self.handle, ctypes.c_void_p(x.data_ptr()), B, T, F,
+                                              ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    @property
+    def noalloc_capacity(self) -> int:
+        return int(self.lib.conet_forward_noalloc_capacity(self.handle))
 
     # ---- training
     def _view(self, fn):

@@ -321,6 +321,8 @@ conet_status conet_create(const conet_config* cfg, const float* w, size_t n_weig
   hipError_t e = hipGetDevice(&M->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&M->n_cu, hipDeviceAttributeMultiprocessorCount, M->device);
   if (e != hipSuccess) { delete M; return hip_fail(e, "hipGetDevice"); }
+  st = noalloc_setup(M->device);
+  if (st != CONET_OK) { delete M; return st; }
 
   const int K = cfg->branches, L = cfg->blocks, C = cfg->channels, Ci = cfg->in_channels, m = cfg->bits_per_symbol;
   const Layout& lay = M->lay;

@@ -124,6 +124,10 @@ size_t arena_bytes(const conet_config& c, int64_t max_res);
 // Carve an Arena out of `base` (256-byte aligned, arena_bytes long).
 void arena_carve(const conet_config& c, int64_t max_res, uint8_t* base, Arena& ar);
 
+// Record the address of the static scratch array of conet_forward_noalloc on `device`
+// (the current device); called once per device from conet_create.
+conet_status noalloc_setup(int device);
+
 hipError_t launch_amax(const void* x, int act_dtype_bytes, int64_t n_re, int C, const float* s0, const float* o0,
                        int prologue, unsigned* out, hipStream_t s);
 
