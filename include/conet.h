@@ -54,7 +54,7 @@ typedef enum {
   CONET_BF16 = 1,     /* BF16 operands and activations, FP32 accumulation and epilogues */
   CONET_FP8E4M3 = 2,  /* OCP e4m3 conv operands (per-output-channel filter scales, static
                          per-tensor activation scales), BF16 residual stream, FP32 accumulation */
-  CONET_FP64 = 3      /* reserved */
+  CONET_FP64 = 3      /* reserved (not accepted by conet_create) */
 } conet_dtype;
 
 typedef struct {
@@ -191,11 +191,14 @@ conet_status conet_forward_profiled(conet_model* model, const float* x, int32_t 
 conet_status conet_featurise(const float* y, int32_t B, int32_t T, int32_t F, int32_t n_rx, int32_t C_in,
                              float* x_out, void* stream);
 
-/* Subcarriers per tile of the fused residual-block kernel that inference forwards of
- * this model use (both convs of a block in one launch, the hidden activation kept on
- * chip; BF16 with C in {16, 32, 64} and K <= 4), or 0 when every block runs as two conv
- * launches (FP32, FP8, other widths; calibration and save_for_backward forwards always
- * do). Returns 0 for a null model. */
+/* Subcarriers per tile of the fused residual-block kernel that forwards of this model use
+ * on a batch that fills the GPU (both convs of a block in one launch, the hidden activation
+ * kept on chip): BF16 with C in {16, 32, 64} on 16x16 MFMAs, BF16 and FP8 with C = 96 on
+ * 32x32 MFMAs, K <= 4. Training models (train = 1, C <= 64) run their save_for_backward
+ * forwards on the same fused kernels, which then also store each block's middle activation.
+ * Batches too small to fill the GPU run on narrower tiles of the same kernels. 0 when every
+ * block runs as two conv launches (FP32, other widths, K > 4); FP8 calibration always does.
+ * Returns 0 for a null model. */
 int32_t conet_block_tile_width(const conet_model* model);
 
 /* Dense-MFMA throughput on the current device, for reading roofline fractions against an

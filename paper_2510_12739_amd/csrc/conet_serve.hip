@@ -428,6 +428,12 @@ static void launch_batch(conet_server* S, int li, std::unique_lock<std::mutex>& 
     if (e != hipSuccess) st = hip_fail(e, "serving D2H");
   }
   ln.t_enqueued = clk::now();
+  if (st != CONET_OK) {
+    // Part of the batch may already be enqueued (copies out of callers' page-locked inputs or
+    // the lane's pinned staging, copies into callers' LLR buffers). Drain the stream before the
+    // requests complete and the staging is reused; the batch fails whatever this returns.
+    (void)hipStreamSynchronize(ln.stream);
+  }
   lk.lock();
   if (st != CONET_OK) {  // fail the whole batch; the lane stays usable
     for (auto& p : ln.batch) {
