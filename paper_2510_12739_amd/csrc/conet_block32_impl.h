@@ -88,6 +88,7 @@ struct GemmCore32 {
   // base[mt]: LDS byte offset of the lane's RE at tap (-1, -1), lane half included.
   __device__ __forceinline__ static void run(f32x16 (&acc)[MT][NOT], const uint8_t* lds, const i32x4* __restrict__ wp,
                                              const int (&base)[MT], int lane) {
+    __builtin_amdgcn_s_setprio(1);  // the MFMA loop issues ahead of the other work-group's waves
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -111,6 +112,7 @@ struct GemmCore32 {
         __builtin_amdgcn_sched_barrier(0);
       }
     }
+    __builtin_amdgcn_s_setprio(0);
   }
 };
 

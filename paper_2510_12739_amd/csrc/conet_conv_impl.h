@@ -254,6 +254,9 @@ struct GemmCore {
   __device__ __forceinline__ static void run(AccV (&acc)[MT][NOT], const uint8_t* lds, const i32x4* __restrict__ wp,
                                              const int (&base)[MT], int lane) {
     const int g = lane >> 4;
+    // A wave in its MFMA loop issues ahead of waves of the other work-group on the SIMD that
+    // are staging or in an epilogue, whose VALU and memory instructions fill the MFMA gaps.
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -310,6 +313,7 @@ struct GemmCore {
           for (int ot = 0; ot < NOT; ++ot) acc[mt][ot] = A::mma(a[s % NA][ot], b[mt], acc[mt][ot]);
       }
     }
+    __builtin_amdgcn_s_setprio(0);
   }
 };
 
