@@ -1,35 +1,26 @@
 """GPU parity of the forward pass (through the C ABI) against the FP64 oracle.
 
-Tolerances (derivations in the design notes):
+Tolerances:
   * FP32 kernels vs FP64: rel-L2 <= 1e-5 and max|d|/RMS <= 1e-4 (FP32 accumulation over
     at most 9*96 terms per conv and 2L+2 layers).
-  * BF16 / FP8 kernels vs the oracle emulating the same roundings: rel-L2 <= 5e-3 (BF16;
-    FP8 below). What remains is FP32 (GPU) vs FP64 (oracle) accumulation deciding
-    the rounding of an intermediate: a 576-term FP32 sum is off by ~sqrt(576) 2^-24 ~ 1.4e-6
-    relative, so about 1.4e-6 / 2^-9 ~ 1e-3 of the stored BF16 values land one ulp (2^-8)
-    apart; sqrt(1e-3) * 2^-8 ~ 1.5e-4 per layer, amplified by the K-way products over
-    2L+2 layers (measured 2e-3 at K=3, L=4), hence 5e-3.
-  * FP8: the e4m3 grid is 16x coarser than BF16's, so rounding flips decided by FP32 vs
-    FP64 round-off are 16x larger and K-way products with LayerNorm amplify them: the
-    oracle's own FP8 output moves by ~1e-2 rel-L2 when its input-layer dequantisation
-    changes by 1e-6 relative. The bound vs the FP8-emulating oracle is therefore 6e-2.
-    FP32 accumulation errors are absolute, not relative: a 576- or 864-term sum that
-    cancels to near zero is off by ~2^-24 sqrt(N) rms(terms), which decides the e4m3
-    rounding of the small activations it feeds. Modelled that way, the oracle's own FP8
-    output moves by 1.2e-3 rel-L2 for one block (K=1, L=1; measured GPU vs oracle 3.4e-3,
-    and 4e-3 / 7e-3 for one fused block at K=2 / 4); each further fused block multiplies
-    flipped values into the product (measured 2e-2 to 6.2e-2 at L=2..3, K=2..4). The
-    fused FP8 kernel and the two-conv FP8 path agree with each other to ~1e-7 rel-L2 on
-    these cases, so the gap is the oracle's FP64 accumulation, not a kernel difference.
-    Bounds: 1.5e-2 for single blocks, 6e-2 to 8e-2 for deeper product chains.
-  * BF16 vs plain FP64: rel-L2 <= 3e-2 and sign agreement >= 99 % (the stated BF16 LLR
-    tolerance). FP8 vs FP64 (stated as measured on the oracle's own FP8 emulation,
-    0.19 for K=4, L=2, C=96): rel-L2 <= 0.25 and sign agreement >= 93 %.
+  * BF16 / FP8 kernels vs the oracle emulating the same roundings (the precision contract of
+    the oracle's Quant): tolerances from the oracle's own model of the GPU's arithmetic
+    (tests/helpers.emulation_with_bound). Each conv sum carries FP32 rounding error, the FP8
+    matrix instructions also truncate each product to 13 fractional bits of the largest
+    product of its group of 8 (measured property of the instructions), and every value rounded
+    to BF16 or e4m3 carries the FP32 error of the operations forming it. Such errors decide
+    roundings next to a rounding boundary, and the K-way products amplify those flips; the
+    model's own spread over two draws, times 4 element-wise and times 2 in rel-L2, is the
+    bound. Tile seams must also look like the interior (mean |d| at most 3x).
+  * vs plain FP64 (the stated LLR tolerances): BF16 rel-L2 <= 3e-2 and sign agreement >= 99 %;
+    FP8 rel-L2 <= 0.25 and sign agreement >= 93 % on the small grids.
 """
+import os
+
 import numpy as np
 import pytest
 
-from helpers import features, max_over_rms, rel_l2, say, sign_agree
+from helpers import elementwise_report, emulation_with_bound, features, max_over_rms, rel_l2, say, sign_agree
 from oracle import conet64 as o
 from synth import ModelConfig, SimConfig, make_blob, workload
 
@@ -53,6 +44,23 @@ def _run(model, X):
 def _oracle(K, L, C, Ci, m, blob, X, mask=-1, quant=None):
     p = o.unpack(blob, K, L, C, Ci, m)
     return o.forward_slots(p, X.astype(np.float64), fuse_mask=None if mask < 0 else mask, quant=quant)
+
+
+def _elementwise(got, p, X64, quant, tw, label, **kw):
+    """Parity against the emulating oracle with the tolerances its GPU error model gives
+    (emulation_with_bound): every LLR within the element-wise bound, rel-L2 within the rel
+    bound, and tile seams no worse on average than the interior (the per-RE arithmetic does
+    not depend on the tiling). Returns the emulation."""
+    emu, bound, rel_bound = emulation_with_bound(p, X64, quant, **kw)
+    rms = float(np.sqrt(np.mean(emu ** 2)))
+    bound = max(bound, 1e-6 * rms)
+    rel_bound = max(rel_bound, 1e-6)
+    rep = elementwise_report(got, emu, tw, f"{label} (bound {bound:.2e} = {bound / rms:.2e} RMS)")
+    say(f"  {label}: rel-L2 vs emulated {rel_l2(got, emu):.2e} (bound {rel_bound:.2e})")
+    assert rep["all"][0] <= bound, (label, rep["all"][0], bound, rep["worst_index"])
+    assert rel_l2(got, emu) <= rel_bound, (label, rel_l2(got, emu), rel_bound)
+    assert rep["tile_seams"][1] <= 3.0 * rep["interior"][1] + 1e-6 * rms, (label, rep["tile_seams"], rep["interior"])
+    return emu
 
 
 # ----------------------------------------------------------------------------- FP32
@@ -145,11 +153,12 @@ def test_bf16_small_grid_vs_emulated_and_fp64():
     sim = SimConfig(F=72, n_rx=4, bits_per_symbol=4, seed=2)
     X = features(sim, 2)
     say("bf16 K=3 L=2 C=64 F=72 B=2")
-    got = _run(_model(K, L, C, Ci, m, "bf16", blob), X)
-    emu = _oracle(K, L, C, Ci, m, blob, X, quant=o.Quant("bf16"))
+    model = _model(K, L, C, Ci, m, "bf16", blob)
+    got = _run(model, X)
+    p = o.unpack(blob, K, L, C, Ci, m)
+    emu = _elementwise(got, p, X.astype(np.float64), o.Quant("bf16"), model.block_tile_width, "bf16 small grid")
     ref = _oracle(K, L, C, Ci, m, blob, X)
     say(f'  rel-L2 vs emulated {rel_l2(got, emu):.2e}, vs fp64 {rel_l2(got, ref):.2e}, sign {sign_agree(got, ref):.4f}')
-    assert rel_l2(got, emu) <= 5e-3, rel_l2(got, emu)
     assert rel_l2(got, ref) <= 3e-2 and sign_agree(got, ref) >= 0.99, (rel_l2(got, ref), sign_agree(got, ref))
 
 
@@ -169,12 +178,13 @@ def test_bf16_full_size_64x3276_sampled_slots():
     got = _run(model, X)
     got2 = _run(model, X)
     np.testing.assert_array_equal(got, got2)                  # deterministic
+    p = o.unpack(blob, mc.K, mc.L, mc.C, mc.C_in, mc.m)
     for s in sampled:
         ref = _oracle(mc.K, mc.L, mc.C, mc.C_in, mc.m, blob, X[s:s + 1])
-        emu = _oracle(mc.K, mc.L, mc.C, mc.C_in, mc.m, blob, X[s:s + 1], quant=o.Quant("bf16"))
+        emu = _elementwise(got[s:s + 1], p, X[s:s + 1].astype(np.float64), o.Quant("bf16"), model.block_tile_width,
+                           f"bf16 full size, slot {s}")
         say(f"  slot {s}: rel-L2 vs emulated {rel_l2(got[s:s + 1], emu):.2e}, vs fp64 {rel_l2(got[s:s + 1], ref):.2e}, "
             f"sign {sign_agree(got[s:s + 1], ref):.4f}")
-        assert rel_l2(got[s:s + 1], emu) <= 5e-3, (s, rel_l2(got[s:s + 1], emu))
         assert rel_l2(got[s:s + 1], ref) <= 3e-2 and sign_agree(got[s:s + 1], ref) >= 0.99
 
 
@@ -192,10 +202,9 @@ def test_fp8_small_grid_vs_emulated_and_fp64():
     model = _model(K, L, C, Ci, m, "fp8", blob)
     model.set_act_scales(scales)
     got = _run(model, X)
-    emu = o.forward_slots(p, X.astype(np.float64), quant=o.Quant("fp8", scales))
+    emu = _elementwise(got, p, X.astype(np.float64), o.Quant("fp8", scales), model.block_tile_width, "fp8 small grid")
     ref = o.forward_slots(p, X.astype(np.float64))
     say(f'  rel-L2 vs emulated {rel_l2(got, emu):.2e}, vs fp64 {rel_l2(got, ref):.2e}, sign {sign_agree(got, ref):.4f}')
-    assert rel_l2(got, emu) <= 6e-2, rel_l2(got, emu)
     assert rel_l2(got, ref) <= 0.25 and sign_agree(got, ref) >= 0.93, (rel_l2(got, ref), sign_agree(got, ref))
 
 
@@ -211,7 +220,7 @@ def test_bf16_96_channel_fused_block_kernel(K, L, mask, fusion, feedback, T, F):
     """BF16 at 96 channels runs each block as one fused kernel on the 32x32x16 MFMA (its own
     filter packing and chunk order), for every launch kind, both fusion operators, feedback
     and a short slot, on two slots with a ragged tile tail: against the BF16-emulating
-    oracle at the BF16 bound (5e-3) and plain FP64 at the stated BF16 LLR tolerance."""
+    oracle (model-derived tolerances) and plain FP64 at the stated BF16 LLR tolerance."""
     from paper_2510_12739_amd import Conet
     C, Ci, m = 96, 16, 4
     mc = ModelConfig(K, L, C, Ci, m, mask)
@@ -224,12 +233,12 @@ def test_bf16_96_channel_fused_block_kernel(K, L, mask, fusion, feedback, T, F):
     model = Conet(K, L, C, Ci, m, blob, dtype="bf16", fuse_mask=mc.mask, fusion=fusion, feedback=feedback)
     assert 0 < model.block_tile_width < F
     got = _run(model, X)
+    tw = model.block_tile_width
     model.close()
-    emu = o.forward_slots(p, X64, quant=o.Quant("bf16"), **kw)
+    emu = _elementwise(got, p, X64, o.Quant("bf16"), tw, "bf16 96 channels", **kw)
     ref = o.forward_slots(p, X64, **kw)
     say(f'  rel-L2 vs emulated {rel_l2(got, emu):.2e}, vs fp64 {rel_l2(got, ref):.2e}, sign {sign_agree(got, ref):.4f}')
     assert got.shape == (2, T, F, m)
-    assert rel_l2(got, emu) <= 5e-3, rel_l2(got, emu)
     assert rel_l2(got, ref) <= 3e-2 and sign_agree(got, ref) >= 0.99, (rel_l2(got, ref), sign_agree(got, ref))
 
 
@@ -241,13 +250,14 @@ def test_fp8_full_size_128x3276_sampled_windows():
     plus a 13-subcarrier margin (none at a slot edge, where the zero padding is the slot's).
     Checks: two full-size runs are bitwise equal; each window run alone on the GPU gives
     bitwise the full-size run's outputs there (per-RE arithmetic does not depend on tiling);
-    against the oracle, at this depth FP8 with random weights is ill-conditioned (the
-    FP8-emulating oracle is 0.43 rel-L2 from FP64 on these windows and moves 0.11 under
-    FP32-sized accumulation noise), so the GPU must be within 0.3 of the emulation and as
-    close to FP64 as the emulation is (within 0.1, sign agreement >= 0.85)."""
+    against the FP8-emulating oracle, the model-derived element-wise and rel-L2 tolerances;
+    against FP64, sign agreement >= 0.85. Weights: the trained network when its blob is in
+    tests/golden (the workload the BER comparison uses), else He-normal random weights (with
+    which FP8 at this depth is ill-conditioned: the emulation itself is ~0.4 rel-L2 from FP64)."""
     w = workload("fp8_b128_f3276")
     mc = w.model
-    blob = make_blob(mc, seed=w.weight_seed)
+    trained = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "trained_fp8_b128_f3276.npy")
+    blob = np.load(trained).astype(np.float32) if os.path.exists(trained) else make_blob(mc, seed=w.weight_seed)
     R = 2 * mc.L + 1
     X = np.concatenate([features(w.sim, 8)] * 16, axis=0)     # 128 slots
     windows = [(0, 0, 64), (77, 1600, 1664), (127, 3212, 3276)]
@@ -268,13 +278,16 @@ def test_fp8_full_size_128x3276_sampled_windows():
         alone = _run(model, Xw)[:, :, off:off + (f1 - f0)]
         np.testing.assert_array_equal(alone, got[s:s + 1, :, f0:f1])
         Xw64 = Xw.astype(np.float64)
-        emu = o.forward(p, Xw64, quant=o.Quant("fp8", scales))[:, :, off:off + (f1 - f0)]
-        ref = o.forward(p, Xw64)[:, :, off:off + (f1 - f0)]
+        own = lambda a: a[:, :, off:off + (f1 - f0)]
         g = got[s:s + 1, :, f0:f1]
-        say(f"  slot {s} [{f0}, {f1}): vs emulated {rel_l2(g, emu):.3f}, vs fp64 {rel_l2(g, ref):.3f} "
-            f"(emulated {rel_l2(emu, ref):.3f}), sign {sign_agree(g, ref):.4f}")
-        assert rel_l2(g, emu) <= 0.3, rel_l2(g, emu)
-        assert abs(rel_l2(g, ref) - rel_l2(emu, ref)) <= 0.1 and sign_agree(g, ref) >= 0.85
+        emu, bound, rel_bound = emulation_with_bound(p, Xw64, o.Quant("fp8", scales), sel=own)
+        ref = own(o.forward(p, Xw64))
+        rep = elementwise_report(g, emu, model.block_tile_width, f"fp8 full size slot {s} [{f0}, {f1}) "
+                                 f"(bound {bound:.2e})")
+        say(f"  slot {s} [{f0}, {f1}): vs emulated {rel_l2(g, emu):.3f} (bound {rel_bound:.3f}), vs fp64 "
+            f"{rel_l2(g, ref):.3f} (emulated {rel_l2(emu, ref):.3f}), sign {sign_agree(g, ref):.4f}")
+        assert rep["all"][0] <= bound and rel_l2(g, emu) <= rel_bound, (rep["all"][0], bound, rel_l2(g, emu), rel_bound)
+        assert sign_agree(g, ref) >= 0.85
     model.close()
 
 
@@ -294,20 +307,20 @@ def test_fp8_calibration_matches_oracle_scales():
     assert np.all(np.isfinite(y))
 
 
-@pytest.mark.parametrize("K,L,mask,fusion,feedback,T,F,bound", [
-    (1, 1, 0, "product", False, 14, 75, 1.5e-2),      # plain block with the head
-    (4, 1, -1, "product", False, 14, 75, 1.5e-2),     # fused main branch with the head, three supports
-    (2, 2, 0b01, "product", False, 14, 75, 6e-2),     # fused main branch (no head), then a plain head block
-    (3, 3, -1, "sum", True, 14, 40, 6e-2),            # feedback: every main branch launched alone
-    (4, 3, 0b101, "product", False, 14, 75, 8e-2),    # main + next supports paired in one launch
-    (4, 2, -1, "product", False, 7, 29, 6e-2),        # short slot: symbols 7..13 are conv padding
+@pytest.mark.parametrize("K,L,mask,fusion,feedback,T,F", [
+    (1, 1, 0, "product", False, 14, 75),      # plain block with the head
+    (4, 1, -1, "product", False, 14, 75),     # fused main branch with the head, three supports
+    (2, 2, 0b01, "product", False, 14, 75),   # fused main branch (no head), then a plain head block
+    (3, 3, -1, "sum", True, 14, 40),          # feedback: every main branch launched alone
+    (4, 3, 0b101, "product", False, 14, 75),  # main + next supports paired in one launch
+    (4, 2, -1, "product", False, 7, 29),      # short slot: symbols 7..13 are conv padding
 ])
-def test_fp8_fused_block_kernel_vs_emulated(K, L, mask, fusion, feedback, T, F, bound):
+def test_fp8_fused_block_kernel_vs_emulated(K, L, mask, fusion, feedback, T, F):
     """FP8 at 96 channels runs each block as one fused kernel on the 32x32x64 MFMA (its own
     filter packing and chunk order). Every launch kind (plain, main with and without the
     head, paired main + supports), both fusion operators, feedback and a short slot, on two
-    slots with a ragged tile tail, against the FP8-emulating oracle
-    (per-case bound, see the module notes) and plain FP64 at the FP8 bounds."""
+    slots with a ragged tile tail, against the FP8-emulating oracle (model-derived
+    tolerances, see the module notes) and plain FP64 at the FP8 bounds."""
     from paper_2510_12739_amd import Conet
     C, Ci, m = 96, 32, 8
     mc = ModelConfig(K, L, C, Ci, m, mask)
@@ -322,11 +335,10 @@ def test_fp8_fused_block_kernel_vs_emulated(K, L, mask, fusion, feedback, T, F, 
     assert 0 < model.block_tile_width < F  # fused kernel, several tiles per slot
     model.set_act_scales(scales)
     got = _run(model, X)
-    emu = o.forward_slots(p, X64, quant=o.Quant("fp8", scales), **kw)
+    emu = _elementwise(got, p, X64, o.Quant("fp8", scales), model.block_tile_width, "fp8 fused block", **kw)
     ref = o.forward_slots(p, X64, **kw)
     say(f'  rel-L2 vs emulated {rel_l2(got, emu):.2e}, vs fp64 {rel_l2(got, ref):.2e}, sign {sign_agree(got, ref):.4f}')
     assert got.shape == (2, T, F, m)
-    assert rel_l2(got, emu) <= bound, rel_l2(got, emu)
     assert rel_l2(got, ref) <= 0.25 and sign_agree(got, ref) >= 0.93, (rel_l2(got, ref), sign_agree(got, ref))
     model.close()
 
@@ -345,7 +357,7 @@ def test_fusion_variants_vs_oracle(dtype, K, L, C, mask, fusion, feedback):
     """Fusion by addition and Example II feedback (Sec. III), through both the fused block
     kernel (BF16, C = 32/64) and the two-conv path (FP32), on a 2-slot grid with a ragged
     tile tail (F = 70): FP32 vs FP64 at the FP32 bounds, BF16 vs the BF16-emulating oracle
-    at 5e-3 and vs FP64 at the stated LLR tolerance."""
+    (model-derived tolerances) and vs FP64 at the stated LLR tolerance."""
     from paper_2510_12739_amd import Conet
     Ci, m = 16, 4
     sim = SimConfig(F=70, n_rx=4, bits_per_symbol=m, seed=41)
@@ -361,9 +373,8 @@ def test_fusion_variants_vs_oracle(dtype, K, L, C, mask, fusion, feedback):
         assert rel_l2(got, ref) <= 1e-5, rel_l2(got, ref)
         assert max_over_rms(got, ref) <= 1e-4
     else:
-        emu = o.forward_slots(p, X.astype(np.float64), fuse_mask=mc.mask, fusion=fusion, feedback=feedback,
-                              quant=o.Quant("bf16"))
-        assert rel_l2(got, emu) <= 5e-3, rel_l2(got, emu)
+        emu = _elementwise(got, p, X.astype(np.float64), o.Quant("bf16"), model.block_tile_width or 32,
+                           f"bf16 {fusion} feedback={feedback}", fuse_mask=mc.mask, fusion=fusion, feedback=feedback)
         assert rel_l2(got, ref) <= 3e-2 and sign_agree(got, ref) >= 0.99
     model.close()
 
@@ -404,19 +415,18 @@ def test_batchnorm_fusion_vs_oracle(dtype, K, L, C, Ci, mask):
     elif dtype == "bf16":
         quant = o.Quant("bf16")
     got = _run(model, X)
+    tw = model.block_tile_width or 32
     model.close()
     ref = o.forward_slots(p, X64, fuse_mask=mc.mask)
     if dtype == "f32":
         assert rel_l2(got, ref) <= 1e-5, rel_l2(got, ref)
         assert max_over_rms(got, ref) <= 1e-4
         return
-    emu = o.forward_slots(p, X64, fuse_mask=mc.mask, quant=quant)
+    emu = _elementwise(got, p, X64, quant, tw, f"batchnorm {dtype}", fuse_mask=mc.mask)
     say(f'  rel-L2 vs emulated {rel_l2(got, emu):.2e}, vs fp64 {rel_l2(got, ref):.2e}, sign {sign_agree(got, ref):.4f}')
     if dtype == "bf16":
-        assert rel_l2(got, emu) <= 5e-3, rel_l2(got, emu)
         assert rel_l2(got, ref) <= 3e-2 and sign_agree(got, ref) >= 0.99
     else:
-        assert rel_l2(got, emu) <= 6e-2, rel_l2(got, emu)
         assert rel_l2(got, ref) <= 0.25 and sign_agree(got, ref) >= 0.93
 
 
