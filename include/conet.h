@@ -236,6 +236,22 @@ conet_status conet_adam_step(conet_model* model, float lr, float beta1, float be
  * else the blob it was created from. Synchronises the device. */
 conet_status conet_get_weights(conet_model* model, float* weights_host, size_t n);
 
+/* Training checkpoint (train models): copy the FP32 master weights and both Adam moments
+ * (each n = conet_weight_count values in blob order) and the number of Adam steps taken to
+ * host memory. Synchronises the device. Errors: EINVAL (null pointers, wrong n), ESTATE (not a
+ * train model), EDEVICE. */
+conet_status conet_save_train_state(conet_model* model, float* master_host, float* m_host, float* v_host, size_t n,
+                                     int32_t* adam_steps);
+
+/* Resume training from conet_save_train_state of a model with the same configuration: load the
+ * master weights, the Adam moments and the step count, and regenerate every filter pack and
+ * per-channel vector from the master copy, so that the next forward, backward and Adam step
+ * are exactly those the saved model would have run. Drops a saved forward. Synchronous.
+ * Errors: EINVAL (null pointers, wrong n, negative step count), ESTATE (not a train model),
+ * EDEVICE. */
+conet_status conet_load_train_state(conet_model* model, const float* master_host, const float* m_host,
+                                     const float* v_host, size_t n, int32_t adam_steps);
+
 /* Bitwise BCE with logits over data REs: loss_dev (1 float) = mean over the B slots'
  * data REs (data_mask [T][F] nonzero; n_data_per_slot of them) and their m bits of
  * max(z,0) - z b + log(1 + e^-|z|); dllr = (sigmoid(z) - b) / count on data REs, 0 on

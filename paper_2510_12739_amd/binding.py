@@ -26,7 +26,8 @@ EXPORTS = ("conet_weight_count", "conet_workspace_bytes", "conet_create", "conet
            "conet_block_tile_width", "conet_mfma_peak", "conet_featurise",
            "conet_serve_create", "conet_serve_submit", "conet_serve_wait", "conet_serve_get_stats",
            "conet_serve_reset_stats", "conet_serve_pause", "conet_serve_destroy", "conet_backward", "conet_grads",
-           "conet_master_weights", "conet_adam_step", "conet_get_weights", "conet_bce", "conet_destroy",
+           "conet_master_weights", "conet_adam_step", "conet_get_weights", "conet_save_train_state",
+           "conet_load_train_state", "conet_bce", "conet_destroy",
            "conet_last_error")
 
 
@@ -111,6 +112,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.conet_adam_step.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
     lib.conet_adam_step.restype = i32
     lib.conet_get_weights.argtypes = [vp, fp, sz]; lib.conet_get_weights.restype = i32
+    lib.conet_save_train_state.argtypes = [vp, fp, fp, fp, sz, ctypes.POINTER(i32)]
+    lib.conet_save_train_state.restype = i32
+    lib.conet_load_train_state.argtypes = [vp, fp, fp, fp, sz, i32]; lib.conet_load_train_state.restype = i32
     lib.conet_bce.argtypes = [vp, vp, vp, vp, i32, i32, i32, i64, vp, vp, vp]; lib.conet_bce.restype = i32
     lib.conet_destroy.argtypes = [vp]; lib.conet_destroy.restype = i32
     lib.conet_last_error.argtypes = []; lib.conet_last_error.restype = ctypes.c_char_p
@@ -259,6 +263,23 @@ class Conet:
         w = np.zeros(weight_count(self.cfg), dtype=np.float32)
         _check(self.lib.conet_get_weights(self.handle, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), w.size))
         return w
+
+    def save_train_state(self):
+        """Checkpoint: (master weights, Adam first moment, second moment, Adam steps taken), host copies."""
+        n = weight_count(self.cfg)
+        bufs = [np.zeros(n, dtype=np.float32) for _ in range(3)]
+        steps = ctypes.c_int32()
+        fp = ctypes.POINTER(ctypes.c_float)
+        _check(self.lib.conet_save_train_state(self.handle, *[b.ctypes.data_as(fp) for b in bufs], n,
+                                               ctypes.byref(steps)))
+        return bufs[0], bufs[1], bufs[2], int(steps.value)
+
+    def load_train_state(self, master, m, v, steps: int):
+        """Resume from save_train_state() of a model with the same configuration."""
+        fp = ctypes.POINTER(ctypes.c_float)
+        arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (master, m, v)]
+        _check(self.lib.conet_load_train_state(self.handle, *[a.ctypes.data_as(fp) for a in arrs], arrs[0].size,
+                                               int(steps)))
 
     def bce(self, llr, bits, data_mask, n_data_per_slot: int, stream=None):
         """Bitwise BCE on device: returns (loss tensor [1], dllr)."""

@@ -490,6 +490,39 @@ conet_status conet_get_weights(conet_model* M, float* w, size_t n) {
   return CONET_OK;
 }
 
+conet_status conet_save_train_state(conet_model* M, float* master, float* m, float* v, size_t n, int32_t* steps) {
+  if (!M || !master || !m || !v || !steps) return fail(CONET_EINVAL, "null argument");
+  if (!M->cfg.train) return fail(CONET_ESTATE, "model was not created with train = 1");
+  if (n != M->bo.n) return fail(CONET_EINVAL, "expected %zu values per tensor, got %zu", M->bo.n, n);
+  const Layout& lay = M->lay;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(master, M->ws + lay.tr_master, n * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(m, M->ws + lay.tr_m, n * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(v, M->ws + lay.tr_v, n * 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "training state readback");
+  *steps = M->adam_steps;
+  return CONET_OK;
+}
+
+conet_status conet_load_train_state(conet_model* M, const float* master, const float* m, const float* v, size_t n,
+                                    int32_t steps) {
+  if (!M || !master || !m || !v) return fail(CONET_EINVAL, "null argument");
+  if (!M->cfg.train) return fail(CONET_ESTATE, "model was not created with train = 1");
+  if (n != M->bo.n) return fail(CONET_EINVAL, "expected %zu values per tensor, got %zu", M->bo.n, n);
+  if (steps < 0) return fail(CONET_EINVAL, "negative Adam step count");
+  const Layout& lay = M->lay;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(M->ws + lay.tr_master, master, n * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(M->ws + lay.tr_m, m, n * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(M->ws + lay.tr_v, v, n * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = repack_all(M, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "training state upload");
+  M->adam_steps = steps;
+  M->saved = false;
+  return CONET_OK;
+}
+
 conet_status conet_bce(conet_model* M, const float* llr, const uint8_t* bits, const uint8_t* data_mask, int32_t B,
                        int32_t T, int32_t F, int64_t n_data_per_slot, float* dllr, float* loss_dev, void* stream) {
   if (!M || !llr || !bits || !data_mask || !dllr || !loss_dev) return fail(CONET_EINVAL, "null argument");

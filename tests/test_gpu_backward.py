@@ -231,3 +231,47 @@ def test_autograd_function_and_training_reduces_loss():
         losses.append(float(loss.cpu()))
     say(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     assert np.mean(losses[-4:]) < np.mean(losses[:4])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_checkpoint_resume_continues_bitwise(dtype):
+    """A training run checkpointed after 3 Adam steps (master weights, both moments, step
+    count) and resumed in a fresh model continues exactly: after 2 more steps on the same
+    batches, the resumed model's weights, moments and losses equal the uninterrupted run's."""
+    w = workload("train_b128_f1024", F=48, batch=4)
+    mc = w.model
+    blob = make_blob(mc, seed=0)
+    dm = torch.from_numpy(data_mask(14, 48).astype(np.uint8)).cuda()
+    n_data = int(dm.sum())
+    from synth.ofdm import simulate_slot
+    batches = []
+    for step in range(5):
+        first = 200 + step * 4
+        X = features(w.sim, 4, first=first)
+        bits = np.stack([simulate_slot(w.sim, first + s).bits for s in range(4)])
+        batches.append((torch.from_numpy(X).cuda(), torch.from_numpy(bits).cuda()))
+
+    def run(model, steps):
+        losses = []
+        for x, bt in steps:
+            llr = model.forward(x, save=True)
+            loss, dllr = model.bce(llr, bt, dm, n_data)
+            model.backward(dllr)
+            model.adam_step(lr=2e-3)
+            losses.append(float(loss.cpu()))
+        return losses
+
+    say(f"checkpoint / resume ({dtype})")
+    a = _model(mc, blob, dtype, max_res=4 * 14 * 48)
+    run(a, batches[:3])
+    ckpt = a.save_train_state()
+    assert ckpt[3] == 3
+    la = run(a, batches[3:])
+    wa, ma, va, na = a.save_train_state()
+    b = _model(mc, make_blob(mc, seed=1), dtype, max_res=4 * 14 * 48)  # other weights: all overwritten
+    b.load_train_state(*ckpt)
+    lb = run(b, batches[3:])
+    wb, mb, vb, nb = b.save_train_state()
+    assert la == lb and na == nb == 5
+    for x, y in ((wa, wb), (ma, mb), (va, vb)):
+        np.testing.assert_array_equal(x, y)
