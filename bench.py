@@ -36,14 +36,20 @@ LLR_TOL = {"bf16": "rel-L2 <= 3e-2 vs FP64, sign agreement >= 0.99",
            "f32": "rel-L2 <= 1e-5 vs FP64"}
 
 
+# Sources that define the forward kernels and the layouts they read (a stored HBM-traffic
+# measurement is valid only for these exact sources).
+FORWARD_KERNEL_SOURCES = ("conet_common.h", "conet_kernels.h", "conet_model.h", "conet_conv_impl.h",
+                          "conet_block_impl.h", "conet_block32_impl.h", "conet_conv.hip", "conet_conv_f32.hip",
+                          "conet_conv_bf16.hip", "conet_conv_fp8.hip", "conet_forward.hip", "conet_api.hip")
+
+
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources; a stored HBM-traffic measurement is valid only for it."""
+    """Hash of the forward-kernel sources; a stored HBM-traffic measurement is valid only for it."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2510_12739_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in FORWARD_KERNEL_SOURCES:
+        h.update(f.encode())
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 
