@@ -211,6 +211,15 @@ int32_t conet_block_tile_width(const conet_model* model);
  * Errors: EINVAL (dtype, iters outside 1..2^24, null outputs), EDEVICE. */
 conet_status conet_mfma_peak(int32_t dtype, int32_t iters, double* tflops_host, double* clock_ghz_host, void* stream);
 
+/* The sum of a[k] b[k] (k < K) as ONE matrix instruction of a kind the conv kernels use
+ * computes it, for checking how the instructions accumulate (the parity tolerances model it):
+ * dtype CONET_BF16 with shape 16: v_mfma_f32_16x16x32_bf16 (K = 32), shape 32:
+ * v_mfma_f32_32x32x16_bf16 (K = 16); CONET_FP8E4M3 with shape 16: the 16x16x128 e4m3
+ * instruction (K = 128), shape 32: the 32x32x64 one (K = 64), unit scales. a_host, b_host: K
+ * operand codes (BF16 bit patterns as uint16, or e4m3fn bytes). Synchronous; allocates and
+ * frees a small device buffer. Errors: EINVAL (dtype, shape, null pointers), EDEVICE. */
+conet_status conet_mfma_dot(int32_t dtype, int32_t shape, const void* a_host, const void* b_host, float* out_host);
+
 /* ---------------------------------------------------------------- training
  * Reverse mode of the forward above (hand-written): the head, the per-RE LayerNorm,
  * the product fusion (d O[k] = dP * prod_{j != k} O[j]), and per block the input

@@ -2,6 +2,6 @@
 
 The Python layer only marshals arguments; see binding.Conet.
 """
-from .binding import (Conet, ConetError, Server, conet_function, featurise, load, make_config, mfma_peak,
+from .binding import (Conet, ConetError, Server, conet_function, featurise, load, make_config, mfma_dot, mfma_peak,
                       pinned_array, weight_count,
                       workspace_bytes, EXPORTS)

@@ -23,7 +23,7 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "ENOMEM", 4: "EDEVICE", 5: "EBUS
 EXPORTS = ("conet_weight_count", "conet_workspace_bytes", "conet_create", "conet_set_act_scales",
            "conet_calibrate", "conet_get_act_scales", "conet_forward", "conet_forward_ragged", "conet_forward_profiled",
            "conet_forward_noalloc", "conet_forward_noalloc_capacity",
-           "conet_block_tile_width", "conet_mfma_peak", "conet_featurise",
+           "conet_block_tile_width", "conet_mfma_peak", "conet_mfma_dot", "conet_featurise",
            "conet_serve_create", "conet_serve_submit", "conet_serve_wait", "conet_serve_get_stats",
            "conet_serve_reset_stats", "conet_serve_pause", "conet_serve_destroy", "conet_backward", "conet_grads",
            "conet_master_weights", "conet_adam_step", "conet_get_weights", "conet_save_train_state",
@@ -93,6 +93,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.conet_block_tile_width.argtypes = [vp]; lib.conet_block_tile_width.restype = i32
     dp = ctypes.POINTER(ctypes.c_double)
     lib.conet_mfma_peak.argtypes = [i32, i32, dp, dp, vp]; lib.conet_mfma_peak.restype = i32
+    lib.conet_mfma_dot.argtypes = [i32, i32, vp, vp, ctypes.POINTER(ctypes.c_float)]; lib.conet_mfma_dot.restype = i32
     lib.conet_featurise.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]; lib.conet_featurise.restype = i32
     lib.conet_serve_create.argtypes = [vp, sz, i32, i32, i32, ctypes.POINTER(vp)]
     lib.conet_serve_create.restype = i32
@@ -447,6 +448,24 @@ def mfma_peak(dtype: str = "bf16", iters: int = 0, stream=None):
     tf, ghz = ctypes.c_double(0.0), ctypes.c_double(0.0)
     _check(lib.conet_mfma_peak(code, iters, ctypes.byref(tf), ctypes.byref(ghz), _stream_ptr(stream)))
     return tf.value, ghz.value
+
+
+def mfma_dot(dtype: str, shape: int, a, b) -> float:
+    """conet_mfma_dot: sum of a[k] b[k] by one matrix instruction (dtype "bf16": a, b are float
+    values rounded to BF16; "fp8": a, b are e4m3fn byte codes)."""
+    lib = load()
+    if dtype == "bf16":
+        def bits(v):
+            u = np.asarray(v, np.float32).view(np.uint32).astype(np.uint64)
+            return (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF).astype(np.uint16)
+        ca, cb = bits(a), bits(b)
+    else:
+        ca, cb = np.asarray(a, np.uint8), np.asarray(b, np.uint8)
+    ca, cb = np.ascontiguousarray(ca), np.ascontiguousarray(cb)
+    out = ctypes.c_float()
+    _check(lib.conet_mfma_dot(DTYPES[dtype], int(shape), ca.ctypes.data_as(ctypes.c_void_p),
+                              cb.ctypes.data_as(ctypes.c_void_p), ctypes.byref(out)))
+    return float(np.float32(out.value))
 
 
 def featurise(y, C_in: int, out=None, stream=None):
