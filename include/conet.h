@@ -61,7 +61,8 @@ typedef struct {
   int32_t branches;        /* K, 1..8; branch 0 is the main net                           */
   int32_t blocks;          /* L >= 1 residual blocks per branch                           */
   int32_t channels;        /* C: 16, 32, 64 or 96                                          */
-  int32_t in_channels;     /* C_in = 4 N_rx: 8, 16 or 32                                   */
+  int32_t in_channels;     /* C_in = 4 N_rx: 8, 16 or 32; 4 N_rx + 8 = 24 (BF16, FP32) with the
+                              noise / interference variance channels                      */
   int32_t bits_per_symbol; /* m, head width, 1..8                                          */
   uint32_t fuse_mask;      /* bit l-1 => fusion + LayerNorm after block l                  */
   float ln_eps;            /* LayerNorm epsilon (1e-5)                                     */
@@ -190,6 +191,15 @@ conet_status conet_forward_profiled(conet_model* model, const float* x, int32_t 
  * a multiple of 4). */
 conet_status conet_featurise(const float* y, int32_t B, int32_t T, int32_t F, int32_t n_rx, int32_t C_in,
                              float* x_out, void* stream);
+
+/* conet_featurise plus the known noise and interference variances of each slot, which the
+ * receiver's input also carries (Sec. II-A concatenates them with the received grid):
+ * variances: device FP32 [B][2] = (sigma_n^2, sigma_i^2) per slot. Channels C_in - 8 ..
+ * C_in - 1 of every RE are (sigma_n^2, sigma_i^2, 0, 0, 0, 0, 0, 0); the antenna groups fill
+ * channels 0 .. C_in - 9 (zeros beyond n_rx). Errors as conet_featurise (ESHAPE when 4 n_rx >
+ * C_in - 8), EINVAL for null variances. */
+conet_status conet_featurise_var(const float* y, const float* variances, int32_t B, int32_t T, int32_t F,
+                                 int32_t n_rx, int32_t C_in, float* x_out, void* stream);
 
 /* Subcarriers per tile of the fused residual-block kernel that forwards of this model use
  * on a batch that fills the GPU (both convs of a block in one launch, the hidden activation

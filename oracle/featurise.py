@@ -43,11 +43,18 @@ def channel_estimate(y: np.ndarray) -> np.ndarray:
     return out
 
 
-def features(y: np.ndarray, C_in: int) -> np.ndarray:
+def features(y: np.ndarray, C_in: int, variances=None) -> np.ndarray:
     """y: (B, T, F, N) complex -> (B, T, F, C_in) float64 with channels 4n..4n+3 =
-    (Re y_n, Im y_n, Re H_n, Im H_n) and zeros for antennas n >= N."""
+    (Re y_n, Im y_n, Re H_n, Im H_n) and zeros for antennas n >= N. With variances (B, 2) --
+    the known noise and interference variances, which Sec. II-A concatenates with the
+    received grid -- channels C_in - 8 and C_in - 7 hold them for every RE of the slot and
+    C_in - 6 .. C_in - 1 are zero."""
     B, T, F, N = y.shape
     X = np.zeros((B, T, F, C_in), dtype=np.float64)
+    if variances is not None:
+        v = np.asarray(variances, dtype=np.float64)
+        X[:, :, :, C_in - 8] = v[:, 0][:, None, None]
+        X[:, :, :, C_in - 7] = v[:, 1][:, None, None]
     for b in range(B):
         H = channel_estimate(y[b])
         for n in range(N):

@@ -23,7 +23,7 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "ENOMEM", 4: "EDEVICE", 5: "EBUS
 EXPORTS = ("conet_weight_count", "conet_workspace_bytes", "conet_create", "conet_set_act_scales",
            "conet_calibrate", "conet_get_act_scales", "conet_forward", "conet_forward_ragged", "conet_forward_profiled",
            "conet_forward_noalloc", "conet_forward_noalloc_capacity",
-           "conet_block_tile_width", "conet_mfma_peak", "conet_mfma_dot", "conet_featurise",
+           "conet_block_tile_width", "conet_mfma_peak", "conet_mfma_dot", "conet_featurise", "conet_featurise_var",
            "conet_serve_create", "conet_serve_submit", "conet_serve_wait", "conet_serve_get_stats",
            "conet_serve_reset_stats", "conet_serve_pause", "conet_serve_destroy", "conet_backward", "conet_grads",
            "conet_master_weights", "conet_adam_step", "conet_get_weights", "conet_save_train_state",
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.conet_mfma_peak.argtypes = [i32, i32, dp, dp, vp]; lib.conet_mfma_peak.restype = i32
     lib.conet_mfma_dot.argtypes = [i32, i32, vp, vp, ctypes.POINTER(ctypes.c_float)]; lib.conet_mfma_dot.restype = i32
     lib.conet_featurise.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]; lib.conet_featurise.restype = i32
+    lib.conet_featurise_var.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]; lib.conet_featurise_var.restype = i32
     lib.conet_serve_create.argtypes = [vp, sz, i32, i32, i32, ctypes.POINTER(vp)]
     lib.conet_serve_create.restype = i32
     lib.conet_serve_submit.argtypes = [vp, ctypes.POINTER(conet_request), ctypes.POINTER(ctypes.c_uint64)]
@@ -468,15 +469,24 @@ def mfma_dot(dtype: str, shape: int, a, b) -> float:
     return float(np.float32(out.value))
 
 
-def featurise(y, C_in: int, out=None, stream=None):
+def featurise(y, C_in: int, out=None, stream=None, variances=None):
     """conet_featurise: y is a contiguous float32 CUDA tensor [B][T][F][n_rx][2]; returns the
-    float32 features [B][T][F][C_in] (LS at the pilots + linear interpolation)."""
+    float32 features [B][T][F][C_in] (LS at the pilots + linear interpolation). With variances
+    (float32 CUDA [B][2]: noise and interference variance per slot), conet_featurise_var: the
+    last 8 channels carry them."""
     import torch
     if not (y.is_cuda and y.dtype == torch.float32 and y.is_contiguous() and y.dim() == 5 and y.shape[-1] == 2):
         raise ValueError("y must be a contiguous float32 CUDA tensor [B][T][F][n_rx][2]")
     B, T, F, n_rx, _ = y.shape
     if out is None:
         out = torch.empty((B, T, F, C_in), dtype=torch.float32, device=y.device)
-    _check(load().conet_featurise(ctypes.c_void_p(y.data_ptr()), B, T, F, n_rx, C_in,
-                                  ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    if variances is None:
+        _check(load().conet_featurise(ctypes.c_void_p(y.data_ptr()), B, T, F, n_rx, C_in,
+                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    else:
+        if not (variances.is_cuda and variances.dtype == torch.float32 and variances.is_contiguous()
+                and tuple(variances.shape) == (B, 2)):
+            raise ValueError("variances must be a contiguous float32 CUDA tensor [B][2]")
+        _check(load().conet_featurise_var(ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(variances.data_ptr()), B, T,
+                                          F, n_rx, C_in, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out

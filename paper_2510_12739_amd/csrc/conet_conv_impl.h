@@ -656,9 +656,10 @@ static hipError_t launch_mode(int mode, ConvArgs& a, int n_tiles, int grid_y, hi
 }
 
 // Channel pairs instantiated: input layers (C_in -> C) and blocks (C -> C) of the
-// workloads (C_in 8/16/32, C 16/32/64/96).
-#define CONET_PAIRS(X) \
-  X(8, 16) X(8, 32) X(8, 64) X(16, 16) X(16, 32) X(16, 64) X(16, 96) X(32, 32) X(32, 96) X(64, 64) X(96, 96)
+// workloads (C_in 8/16/32, and 24 = 4 antennas + the variance channels; C 16/32/64/96).
+#define CONET_PAIRS(X)                                                                                    \
+  X(8, 16) X(8, 32) X(8, 64) X(16, 16) X(16, 32) X(16, 64) X(16, 96) X(24, 32) X(24, 64) X(32, 32) X(32, 96) \
+  X(64, 64) X(96, 96)
 #define CONET_PAIRS_FP8(X) X(16, 32) X(16, 64) X(32, 32) X(32, 64) X(32, 96) X(64, 64) X(96, 96)
 
 template <class A>

@@ -9,8 +9,10 @@ What it simulates (paper, Sec. II, Eq. (1), and the simulation setup of Sec. IV)
   * square Gray M-QAM mapping with unit average energy (Sec. II; 64-QAM in Sec. IV);
   * a TTI of T = 14 OFDM symbols over F subcarriers, with fixed DMRS pilots on
     designated subcarriers (Sec. II; Sec. II-A says the pilots are fixed);
-  * the per-RE SIMO observation y = h x + n of Eq. (1), with the interference term
-    g z set to zero and the FFT/IFFT pair omitted (without ICI or timing offset the
+  * the per-RE SIMO observation y = h x + g z + n of Eq. (1); the interference term g z
+    (another transmitter's QAM symbols through its own Rayleigh channel, a random share
+    of the noise-plus-interference power) only where a configuration asks for it, and
+    the FFT/IFFT pair omitted (without ICI or timing offset the
     pair is the identity on a per-RE model);
   * LS channel estimates at the pilots, linearly interpolated over the grid (Sec. I);
   * the real NHWC input tensor: Re/Im of Y and of the LS estimate per rx antenna
@@ -28,7 +30,10 @@ Random-number contract: slot s of a configuration with seed S draws from
 numpy.random.Generator(PCG64(SeedSequence([S, s]))) in this order:
 bits (T, F, m) -> Doppler f_D (if the channel is time-varying) -> SNR (if ranged)
 -> tap gains (n_taps, N, T) real part then imaginary part -> noise (T, F, N) real
-part then imaginary part. Any slot can therefore be regenerated alone.
+part then imaginary part [-> with an interferer: its power share, its bits (T, F, m),
+its Doppler, its tap gains real then imaginary]. Any slot can therefore be regenerated
+alone, and configurations without an interferer draw exactly what they drew before it
+existed.
 """
 from __future__ import annotations
 
@@ -58,6 +63,16 @@ class SimConfig:
     snr_range_db: Tuple[float, float] = (-5.0, 25.0)
     seed: int = 0
     T: int = T_SYMBOLS
+    # Interference g z of Eq. (1): a second transmitter's QAM symbols (same modulation, data on
+    # every RE) through its own Rayleigh channel. Per slot its share of the noise-plus-
+    # interference power is U[lo, hi] (the paper trains with 10-90 %); None: no interferer.
+    interference_share: Optional[Tuple[float, float]] = None
+    # Append the known noise and interference variances to the input (Sec. II-A): 8 more
+    # channels (sigma_n^2, sigma_i^2, then zeros, so the width stays a multiple of 8).
+    variance_channels: bool = False
+
+
+VARIANCE_CHANNELS = 8
 
 
 @dataclass
@@ -68,10 +83,11 @@ class Slot:
     H: np.ndarray            # (T, F, N) complex128, true channel
     y: np.ndarray            # (T, F, N) complex128, received grid
     H_ls: np.ndarray         # (T, F, N) complex128, LS + linear interpolation
-    noise_var: float
+    noise_var: float         # noise + interference variance per RE and antenna (1 / SINR)
     snr_db: float
     doppler_hz: float
-    features: np.ndarray     # (T, F, 4N) float32, NHWC input of the network
+    features: np.ndarray     # (T, F, 4N [+ 8]) float32, NHWC input of the network
+    interf_var: float = 0.0  # the interference's part of noise_var
 
 
 # ----------------------------------------------------------------------------- QAM
@@ -195,15 +211,22 @@ def ls_estimate(y: np.ndarray) -> np.ndarray:
     return h0[None] + (t - t0) / float(t1 - t0) * (h1 - h0)[None]
 
 
-def make_features(y: np.ndarray, H_ls: np.ndarray) -> np.ndarray:
-    """X[t, f, 4n + (0,1,2,3)] = (Re y_n, Im y_n, Re H_n, Im H_n), float32, antenna-major."""
+def make_features(y: np.ndarray, H_ls: np.ndarray, variances: Optional[Tuple[float, float]] = None) -> np.ndarray:
+    """X[t, f, 4n + (0,1,2,3)] = (Re y_n, Im y_n, Re H_n, Im H_n), float32, antenna-major;
+    with variances = (sigma_n^2, sigma_i^2) also channels 4N, 4N + 1 = those (constant over
+    the slot) and 4N + 2 .. 4N + 7 = 0."""
     T, F, N = y.shape
     X = np.empty((T, F, N, 4), dtype=np.float64)
     X[..., 0] = y.real
     X[..., 1] = y.imag
     X[..., 2] = H_ls.real
     X[..., 3] = H_ls.imag
-    return X.reshape(T, F, 4 * N).astype(np.float32)
+    X = X.reshape(T, F, 4 * N)
+    if variances is not None:
+        V = np.zeros((T, F, VARIANCE_CHANNELS))
+        V[..., 0], V[..., 1] = variances
+        X = np.concatenate([X, V], axis=-1)
+    return X.astype(np.float32)
 
 
 # ----------------------------------------------------------------------------- slots
@@ -242,12 +265,28 @@ def simulate_slot(cfg: SimConfig, slot: int, noise_var_override: Optional[float]
             gains = np.repeat(w[..., :1], T, axis=-1)
         H = freq_response(gains, cfg.n_taps, F)
 
-    noise_var = 10.0 ** (-snr_db / 10.0) if noise_var_override is None else float(noise_var_override)
-    n = np.sqrt(noise_var / 2.0) * (nr + 1j * ni)
-    y = H * x[..., None] + n
+    total = 10.0 ** (-snr_db / 10.0) if noise_var_override is None else float(noise_var_override)
+    share, gz = 0.0, 0.0
+    if cfg.interference_share is not None:
+        share = float(rng.uniform(*cfg.interference_share))
+        zbits = rng.integers(0, 2, size=(T, F, m), dtype=np.uint8)
+        doppler_i = float(rng.uniform(0.0, cfg.max_doppler_hz)) if cfg.max_doppler_hz > 0 else 0.0
+        gr = rng.standard_normal((cfg.n_taps, N, T))
+        gi = rng.standard_normal((cfg.n_taps, N, T))
+        wg = (gr + 1j * gi) / np.sqrt(2.0)
+        if cfg.max_doppler_hz > 0:
+            ggains = correlated_gains(wg, jakes_covariance(T, doppler_i))
+        else:
+            ggains = np.repeat(wg[..., :1], T, axis=-1)
+        G = freq_response(ggains, cfg.n_taps, F)
+        gz = np.sqrt(share * total) * G * qam_map(zbits)[..., None]   # unit-power z and G
+    interf_var = share * total
+    n = np.sqrt((total - interf_var) / 2.0) * (nr + 1j * ni)
+    y = H * x[..., None] + gz + n
     H_ls = ls_estimate(y)
-    return Slot(bits=bits, x=x, H=H, y=y, H_ls=H_ls, noise_var=noise_var, snr_db=snr_db,
-                doppler_hz=doppler, features=make_features(y, H_ls))
+    var = ((total - interf_var), interf_var) if cfg.variance_channels else None
+    return Slot(bits=bits, x=x, H=H, y=y, H_ls=H_ls, noise_var=total, snr_db=snr_db,
+                doppler_hz=doppler, features=make_features(y, H_ls, var), interf_var=interf_var)
 
 
 def simulate_batch(cfg: SimConfig, n_slots: int, first_slot: int = 0):

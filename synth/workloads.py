@@ -1,4 +1,4 @@
-"""The five named workloads: grid, antennas, modulation, channel, model and seeds."""
+"""The six named workloads: grid, antennas, modulation, channel, model and seeds."""
 from __future__ import annotations
 
 from dataclasses import dataclass
@@ -39,6 +39,13 @@ WORKLOADS = {
                                  SimConfig(F=1024, n_rx=4, bits_per_symbol=4, n_taps=8, max_doppler_hz=400.0,
                                            seed=4),
                                  ModelConfig(K=3, L=4, C=64, C_in=16, m=4), "bf16"),
+    # Interference-limited uplink (Sec. IV): 64 slots of 3276 x 14, 4 rx, 64-QAM; an interferer
+    # holds 10-90 % of the noise-plus-interference power, and its variance and the noise's
+    # feed 8 more input channels (C_in = 16 + 8). K=3 L=4 C=64.
+    "interf_bf16_b64_f3276": Workload("interf_bf16_b64_f3276", 64,
+                                      SimConfig(F=3276, n_rx=4, bits_per_symbol=6, n_taps=8, max_doppler_hz=400.0,
+                                                seed=6, interference_share=(0.1, 0.9), variance_channels=True),
+                                      ModelConfig(K=3, L=4, C=64, C_in=24, m=6), "bf16"),
     # Serving trunk: K=3 L=4 C=64, inputs padded to 16 channels, head width 6.
     "serve_bf16": Workload("serve_bf16", 1,
                            SimConfig(F=3276, n_rx=4, bits_per_symbol=6, n_taps=8, max_doppler_hz=400.0,

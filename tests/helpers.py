@@ -85,3 +85,20 @@ def elementwise_report(got, ref, tw: int, label: str = "") -> dict:
     say(f"  {label} max|d| {out['all'][0]:.3e} at (slot, t, f, bit) = {out['worst_index']}; "
         + ", ".join(f"{k} max {v[0]:.2e} mean {v[1]:.2e}" for k, v in out.items() if k not in ("all", "worst_index")))
     return out
+
+
+def check_vs_emulation(got, p, X64, quant, tw, label, **kw):
+    """Parity against the emulating oracle with the tolerances its GPU error model gives
+    (emulation_with_bound): every LLR within the element-wise bound, rel-L2 within the rel
+    bound, and tile seams no worse on average than the interior (the per-RE arithmetic does
+    not depend on the tiling). Returns the emulation."""
+    emu, bound, rel_bound = emulation_with_bound(p, X64, quant, **kw)
+    rms = float(np.sqrt(np.mean(emu ** 2)))
+    bound = max(bound, 1e-6 * rms)
+    rel_bound = max(rel_bound, 1e-6)
+    rep = elementwise_report(got, emu, tw, f"{label} (bound {bound:.2e} = {bound / rms:.2e} RMS)")
+    say(f"  {label}: rel-L2 vs emulated {rel_l2(got, emu):.2e} (bound {rel_bound:.2e})")
+    assert rep["all"][0] <= bound, (label, rep["all"][0], bound, rep["worst_index"])
+    assert rel_l2(got, emu) <= rel_bound, (label, rel_l2(got, emu), rel_bound)
+    assert rep["tile_seams"][1] <= 3.0 * rep["interior"][1] + 1e-6 * rms, (label, rep["tile_seams"], rep["interior"])
+    return emu

@@ -20,6 +20,7 @@ import os
 import numpy as np
 import pytest
 
+from helpers import check_vs_emulation as _elementwise
 from helpers import elementwise_report, emulation_with_bound, features, max_over_rms, rel_l2, say, sign_agree
 from oracle import conet64 as o
 from synth import ModelConfig, SimConfig, make_blob, workload
@@ -44,23 +45,6 @@ def _run(model, X):
 def _oracle(K, L, C, Ci, m, blob, X, mask=-1, quant=None):
     p = o.unpack(blob, K, L, C, Ci, m)
     return o.forward_slots(p, X.astype(np.float64), fuse_mask=None if mask < 0 else mask, quant=quant)
-
-
-def _elementwise(got, p, X64, quant, tw, label, **kw):
-    """Parity against the emulating oracle with the tolerances its GPU error model gives
-    (emulation_with_bound): every LLR within the element-wise bound, rel-L2 within the rel
-    bound, and tile seams no worse on average than the interior (the per-RE arithmetic does
-    not depend on the tiling). Returns the emulation."""
-    emu, bound, rel_bound = emulation_with_bound(p, X64, quant, **kw)
-    rms = float(np.sqrt(np.mean(emu ** 2)))
-    bound = max(bound, 1e-6 * rms)
-    rel_bound = max(rel_bound, 1e-6)
-    rep = elementwise_report(got, emu, tw, f"{label} (bound {bound:.2e} = {bound / rms:.2e} RMS)")
-    say(f"  {label}: rel-L2 vs emulated {rel_l2(got, emu):.2e} (bound {rel_bound:.2e})")
-    assert rep["all"][0] <= bound, (label, rep["all"][0], bound, rep["worst_index"])
-    assert rel_l2(got, emu) <= rel_bound, (label, rel_l2(got, emu), rel_bound)
-    assert rep["tile_seams"][1] <= 3.0 * rep["interior"][1] + 1e-6 * rms, (label, rep["tile_seams"], rep["interior"])
-    return emu
 
 
 # ----------------------------------------------------------------------------- FP32
