@@ -303,17 +303,19 @@ def serve_measure(loads=(0.5,), duration_s=1.5, n_streams=3, seed=13, grid=False
     return out
 
 
-def depth_latency(args):
-    """Depth vs latency on this GPU (the paper's claim that inference time follows the number
-    of sequentially dependent layers): CoNet with K = 2 branches of L = 6 blocks (2L + 2 = 14
-    sequential conv layers) against a single pre-activation ResNet of L = 11 blocks (24
-    layers), both fed the same synthetic slots with random He-normal weights and near-equal
-    parameter counts. Reports the latency of one slot (median of `--steps` forwards, each
-    timed by HIP events with the GPU otherwise idle) and the throughput at a 32-slot batch."""
+def depth_latency_measure(calls=100):
+    """Depth vs latency on this GPU (the paper's claim that inference time follows the number of
+    sequentially dependent layers, Sec. IV): CoNet with K = 2 branches of L = 6 blocks (2L + 2 =
+    14 sequential conv layers) against single pre-activation ResNets of L = 11 blocks (24 layers,
+    the depth the paper compares with; 8 % fewer block parameters at equal width) and L = 12
+    blocks (26 layers, exactly CoNet's 24 block convolutions of C x C, so equal parameters), at
+    C = 64 and C = 96, all fed the same synthetic slots with random He-normal weights. Reports
+    the latency of one slot (`calls` forwards, each timed alone by HIP events) and the
+    throughput at a 32-slot batch."""
     import torch
     from paper_2510_12739_amd import Conet
     from synth import features_fast, make_blob, workload
-    from synth.weights import ModelConfig
+    from synth.weights import ModelConfig, blob_size
 
     w = workload("bf16_b64_f3276")
     F, T, Ci, m = w.sim.F, w.sim.T, w.model.C_in, w.model.m
@@ -321,18 +323,17 @@ def depth_latency(args):
     stream = torch.cuda.current_stream()
     out_rows = []
     for C in (64, 96):
-        for name, K, L, mask in (("conet_K2_L6", 2, 6, -1), ("resnet_K1_L11", 1, 11, 0)):
+        for name, K, L, mask in (("conet_K2_L6", 2, 6, -1), ("resnet_K1_L11", 1, 11, 0), ("resnet_K1_L12", 1, 12, 0)):
             mc = ModelConfig(K, L, C, Ci, m, mask)
             model = Conet(K, L, C, Ci, m, make_blob(mc, seed=11), dtype="bf16", fuse_mask=mc.mask, max_res=32 * T * F)
-            block_params = K * L * 2 * 9 * C * C
-            seq_layers = 2 * L + 2
+            params = blob_size(mc)
             x1 = X[:1].contiguous()
             o1 = torch.empty((1, T, F, m), dtype=torch.float32, device="cuda")
             for _ in range(5):
                 model.forward(x1, out=o1)
             torch.cuda.synchronize()
             lat = []
-            for _ in range(args.steps):
+            for _ in range(calls):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
                 model.forward(x1, out=o1)
@@ -350,8 +351,9 @@ def depth_latency(args):
             e1.record(stream)
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / 5
-            row = {"model": name, "C": C, "K": K, "L": L, "sequential_conv_layers": seq_layers,
-                   "block_params": block_params, "fused_block_tile_width": model.block_tile_width,
+            row = {"model": name, "C": C, "K": K, "L": L, "sequential_conv_layers": 2 * L + 2,
+                   "params": params, "block_params": K * L * 2 * 9 * C * C,
+                   "fused_block_tile_width": model.block_tile_width,
                    "latency_1slot_us": {"p50": round(float(np.median(lat)), 1),
                                         "p10": round(float(np.percentile(lat, 10)), 1),
                                         "p90": round(float(np.percentile(lat, 90)), 1)},
@@ -362,9 +364,17 @@ def depth_latency(args):
             model.close()
     res = {"experiment": "depth_vs_latency", "slot": f"{T}x{F} REs, C_in={Ci}, m={m}, BF16", "rows": out_rows}
     for C in (64, 96):
-        a = [r for r in out_rows if r["C"] == C]
-        res[f"C{C}_latency_ratio_conet_over_resnet"] = round(a[0]["latency_1slot_us"]["p50"] / a[1]["latency_1slot_us"]["p50"], 3)
-        res[f"C{C}_throughput_ratio_conet_over_resnet"] = round(a[0]["batch32_res_per_s"] / a[1]["batch32_res_per_s"], 3)
+        a = {r["model"]: r for r in out_rows if r["C"] == C}
+        for rn in ("resnet_K1_L11", "resnet_K1_L12"):
+            res[f"C{C}_latency_ratio_conet_over_{rn}"] = round(
+                a["conet_K2_L6"]["latency_1slot_us"]["p50"] / a[rn]["latency_1slot_us"]["p50"], 3)
+            res[f"C{C}_throughput_ratio_conet_over_{rn}"] = round(
+                a["conet_K2_L6"]["batch32_res_per_s"] / a[rn]["batch32_res_per_s"], 3)
+    return res
+
+
+def depth_latency(args):
+    res = depth_latency_measure(calls=args.steps)
     print(json.dumps(res), flush=True)
     if args.json_out:
         with open(args.json_out, "w") as f:
@@ -742,6 +752,9 @@ def headline(args):
                                 "frac_of_hbm_peak": round(f_bytes / (f_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         del y_dev, xf
         torch.cuda.empty_cache()
+
+    if full:
+        result["depth_vs_latency"] = depth_latency_measure(calls=50)
 
     if full and not args.no_serve:
         result["serving"] = serve_measure(loads=args.serve_loads, duration_s=args.serve_seconds, grid=True, pinned=True)

@@ -363,6 +363,31 @@ def test_fusion_variants_vs_oracle(dtype, K, L, C, mask, fusion, feedback):
     model.close()
 
 
+@pytest.mark.parametrize("K,L,C,mask", [
+    (2, 6, 96, -1),     # CoNet of the depth-latency comparison: 14 sequential layers
+    (1, 11, 96, 0),     # the 24-layer pre-activation ResNet it is compared with
+    (1, 12, 64, 0),     # the equal-parameter 26-layer ResNet, at C = 64
+])
+def test_depth_latency_models_bf16(K, L, C, mask):
+    """The networks the benchmark's depth-vs-latency experiment times (Sec. IV's comparison of
+    a 14-layer CoNet with a 24-layer ResNet), at BF16 on a 2-slot grid with a ragged tail:
+    against the emulating oracle with model-derived tolerances and against FP64."""
+    Ci, m = 16, 4
+    sim = SimConfig(F=70, n_rx=4, bits_per_symbol=m, seed=43)
+    mc = ModelConfig(K, L, C, Ci, m, mask)
+    blob = make_blob(mc, seed=44, perturb=True)
+    X = features(sim, 2)
+    say(f"depth-latency model bf16 K={K} L={L} C={C}")
+    model = _model(K, L, C, Ci, m, "bf16", blob, mc.mask)
+    got = _run(model, X)
+    p = o.unpack(blob, K, L, C, Ci, m)
+    _elementwise(got, p, X.astype(np.float64), o.Quant("bf16"), model.block_tile_width, f"bf16 K={K} L={L} C={C}",
+                 fuse_mask=mc.mask)
+    ref = _oracle(K, L, C, Ci, m, blob, X, mc.mask)
+    assert rel_l2(got, ref) <= 3e-2 and sign_agree(got, ref) >= 0.99, (rel_l2(got, ref), sign_agree(got, ref))
+    model.close()
+
+
 @pytest.mark.parametrize("dtype,K,L,C,Ci,mask", [
     ("f32", 2, 2, 32, 16, -1),       # two-conv path (fusion epilogue of the second conv)
     ("bf16", 3, 3, 64, 16, -1),      # fused 16x16 kernels: paired launches, main branch with the head
