@@ -58,9 +58,14 @@ LN_EPS = 1e-5
 
 # ----------------------------------------------------------------------------- params
 
-def unpack(blob: np.ndarray, K: int, L: int, C: int, C_in: int, m: int, norm: str = "ln") -> Dict:
+def unpack(blob: np.ndarray, K: int, L: int, C: int, C_in: int, m: int, norm: str = "ln",
+           support_blocks: int = 0, fusion: str = "product", block: str = "standard") -> Dict:
     """Parse the packed FP32 parameter vector into FP64 arrays (blob order of the C header).
-    norm="bn": the blob ends with the BatchNorm running mean and variance of every block."""
+    support_blocks: blocks of each support net (0: L; Sec. III lets the support net be
+    shallower). fusion="concat": after the head, per block l the projection Wc_l (C, K C),
+    bc_l (C) of the concatenated branch outputs. norm="bn": the blob ends with the BatchNorm
+    running mean and variance of every block. block="ds": depthwise-separable blocks (Sec. II-A), each
+    conv a depthwise 3x3 filter D (C, 3, 3) followed by a 1x1 conv P (C, C) with bias."""
     v = np.asarray(blob, dtype=np.float64).ravel()
     pos = [0]
 
@@ -70,15 +75,30 @@ def unpack(blob: np.ndarray, K: int, L: int, C: int, C_in: int, m: int, norm: st
         pos[0] += n
         return out
 
-    p = {"K": K, "L": L, "C": C, "C_in": C_in, "m": m, "branch": []}
-    for _k in range(K):
+    Ls = L if support_blocks in (0, None) else int(support_blocks)
+    if not 1 <= Ls <= L:
+        raise ValueError(f"support_blocks must be 1..L (got {support_blocks})")
+    if block not in ("standard", "ds"):
+        raise ValueError(f"unknown block {block!r}")
+    if fusion not in ("product", "sum", "concat"):
+        raise ValueError(f"unknown fusion {fusion!r}")
+    p = {"K": K, "L": L, "C": C, "C_in": C_in, "m": m, "branch": [], "Ls": Ls, "block": block}
+    for k in range(K):
         br = {"W_in": take(C, C_in, 3, 3), "b_in": take(C), "blocks": []}
-        for _l in range(L):
+        for _l in range(L if k == 0 else Ls):
             blk = {}
             blk["s0"] = take(C); blk["o0"] = take(C)
-            blk["W1"] = take(C, C, 3, 3); blk["b1"] = take(C)
+            if block == "ds":
+                blk["D1"] = take(C, 3, 3); blk["P1"] = take(C, C)
+            else:
+                blk["W1"] = take(C, C, 3, 3)
+            blk["b1"] = take(C)
             blk["s1"] = take(C); blk["o1"] = take(C)
-            blk["W2"] = take(C, C, 3, 3); blk["b2"] = take(C)
+            if block == "ds":
+                blk["D2"] = take(C, 3, 3); blk["P2"] = take(C, C)
+            else:
+                blk["W2"] = take(C, C, 3, 3)
+            blk["b2"] = take(C)
             br["blocks"].append(blk)
         p["branch"].append(br)
     p["gamma"] = []
@@ -88,6 +108,12 @@ def unpack(blob: np.ndarray, K: int, L: int, C: int, C_in: int, m: int, norm: st
         p["beta"].append(take(C))
     p["W_h"] = take(m, C)
     p["b_h"] = take(m)
+    if fusion == "concat":
+        p["Wc"], p["bc"] = [], []
+        for _l in range(L):
+            p["Wc"].append(take(C, K * C))
+            p["bc"].append(take(C))
+    p["fusion"] = fusion
     p["norm"] = norm
     if norm == "bn":
         p["bn_mean"], p["bn_var"] = [], []
@@ -104,13 +130,18 @@ def unpack(blob: np.ndarray, K: int, L: int, C: int, C_in: int, m: int, norm: st
 def pack(p: Dict) -> np.ndarray:
     """Inverse of unpack (gradients are returned in blob order)."""
     parts = []
+    keys = ("s0", "o0", "D1", "P1", "b1", "s1", "o1", "D2", "P2", "b2") if p.get("block") == "ds" else \
+        ("s0", "o0", "W1", "b1", "s1", "o1", "W2", "b2")
     for br in p["branch"]:
         parts += [br["W_in"], br["b_in"]]
         for blk in br["blocks"]:
-            parts += [blk[k] for k in ("s0", "o0", "W1", "b1", "s1", "o1", "W2", "b2")]
+            parts += [blk[k] for k in keys]
     for g, b in zip(p["gamma"], p["beta"]):
         parts += [g, b]
     parts += [p["W_h"], p["b_h"]]
+    if p.get("fusion") == "concat":
+        for W, b in zip(p["Wc"], p["bc"]):
+            parts += [W, b]
     if p.get("norm", "ln") == "bn":
         for mu, var in zip(p["bn_mean"], p["bn_var"]):
             parts += [mu, var]
@@ -190,6 +221,20 @@ def conv3x3_bruteforce(x: np.ndarray, W: np.ndarray, b: Optional[np.ndarray] = N
                                 if 0 <= tt < T and 0 <= ff < F:
                                     s += W[o, i, dt + 1, df + 1] * x[bb, tt, ff, i]
                     out[bb, t, f, o] = s
+    return out
+
+
+def dwconv3x3(x: np.ndarray, D: np.ndarray) -> np.ndarray:
+    """Depthwise 3x3 cross-correlation (each channel filtered by its own 3x3 filter), zero
+    "same" padding inside each slot: out[b,t,f,c] = sum_{dt,df} D[c,dt+1,df+1] x[b,t+dt,f+df,c].
+    x: (B, T, F, C); D: (C, 3, 3)."""
+    B, T, F, C = x.shape
+    xp = np.zeros((B, T + 2, F + 2, C), dtype=np.float64)
+    xp[:, 1:-1, 1:-1, :] = x
+    out = np.zeros((B, T, F, C), dtype=np.float64)
+    for a in range(3):
+        for c in range(3):
+            out += D[:, a, c][None, None, None, :] * xp[:, a:a + T, c:c + F, :]
     return out
 
 
@@ -316,8 +361,27 @@ def _conv_acc(xq: np.ndarray, Wq: np.ndarray, b: Optional[np.ndarray], noise, fp
     return c
 
 
+def _ds_conv_acc(q: "Quant", xq: np.ndarray, D: np.ndarray, P: np.ndarray, b: np.ndarray, noise) -> np.ndarray:
+    """Depthwise-separable conv (Sec. II-A): the depthwise 3x3 filter D, then the 1x1 conv P
+    with bias b, on an operand xq already rounded. The depthwise output is the 1x1 conv's
+    operand and is rounded as one; filters are rounded as conv operands. With `noise`, each
+    sum carries _conv_acc's FP32-accumulation error model (9 terms, then C terms)."""
+    Dq = D if q.kind is None else round_bf16(D)
+    Pq = P if q.kind is None else round_bf16(P)
+    d = dwconv3x3(xq, Dq)
+    if noise is not None:
+        sq = np.sqrt(np.maximum(dwconv3x3(xq * xq, Dq * Dq), 0.0))
+        d = d + FP32_UNIT * np.sqrt(9 / 2.0) * sq * noise.standard_normal(d.shape)
+    dq = d if q.kind is None else round_bf16(_fp32_formed(q, d))
+    c = dq @ Pq.T + b
+    if noise is not None:
+        sq = np.sqrt(np.maximum((dq * dq) @ (Pq * Pq).T, 0.0))
+        c = c + FP32_UNIT * np.sqrt(P.shape[1] / 2.0) * sq * noise.standard_normal(c.shape)
+    return c
+
+
 def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Optional[Quant] = None,
-            keep: bool = False, calib: Optional[np.ndarray] = None, fusion: str = "product",
+            keep: bool = False, calib: Optional[np.ndarray] = None, fusion: Optional[str] = None,
             feedback: bool = False, norm: Optional[str] = None, bn_stats: Optional[Dict] = None,
             acc_noise: Optional[np.random.Generator] = None):
     """CoNet forward for a batch X (B, T, F, C_in) -> LLR (B, T, F, m).
@@ -325,22 +389,34 @@ def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Opti
     keep=True also returns the intermediate tensors the backward needs.
     calib, if given, receives the running max |.| of every conv input operand
     (indexing of act_scale_index), which is how static activation scales are set.
-    fusion: "product" (Example I) or "sum" (fusion by addition); feedback: Example II's
-    main -> support feedback after every fusion. norm: "ln", "bn" (running statistics of
+    fusion: "product" (Example I), "sum" (fusion by addition) or "concat" (fusion by
+    concatenation: the K outputs side by side, projected back to C channels by p's 1x1 conv
+    Wc_l, bc_l); default: p's own. feedback: Example II's main -> support feedback after every
+    fusion. Support nets shallower than the main net (p["Ls"] < L) take part in the fusions
+    after their own blocks only. norm: "ln", "bn" (running statistics of
     p) or "bn_batch" (this batch's statistics, recorded into bn_stats[l - 1] = (mean, var)
     if given); default: p's own. The backward covers the defaults only.
     acc_noise: a numpy Generator; every conv and the head then carry the FP32-accumulation
     error model of _conv_acc, and every value rounded to BF16 or e4m3 the FP32 error of the
     operations that formed it (_fp32_formed); for deriving tolerances, never for results.
     """
-    if fusion not in ("product", "sum"):
+    fusion = fusion or p.get("fusion", "product")
+    if fusion not in ("product", "sum", "concat"):
         raise ValueError(f"unknown fusion {fusion!r}")
+    if fusion == "concat" and "Wc" not in p:
+        raise ValueError("fusion by concatenation needs the projection weights (unpack(..., fusion='concat'))")
+    ds = p.get("block", "standard") == "ds"
     norm = norm or p.get("norm", "ln")
     if norm not in ("ln", "bn", "bn_batch"):
         raise ValueError(f"unknown norm {norm!r}")
     K, L = p["K"], p["L"]
+    Ls = p.get("Ls", L)
     mask = ((1 << L) - 1) if fuse_mask is None else int(fuse_mask)
+    if mask >> Ls:
+        raise ValueError(f"fusion after block {mask.bit_length()} but the support nets have {Ls} blocks")
     q = quant or Quant()
+    if q.kind == "fp8" and (ds or fusion == "concat"):
+        raise ValueError("the FP8 contract covers standard blocks with product or sum fusion")
     if acc_noise is not None and q.kind is not None:  # the error model also perturbs rounding inputs
         q = Quant(q.kind, q.act_scales, noise=acc_noise)
     X = np.asarray(X, dtype=np.float64)
@@ -360,7 +436,8 @@ def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Opti
     for l in range(1, L + 1):
         lev = {"x": a, "pre": [], "c1": [], "z1": [], "h": [], "O": [], "mrb": []}
         O = []
-        for k in range(K):
+        Kl = K if l <= Ls else 1  # branches that have block l
+        for k in range(Kl):
             blk = p["branch"][k]["blocks"][l - 1]
             x = a[k]
             mrb = (k == 0 and fused_prev)
@@ -368,15 +445,21 @@ def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Opti
             if calib is not None:
                 i0 = act_scale_index(K, L, k, l, 0)
                 calib[i0] = max(calib[i0], float(np.abs(pre).max()))
-            c1 = _conv_acc(_operand(q, pre, act_scale_index(K, L, k, l, 0)), _weights(q, blk["W1"]), blk["b1"],
-                           acc_noise, q.kind == "fp8")
+            if ds:
+                c1 = _ds_conv_acc(q, _operand(q, pre, 0), blk["D1"], blk["P1"], blk["b1"], acc_noise)
+            else:
+                c1 = _conv_acc(_operand(q, pre, act_scale_index(K, L, k, l, 0)), _weights(q, blk["W1"]), blk["b1"],
+                               acc_noise, q.kind == "fp8")
             z1 = blk["s1"] * c1 + blk["o1"]
             h = q.store(relu(z1)) if q.kind is None or q.kind == "bf16" else relu(z1)
             if calib is not None:
                 i1 = act_scale_index(K, L, k, l, 1)
                 calib[i1] = max(calib[i1], float(np.abs(h).max()))
-            c2 = _conv_acc(_operand(q, h, act_scale_index(K, L, k, l, 1)), _weights(q, blk["W2"]), blk["b2"],
-                           acc_noise, q.kind == "fp8")
+            if ds:
+                c2 = _ds_conv_acc(q, _operand(q, h, 0), blk["D2"], blk["P2"], blk["b2"], acc_noise)
+            else:
+                c2 = _conv_acc(_operand(q, h, act_scale_index(K, L, k, l, 1)), _weights(q, blk["W2"]), blk["b2"],
+                               acc_noise, q.kind == "fp8")
             Ok = x + c2
             O.append(Ok)
             if keep:
@@ -385,9 +468,17 @@ def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Opti
         last = (l == L)
         if fused_after(mask, l):
             # the support outputs enter the fusion as stored (rounded under emulation)
-            P = O[0].copy()
-            for k in range(1, K):
-                P = P + q.store(O[k]) if fusion == "sum" else P * q.store(O[k])
+            if fusion == "concat":  # a 1x1 conv over the K outputs side by side: conv operands
+                cat = np.concatenate([_operand(q, O[0], 0)] + [q.store(O[k]) for k in range(1, K)], axis=-1)
+                Wq = _weights(q, p["Wc"][l - 1][:, :, None, None])[:, :, 0, 0]
+                P = cat @ Wq.T + p["bc"][l - 1]
+                if acc_noise is not None:
+                    sq = np.sqrt(np.maximum((cat * cat) @ (Wq * Wq).T, 0.0))
+                    P = P + FP32_UNIT * np.sqrt(K * p["C"] / 2.0) * sq * acc_noise.standard_normal(P.shape)
+            else:
+                P = O[0].copy()
+                for k in range(1, K):
+                    P = P + q.store(O[k]) if fusion == "sum" else P * q.store(O[k])
             if norm == "ln":  # over the C channels of each RE
                 mu = P.mean(axis=-1, keepdims=True)
                 var = ((P - mu) ** 2).mean(axis=-1, keepdims=True)
@@ -408,7 +499,7 @@ def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Opti
             if keep:
                 lev["P"] = P; lev["ahat"] = ahat; lev["sig"] = sig
         else:
-            new = [O[0] if last else q.store(O[0])] + [q.store(O[k]) for k in range(1, K)]
+            new = [O[0] if last else q.store(O[0])] + [q.store(O[k]) for k in range(1, Kl)]
         if keep:
             lev["O"] = O
             cache["levels"].append(lev)
@@ -421,7 +512,7 @@ def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Opti
         llr = llr + FP32_UNIT * np.sqrt(p["C"] / 2.0) * np.sqrt(sq) * acc_noise.standard_normal(llr.shape)
     if keep:
         cache["aL"] = a[0]
-        cache["variant"] = (fusion, feedback, norm)
+        cache["variant"] = (fusion, feedback, norm) + (() if (Ls == L and not ds) else (Ls, ds))
         return llr, cache
     return llr
 

@@ -41,6 +41,7 @@ def _scale_idx(K, L, k, l, which):
 
 def _contract_net(p, X, mask, kind, scales=None, fusion="product", feedback=False):
     K, L, C = p["K"], p["L"], p["C"]
+    Ls, ds = p.get("Ls", L), p.get("block") == "ds"
     tt = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
     ch = lambda v: tt(v)[None, :, None, None]
 
@@ -59,29 +60,41 @@ def _contract_net(p, X, mask, kind, scales=None, fusion="product", feedback=Fals
     def conv(a, idx, W, b):
         return torch.nn.functional.conv2d(operand(a, idx), weight(W), tt(b), padding=1)
 
+    def ds_conv(a, D, P, b):  # depthwise (groups = C), its output rounded as the 1x1 conv's operand
+        d = torch.nn.functional.conv2d(operand(a, 0), weight(D[:, None]), padding=1, groups=C)
+        return torch.nn.functional.conv2d(operand(d, 0), weight(P[:, :, None, None]), tt(b))
+
     store = _bf16
     x = tt(X).permute(0, 3, 1, 2)
     a = [store(torch.relu(conv(x, 0, p["branch"][k]["W_in"], p["branch"][k]["b_in"]))) for k in range(K)]
     fused_prev = False
     for l in range(1, L + 1):
         outs = []
-        for k in range(K):
+        for k in range(K if l <= Ls else 1):
             blk = p["branch"][k]["blocks"][l - 1]
             pre = torch.relu(a[k]) if (k == 0 and fused_prev) else torch.relu(ch(blk["s0"]) * a[k] + ch(blk["o0"]))
+            if ds:
+                h = torch.relu(ch(blk["s1"]) * ds_conv(pre, blk["D1"], blk["P1"], blk["b1"]) + ch(blk["o1"]))
+                outs.append(a[k] + ds_conv(h, blk["D2"], blk["P2"], blk["b2"]))
+                continue
             h = torch.relu(ch(blk["s1"]) * conv(pre, _scale_idx(K, L, k, l, 0), blk["W1"], blk["b1"]) + ch(blk["o1"]))
             outs.append(a[k] + conv(h, _scale_idx(K, L, k, l, 1), blk["W2"], blk["b2"]))
         last = l == L
         fused = bool((mask >> (l - 1)) & 1)
-        if fused:
+        if fused and fusion == "concat":      # a 1x1 conv of the outputs side by side
+            cat = torch.cat([operand(outs[0], 0)] + [store(outs[k]) for k in range(1, K)], dim=1)
+            P = torch.nn.functional.conv2d(cat, weight(p["Wc"][l - 1][:, :, None, None]), tt(p["bc"][l - 1]))
+        elif fused:
             P = outs[0]                       # the main output is consumed inside its block
             for k in range(1, K):             # the supports' outputs left their blocks: BF16
                 P = P + store(outs[k]) if fusion == "sum" else P * store(outs[k])
+        if fused:
             A = torch.nn.functional.layer_norm(P.permute(0, 2, 3, 1), (C,), tt(p["gamma"][l - 1]),
                                                tt(p["beta"][l - 1]), eps=o.LN_EPS).permute(0, 3, 1, 2)
             sup = [store(store(outs[k]) + A) if feedback else store(outs[k]) for k in range(1, K)]
             a = [A if last else store(A)] + sup
         else:
-            a = [outs[0] if last else store(outs[0])] + [store(outs[k]) for k in range(1, K)]
+            a = [outs[0] if last else store(outs[0])] + [store(outs[k]) for k in range(1, len(outs))]
         fused_prev = fused
     return (a[0].permute(0, 2, 3, 1).numpy() @ p["W_h"].T) + p["b_h"]
 
@@ -111,6 +124,32 @@ def test_quant_emulation_follows_the_contract(kind, K, L, C, Ci, m, mask, fusion
     # rounding happened (the emulation is not the exact network) ...
     assert np.linalg.norm(got - exact) > 1e-4 * np.linalg.norm(exact)
     # ... at exactly the contract's points: equal to FP64 round-off
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-10 * np.abs(want).max())
+
+
+VARIANT_CASES = [
+    # K, L, C, C_in, m, mask, support_blocks, fusion, block, feedback
+    (2, 3, 16, 8, 2, 0b011, 2, "product", "standard", False),   # shallower support net
+    (3, 2, 16, 8, 4, 0b11, 0, "concat", "standard", False),     # fusion by concatenation
+    (2, 3, 16, 8, 4, 0b001, 1, "concat", "standard", True),
+    (2, 2, 16, 8, 2, 0b11, 0, "product", "ds", False),          # depthwise-separable blocks
+    (3, 3, 32, 16, 4, 0b011, 2, "sum", "ds", True),
+]
+
+
+@pytest.mark.parametrize("K,L,C,Ci,m,mask,Ls,fusion,block,feedback", VARIANT_CASES)
+def test_quant_emulation_of_block_and_fusion_variants(K, L, C, Ci, m, mask, Ls, fusion, block, feedback):
+    """The BF16 contract on the variants: the depthwise output and the concatenated outputs are
+    conv operands, rounded as such; shallower supports drop out after their last block."""
+    mc = ModelConfig(K, L, C, Ci, m, mask, Ls, fusion, block)
+    p = o.unpack(make_blob(mc, seed=41 + K + L, perturb=True), K, L, C, Ci, m, support_blocks=Ls, fusion=fusion,
+                 block=block)
+    X = np.random.default_rng(6 + K).standard_normal((2, 14, 11, Ci))
+    kw = dict(fuse_mask=mask, feedback=feedback)
+    got = o.forward(p, X, quant=o.Quant("bf16"), **kw)
+    want = _contract_net(p, X, mask, "bf16", None, fusion, feedback)
+    exact = o.forward(p, X, **kw)
+    assert np.linalg.norm(got - exact) > 1e-4 * np.linalg.norm(exact)
     np.testing.assert_allclose(got, want, rtol=0, atol=1e-10 * np.abs(want).max())
 
 
