@@ -81,19 +81,36 @@ typedef struct {
                               gamma (P - mean) / sqrt(var + ln_eps) + beta per channel; the
                               blob then ends with mean_l, var_l (C each) for l = 1..L.
                               Inference only (train = 1 needs CONET_NORM_LN)                   */
+  int32_t support_blocks;  /* blocks of every support branch, 1..L; 0 => L. Sec. III lets the
+                              support net be shallower than the main net: after block
+                              support_blocks the main branch continues alone, so fuse_mask may
+                              only hold bits 0 .. support_blocks - 1. Inference only          */
+  int32_t block_type;      /* CONET_BLOCK_STANDARD (0): 3x3 convs; CONET_BLOCK_SEPARABLE (1):
+                              each block conv is a depthwise 3x3 filter followed by a 1x1 conv
+                              (Sec. II-A). Separable: FP32 or BF16, C in {32, 64}, inference  */
 } conet_config;
 
-enum { CONET_FUSE_PRODUCT = 0, CONET_FUSE_SUM = 1 };
+/* CONET_FUSE_CONCAT: P = Wc_l [O[0]; O[1]; ...; O[K-1]] + bc_l, the K outputs side by side
+ * (K C channels) projected back to C by a 1x1 conv per block (Sec. III names concatenation
+ * as a fusion operation), then the normalisation. FP32 or BF16, C in {32, 64}, K <= 4,
+ * inference only. */
+enum { CONET_FUSE_PRODUCT = 0, CONET_FUSE_SUM = 1, CONET_FUSE_CONCAT = 2 };
 enum { CONET_NORM_LN = 0, CONET_NORM_BN = 1 };
+enum { CONET_BLOCK_STANDARD = 0, CONET_BLOCK_SEPARABLE = 1 };
 
 typedef struct conet_model conet_model;
 
 /* Number of FP32 values in the packed parameter blob. Blob order (all FP32):
  *   for k in 0..K-1: W_in[C][C_in][3][3], b_in[C],
- *                    for l in 1..L: s0[C], o0[C], W1[C][C][3][3], b1[C], s1[C], o1[C],
- *                                   W2[C][C][3][3], b2[C]
+ *                    for l in 1..L_k: s0[C], o0[C], W1[C][C][3][3], b1[C], s1[C], o1[C],
+ *                                     W2[C][C][3][3], b2[C]
  *   for l in 1..L: gamma[C], beta[C]
  *   W_h[m][C], b_h[m]
+ *   [CONET_FUSE_CONCAT: for l in 1..L: Wc[C][K C], bc[C]]
+ *   [CONET_NORM_BN: for l in 1..L: mean[C], var[C]]
+ * L_0 = L and L_k = support_blocks (k >= 1). Separable blocks hold D1[C][3][3], P1[C][C]
+ * in place of W1 and D2[C][3][3], P2[C][C] in place of W2 (depthwise filter, then the 1x1
+ * conv; out(t,f,c) of the depthwise filter reads in(t+dt, f+df, c) with D[c][dt+1][df+1]).
  * Filters are indexed [out][in][dt+1][df+1] and correlate: out(t,f) reads in(t+dt, f+df).
  * s0/o0 and s1/o1 are the per-channel affines in front of the block's ReLUs (inference
  * form of its normalisations); s0/o0 are ignored in a main-net block after a fusion.

@@ -42,7 +42,8 @@ class conet_config(ctypes.Structure):
                 ("in_channels", ctypes.c_int32), ("bits_per_symbol", ctypes.c_int32),
                 ("fuse_mask", ctypes.c_uint32), ("ln_eps", ctypes.c_float), ("dtype", ctypes.c_int32),
                 ("train", ctypes.c_int32), ("max_res", ctypes.c_int64), ("fusion_op", ctypes.c_int32),
-                ("feedback", ctypes.c_int32), ("norm", ctypes.c_int32)]
+                ("feedback", ctypes.c_int32), ("norm", ctypes.c_int32), ("support_blocks", ctypes.c_int32),
+                ("block_type", ctypes.c_int32)]
 
 
 class conet_request(ctypes.Structure):
@@ -129,16 +130,20 @@ def _check(st: int):
         raise ConetError(st, load().conet_last_error().decode())
 
 
-FUSIONS = {"product": 0, "sum": 1}
+FUSIONS = {"product": 0, "sum": 1, "concat": 2}
 NORMS = {"ln": 0, "bn": 1}
+BLOCKS = {"standard": 0, "ds": 1}
 
 
 def make_config(K: int, L: int, C: int, C_in: int, m: int, dtype: str = "bf16", fuse_mask: int = -1,
                 max_res: int = 1 << 20, ln_eps: float = 1e-5, train: bool = False, fusion: str = "product",
-                feedback: bool = False, norm: str = "ln") -> conet_config:
-    mask = ((1 << L) - 1) if fuse_mask < 0 else int(fuse_mask)
+                feedback: bool = False, norm: str = "ln", support_blocks: int = 0,
+                block: str = "standard") -> conet_config:
+    """fuse_mask -1: fusion after every block the support branches have (support_blocks, or L)."""
+    Ls = L if support_blocks <= 0 else support_blocks
+    mask = ((1 << Ls) - 1) if fuse_mask < 0 else int(fuse_mask)
     return conet_config(K, L, C, C_in, m, mask, ln_eps, DTYPES[dtype], 1 if train else 0, int(max_res),
-                        FUSIONS[fusion], 1 if feedback else 0, NORMS[norm])
+                        FUSIONS[fusion], 1 if feedback else 0, NORMS[norm], int(support_blocks), BLOCKS[block])
 
 
 def weight_count(cfg: conet_config) -> int:
@@ -164,12 +169,13 @@ class Conet:
 
     def __init__(self, K: int, L: int, C: int, C_in: int, m: int, blob: np.ndarray, dtype: str = "bf16",
                  fuse_mask: int = -1, max_res: int = 1 << 20, device=None, train: bool = False,
-                 fusion: str = "product", feedback: bool = False, norm: str = "ln"):
+                 fusion: str = "product", feedback: bool = False, norm: str = "ln", support_blocks: int = 0,
+                 block: str = "standard"):
         import torch
         self.lib = load()
         self.train = train
         self.cfg = make_config(K, L, C, C_in, m, dtype, fuse_mask, max_res, train=train, fusion=fusion,
-                               feedback=feedback, norm=norm)
+                               feedback=feedback, norm=norm, support_blocks=support_blocks, block=block)
         self.K, self.L, self.C, self.C_in, self.m, self.dtype = K, L, C, C_in, m, dtype
         n = weight_count(self.cfg)
         if n == 0:

@@ -166,12 +166,24 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static int act_bytes(int dtype) { return dtype == DT_F32 ? 4 : 2; }
 size_t act_bytes_of(int dtype) { return (size_t)act_bytes(dtype); }
-static int hid_bytes(int dtype) { return dtype == DT_F32 ? 4 : (dtype == DT_BF16 ? 2 : 1); }
+// middle-activation buffers: the two-conv path's h; separable blocks keep h on chip and use
+// branch 0's buffer for the FP32 main output a fusion or the head reads
+static int hid_bytes(const conet_config& c) {
+  if (c.block_type == CONET_BLOCK_SEPARABLE) return 4;
+  return c.dtype == DT_F32 ? 4 : (c.dtype == DT_BF16 ? 2 : 1);
+}
+
+static size_t block_params(const conet_config& c) {
+  const size_t C = c.channels;
+  return c.block_type == CONET_BLOCK_SEPARABLE ? 6 * C + 2 * (9 * C + C * C) : 6 * C + 2 * 9 * C * C;
+}
 
 size_t n_params(const conet_config& c) {
   const size_t K = c.branches, L = c.blocks, C = c.channels, Ci = c.in_channels, m = c.bits_per_symbol;
   const size_t bn = c.norm == CONET_NORM_BN ? 2 * L * C : 0;  // running mean and variance per block
-  return K * (C * Ci * 9 + C + L * (6 * C + 2 * 9 * C * C)) + 2 * L * C + m * C + m + bn;
+  const size_t cat = c.fusion_op == CONET_FUSE_CONCAT ? L * (C * K * C + C) : 0;
+  const size_t blocks = L + (K - 1) * (size_t)support_depth(c);
+  return K * (C * Ci * 9 + C) + blocks * block_params(c) + 2 * L * C + m * C + m + cat + bn;
 }
 
 conet_status check_config(const conet_config* c) {
@@ -185,8 +197,16 @@ conet_status check_config(const conet_config* c) {
   if (!conv_supported(c->dtype, c->channels, c->channels))
     return fail(CONET_EINVAL, "no kernel for C=%d -> C=%d at dtype %d", c->channels, c->channels, c->dtype);
   if (c->train != 0 && c->train != 1) return fail(CONET_EINVAL, "train must be 0 or 1");
-  if (c->fusion_op != CONET_FUSE_PRODUCT && c->fusion_op != CONET_FUSE_SUM)
-    return fail(CONET_EINVAL, "fusion_op must be CONET_FUSE_PRODUCT or CONET_FUSE_SUM");
+  if (c->fusion_op != CONET_FUSE_PRODUCT && c->fusion_op != CONET_FUSE_SUM && c->fusion_op != CONET_FUSE_CONCAT)
+    return fail(CONET_EINVAL, "fusion_op must be CONET_FUSE_PRODUCT, CONET_FUSE_SUM or CONET_FUSE_CONCAT");
+  if (c->support_blocks < 0 || c->support_blocks > c->blocks)
+    return fail(CONET_EINVAL, "support_blocks must be 0..L (got %d)", c->support_blocks);
+  if (c->block_type != CONET_BLOCK_STANDARD && c->block_type != CONET_BLOCK_SEPARABLE)
+    return fail(CONET_EINVAL, "block_type must be CONET_BLOCK_STANDARD or CONET_BLOCK_SEPARABLE");
+  if (c->block_type == CONET_BLOCK_SEPARABLE && !ds_supported(c->dtype, c->channels))
+    return fail(CONET_EINVAL, "separable blocks run in FP32 or BF16 with C = 32 or 64");
+  if (c->fusion_op == CONET_FUSE_CONCAT && !concat_supported(c->dtype, c->channels, c->branches))
+    return fail(CONET_EINVAL, "fusion by concatenation runs in FP32 or BF16 with C = 32 or 64 and K <= 4");
   if (c->feedback != 0 && c->feedback != 1) return fail(CONET_EINVAL, "feedback must be 0 or 1");
   if (c->norm != CONET_NORM_LN && c->norm != CONET_NORM_BN) return fail(CONET_EINVAL, "norm must be CONET_NORM_LN or CONET_NORM_BN");
   if (c->train) {
@@ -199,10 +219,14 @@ conet_status check_config(const conet_config* c) {
     if (c->fusion_op != CONET_FUSE_PRODUCT || c->feedback)
       return fail(CONET_EINVAL, "training supports product fusion without feedback");
     if (c->norm != CONET_NORM_LN) return fail(CONET_EINVAL, "training supports LayerNorm after the fusion");
+    if (support_depth(*c) != c->blocks || c->block_type != CONET_BLOCK_STANDARD)
+      return fail(CONET_EINVAL, "training supports standard blocks and support branches of depth L");
   }
   if (c->max_res < 1) return fail(CONET_EINVAL, "max_res must be positive");
   if (!(c->ln_eps > 0.f)) return fail(CONET_EINVAL, "ln_eps must be positive");
   if (c->blocks < 32 && (c->fuse_mask >> c->blocks) != 0) return fail(CONET_EINVAL, "fuse_mask has bits beyond L");
+  if (support_depth(*c) < 32 && (c->fuse_mask >> support_depth(*c)) != 0)
+    return fail(CONET_EINVAL, "fuse_mask has bits beyond the support branches' %d blocks", support_depth(*c));
   return CONET_OK;
 }
 
@@ -211,7 +235,7 @@ size_t arena_bytes(const conet_config& c, int64_t max_res) {
   const size_t max_tiles = 3 * ((size_t)max_res / 16 + 4096);
   size_t off = align256(max_tiles * sizeof(TileDesc)) + 256;           // descriptors + amax counters
   off += 2 * K * align256(R * C * act_bytes(c.dtype));
-  off += K * align256(R * C * hid_bytes(c.dtype));
+  off += K * align256(R * C * hid_bytes(c));
   return off;
 }
 
@@ -227,19 +251,21 @@ void arena_carve(const conet_config& c, int64_t max_res, uint8_t* base, Arena& a
   off += 256;
   for (int p = 0; p < 2; ++p)
     for (int k = 0; k < K; ++k) { ar.act[p][k] = base + off; off += align256(R * C * act_bytes(c.dtype)); }
-  for (int k = 0; k < K; ++k) { ar.hid[k] = base + off; off += align256(R * C * hid_bytes(c.dtype)); }
+  for (int k = 0; k < K; ++k) { ar.hid[k] = base + off; off += align256(R * C * hid_bytes(c)); }
 }
 
 // Workspace: [packed filters][FP32 vectors][activation arena]
 void plan_layout(const conet_config& c, Layout& lay) {
   const int K = c.branches, L = c.blocks, C = c.channels, Ci = c.in_channels, m = c.bits_per_symbol;
+  const bool ds = c.block_type == CONET_BLOCK_SEPARABLE;
+  const size_t blk_pack = ds ? packed_bytes_1x1(c.dtype, C, C) : packed_bytes(c.dtype, C, C);
   size_t off = 0;
   for (int k = 0; k < K; ++k) {
     lay.w_in[k] = off; off = align256(off + packed_bytes(c.dtype, Ci, C));
-    for (int l = 0; l < L; ++l) {
-      lay.w1[k][l] = off; off = align256(off + packed_bytes(c.dtype, C, C));
-      lay.w2[k][l] = off; off = align256(off + packed_bytes(c.dtype, C, C));
-      if (block_uses_mfma32(c.dtype, C) && !c.train) {
+    for (int l = 0; l < branch_blocks(c, k); ++l) {
+      lay.w1[k][l] = off; off = align256(off + blk_pack);
+      lay.w2[k][l] = off; off = align256(off + blk_pack);
+      if (block_uses_mfma32(c.dtype, C) && !c.train && !ds) {
         lay.w1f[k][l] = off; off = align256(off + packed_bytes32(c.dtype, C, C));
         lay.w2f[k][l] = off; off = align256(off + packed_bytes32(c.dtype, C, C));
       } else {
@@ -248,16 +274,22 @@ void plan_layout(const conet_config& c, Layout& lay) {
       }
     }
   }
-  // FP32 vectors: per branch b_in, wscale_in; per (k,l): s0 o0 b1 s1 o1 b2 ws1 ws2; per l gamma beta; Wh bh
+  if (c.fusion_op == CONET_FUSE_CONCAT)
+    for (int l = 0; l < L; ++l) { lay.w_cat[l] = off; off = align256(off + packed_bytes_1x1(c.dtype, K * C, C)); }
+  // FP32 vectors: per branch b_in, wscale_in; per (k,l): s0 o0 b1 s1 o1 b2 ws1 ws2 (and the
+  // depthwise filters of separable blocks); per l gamma beta (and bc); Wh bh
   size_t nv = 0;
   for (int k = 0; k < K; ++k) {
     lay.v_bin[k] = nv; nv += C;
     lay.v_wsin[k] = nv; nv += C;
-    for (int l = 0; l < L; ++l) {
+    for (int l = 0; l < branch_blocks(c, k); ++l) {
       lay.v_blk[k][l] = nv; nv += 8 * C;
+      if (ds) { lay.v_dw[k][l] = nv; nv += 18 * C; }
     }
   }
   for (int l = 0; l < L; ++l) { lay.v_gamma[l] = nv; nv += C; lay.v_beta[l] = nv; nv += C; }
+  if (c.fusion_op == CONET_FUSE_CONCAT)
+    for (int l = 0; l < L; ++l) { lay.v_bcat[l] = nv; nv += C; }
   lay.v_wh = nv; nv += (size_t)m * C;
   lay.v_bh = nv; nv += m;
   lay.n_vec = nv;
@@ -335,8 +367,31 @@ conet_status conet_create(const conet_config* cfg, const float* w, size_t n_weig
     pack_filter(cfg->dtype, Ci, C, p, img.data() + lay.w_in[k], vec + lay.v_wsin[k]);
     p += (size_t)C * Ci * 9;
     memcpy(vec + lay.v_bin[k], p, C * 4); p += C;
-    for (int l = 0; l < L; ++l) {
+    for (int l = 0; l < branch_blocks(*cfg, k); ++l) {
       float* vb = vec + lay.v_blk[k][l];  // s0 o0 b1 s1 o1 b2 ws1 ws2
+      if (cfg->block_type == CONET_BLOCK_SEPARABLE) {
+        float* dw = vec + lay.v_dw[k][l];  // [9][C] per conv, tap-major
+        for (int i = 0; i < 2; ++i) {
+          // s0 o0 D1 P1 b1 | s1 o1 D2 P2 b2
+          memcpy(vb + (3 * i) * C, p, C * 4); p += C;        // s0 / s1
+          memcpy(vb + (3 * i + 1) * C, p, C * 4); p += C;    // o0 / o1
+          // depthwise filters are conv operands: BF16 models hold them rounded to BF16
+          for (int ch = 0; ch < C; ++ch)
+            for (int tap = 0; tap < 9; ++tap) {
+              float w = p[ch * 9 + tap];
+              if (cfg->dtype == DT_BF16) {
+                const uint32_t u = (uint32_t)bf16_bits(w) << 16;
+                memcpy(&w, &u, 4);
+              }
+              dw[(size_t)i * 9 * C + tap * C + ch] = w;
+            }
+          p += (size_t)9 * C;
+          pack_1x1(cfg->dtype, C, C, p, img.data() + (i == 0 ? lay.w1[k][l] : lay.w2[k][l]));
+          p += (size_t)C * C;
+          memcpy(vb + (i == 0 ? 2 : 5) * C, p, C * 4); p += C;  // b1 / b2
+        }
+        continue;
+      }
       memcpy(vb + 0 * C, p, C * 4); p += C;                 // s0
       memcpy(vb + 1 * C, p, C * 4); p += C;                 // o0
       pack_filter(cfg->dtype, C, C, p, img.data() + lay.w1[k][l], vb + 6 * C);
@@ -357,6 +412,12 @@ conet_status conet_create(const conet_config* cfg, const float* w, size_t n_weig
   }
   memcpy(vec + lay.v_wh, p, (size_t)m * C * 4); p += (size_t)m * C;
   memcpy(vec + lay.v_bh, p, m * 4); p += m;
+  if (cfg->fusion_op == CONET_FUSE_CONCAT)
+    for (int l = 0; l < L; ++l) {
+      pack_1x1(cfg->dtype, K * C, C, p, img.data() + lay.w_cat[l]);
+      p += (size_t)C * K * C;
+      memcpy(vec + lay.v_bcat[l], p, C * 4); p += C;
+    }
   if (cfg->norm == CONET_NORM_BN) {
     // BatchNorm with running statistics is a per-channel affine: fold it into gamma/beta,
     // gamma' = gamma / sqrt(var + eps), beta' = beta - mean gamma'
@@ -377,7 +438,7 @@ conet_status conet_create(const conet_config* cfg, const float* w, size_t n_weig
   if (e != hipSuccess) { delete M; return hip_fail(e, "upload of packed weights"); }
   M->act_scales.assign(1 + 2 * K * L, 1.0f);
   M->scales_set = false;
-  blob_offsets(*cfg, M->bo);
+  if (cfg->train) blob_offsets(*cfg, M->bo);
   if (cfg->train) {
     conet_status st = train_init(M);
     if (st != CONET_OK) { delete M; return st; }

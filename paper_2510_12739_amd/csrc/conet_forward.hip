@@ -127,7 +127,7 @@ struct FusedScheduler {
   // Training forwards also pass hid(k) (where h is saved) and o0 (the main branch's output
   // before the fusion, or branch 0's before the head); both null otherwise.
   template <class InFn, class OutFn, class HidFn, class MarkFn>
-  conet_status block(int l, bool fuse, bool fused_prev, bool last, InFn in, OutFn out, HidFn hid, void* o0,
+  conet_status block(int l, bool fuse, bool fused_prev, bool last, int Kl, InFn in, OutFn out, HidFn hid, void* o0,
                      MarkFn& mark) {
     const conet_config& c = M->cfg;
     const Layout& lay = M->lay;
@@ -140,7 +140,7 @@ struct FusedScheduler {
     if (!fuse) {
       st = flush(sa);
       if (st != CONET_OK) return st;
-      const int nk = last ? 1 : K;  // after the last block only branch 0 feeds the head
+      const int nk = last ? 1 : Kl;  // after the last block only branch 0 feeds the head
       BlockArgs b = {};
       base(b);
       for (int k = 0; k < nk; ++k) {
@@ -220,7 +220,10 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
   const int tw_in = conv_tile_width(dt, Ci, C), tw_blk = conv_tile_width(dt, C, C);
   // Inference runs each block as one fused launch when a fused kernel exists for
   // (dtype, C); calibration and the training forward (which stores h) use two convs.
-  int tw_fb = calib ? 0 : block_tile_width(dt, C, K, TW_WIDE, c.train != 0);
+  const bool ds = c.block_type == CONET_BLOCK_SEPARABLE;
+  const bool concat = c.fusion_op == CONET_FUSE_CONCAT;
+  const int Ls = support_depth(c);
+  int tw_fb = (calib || ds) ? 0 : block_tile_width(dt, C, K, TW_WIDE, c.train != 0);
   // a batch whose wide tiles cannot fill the GPU once (a slot, a serving batch) runs on
   // narrow tiles: more, shorter work-groups per launch; if its paired launches (K branches
   // per tile) would then hold more than two work-groups per CU, on the build for three
@@ -248,15 +251,17 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
   hipError_t e;
 
   // tile geometry for every tile width in use
-  int n_tiles_in = 0, n_tiles_blk = 0, n_tiles_fb = 0;
+  int n_tiles_in = 0, n_tiles_blk = 0, n_tiles_fb = 0, n_tiles_ds = 0;
   const TileDesc* d_in = nullptr;
   const TileDesc* d_blk = nullptr;
   const TileDesc* d_fb = nullptr;
+  const TileDesc* d_ds = nullptr;
   int64_t n_re = 0;
   if (geo.uniform) {
     n_tiles_in = geo.B * ((geo.F + tw_in - 1) / tw_in);
     n_tiles_blk = geo.B * ((geo.F + tw_blk - 1) / tw_blk);
     if (tw_fb) n_tiles_fb = geo.B * ((geo.F + tw_fb - 1) / tw_fb);
+    if (ds) n_tiles_ds = geo.B * ((geo.F + DS_TW - 1) / DS_TW);
     n_re = (int64_t)geo.B * geo.T * geo.F;
   } else {
     std::vector<TileDesc> h;
@@ -275,10 +280,14 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
     n_tiles_blk = (int)(h.size() - o_blk);
     const size_t o_in = tw_in != tw_blk ? build(tw_in) : o_blk;
     n_tiles_in = (int)(tw_in != tw_blk ? h.size() - o_in : n_tiles_blk);
-    size_t o_fb = 0;
+    size_t o_fb = 0, o_ds = 0;
     if (tw_fb) {
       o_fb = build(tw_fb);
       n_tiles_fb = (int)(h.size() - o_fb);
+    }
+    if (ds) {
+      o_ds = build(DS_TW);
+      n_tiles_ds = (int)(h.size() - o_ds);
     }
     if (h.size() > ar.max_tiles) return fail(CONET_ESHAPE, "ragged batch needs %zu tiles, capacity %zu", h.size(), ar.max_tiles);
     if (n_re > ar.max_res) return fail(CONET_ESHAPE, "ragged batch has %lld REs, buffers hold %lld", (long long)n_re, (long long)ar.max_res);
@@ -293,6 +302,7 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
     d_blk = dt_dev + o_blk;
     d_in = dt_dev + o_in;
     d_fb = dt_dev + o_fb;
+    d_ds = dt_dev + o_ds;
   }
   if (n_tiles_in == 0 || n_tiles_blk == 0) return CONET_OK;
 
@@ -362,6 +372,33 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
     add_units(K);
   }
 
+  // the fusion epilogue pass that follows a level's block launches when no block kernel folds
+  // the fusion in (by concatenation, or after separable blocks), or that runs the head after
+  // an unfused last separable block: reads the stored outputs at out_p, writes A in place
+  auto epilogue = [&](int l, bool fuse, bool last, int out_p, const void* main, bool main_f32) -> conet_status {
+    FuseArgs f = {};
+    f.main = main;
+    f.main_f32 = main_f32 ? 1 : 0;
+    for (int k = 1; k < K; ++k) f.sup[k] = actp(out_p, k);
+    f.K = K;
+    f.wcat = ws + lay.w_cat[l];
+    f.bcat = vec + lay.v_bcat[l];
+    f.gamma = vec + lay.v_gamma[l];
+    f.beta = vec + lay.v_beta[l];
+    f.norm_affine = c.norm == CONET_NORM_BN;
+    f.eps = c.ln_eps;
+    f.out = last ? nullptr : actp(out_p, 0);
+    f.feedback = fuse && c.feedback && !last;
+    f.Wh = vec + lay.v_wh;
+    f.bh = vec + lay.v_bh;
+    f.llr = last ? llr : nullptr;
+    f.m = c.bits_per_symbol;
+    f.n_re = n_re;
+    const int mode = !fuse ? EPI_NONE : concat ? EPI_CONCAT : c.fusion_op == CONET_FUSE_SUM ? EPI_SUM : EPI_PRODUCT;
+    const hipError_t e2 = launch_fuse_epilogue(dt, C, mode, f, s);
+    return e2 == hipSuccess ? CONET_OK : hip_fail(e2, "fusion epilogue launch");
+  };
+
   int cur = 0;
   bool fused_prev = false;
   FusedScheduler fsched{M, geo, n_tiles_fb, d_fb, tw_fb, wclass, llr, s, units};
@@ -369,13 +406,61 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
     lvl = l;
     const bool last = (l == L - 1);
     const bool fuse = (c.fuse_mask >> l) & 1u;
-    const int nk = (last && !fuse) ? 1 : K;
+    const int Kl = l < Ls ? K : 1;  // branches that have block l
+    if (ds) {  // separable blocks: one launch over the branches, then the epilogue pass
+      const int in_p = cur, out_p = 1 - cur;
+      const bool main_f32 = last || (fuse && !concat);  // the main output is read unrounded
+      const int nk = (last && !fuse) ? 1 : Kl;
+      DsArgs d = {};
+      d.T = geo.T;
+      d.F = geo.uniform ? geo.F : 0;
+      d.tiles_per_slot = geo.uniform ? (geo.F + DS_TW - 1) / DS_TW : 0;
+      d.tiles = geo.uniform ? nullptr : d_ds;
+      for (int k = 0; k < nk; ++k) {
+        const float* vb = vec + lay.v_blk[k][l];
+        const float* dw = vec + lay.v_dw[k][l];
+        const bool mrb = (k == 0 && fused_prev);
+        d.x[k] = actp(in_p, k);
+        d.out[k] = (k == 0 && main_f32) ? ar.hid[0] : actp(out_p, k);
+        d.out_f32[k] = (k == 0 && main_f32) ? 1 : 0;
+        d.pre_s[k] = mrb ? nullptr : vb;
+        d.pre_o[k] = mrb ? nullptr : vb + C;
+        d.dw1[k] = dw;
+        d.dw2[k] = dw + 9 * C;
+        d.pw1[k] = ws + lay.w1[k][l];
+        d.pw2[k] = ws + lay.w2[k][l];
+        d.b1[k] = vb + 2 * C;
+        d.post_s[k] = vb + 3 * C;
+        d.post_o[k] = vb + 4 * C;
+        d.b2[k] = vb + 5 * C;
+      }
+      e = mark();  // (a)
+      if (e == hipSuccess) e = launch_ds_block(dt, C, d, n_tiles_ds, nk, s);
+      if (e != hipSuccess) return hip_fail(e, "separable block launch");
+      add_units(2 * nk);
+      e = mark();  // (b)
+      if (e != hipSuccess) return hip_fail(e, "event record");
+      if (fuse || last) {
+        conet_status st = epilogue(l, fuse, last, out_p, d.out[0], main_f32);
+        if (st != CONET_OK) return st;
+      }
+      e = mark();  // (c)
+      if (e != hipSuccess) return hip_fail(e, "event record");
+      cur = 1 - cur;
+      fused_prev = fuse;
+      continue;
+    }
+    // fusion by concatenation: the block kernels store every branch output, the epilogue fuses
+    const bool fuse_k = fuse && !concat;
+    const bool last_k = last && !(fuse && concat);
+    const int nk = (last_k && !fuse_k) ? 1 : Kl;
     if (tw_fb) {
       const int in_p = cur, out_p = 1 - cur;
-      conet_status st = fsched.block(l, fuse, fused_prev, last, [&](int k) { return actp(in_p, k); },
+      conet_status st = fsched.block(l, fuse_k, fused_prev, last_k, Kl, [&](int k) { return actp(in_p, k); },
                                      [&](int k) { return actp(out_p, k); },
                                      [&](int k) -> void* { return save ? hidp(k) : nullptr; },
                                      save ? ar.lvl_o0[l] : nullptr, mark);
+      if (st == CONET_OK && fuse && concat) st = epilogue(l, true, last, out_p, actp(out_p, 0), false);
       if (st != CONET_OK) return st;
       cur = 1 - cur;
       fused_prev = fuse;
@@ -449,7 +534,7 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
     a2.Wh = vec + lay.v_wh;
     a2.bh = vec + lay.v_bh;
     a2.m = c.bits_per_symbol;
-    if (fuse) {
+    if (fuse_k) {
       // support branches first (their outputs are stored: the next block's inputs and
       // this block's product operands), then the main branch with the fusion epilogue
       if (K > 1) {
@@ -465,26 +550,30 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
       }
       ConvArgs am = a2;
       for (int k = 1; k < K; ++k) am.sup[k] = actp(1 - cur, k);
-      am.out[0] = last ? nullptr : actp(1 - cur, 0);
-      am.llr = (last && !calib) ? llr : nullptr;
+      am.out[0] = last_k ? nullptr : actp(1 - cur, 0);
+      am.llr = (last_k && !calib) ? llr : nullptr;
       am.save_o0 = save ? ar.lvl_o0[l] : nullptr;
       am.k_off = 0;
       am.fusion_sum = c.fusion_op == CONET_FUSE_SUM;
       am.norm_affine = c.norm == CONET_NORM_BN;
-      am.feedback = c.feedback && !last;
+      am.feedback = c.feedback && !last_k;
       e = mark();
       if (e == hipSuccess) e = launch_conv(dt, 4, C, C, am, n_tiles_blk, 1, s);
       if (e != hipSuccess) return hip_fail(e, "fused conv 2 launch");
       add_units(1);
     } else {
-      for (int k = 0; k < nk; ++k) a2.out[k] = last ? nullptr : actp(1 - cur, k);
-      a2.llr = (last && !calib) ? llr : nullptr;
-      a2.save_o0 = (save && last) ? ar.lvl_o0[l] : nullptr;
+      for (int k = 0; k < nk; ++k) a2.out[k] = last_k ? nullptr : actp(1 - cur, k);
+      a2.llr = (last_k && !calib) ? llr : nullptr;
+      a2.save_o0 = (save && last_k) ? ar.lvl_o0[l] : nullptr;
       e = mark();
       if (e == hipSuccess) e = launch_conv(dt, 2, C, C, a2, n_tiles_blk, nk, s);
       if (e == hipSuccess) add_units(nk);
       if (e == hipSuccess) e = mark();  // no third launch in an unfused block
       if (e != hipSuccess) return hip_fail(e, "block conv 2 launch");
+    }
+    if (fuse && concat) {
+      conet_status st = epilogue(l, true, last, 1 - cur, actp(1 - cur, 0), false);
+      if (st != CONET_OK) return st;
     }
     cur = 1 - cur;
     fused_prev = fuse;

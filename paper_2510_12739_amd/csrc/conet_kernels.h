@@ -122,6 +122,60 @@ int block_tile_width(int dtype, int C, int K, int wclass, bool train = false);
 enum { BLOCK_PLAIN = 0, BLOCK_MAIN = 1, BLOCK_PAIR = 2 };
 hipError_t launch_block(int dtype, int kind, int wclass, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
 
+// ---------------------------------------------------------------- block and fusion variants
+// Depthwise-separable residual block (both separable convs in one launch, h in LDS), per
+// branch blockIdx.y + k_off: out = x + P2 dw2(ReLU(s1 (P1 dw1(pre(x)) + b1) + o1)) + b2, on
+// tiles of DS_TW subcarriers.
+constexpr int DS_TW = 16;
+struct DsArgs {
+  const void* x[KMAX_ARGS];        // block input [RE][C] Act
+  void* out[KMAX_ARGS];            // block output [RE][C]: Act, or FP32 where out_f32[k]
+  int out_f32[KMAX_ARGS];
+  const float* pre_s[KMAX_ARGS];   // pre-activation affine; null => ReLU only (MRB)
+  const float* pre_o[KMAX_ARGS];
+  const float* dw1[KMAX_ARGS];     // depthwise filters, FP32 [tap = 3 (dt + 1) + df + 1][C]
+  const float* dw2[KMAX_ARGS];
+  const void* pw1[KMAX_ARGS];      // 1x1 filters in pack_1x1 order
+  const void* pw2[KMAX_ARGS];
+  const float* b1[KMAX_ARGS];
+  const float* b2[KMAX_ARGS];
+  const float* post_s[KMAX_ARGS];  // affine after the first separable conv
+  const float* post_o[KMAX_ARGS];
+  int k_off;
+  int T, F, tiles_per_slot, tw;    // tw: set by the launcher
+  const TileDesc* tiles;           // ragged batches, else null
+};
+bool ds_supported(int dtype, int C);
+hipError_t launch_ds_block(int dtype, int C, DsArgs& a, int n_tiles, int grid_y, hipStream_t s);
+
+// Per-RE fusion epilogue over stored block outputs: P = main (EPI_NONE), main * prod sup[k]
+// (EPI_PRODUCT), main + sum sup[k] (EPI_SUM) or Wc [main; sup[1]; ..] + bc (EPI_CONCAT, MFMA);
+// then LayerNorm (gamma, beta) or the affine gamma P + beta (norm_affine) -- none for
+// EPI_NONE -- giving A; A is stored to `out` (nullable), added into every sup[k] with
+// feedback, and fed to the head when llr is set.
+enum { EPI_NONE = 0, EPI_PRODUCT = 1, EPI_SUM = 2, EPI_CONCAT = 3 };
+struct FuseArgs {
+  const void* main;                // [RE][C] FP32 (main_f32) or Act
+  int main_f32;
+  void* sup[KMAX_ARGS];            // k = 1..K-1: stored support outputs [RE][C] Act
+  int K;
+  const void* wcat;                // EPI_CONCAT: Wc in pack_1x1 order (C x K C)
+  const float* bcat;
+  const float* gamma;
+  const float* beta;
+  int norm_affine;
+  float eps;
+  void* out;                       // A [RE][C] Act, or null
+  int feedback;
+  const float* Wh;
+  const float* bh;
+  float* llr;                      // [RE][m] FP32, or null
+  int m;
+  int64_t n_re;
+};
+bool concat_supported(int dtype, int C, int K);
+hipError_t launch_fuse_epilogue(int dtype, int C, int mode, FuseArgs& a, hipStream_t s);
+
 // ---------------------------------------------------------------- training kernels
 // Filter gradient of a 3x3 conv over a batch: dW[o][tap*CIN + ch] = sum_re dOut[re][o] *
 // In[re shifted by tap][ch] (In optionally through the block's pre-activation), and

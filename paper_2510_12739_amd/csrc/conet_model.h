@@ -23,6 +23,8 @@ struct Layout {
   size_t v_bin[KMAX_ARGS], v_wsin[KMAX_ARGS];
   size_t v_blk[KMAX_ARGS][LMAX];   // s0 o0 b1 s1 o1 b2 ws1 ws2 (8 C each)
   size_t v_gamma[LMAX], v_beta[LMAX], v_wh, v_bh;
+  size_t v_dw[KMAX_ARGS][LMAX];    // separable blocks: depthwise filters dw1, dw2 ([9][C] each)
+  size_t w_cat[LMAX], v_bcat[LMAX];  // fusion by concatenation: packed Wc_l, bc_l
   size_t arena;                    // activation arena (see Arena)
   // training (cfg.train): FP32 master, gradients, Adam moments, input-gradient filter
   // packs, index maps for regenerating packs from the master, scratch, saved levels
@@ -118,6 +120,12 @@ void pack_filter(int dtype, int cin, int cout, const float* W, uint8_t* dst, flo
 size_t packed_bytes(int dtype, int cin, int cout);
 void pack_filter32(int dtype, int cin, int cout, const float* W, const float* wscale, uint8_t* dst);
 size_t packed_bytes32(int dtype, int cin, int cout);
+void pack_1x1(int dtype, int cin, int cout, const float* W, uint8_t* dst);
+size_t packed_bytes_1x1(int dtype, int cin, int cout);
+uint16_t bf16_bits(float v);
+// blocks of branch k: L for the main branch, support_blocks (0 => L) for the others
+inline int support_depth(const conet_config& c) { return c.support_blocks > 0 ? c.support_blocks : c.blocks; }
+inline int branch_blocks(const conet_config& c, int k) { return k == 0 ? c.blocks : support_depth(c); }
 
 // Bytes of activation buffers (plus descriptor capacity) for `max_res` REs.
 size_t arena_bytes(const conet_config& c, int64_t max_res);
