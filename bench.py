@@ -373,6 +373,63 @@ def depth_latency_measure(calls=100):
     return res
 
 
+def variants_measure(steps=10):
+    """The block and fusion variants on the BF16 headline batch (64 slots of 3276 x 14, K=3, L=4,
+    C=64, random He-normal weights): depthwise-separable blocks with product fusion, fusion by
+    concatenation after standard blocks, and support nets of 2 blocks. Per variant: time per
+    forward and REs/s; for the separable network also the roofline of its block kernel (HBM-
+    bound: algorithmic bytes = block inputs read + outputs written, per launch) and of the
+    fusion epilogue pass, from the per-stage HIP events of conet_forward_profiled."""
+    import torch
+    from paper_2510_12739_amd import Conet
+    from synth import ModelConfig, features_fast, make_blob, workload
+
+    w = workload("bf16_b64_f3276")
+    X = torch.from_numpy(features_fast(w.sim, w.batch, n_distinct=8)).cuda()
+    B, T, F = X.shape[:3]
+    res = B * T * F
+    K, L, C, Ci, m = 3, 4, 64, w.model.C_in, w.model.m
+    out = torch.empty((B, T, F, m), dtype=torch.float32, device="cuda")
+    rows = {}
+    for name, kw in (("separable_product", dict(block="ds")), ("standard_concat", dict(fusion="concat")),
+                     ("standard_product_support2", dict(support_blocks=2))):
+        mc = ModelConfig(K, L, C, Ci, m, -1, kw.get("support_blocks", 0), kw.get("fusion", "product"),
+                         kw.get("block", "standard"))
+        print(f"[bench] variant {name}", file=sys.stderr, flush=True)
+        model = Conet(K, L, C, Ci, m, make_blob(mc, seed=21), dtype="bf16", max_res=res, **kw)
+        for _ in range(2):
+            model.forward(X, out=out)
+        torch.cuda.synchronize()
+        stage = []
+        for _ in range(steps):
+            _, ms, units = model.forward_profiled(X, out=out, units=True)
+            stage.append(ms)
+        stage = np.array(stage, dtype=np.float64)
+        call = stage.sum(axis=1)
+        row = {"call_ms_p50": round(float(np.median(call)), 4), "res_per_s": round(res / (np.median(call) * 1e-3), 1)}
+        if name == "separable_product":
+            # stage 1 + 3l: the block launch over the branches; 2 + 3l: the fusion epilogue pass
+            blk = [(stage[:, 1 + 3 * l].mean(), (K if l < L - 1 else 1)) for l in range(L)]
+            fused = [blk[l] for l in range(L - 1)]
+            main_extra = 2 * C  # the main branch's FP32 output (4 C bytes instead of 2 C)
+            by = [res * (n * 4 * C + main_extra) for _, n in fused]
+            gbs = [b / (ms * 1e-3) / 1e9 for (ms, _), b in zip(fused, by)]
+            row["block_kernel"] = {"mean_launch_ms": round(float(np.mean([ms for ms, _ in fused])), 4),
+                                   "bytes_per_launch": int(np.mean(by)), "achieved_GB_per_s": round(float(np.mean(gbs)), 1),
+                                   "frac_of_hbm_peak": round(float(np.mean(gbs)) / HBM_PEAK_GBS, 4),
+                                   "per_re_branch_bytes": 4 * C, "flops_per_re_branch": 2 * (18 * C + 2 * C * C)}
+            epi = [stage[:, 2 + 3 * l].mean() for l in range(L - 1)]
+            eb = res * (4 * C + (K - 1) * 2 * C + 2 * C)  # FP32 main + BF16 supports read, A written
+            row["fusion_epilogue"] = {"mean_ms": round(float(np.mean(epi)), 4), "bytes": eb,
+                                      "achieved_GB_per_s": round(eb / (float(np.mean(epi)) * 1e-3) / 1e9, 1)}
+        if name == "standard_concat":
+            epi = [stage[:, 3 + 3 * l].mean() for l in range(L)]
+            row["concat_stage_ms"] = [round(float(v), 4) for v in epi]
+        rows[name] = row
+        model.close()
+    return {"workload": f"{B} slots x {T} x {F}, K={K} L={L} C={C} BF16, random weights", "variants": rows}
+
+
 def depth_latency(args):
     res = depth_latency_measure(calls=args.steps)
     print(json.dumps(res), flush=True)
@@ -750,11 +807,33 @@ def headline(args):
         result["featuriser"] = {"ms": round(f_ms, 4), "bytes": f_bytes,
                                 "GB_per_s": round(f_bytes / (f_ms * 1e-3) / 1e9, 1),
                                 "frac_of_hbm_peak": round(f_bytes / (f_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        del y_dev, xf
+        # the forward straight from the received grid (features formed in the input layer's
+        # staging) against the featuriser pass followed by the forward on features
+        from paper_2510_12739_amd import Conet
+        model = Conet(mc.K, mc.L, mc.C, mc.C_in, mc.m, blob, dtype=dtype, max_res=B * T * F)
+        if dtype == "fp8":
+            model.calibrate(xf[:min(4, B)])
+        yo = torch.empty((B, T, F, mc.m), dtype=torch.float32, device="cuda")
+        timings = {}
+        for name, fn in (("featurise_then_forward", lambda: (featurise(y_dev, mc.C_in, out=xf), model.forward(xf, out=yo))),
+                         ("forward_from_grid", lambda: model.forward_grid(y_dev, out=yo))):
+            for _ in range(2):
+                fn()
+            fe0.record(stream)
+            for _ in range(5):
+                fn()
+            fe1.record(stream)
+            torch.cuda.synchronize()
+            timings[name] = round(fe0.elapsed_time(fe1) / 5, 4)
+        model.close()
+        result["featuriser"]["ms_per_batch"] = timings
+        result["featuriser"]["grid_to_llr_res_per_s"] = round(B * T * F / (timings["forward_from_grid"] * 1e-3), 1)
+        del y_dev, xf, yo
         torch.cuda.empty_cache()
 
     if full:
         result["depth_vs_latency"] = depth_latency_measure(calls=50)
+        result["variants"] = variants_measure()
 
     if full and not args.no_serve:
         result["serving"] = serve_measure(loads=args.serve_loads, duration_s=args.serve_seconds, grid=True, pinned=True)

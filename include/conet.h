@@ -209,6 +209,18 @@ conet_status conet_forward_profiled(conet_model* model, const float* x, int32_t 
 conet_status conet_featurise(const float* y, int32_t B, int32_t T, int32_t F, int32_t n_rx, int32_t C_in,
                              float* x_out, void* stream);
 
+/* Forward pass from the received grid: y (device, FP32 [B][T][F][n_rx][2], Re/Im per
+ * antenna, the layout conet_featurise reads) -> llr (device, FP32 [B][T][F][m]). The input
+ * layer forms the features while it stages its tiles -- the steps of conet_featurise (LS at
+ * the pilots, linear interpolation; Sec. I and II-A), bit-identical to them -- so the
+ * features never go through HBM; channels 4 n_rx .. C_in - 1 are zero (no variance
+ * channels: models that take them run conet_featurise_var, then conet_forward). Same
+ * results as conet_featurise followed by conet_forward. Errors: EINVAL (null pointers),
+ * ESHAPE (T < 12 or T > 14, F < 1, n_rx < 1, 4 n_rx > C_in, B*T*F > max_res), ESTATE
+ * (FP8 model without activation scales), EDEVICE. */
+conet_status conet_forward_grid(conet_model* model, const float* y, int32_t B, int32_t T, int32_t F, int32_t n_rx,
+                                float* llr, void* stream);
+
 /* conet_featurise plus the known noise and interference variances of each slot, which the
  * receiver's input also carries (Sec. II-A concatenates them with the received grid):
  * variances: device FP32 [B][2] = (sigma_n^2, sigma_i^2) per slot. Channels C_in - 8 ..
@@ -217,6 +229,34 @@ conet_status conet_featurise(const float* y, int32_t B, int32_t T, int32_t F, in
  * C_in - 8), EINVAL for null variances. */
 conet_status conet_featurise_var(const float* y, const float* variances, int32_t B, int32_t T, int32_t F,
                                  int32_t n_rx, int32_t C_in, float* x_out, void* stream);
+
+/* ---------------------------------------------------------------- on-device slot generator
+ * Training batches generated on the GPU (the step before the receiver's input, Sec. II, Eq.
+ * (1)): uniform bits, square Gray QAM with the fixed pilots (symbols 2 and 11, even
+ * subcarriers, (1 + j)/sqrt(2)), a Rayleigh tapped-delay-line channel (n_taps taps 200 ns
+ * apart, exponential power delay profile with 300 ns decay, unit total power) whose taps vary
+ * over the slot by Clarke's isotropic scattering at a Doppler f_D ~ U[0, max_doppler_hz]
+ * (16 sinusoids per tap and antenna), and white Gaussian noise of variance 10^(-SNR/10),
+ * SNR ~ U[snr_lo_db, snr_hi_db] per slot; 30 kHz subcarriers, 14 symbols per 0.5 ms. Random
+ * numbers: Philox4x32-10 keyed by `seed`, counter (slot, stream, index, 0), so slot s is the
+ * same in any batch. */
+typedef struct {
+  int32_t F;                /* subcarriers                                              */
+  int32_t T;                /* OFDM symbols, 12..14                                     */
+  int32_t n_rx;             /* receive antennas, 1..8                                   */
+  int32_t bits_per_symbol;  /* m: 2, 4, 6 or 8                                           */
+  int32_t n_taps;           /* 1..16                                                    */
+  float max_doppler_hz;
+  float snr_lo_db, snr_hi_db;
+  uint64_t seed;
+} conet_sim_config;
+
+/* Slots first_slot .. first_slot + B - 1: y (device, FP32 [B][T][F][n_rx][2], the layout
+ * conet_featurise and conet_forward_grid read), bits (device, uint8 [B][T][F][m], 0/1; pilot
+ * REs carry bits that were not sent), noise_var (device, FP32 [B], nullable). Errors:
+ * EINVAL (null pointers, parameters out of range), ESHAPE (B > 65535, T, F), EDEVICE. */
+conet_status conet_simulate(const conet_sim_config* cfg, int64_t first_slot, int32_t B, float* y, uint8_t* bits,
+                            float* noise_var, void* stream);
 
 /* Subcarriers per tile of the fused residual-block kernel that forwards of this model use
  * on a batch that fills the GPU (both convs of a block in one launch, the hidden activation

@@ -3,5 +3,5 @@
 The Python layer only marshals arguments; see binding.Conet.
 """
 from .binding import (Conet, ConetError, Server, conet_function, featurise, load, make_config, mfma_dot, mfma_peak,
-                      pinned_array, weight_count,
+                      pinned_array, simulate, weight_count,
                       workspace_bytes, EXPORTS)

@@ -22,8 +22,8 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "ENOMEM", 4: "EDEVICE", 5: "EBUS
 # Every symbol include/conet.h declares.
 EXPORTS = ("conet_weight_count", "conet_workspace_bytes", "conet_create", "conet_set_act_scales",
            "conet_calibrate", "conet_get_act_scales", "conet_forward", "conet_forward_ragged", "conet_forward_profiled",
-           "conet_forward_noalloc", "conet_forward_noalloc_capacity",
-           "conet_block_tile_width", "conet_mfma_peak", "conet_mfma_dot", "conet_featurise", "conet_featurise_var",
+           "conet_forward_noalloc", "conet_forward_noalloc_capacity", "conet_forward_grid",
+           "conet_block_tile_width", "conet_mfma_peak", "conet_mfma_dot", "conet_featurise", "conet_featurise_var", "conet_simulate",
            "conet_serve_create", "conet_serve_submit", "conet_serve_wait", "conet_serve_get_stats",
            "conet_serve_reset_stats", "conet_serve_pause", "conet_serve_destroy", "conet_backward", "conet_grads",
            "conet_master_weights", "conet_adam_step", "conet_get_weights", "conet_save_train_state",
@@ -44,6 +44,12 @@ class conet_config(ctypes.Structure):
                 ("train", ctypes.c_int32), ("max_res", ctypes.c_int64), ("fusion_op", ctypes.c_int32),
                 ("feedback", ctypes.c_int32), ("norm", ctypes.c_int32), ("support_blocks", ctypes.c_int32),
                 ("block_type", ctypes.c_int32)]
+
+
+class conet_sim_config(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_int32), ("T", ctypes.c_int32), ("n_rx", ctypes.c_int32),
+                ("bits_per_symbol", ctypes.c_int32), ("n_taps", ctypes.c_int32), ("max_doppler_hz", ctypes.c_float),
+                ("snr_lo_db", ctypes.c_float), ("snr_hi_db", ctypes.c_float), ("seed", ctypes.c_uint64)]
 
 
 class conet_request(ctypes.Structure):
@@ -96,6 +102,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.conet_mfma_peak.argtypes = [i32, i32, dp, dp, vp]; lib.conet_mfma_peak.restype = i32
     lib.conet_mfma_dot.argtypes = [i32, i32, vp, vp, ctypes.POINTER(ctypes.c_float)]; lib.conet_mfma_dot.restype = i32
     lib.conet_featurise.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]; lib.conet_featurise.restype = i32
+    lib.conet_forward_grid.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp]; lib.conet_forward_grid.restype = i32
+    lib.conet_simulate.argtypes = [ctypes.POINTER(conet_sim_config), ctypes.c_int64, i32, vp, vp, vp, vp]
+    lib.conet_simulate.restype = i32
     lib.conet_featurise_var.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]; lib.conet_featurise_var.restype = i32
     lib.conet_serve_create.argtypes = [vp, sz, i32, i32, i32, ctypes.POINTER(vp)]
     lib.conet_serve_create.restype = i32
@@ -325,6 +334,20 @@ class Conet:
                                                _stream_ptr(stream)))
         return (out, ms, un) if units else (out, ms)
 
+    def forward_grid(self, y, out=None, stream=None):
+        """conet_forward_grid: y is the received grid, a contiguous float32 CUDA tensor
+        [B][T][F][n_rx][2]; the input layer forms the features while staging. Returns LLRs
+        [B][T][F][m]."""
+        import torch
+        if not (y.is_cuda and y.dtype == torch.float32 and y.is_contiguous() and y.dim() == 5 and y.shape[-1] == 2):
+            raise ValueError("y must be a contiguous float32 CUDA tensor [B][T][F][n_rx][2]")
+        B, T, F, n_rx, _ = y.shape
+        if out is None:
+            out = torch.empty((B, T, F, self.m), dtype=torch.float32, device=y.device)
+        _check(self.lib.conet_forward_grid(self.handle, ctypes.c_void_p(y.data_ptr()), B, T, F, n_rx,
+                                           ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
     def forward_ragged(self, x_packed, T: int, F_list: Sequence[int], out=None, stream=None):
         """Slots of different widths packed back to back: x_packed [sum T*F_s, C_in]."""
         import torch
@@ -496,3 +519,21 @@ def featurise(y, C_in: int, out=None, stream=None, variances=None):
         _check(load().conet_featurise_var(ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(variances.data_ptr()), B, T,
                                           F, n_rx, C_in, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
+
+
+def simulate(F: int, n_rx: int, bits_per_symbol: int, first_slot: int, B: int, n_taps: int = 8,
+             max_doppler_hz: float = 400.0, snr_db=(-5.0, 25.0), seed: int = 0, T: int = 14, out=None, stream=None):
+    """conet_simulate: slots first_slot .. first_slot + B - 1 generated on the current GPU.
+    Returns (y float32 [B][T][F][n_rx][2], bits uint8 [B][T][F][m], noise_var float32 [B]);
+    `out` may pass those three tensors to fill."""
+    import torch
+    cfg = conet_sim_config(F, T, n_rx, bits_per_symbol, n_taps, max_doppler_hz, snr_db[0], snr_db[1], seed)
+    if out is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+        out = (torch.empty((B, T, F, n_rx, 2), dtype=torch.float32, device=dev),
+               torch.empty((B, T, F, bits_per_symbol), dtype=torch.uint8, device=dev),
+               torch.empty((B,), dtype=torch.float32, device=dev))
+    y, bits, nv = out
+    _check(load().conet_simulate(ctypes.byref(cfg), int(first_slot), B, ctypes.c_void_p(y.data_ptr()),
+                                 ctypes.c_void_p(bits.data_ptr()), ctypes.c_void_p(nv.data_ptr()), _stream_ptr(stream)))
+    return y, bits, nv

@@ -492,6 +492,22 @@ conet_status conet_forward(conet_model* M, const float* x, int32_t B, int32_t T,
   return run_forward(M, M->arena, x, geo, llr, (hipStream_t)stream, nullptr);
 }
 
+conet_status conet_forward_grid(conet_model* M, const float* y, int32_t B, int32_t T, int32_t F, int32_t n_rx,
+                                float* llr, void* stream) {
+  if (!M) return fail(CONET_EINVAL, "null model");
+  if (B == 0) return CONET_OK;
+  if (!y || !llr) return fail(CONET_EINVAL, "null tensor pointer");
+  if (B < 0 || T <= PILOT_T1 || T > TMAX || F < 1)
+    return fail(CONET_ESHAPE, "bad shape B=%d T=%d F=%d (need 12 <= T <= 14: both pilot symbols)", B, T, F);
+  if (n_rx < 1 || 4 * n_rx > M->cfg.in_channels)
+    return fail(CONET_ESHAPE, "n_rx = %d needs 4 n_rx <= C_in = %d", n_rx, M->cfg.in_channels);
+  if ((int64_t)B * T * F > M->cfg.max_res) return fail(CONET_ESHAPE, "B*T*F = %lld exceeds max_res %lld", (long long)B * T * F, (long long)M->cfg.max_res);
+  if (M->cfg.dtype == DT_FP8 && !M->scales_set) return fail(CONET_ESTATE, "FP8 model needs activation scales (set or calibrate)");
+  Geometry geo;
+  geo.uniform = true; geo.B = B; geo.T = T; geo.F = F; geo.grid_rx = n_rx;
+  return run_forward(M, M->arena, y, geo, llr, (hipStream_t)stream, nullptr);
+}
+
 conet_status conet_forward_ragged(conet_model* M, const float* x, int32_t n_slots, int32_t T, const int32_t* F_host,
                                   float* llr, void* stream) {
   if (!M) return fail(CONET_EINVAL, "null model");

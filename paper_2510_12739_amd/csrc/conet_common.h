@@ -97,6 +97,34 @@ struct ArithF64 {
   }
 };
 
+// ---------------------------------------------------------------- LS channel estimate
+// Pilots: OFDM symbols 2 and 11, even subcarriers, value p = (1 + j)/sqrt(2). Shared by the
+// featuriser and the input conv's grid staging, so both form bit-identical features.
+constexpr int PILOT_T0 = 2, PILOT_T1 = 11;
+
+// y / p = y conj(p) / |p|^2 = ((a + b) + j (b - a)) / sqrt(2)
+__device__ __forceinline__ float2 div_pilot(float2 y) {
+  const float r = 0.70710678118654752f;
+  return make_float2((y.x + y.y) * r, (y.y - y.x) * r);
+}
+
+// LS estimate on one pilot symbol at subcarrier f of one antenna (row: pointer to that
+// antenna's sample at subcarrier 0 of the symbol, stride floats2 per subcarrier): y / p on
+// even f, the mean of the two even neighbours on odd f, the left neighbour on a last odd f.
+__device__ __forceinline__ float2 pilot_row_estimate(const float2* __restrict__ row, int64_t stride, int f, int F) {
+  if ((f & 1) == 0) return div_pilot(row[(int64_t)f * stride]);
+  const float2 l = div_pilot(row[(int64_t)(f - 1) * stride]);
+  if (f + 1 >= F) return l;
+  const float2 r = div_pilot(row[(int64_t)(f + 1) * stride]);
+  return make_float2(0.5f * (l.x + r.x), 0.5f * (l.y + r.y));
+}
+
+// Every symbol t on the line through the two pilot symbols: h0 + (t - 2) / 9 (h1 - h0).
+__device__ __forceinline__ float2 interp_symbol(float2 h0, float2 h1, int t) {
+  const float w = (float)(t - PILOT_T0) / (float)(PILOT_T1 - PILOT_T0);
+  return make_float2(fmaf(w, h1.x - h0.x, h0.x), fmaf(w, h1.y - h0.y, h0.y));
+}
+
 // ---------------------------------------------------------------- tile geometry
 // A tile is one slot, all of its T <= 14 OFDM symbols and TW consecutive subcarriers.
 struct TileDesc {

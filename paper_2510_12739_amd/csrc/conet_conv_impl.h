@@ -195,6 +195,46 @@ __device__ __forceinline__ void stage_tile(uint8_t* lds, const InT* __restrict__
   }
 }
 
+// Stage the input layer's halo tile straight from the received grid y (FP32 [RE][n_rx][2]):
+// the features of every position -- Re y, Im y and the LS channel estimate interpolated to
+// its symbol, per antenna, zeros for antennas n_rx .. CIN/4 - 1 -- are formed on the fly with
+// the featuriser's own steps (bit-identical to conet_featurise), then rounded to Op. One
+// thread per (antenna group, position); the pilot-row samples a column needs are re-read
+// from cache by the 16 rows that use them. Needs T >= 12 (both pilot symbols).
+template <class A, int CIN, int XW, int COFF, int PITCH, int NT>
+__device__ __forceinline__ void stage_grid_tile(uint8_t* lds, const float2* __restrict__ y, const TileDesc& td, int T,
+                                                int n_rx, float qscale) {
+  using Op = typename A::Op;
+  constexpr int CPP = CIN / 4;  // antenna groups per position
+  constexpr int NPOS = TROWS * XW;
+  constexpr int PPR = NT / CPP;
+  const int tid = threadIdx.x;
+  if (tid >= PPR * CPP) return;
+  const int n = tid % CPP, p0 = tid / CPP;
+  const float2* __restrict__ slot = y + td.re_base * n_rx + n;  // antenna n's sample of (t = 0, f = 0)
+  for (int pos = p0; pos < NPOS; pos += PPR) {
+    const int r = pos / XW, c = pos - r * XW;
+    const int t = r - 1, f = td.f0 + c - COFF;
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    if (n < n_rx && t >= 0 && t < T && f >= 0 && f < td.F) {
+      const float2 yv = slot[((int64_t)t * td.F + f) * n_rx];
+      const float2 h0 = pilot_row_estimate(slot + (int64_t)PILOT_T0 * td.F * n_rx, n_rx, f, td.F);
+      const float2 h1 = pilot_row_estimate(slot + (int64_t)PILOT_T1 * td.F * n_rx, n_rx, f, td.F);
+      const float2 h = interp_symbol(h0, h1, t);
+      v[0] = yv.x; v[1] = yv.y; v[2] = h.x; v[3] = h.y;
+    }
+    uint8_t* dst = lds + pos * PITCH + 4 * n * (int)sizeof(Op);
+    if constexpr (sizeof(Op) == 1) {
+      *reinterpret_cast<uint32_t*>(dst) = pack4_e4m3(v[0] * qscale, v[1] * qscale, v[2] * qscale, v[3] * qscale);
+    } else if constexpr (sizeof(Op) == 2) {
+      __bf16 bb[4] = {f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
+      *reinterpret_cast<uint2*>(dst) = *reinterpret_cast<const uint2*>(bb);
+    } else {
+      *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- GEMM core
 // acc[mt][ot] += W (o-tile ot) x X^T (M-tile mt) over all K steps, for MT M-tiles of
 // 16 REs each. The caller gives, per M-tile, the LDS byte offset of this lane's RE for
@@ -479,8 +519,12 @@ __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
 
   int prologue = 0;
   if (MODE == 1) prologue = args.pre_s[k0] ? 1 : 2;
-  stage_tile<A, InT, CIN, TW + 2, 1, PITCH, NT>(lds, reinterpret_cast<const InT*>(args.in[k0]), td, T, prologue,
-                                         args.pre_s[k0], args.pre_o[k0], args.in_qscale[k0]);
+  if (MODE == 0 && args.grid_rx > 0)
+    stage_grid_tile<A, CIN, TW + 2, 1, PITCH, NT>(lds, reinterpret_cast<const float2*>(args.in[k0]), td, T,
+                                                  args.grid_rx, args.in_qscale[k0]);
+  else
+    stage_tile<A, InT, CIN, TW + 2, 1, PITCH, NT>(lds, reinterpret_cast<const InT*>(args.in[k0]), td, T, prologue,
+                                                  args.pre_s[k0], args.pre_o[k0], args.in_qscale[k0]);
   __syncthreads();
   // the input layer can run every branch from one staged tile (the features are shared)
   const int nb = (MODE == 0 && args.inner_branches > 1) ? args.inner_branches : 1;

@@ -24,23 +24,6 @@
 
 namespace conet {
 
-constexpr int PILOT_T0 = 2, PILOT_T1 = 11;
-
-// y / p for p = (1 + j)/sqrt(2): y * conj(p) / |p|^2 = ((a + b) + j (b - a)) / sqrt(2)
-__device__ __forceinline__ float2 div_pilot(float2 y) {
-  const float r = 0.70710678118654752f;
-  return make_float2((y.x + y.y) * r, (y.y - y.x) * r);
-}
-
-// LS estimate on pilot symbol row `row` (pointer to y[b][s][0][n], stride per subcarrier)
-__device__ __forceinline__ float2 pilot_row_estimate(const float2* __restrict__ row, int64_t stride, int f, int F) {
-  if ((f & 1) == 0) return div_pilot(row[(int64_t)f * stride]);
-  const float2 l = div_pilot(row[(int64_t)(f - 1) * stride]);
-  if (f + 1 >= F) return l;
-  const float2 r = div_pilot(row[(int64_t)(f + 1) * stride]);
-  return make_float2(0.5f * (l.x + r.x), 0.5f * (l.y + r.y));
-}
-
 // n_groups = C_in / 4 float4 groups per RE: groups n < n_ant_out are antenna n's (zeros for
 // n >= n_rx); with `var` ([B] pairs sigma_n^2, sigma_i^2), the last two groups hold the slot's
 // variances and zeros.
@@ -69,12 +52,11 @@ __global__ void __launch_bounds__(256) featurise_kernel(const float2* __restrict
   }
   const float2 h0 = pilot_row_estimate(y + (slot0 + (int64_t)PILOT_T0 * F) * n_rx + n, n_rx, f, F);
   const float2 h1 = pilot_row_estimate(y + (slot0 + (int64_t)PILOT_T1 * F) * n_rx + n, n_rx, f, F);
-  const float2 dh = make_float2(h1.x - h0.x, h1.y - h0.y);
   const float2* yp = y + (slot0 + f) * n_rx + n;
   for (int t = 0; t < T; ++t) {
-    const float w = (float)(t - PILOT_T0) / (float)(PILOT_T1 - PILOT_T0);
     const float2 yv = yp[(int64_t)t * F * n_rx];
-    xp[(int64_t)t * sym] = make_float4(yv.x, yv.y, h0.x + w * dh.x, h0.y + w * dh.y);
+    const float2 h = interp_symbol(h0, h1, t);
+    xp[(int64_t)t * sym] = make_float4(yv.x, yv.y, h.x, h.y);
   }
 }
 

@@ -334,6 +334,7 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
   };
   auto to_scale = [](float amax) { return amax > 0.f ? amax / E4M3_MAX : 1.0f; };
   if (calib && !geo.uniform) return fail(CONET_EINVAL, "calibration takes a uniform batch");
+  if ((calib || save) && geo.grid_rx) return fail(CONET_EINVAL, "calibration and training forwards take features");
 
   int stage = 0;
   auto mark = [&]() -> hipError_t {
@@ -365,6 +366,7 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
       a.in_qscale[k] = 1.0f / sc[0];
       a.deq[k] = sc[0];
     }
+    a.grid_rx = geo.grid_rx;  // features formed while staging the received grid
     e = mark();
     a.inner_branches = K;  // the features are staged once per tile for all branches
     if (e == hipSuccess) e = launch_conv(dt, 0, Ci, C, a, n_tiles_in, 1, s);

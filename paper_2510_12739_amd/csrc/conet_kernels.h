@@ -50,6 +50,8 @@ struct ConvArgs {
   void* save_o0;                   // mode 4 (training): also store the main output before fusion
   int inner_branches;              // mode 0: run branches k_off .. k_off + n - 1 in every work-group
                                    // (one staged feature tile; launch with grid.y = 1)
+  int grid_rx;                     // mode 0: > 0 => in[] is the received grid, FP32 [RE][grid_rx][2],
+                                   // and the features are formed while staging (LS + interpolation)
   int fusion_sum;                  // mode 4: fuse by addition instead of the product
   int norm_affine;                 // mode 4: gamma/beta are a per-channel affine (BatchNorm with
                                    // running statistics folded in) instead of LayerNorm's

@@ -72,6 +72,7 @@ struct Geometry {
   // upload is an asynchronous copy; null: a pageable copy
   TileDesc* tiles_pin = nullptr;
   size_t tiles_pin_cap = 0;
+  int grid_rx = 0;                         // > 0: x is the received grid [RE][grid_rx][2] (FP32)
 };
 
 }  // namespace conet

@@ -71,7 +71,8 @@ struct DsShape {
   static constexpr int W1 = DS_TW + 2;                // columns of d1 and h: the tile +- 1
   static constexpr int PRE = TMAX * W0 * PITCH;       // pre(x), later the second depthwise output
   static constexpr int MID = TMAX * W1 * PITCH;       // d1, later h
-  static constexpr int LDS = PRE + MID + 2 * 9 * C * 4;
+  static constexpr int LDS = PRE + MID;
+  static constexpr int NSTAGE = (TMAX * W0 * CH + 255) / 256;  // staging items per thread
   static constexpr int NOT = C / 16;
   static constexpr int NS = C / (4 * VEC);            // K steps of a 1x1 conv
   static constexpr int MT = 4;                        // RE tiles of 16 per wave and conv
@@ -99,13 +100,23 @@ __device__ __forceinline__ i32x4 f_to_chunk(const float* f) {
 }
 
 // Depthwise 3x3 over `n_cols` output columns: out column c reads in columns c .. c + 2 (the
-// input region is two columns wider); rows outside [0, T) read as zero.
+// input region is two columns wider); rows outside [0, T) read as zero. The work-group's 256
+// threads stride over (position, chunk) items by a multiple of the chunks per position, so a
+// thread always handles the same 16-byte channel chunk and keeps its 9 x VEC filter taps in
+// registers (filt: [tap][C] FP32 in global memory).
 template <class A, int C>
-__device__ __forceinline__ void depthwise(const uint8_t* in, int in_w, uint8_t* out, int n_cols, const float* filt,
-                                          int T) {
+__device__ __forceinline__ void depthwise(const uint8_t* in, int in_w, uint8_t* out, int n_cols,
+                                          const float* __restrict__ filt, int T) {
   using S = DsShape<A, C>;
+  static_assert(256 % S::CH == 0, "a thread's chunk must not change between items");
+  const int c16 = threadIdx.x % S::CH;
+  float w[9][A::VEC];
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+    for (int j = 0; j < A::VEC; ++j) w[tap][j] = filt[tap * C + c16 * A::VEC + j];
   for (int i = threadIdx.x; i < T * n_cols * S::CH; i += 256) {
-    const int c16 = i % S::CH, pos = i / S::CH, col = pos % n_cols, t = pos / n_cols;
+    const int pos = i / S::CH, col = pos % n_cols, t = pos / n_cols;
     float acc[A::VEC];
 #pragma unroll
     for (int j = 0; j < A::VEC; ++j) acc[j] = 0.f;
@@ -117,9 +128,8 @@ __device__ __forceinline__ void depthwise(const uint8_t* in, int in_w, uint8_t* 
       for (int df = 0; df < 3; ++df) {
         float v[A::VEC];
         chunk_to_f<A>(*reinterpret_cast<const i32x4*>(in + (tt * in_w + col + df) * S::PITCH + c16 * 16), v);
-        const float* w = filt + ((dt + 1) * 3 + df) * C + c16 * A::VEC;
 #pragma unroll
-        for (int j = 0; j < A::VEC; ++j) acc[j] = fmaf(w[j], v[j], acc[j]);
+        for (int j = 0; j < A::VEC; ++j) acc[j] = fmaf(w[(dt + 1) * 3 + df][j], v[j], acc[j]);
       }
     }
     *reinterpret_cast<i32x4*>(out + (t * n_cols + col) * S::PITCH + c16 * 16) = f_to_chunk<A>(acc);
@@ -170,37 +180,52 @@ __global__ void __launch_bounds__(256, 2) ds_block_kernel(DsArgs args) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS];
   uint8_t* pre = lds;
   uint8_t* mid = lds + S::PRE;
-  float* filt = reinterpret_cast<float*>(lds + S::PRE + S::MID);
   const int k = blockIdx.y + args.k_off;
   const TileDesc td = ds_tile(args, blockIdx.x);
   const int T = args.T, lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
   const Op* __restrict__ x = reinterpret_cast<const Op*>(args.x[k]);
-  const float* __restrict__ ps = args.pre_s[k];
-  const float* __restrict__ po = args.pre_o[k];
 
-  for (int i = threadIdx.x; i < 9 * C; i += 256) {
-    filt[i] = args.dw1[k][i];
-    filt[9 * C + i] = args.dw2[k][i];
-  }
-  // pre(x) = ReLU(s0 x + o0), or ReLU(x) in a main block after a fusion; zero outside the slot
-  for (int i = threadIdx.x; i < TMAX * S::W0 * S::CH; i += 256) {
-    const int c16 = i % S::CH, pos = i / S::CH, col = pos % S::W0, t = pos / S::W0;
-    const int f = td.f0 - 2 + col;
-    i32x4 v = {0, 0, 0, 0};
-    if (t < T && f >= 0 && f < td.F) {
-      float e[A::VEC];
-      chunk_to_f<A>(*reinterpret_cast<const i32x4*>(x + (td.re_base + (int64_t)t * td.F + f) * C + c16 * A::VEC), e);
+  // pre(x) = ReLU(s0 x + o0), or ReLU(x) in a main block after a fusion; zero outside the slot.
+  // A thread keeps one channel chunk (its prologue parameters in registers) and issues all of
+  // its loads before converting any, so their latencies overlap.
+  {
+    const int c16 = threadIdx.x % S::CH;
+    const bool aff = args.pre_s[k] != nullptr;
+    float sv[A::VEC], ov[A::VEC];
 #pragma unroll
-      for (int j = 0; j < A::VEC; ++j) {
-        const int c = c16 * A::VEC + j;
-        e[j] = fmaxf(ps ? fmaf(ps[c], e[j], po[c]) : e[j], 0.f);
-      }
-      v = f_to_chunk<A>(e);
+    for (int j = 0; j < A::VEC; ++j) {
+      sv[j] = aff ? args.pre_s[k][c16 * A::VEC + j] : 1.f;
+      ov[j] = aff ? args.pre_o[k][c16 * A::VEC + j] : 0.f;
     }
-    *reinterpret_cast<i32x4*>(pre + pos * S::PITCH + c16 * 16) = v;
+    i32x4 raw[S::NSTAGE];
+#pragma unroll
+    for (int it = 0; it < S::NSTAGE; ++it) {
+      const int i = threadIdx.x + it * 256;
+      const int pos = i / S::CH, col = pos % S::W0, t = pos / S::W0;
+      const int f = td.f0 - 2 + col;
+      raw[it] = i32x4{0, 0, 0, 0};
+      if (i < TMAX * S::W0 * S::CH && t < T && f >= 0 && f < td.F)
+        raw[it] = *reinterpret_cast<const i32x4*>(x + (td.re_base + (int64_t)t * td.F + f) * C + c16 * A::VEC);
+    }
+#pragma unroll
+    for (int it = 0; it < S::NSTAGE; ++it) {
+      const int i = threadIdx.x + it * 256;
+      if (i >= TMAX * S::W0 * S::CH) break;
+      const int pos = i / S::CH, col = pos % S::W0, t = pos / S::W0;
+      const int f = td.f0 - 2 + col;
+      i32x4 v = {0, 0, 0, 0};
+      if (t < T && f >= 0 && f < td.F) {
+        float e[A::VEC];
+        chunk_to_f<A>(raw[it], e);
+#pragma unroll
+        for (int j = 0; j < A::VEC; ++j) e[j] = fmaxf(fmaf(sv[j], e[j], ov[j]), 0.f);
+        v = f_to_chunk<A>(e);
+      }
+      *reinterpret_cast<i32x4*>(pre + pos * S::PITCH + c16 * 16) = v;
+    }
   }
   __syncthreads();
-  depthwise<A, C>(pre, S::W0, mid, S::W1, filt, T);
+  depthwise<A, C>(pre, S::W0, mid, S::W1, args.dw1[k], T);
   __syncthreads();
 
   typename S::AccTile acc;
@@ -233,7 +258,7 @@ __global__ void __launch_bounds__(256, 2) ds_block_kernel(DsArgs args) {
     }
   }
   __syncthreads();
-  depthwise<A, C>(mid, S::W1, pre, DS_TW, filt + 9 * C, T);
+  depthwise<A, C>(mid, S::W1, pre, DS_TW, args.dw2[k], T);
   __syncthreads();
   pointwise<A, C>(acc, pre, T * DS_TW, reinterpret_cast<const i32x4*>(args.pw2[k]));
   {

@@ -65,3 +65,57 @@ def test_featurise_errors():
     y = torch.zeros((1, 14, 8, 5, 2), dtype=torch.float32, device="cuda")
     with pytest.raises(ConetError, match="ESHAPE"):
         featurise(y, 16)  # 5 antennas need 20 channels
+
+
+# ----------------------------------------------------------------------------- forward from the grid
+
+@pytest.mark.parametrize("dtype,K,L,C,n_rx,C_in,T,F,B", [
+    ("f32", 2, 2, 32, 4, 16, 14, 71, 2),
+    ("bf16", 3, 3, 64, 4, 16, 14, 3276, 2),   # the throughput workload's grid
+    ("bf16", 2, 2, 96, 2, 16, 12, 45, 3),     # 2 antennas into a 4-antenna input layer, T = 12
+    ("fp8", 4, 2, 96, 8, 32, 14, 48, 2),
+])
+def test_forward_from_grid_equals_featurise_then_forward(dtype, K, L, C, n_rx, C_in, T, F, B):
+    """conet_forward_grid forms the features inside the input layer's staging with the
+    featuriser's own steps, so its LLRs equal conet_featurise + conet_forward bit for bit;
+    and both match the oracle's features + forward (FP32 at the FP32 forward bound)."""
+    from paper_2510_12739_amd import Conet, featurise
+    from oracle import conet64 as o
+    from synth import ModelConfig, make_blob
+    m = 4
+    sim = SimConfig(F=F, n_rx=n_rx, bits_per_symbol=m, seed=53, T=T)
+    y = _y(sim, B)
+    y32 = np.ascontiguousarray(np.stack([y.real, y.imag], axis=-1).astype(np.float32))
+    blob = make_blob(ModelConfig(K, L, C, C_in, m), seed=54, perturb=True)
+    say(f"forward from grid {dtype} K={K} L={L} C={C} n_rx={n_rx} T={T} F={F} B={B}")
+    model = Conet(K, L, C, C_in, m, blob, dtype=dtype, max_res=B * T * F)
+    yd = torch.from_numpy(y32).cuda()
+    x = featurise(yd, C_in)
+    if dtype == "fp8":
+        model.calibrate(x)
+    a = model(x).cpu().numpy()
+    b = model.forward_grid(yd).cpu().numpy()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a, b)
+    if dtype == "f32":
+        yq = y32[..., 0].astype(np.float64) + 1j * y32[..., 1].astype(np.float64)
+        p = o.unpack(blob, K, L, C, C_in, m)
+        ref = o.forward_slots(p, fz.features(yq, C_in))
+        rel = np.linalg.norm(b - ref) / np.linalg.norm(ref)
+        assert rel <= 1e-5 and np.abs(b - ref).max() <= 1e-4 * np.sqrt(np.mean(ref ** 2)), rel
+    model.close()
+
+
+def test_forward_from_grid_errors():
+    from paper_2510_12739_amd import Conet, ConetError
+    from synth import ModelConfig, make_blob
+    model = Conet(2, 1, 32, 16, 2, make_blob(ModelConfig(2, 1, 32, 16, 2), seed=1), dtype="f32", max_res=14 * 64)
+    say("forward from grid: errors")
+    with pytest.raises(ConetError, match="ESHAPE"):
+        model.forward_grid(torch.zeros((1, 11, 8, 4, 2), dtype=torch.float32, device="cuda"))  # no symbol 11
+    with pytest.raises(ConetError, match="ESHAPE"):
+        model.forward_grid(torch.zeros((1, 14, 8, 5, 2), dtype=torch.float32, device="cuda"))  # 20 > C_in
+    with pytest.raises(ConetError, match="ESHAPE"):
+        model.forward_grid(torch.zeros((1, 14, 65, 4, 2), dtype=torch.float32, device="cuda"))  # > max_res
+    assert model.forward_grid(torch.zeros((0, 14, 8, 4, 2), dtype=torch.float32, device="cuda")).shape[0] == 0
+    model.close()
