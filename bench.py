@@ -465,9 +465,19 @@ def train_bench(args):
     n_data = int(dm.sum())
     llr = torch.empty((B, T, F, mc.m), dtype=torch.float32, device="cuda")
 
+    sim_bufs = None
+    counter = [0]
+
     def step():
+        nonlocal sim_bufs
+        if args.device_data:  # a fresh batch every step, generated and featurised on the GPU
+            from paper_2510_12739_amd import featurise, simulate
+            sim_bufs = simulate(F, w.sim.n_rx, mc.m, counter[0] * B, B, n_taps=w.sim.n_taps,
+                                max_doppler_hz=w.sim.max_doppler_hz, seed=w.sim.seed + 7000, out=sim_bufs)
+            counter[0] += 1
+            featurise(sim_bufs[0], mc.C_in, out=x)
         model.forward(x, out=llr, save=True)
-        loss, dllr = model.bce(llr, bt, dmt, n_data)
+        loss, dllr = model.bce(llr, sim_bufs[1] if args.device_data else bt, dmt, n_data)
         model.backward(dllr)
         model.adam_step(lr=1e-3)
         return loss
@@ -490,7 +500,9 @@ def train_bench(args):
     result = {"metric": "training REs/sec (forward + BCE + backward + Adam)", "value": round(res / (ms * 1e-3), 1),
               "unit": "REs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
-              "data": "synthetic (seeded OFDM simulator; He-normal weights; FP32 master + Adam)",
+              "data": ("synthetic, a fresh batch per step generated and featurised on the GPU (conet_simulate + "
+                       "conet_featurise, inside the timed step)" if args.device_data else
+                       "synthetic (seeded OFDM simulator, batch resident in HBM)") + "; He-normal weights; FP32 master + Adam",
               "config": {"workload": w.name, "slots": B, "T": T, "F": F, "K": mc.K, "L": mc.L, "C": mc.C,
                          "C_in": mc.C_in, "m": mc.m, "res_per_step": res, "parallelism": "single-gpu"},
               "loss_first_last": [round(float(losses[0].cpu()), 5), round(float(losses[-1].cpu()), 5)],
@@ -863,6 +875,8 @@ def main():
                     "featuriser or serving)")
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.1, 0.25, 0.5, 0.75, 1.0])
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--device-data", action="store_true",
+                    help="with --train: generate every step's batch on the GPU (conet_simulate), inside the timed step")
     ap.add_argument("--depth-latency", action="store_true",
                     help="only the depth-vs-latency experiment (CoNet K=2 L=6 vs ResNet K=1 L=11)")
     ap.add_argument("--copy-probe", type=int, default=0,

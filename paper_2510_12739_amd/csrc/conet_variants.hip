@@ -5,8 +5,9 @@
 // one branch for a tile of DS_TW subcarriers x all T symbols of one slot; h never leaves LDS:
 //   stage pre(x) over DS_TW + 4 columns (rounded to the operand type, zero outside the slot)
 //   -> depthwise 1 over DS_TW + 2 columns (VALU: FP32 sums of 9 products, rounded as the
-//      1x1 conv's operand) -> 1x1 conv 1 on MFMA -> bias, affine, ReLU, zero outside the
-//      slot = h -> depthwise 2 over DS_TW columns -> 1x1 conv 2 on MFMA -> + bias + x.
+//      1x1 conv's operand, formed in the registers that feed the MFMA) -> 1x1 conv 1 on MFMA
+//   -> bias, affine, ReLU, zero outside the slot = h (to LDS) -> depthwise 2 over DS_TW
+//      columns, again straight into the B fragments -> 1x1 conv 2 on MFMA -> + bias + x.
 // Per RE and branch the block reads and writes C activations (plus a 4-column halo) for
 // 2 (18 C + 2 C^2) FLOPs: 73 FLOP per HBM byte at C = 64 in BF16, far below the ratio of
 // the MI355X's BF16 MFMA rate to its HBM bandwidth, so the kernel is HBM-bound.
@@ -69,8 +70,8 @@ struct DsShape {
   static constexpr int PITCH = C * (int)sizeof(Op) + 16;  // bytes per staged position
   static constexpr int W0 = DS_TW + 4;                // columns of pre(x): the tile +- 2
   static constexpr int W1 = DS_TW + 2;                // columns of d1 and h: the tile +- 1
-  static constexpr int PRE = TMAX * W0 * PITCH;       // pre(x), later the second depthwise output
-  static constexpr int MID = TMAX * W1 * PITCH;       // d1, later h
+  static constexpr int PRE = TMAX * W0 * PITCH;       // pre(x)
+  static constexpr int MID = TMAX * W1 * PITCH;       // h
   static constexpr int LDS = PRE + MID;
   static constexpr int NSTAGE = (TMAX * W0 * CH + 255) / 256;  // staging items per thread
   static constexpr int NOT = C / 16;
@@ -99,66 +100,61 @@ __device__ __forceinline__ i32x4 f_to_chunk(const float* f) {
   return raw;
 }
 
-// Depthwise 3x3 over `n_cols` output columns: out column c reads in columns c .. c + 2 (the
-// input region is two columns wider); rows outside [0, T) read as zero. The work-group's 256
-// threads stride over (position, chunk) items by a multiple of the chunks per position, so a
-// thread always handles the same 16-byte channel chunk and keeps its 9 x VEC filter taps in
-// registers (filt: [tap][C] FP32 in global memory).
+// One separable conv over the n_cols-wide region of positions (t, col), t < T: the depthwise
+// 3x3 filter (output column col reads input columns col .. col + 2 of `in`, which is two
+// columns wider; rows outside [0, T) read as zero) feeds the 1x1 conv's B fragments straight
+// from registers -- each depthwise output is one lane's operand chunk and is used once -- so
+// it is never stored. Per K step s the lane's chunk is 4 s + l / 16; its 9 x VEC taps are
+// loaded once per step. acc[mt][ot] covers RE tiles wave + 4 mt (tiles past the region
+// compute position 0 and are discarded).
 template <class A, int C>
-__device__ __forceinline__ void depthwise(const uint8_t* in, int in_w, uint8_t* out, int n_cols,
-                                          const float* __restrict__ filt, int T) {
-  using S = DsShape<A, C>;
-  static_assert(256 % S::CH == 0, "a thread's chunk must not change between items");
-  const int c16 = threadIdx.x % S::CH;
-  float w[9][A::VEC];
-#pragma unroll
-  for (int tap = 0; tap < 9; ++tap)
-#pragma unroll
-    for (int j = 0; j < A::VEC; ++j) w[tap][j] = filt[tap * C + c16 * A::VEC + j];
-  for (int i = threadIdx.x; i < T * n_cols * S::CH; i += 256) {
-    const int pos = i / S::CH, col = pos % n_cols, t = pos / n_cols;
-    float acc[A::VEC];
-#pragma unroll
-    for (int j = 0; j < A::VEC; ++j) acc[j] = 0.f;
-#pragma unroll
-    for (int dt = -1; dt <= 1; ++dt) {
-      const int tt = t + dt;
-      if (tt < 0 || tt >= T) continue;
-#pragma unroll
-      for (int df = 0; df < 3; ++df) {
-        float v[A::VEC];
-        chunk_to_f<A>(*reinterpret_cast<const i32x4*>(in + (tt * in_w + col + df) * S::PITCH + c16 * 16), v);
-#pragma unroll
-        for (int j = 0; j < A::VEC; ++j) acc[j] = fmaf(w[(dt + 1) * 3 + df][j], v[j], acc[j]);
-      }
-    }
-    *reinterpret_cast<i32x4*>(out + (t * n_cols + col) * S::PITCH + c16 * 16) = f_to_chunk<A>(acc);
-  }
-}
-
-// 1x1 conv of the n_pos staged positions of `in` (PITCH apart): acc[mt][ot] for the RE tiles
-// wave + 4 mt. Tiles past n_pos read position 0 (their results are discarded).
-template <class A, int C>
-__device__ __forceinline__ void pointwise(typename DsShape<A, C>::AccTile& acc, const uint8_t* in, int n_pos,
+__device__ __forceinline__ void separable(typename DsShape<A, C>::AccTile& acc, const uint8_t* in, int in_w,
+                                          int n_cols, int T, const float* __restrict__ dw,
                                           const i32x4* __restrict__ wp) {
   using S = DsShape<A, C>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
-  i32x4 a[S::NS][S::NOT];
-#pragma unroll
-  for (int s = 0; s < S::NS; ++s)
-#pragma unroll
-    for (int ot = 0; ot < S::NOT; ++ot) a[s][ot] = wp[(s * S::NOT + ot) * 64 + lane];
+  const int n_pos = T * n_cols;
+  int tt0[S::MT], cc0[S::MT];
 #pragma unroll
   for (int mt = 0; mt < S::MT; ++mt) {
-#pragma unroll
-    for (int ot = 0; ot < S::NOT; ++ot) acc[mt][ot] = typename A::AccV{0.f, 0.f, 0.f, 0.f};
     int pos = (wave + 4 * mt) * 16 + (lane & 15);
     if (pos >= n_pos) pos = 0;
+    tt0[mt] = pos / n_cols;
+    cc0[mt] = pos - tt0[mt] * n_cols;
 #pragma unroll
-    for (int s = 0; s < S::NS; ++s) {
-      const i32x4 b = *reinterpret_cast<const i32x4*>(in + pos * S::PITCH + (4 * s + g) * 16);
+    for (int ot = 0; ot < S::NOT; ++ot) acc[mt][ot] = typename A::AccV{0.f, 0.f, 0.f, 0.f};
+  }
 #pragma unroll
-      for (int ot = 0; ot < S::NOT; ++ot) acc[mt][ot] = A::mma(&a[s][ot], &b, acc[mt][ot]);
+  for (int s = 0; s < S::NS; ++s) {
+    const int chunk = 4 * s + g;
+    i32x4 a[S::NOT];
+#pragma unroll
+    for (int ot = 0; ot < S::NOT; ++ot) a[ot] = wp[(s * S::NOT + ot) * 64 + lane];
+    float w[9][A::VEC];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+      for (int j = 0; j < A::VEC; ++j) w[tap][j] = dw[tap * C + chunk * A::VEC + j];
+#pragma unroll
+    for (int mt = 0; mt < S::MT; ++mt) {
+      float d[A::VEC];
+#pragma unroll
+      for (int j = 0; j < A::VEC; ++j) d[j] = 0.f;
+#pragma unroll
+      for (int dt = -1; dt <= 1; ++dt) {
+        const int tt = tt0[mt] + dt;
+        if (tt < 0 || tt >= T) continue;
+#pragma unroll
+        for (int df = 0; df < 3; ++df) {
+          float v[A::VEC];
+          chunk_to_f<A>(*reinterpret_cast<const i32x4*>(in + (tt * in_w + cc0[mt] + df) * S::PITCH + chunk * 16), v);
+#pragma unroll
+          for (int j = 0; j < A::VEC; ++j) d[j] = fmaf(w[(dt + 1) * 3 + df][j], v[j], d[j]);
+        }
+      }
+      const i32x4 b = f_to_chunk<A>(d);  // the 1x1 conv's operand, rounded
+#pragma unroll
+      for (int ot = 0; ot < S::NOT; ++ot) acc[mt][ot] = A::mma(&a[ot], &b, acc[mt][ot]);
     }
   }
 }
@@ -173,8 +169,9 @@ __device__ __forceinline__ TileDesc ds_tile(const DsArgs& a, int bid) {
   return d;
 }
 
+// two work-groups per CU where the LDS allows it (not at C = 64 in FP32: 149 KB)
 template <class A, int C>
-__global__ void __launch_bounds__(256, 2) ds_block_kernel(DsArgs args) {
+__global__ void __launch_bounds__(256, (DsShape<A, C>::LDS <= 80 * 1024 ? 2 : 1)) ds_block_kernel(DsArgs args) {
   using S = DsShape<A, C>;
   using Op = typename A::Op;
   __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS];
@@ -225,12 +222,9 @@ __global__ void __launch_bounds__(256, 2) ds_block_kernel(DsArgs args) {
     }
   }
   __syncthreads();
-  depthwise<A, C>(pre, S::W0, mid, S::W1, args.dw1[k], T);
-  __syncthreads();
 
   typename S::AccTile acc;
-  pointwise<A, C>(acc, mid, T * S::W1, reinterpret_cast<const i32x4*>(args.pw1[k]));
-  __syncthreads();  // every wave has read d1: h may overwrite it
+  separable<A, C>(acc, pre, S::W0, S::W1, T, args.dw1[k], reinterpret_cast<const i32x4*>(args.pw1[k]));
   {
     const float* b1 = args.b1[k];
     const float* s1 = args.post_s[k];
@@ -258,9 +252,7 @@ __global__ void __launch_bounds__(256, 2) ds_block_kernel(DsArgs args) {
     }
   }
   __syncthreads();
-  depthwise<A, C>(mid, S::W1, pre, DS_TW, args.dw2[k], T);
-  __syncthreads();
-  pointwise<A, C>(acc, pre, T * DS_TW, reinterpret_cast<const i32x4*>(args.pw2[k]));
+  separable<A, C>(acc, mid, S::W1, DS_TW, T, args.dw2[k], reinterpret_cast<const i32x4*>(args.pw2[k]));
   {
     const float* b2 = args.b2[k];
     const bool f32 = args.out_f32[k] != 0;
