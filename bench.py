@@ -636,10 +636,25 @@ def c1_latency(calls=100, warmup=10):
         e1.record(stream)
         torch.cuda.synchronize()
         lat.append(e0.elapsed_time(e1) * 1e3)
+    # the same forward recorded once as a HIP graph and replayed with one launch
+    g = model.record(x, out)
+    for _ in range(warmup):
+        g.launch()
+    torch.cuda.synchronize()
+    lat_g = []
+    for _ in range(calls):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        lat_g.append(e0.elapsed_time(e1) * 1e3)
+    g.close()
     model.close()
-    return {"workload": w.name, "dtype": "f32", "calls": calls,
-            "latency_us": {"p10": round(float(np.percentile(lat, 10)), 1), "p50": round(float(np.median(lat)), 1),
-                           "p90": round(float(np.percentile(lat, 90)), 1)}}
+    q = lambda v: {"p10": round(float(np.percentile(v, 10)), 1), "p50": round(float(np.median(v)), 1),
+                   "p90": round(float(np.percentile(v, 90)), 1)}
+    return {"workload": w.name, "dtype": "f32", "calls": calls, "latency_us": q(lat),
+            "latency_us_recorded_graph": q(lat_g)}
 
 
 def snr_at(snr, ber, target):
@@ -655,7 +670,7 @@ def snr_at(snr, ber, target):
 def ber_leg(wl, dtypes):
     """BER against SNR of the trained network at each GPU precision on the slots whose FP64 BER
     tests/golden/ber_<wl>.json holds (common random numbers), and the horizontal gap to the FP64
-    curve at BER 1e-3 (1e-2 if the FP64 curve does not reach 1e-3)."""
+    curve at BER 1e-3 (else the lowest of 1e-2, 1e-1 that the FP64 curve reaches)."""
     import torch
     from paper_2510_12739_amd import Conet
     from synth import SimConfig, simulate_slot, workload
@@ -681,7 +696,7 @@ def ber_leg(wl, dtypes):
     bits = np.stack(bits).reshape(len(snr), n_sl, T, F, mc.m)
     mask = np.broadcast_to(data_mask(T, F)[None, None, :, :, None], bits.shape)
     ber64 = np.array([r["errors_fp64"] / r["bits"] for r in g["points"]])
-    target = 1e-3 if ber64.min() <= 1e-3 else 1e-2
+    target = next(v for v in (1e-3, 1e-2, 1e-1, 2e-1) if ber64.min() <= v)  # the lowest the FP64 curve reaches
     s64 = snr_at(snr, ber64, target)
     out = {"workload": wl, "weights": g["weights"], "slots": f"{len(snr)} SNR points x {n_sl} slots of {T}x{F} REs",
            "target_ber": target, "snr_db_at_target": {"fp64": s64}, "delta_db": {}, "ber": {"snr_db": snr,

@@ -221,6 +221,22 @@ conet_status conet_featurise(const float* y, int32_t B, int32_t T, int32_t F, in
 conet_status conet_forward_grid(conet_model* model, const float* y, int32_t B, int32_t T, int32_t F, int32_t n_rx,
                                 float* llr, void* stream);
 
+/* ---------------------------------------------------------------- recorded forward
+ * A forward of fixed shape and buffers recorded once as a HIP graph and replayed with one
+ * launch: at a batch of one slot the device otherwise waits for the host between the
+ * forward's dependent kernels. conet_graph_create records conet_forward(model, x, B, T, F,
+ * llr) (uniform batch, no save) on a private stream without running it; each
+ * conet_graph_launch on `stream` then computes llr from the current contents of x, exactly
+ * as conet_forward would. x, llr and the model must outlive the graph; replays of one graph
+ * (or of graphs of one model) must not overlap in time: they share the model's activation
+ * buffers. Errors: EINVAL (null arguments), ESHAPE (as conet_forward), ESTATE (FP8 model
+ * without activation scales), EDEVICE. */
+typedef struct conet_graph conet_graph;
+conet_status conet_graph_create(conet_model* model, const float* x, int32_t B, int32_t T, int32_t F, float* llr,
+                                conet_graph** out);
+conet_status conet_graph_launch(conet_graph* graph, void* stream);
+conet_status conet_graph_destroy(conet_graph* graph);
+
 /* conet_featurise plus the known noise and interference variances of each slot, which the
  * receiver's input also carries (Sec. II-A concatenates them with the received grid):
  * variances: device FP32 [B][2] = (sigma_n^2, sigma_i^2) per slot. Channels C_in - 8 ..

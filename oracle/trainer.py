@@ -36,11 +36,36 @@ import torch.nn.functional as Fn
 from . import conet64 as o
 
 
-class TorchConet(torch.nn.Module):
-    """CoNet with its parameters held as torch tensors in the blob's structure."""
+def _ste(x: torch.Tensor, q: torch.Tensor) -> torch.Tensor:
+    """q in the forward, the identity's gradient in the backward (straight-through)."""
+    return x + (q - x).detach()
 
-    def __init__(self, p: Dict, fuse_mask: Optional[int] = None, dtype=torch.float32):
+
+def fq_e4m3(x: torch.Tensor, per_channel: bool = False) -> torch.Tensor:
+    """Fake e4m3 quantisation of a conv operand (per tensor) or filter (per output channel):
+    scale amax / 448, saturating round to nearest even onto e4m3, rescaled."""
+    a = x.detach().abs()
+    amax = a.flatten(1).amax(dim=1).view(-1, *([1] * (x.dim() - 1))) if per_channel else a.amax()
+    s = torch.where(amax > 0, amax / o.E4M3_MAX, torch.ones_like(amax))
+    q = (x / s).clamp(-o.E4M3_MAX, o.E4M3_MAX).to(torch.float8_e4m3fn).to(x.dtype) * s
+    return _ste(x, q)
+
+
+def fq_bf16(x: torch.Tensor) -> torch.Tensor:
+    return _ste(x, x.to(torch.bfloat16).to(x.dtype))
+
+
+class TorchConet(torch.nn.Module):
+    """CoNet with its parameters held as torch tensors in the blob's structure.
+
+    fake_quant="fp8": the forward applies the FP8 contract's roundings (conv operands per
+    tensor and filters per output channel onto e4m3, stored block outputs to BF16) with
+    straight-through gradients, for fine-tuning a network that will run in FP8 (activation
+    scales here come from each batch; deployment calibrates static ones)."""
+
+    def __init__(self, p: Dict, fuse_mask: Optional[int] = None, dtype=torch.float32, fake_quant: Optional[str] = None):
         super().__init__()
+        self.fq = fake_quant
         self.K, self.L, self.C = p["K"], p["L"], p["C"]
         self.mask = ((1 << self.L) - 1) if fuse_mask is None else int(fuse_mask)
         P = lambda a: torch.nn.Parameter(torch.tensor(np.asarray(a), dtype=dtype))
@@ -62,27 +87,32 @@ class TorchConet(torch.nn.Module):
     def forward(self, X: torch.Tensor) -> torch.Tensor:
         """X: (B, T, F, C_in) -> LLR (B, T, F, m)."""
         ch = lambda v: v[None, :, None, None]
+        fq = self.fq == "fp8"
+        conv = (lambda z, W, bias: Fn.conv2d(fq_e4m3(z), fq_e4m3(W, True), bias, padding=1)) if fq else \
+            (lambda z, W, bias: Fn.conv2d(z, W, bias, padding=1))
+        st = fq_bf16 if fq else (lambda z: z)
         x = X.permute(0, 3, 1, 2)
-        a = [torch.relu(Fn.conv2d(x, self.W_in[k], self.b_in[k], padding=1)) for k in range(self.K)]
+        a = [st(torch.relu(conv(x, self.W_in[k], self.b_in[k]))) for k in range(self.K)]
         fused_prev = False
         for l in range(self.L):
             outs = []
+            last = l == self.L - 1
             for k in range(self.K):
                 b = lambda n: self._b(k, l, n)
                 pre = torch.relu(a[k]) if (k == 0 and fused_prev) else torch.relu(ch(b("s0")) * a[k] + ch(b("o0")))
-                h = torch.relu(ch(b("s1")) * Fn.conv2d(pre, b("W1"), b("b1"), padding=1) + ch(b("o1")))
-                outs.append(a[k] + Fn.conv2d(h, b("W2"), b("b2"), padding=1))
+                h = torch.relu(ch(b("s1")) * conv(pre, b("W1"), b("b1")) + ch(b("o1")))
+                outs.append(a[k] + conv(h, b("W2"), b("b2")))
             fused = bool((self.mask >> l) & 1)
             if fused:
                 P = outs[0]
                 for k in range(1, self.K):
-                    P = P * outs[k]
+                    P = P * st(outs[k])
                 mu = P.mean(dim=1, keepdim=True)
                 var = ((P - mu) ** 2).mean(dim=1, keepdim=True)
                 A = ch(self.gamma[l]) * (P - mu) / torch.sqrt(var + o.LN_EPS) + ch(self.beta[l])
-                a = [A] + outs[1:]
+                a = [A if last else st(A)] + [st(v) for v in outs[1:]]
             else:
-                a = outs
+                a = [outs[0] if last else st(outs[0])] + [st(v) for v in outs[1:]]
             fused_prev = fused
         return torch.einsum("bctf,mc->btfm", a[0], self.W_h) + self.b_h
 
@@ -129,7 +159,7 @@ def _make_batch(args):
 def train(p0: Dict, sim_kwargs: Dict, steps: int, batch: int, out_path: str, lr: float = 1e-3,
           lr_final: float = 1e-5, clip: float = 1.0, threads: int = 6, workers: int = 2,
           save_every: int = 200, log_every: int = 50, max_seconds: Optional[float] = None,
-          first_slot: int = 0) -> np.ndarray:
+          first_slot: int = 0, fake_quant: Optional[str] = None) -> np.ndarray:
     """Train from parameters p0 (conet64.unpack form) on simulator batches.
 
     sim_kwargs: synth.SimConfig fields of the training data (its seed must differ from
@@ -139,13 +169,13 @@ def train(p0: Dict, sim_kwargs: Dict, steps: int, batch: int, out_path: str, lr:
     """
     torch.set_num_threads(threads)
     torch.manual_seed(0)
-    net = TorchConet(p0)
+    net = TorchConet(p0, fake_quant=fake_quant)
     opt = torch.optim.Adam(net.parameters(), lr=lr, betas=(0.9, 0.999), eps=1e-8)
     from synth import data_mask as dmask
     T = sim_kwargs.get("T", 14)
     dm = torch.from_numpy(dmask(T, sim_kwargs["F"]))
     log = {"sim": sim_kwargs, "steps": steps, "batch": batch, "lr": lr, "lr_final": lr_final, "clip": clip,
-           "first_slot": first_slot, "loss": []}
+           "first_slot": first_slot, "fake_quant": fake_quant, "loss": []}
     t0 = time.time()
     ctx = mp.get_context("fork")
     with ctx.Pool(workers, initializer=_init_worker, initargs=(sim_kwargs,)) as pool:

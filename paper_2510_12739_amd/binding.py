@@ -24,6 +24,7 @@ EXPORTS = ("conet_weight_count", "conet_workspace_bytes", "conet_create", "conet
            "conet_calibrate", "conet_get_act_scales", "conet_forward", "conet_forward_ragged", "conet_forward_profiled",
            "conet_forward_noalloc", "conet_forward_noalloc_capacity", "conet_forward_grid",
            "conet_block_tile_width", "conet_mfma_peak", "conet_mfma_dot", "conet_featurise", "conet_featurise_var", "conet_simulate",
+           "conet_graph_create", "conet_graph_launch", "conet_graph_destroy",
            "conet_serve_create", "conet_serve_submit", "conet_serve_wait", "conet_serve_get_stats",
            "conet_serve_reset_stats", "conet_serve_pause", "conet_serve_destroy", "conet_backward", "conet_grads",
            "conet_master_weights", "conet_adam_step", "conet_get_weights", "conet_save_train_state",
@@ -105,6 +106,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.conet_forward_grid.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp]; lib.conet_forward_grid.restype = i32
     lib.conet_simulate.argtypes = [ctypes.POINTER(conet_sim_config), ctypes.c_int64, i32, vp, vp, vp, vp]
     lib.conet_simulate.restype = i32
+    lib.conet_graph_create.argtypes = [vp, vp, i32, i32, i32, vp, ctypes.POINTER(vp)]
+    lib.conet_graph_create.restype = i32
+    lib.conet_graph_launch.argtypes = [vp, vp]; lib.conet_graph_launch.restype = i32
+    lib.conet_graph_destroy.argtypes = [vp]; lib.conet_graph_destroy.restype = i32
     lib.conet_featurise_var.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]; lib.conet_featurise_var.restype = i32
     lib.conet_serve_create.argtypes = [vp, sz, i32, i32, i32, ctypes.POINTER(vp)]
     lib.conet_serve_create.restype = i32
@@ -348,6 +353,16 @@ class Conet:
                                            ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
+    def record(self, x, out):
+        """conet_graph_create: the forward of x into out recorded as a HIP graph; returns a
+        ForwardGraph whose launch() recomputes out from x's current contents."""
+        self._check_x(x)
+        B, T, F, _ = x.shape
+        h = ctypes.c_void_p()
+        _check(self.lib.conet_graph_create(self.handle, ctypes.c_void_p(x.data_ptr()), B, T, F,
+                                           ctypes.c_void_p(out.data_ptr()), ctypes.byref(h)))
+        return ForwardGraph(self, h, x, out)
+
     def forward_ragged(self, x_packed, T: int, F_list: Sequence[int], out=None, stream=None):
         """Slots of different widths packed back to back: x_packed [sum T*F_s, C_in]."""
         import torch
@@ -379,6 +394,28 @@ def pinned_array(shape, dtype=np.float32) -> np.ndarray:
     tdt = {np.dtype(np.float32): torch.float32, np.dtype(np.uint8): torch.uint8}[np.dtype(dtype)]
     n = int(np.prod(shape))
     return torch.zeros(n, dtype=tdt, pin_memory=True).numpy().reshape(shape)
+
+
+class ForwardGraph:
+    """A recorded forward (conet_graph_*): keeps its model and buffers alive."""
+
+    def __init__(self, model, handle, x, out):
+        self.model, self.handle, self.x, self.out = model, handle, x, out
+
+    def launch(self, stream=None):
+        _check(self.model.lib.conet_graph_launch(self.handle, _stream_ptr(stream)))
+        return self.out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.model.lib.conet_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

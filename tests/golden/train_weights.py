@@ -37,6 +37,8 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--resume", action="store_true",
                     help="start from the blob already written (fresh Adam state, training slots after those used)")
+    ap.add_argument("--fake-quant", default=None, choices=["fp8"],
+                    help="fine-tune with the FP8 contract's roundings in the forward (straight-through)")
     args = ap.parse_args()
     w = workload(args.workload)
     mc = w.model
@@ -52,7 +54,8 @@ def main():
         prev = json.load(open(os.path.splitext(out)[0] + ".json"))
         first = prev.get("first_slot", 0) + prev["steps_done"] * prev["batch"]
     trainer.train(p0, sim, steps=args.steps, batch=args.batch, out_path=out, lr=args.lr,
-                  threads=args.threads, workers=args.workers, max_seconds=args.minutes * 60.0, first_slot=first)
+                  threads=args.threads, workers=args.workers, max_seconds=args.minutes * 60.0, first_slot=first,
+                  fake_quant=args.fake_quant)
     print("wrote", out)
 
 

@@ -3,7 +3,9 @@
 The paper's claims are BER-vs-SNR comparisons (Sec. IV, Figs. 6-8), so the precision bar is
 stated the same way: the horizontal gap, in dB at a target BER, between the BER curve of the
 GPU forward at a precision and the FP64 oracle's curve of the same trained network on the same
-slots (common random numbers). Target BER: 1e-3 if the FP64 curve reaches it, else 1e-2;
+slots (common random numbers). Target BER: the lowest of 1e-3, 1e-2, 1e-1 that the FP64 curve
+reaches (the 256-QAM network trained for 85 CPU-minutes floors near 8e-2, so its gap is taken
+at 1e-1, on the steep part of its curve);
 curves are interpolated linearly in log10 BER over a 1 dB SNR grid. Bar: |gap| <= 0.1 dB.
 
 The FP64 curve is stored (tests/golden/ber_<workload>.json, written by
@@ -74,7 +76,7 @@ def test_ber_delta_vs_fp64(wl, dtypes):
     e64 = int(((cl.hard_bits(llr64) != bits[sl]) & mask[sl]).sum())
     say(f"BER {wl}: FP64 point {snr[i0]:+.0f} dB recomputed {e64} errors, stored {g['points'][i0]['errors_fp64']}")
     assert e64 == g["points"][i0]["errors_fp64"]
-    target = 1e-3 if ber64.min() <= 1e-3 else 1e-2
+    target = next(v for v in (1e-3, 1e-2, 1e-1) if ber64.min() <= v)  # the lowest the FP64 curve reaches
     assert ber64.max() >= target >= ber64.min(), "the FP64 curve does not cross the target BER"
     x = torch.from_numpy(X).cuda()
     for dt in dtypes:
