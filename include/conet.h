@@ -54,7 +54,7 @@ typedef enum {
   CONET_BF16 = 1,     /* BF16 operands and activations, FP32 accumulation and epilogues */
   CONET_FP8E4M3 = 2,  /* OCP e4m3 conv operands (per-output-channel filter scales, static
                          per-tensor activation scales), BF16 residual stream, FP32 accumulation */
-  CONET_FP64 = 3      /* reserved (not accepted by conet_create) */
+  CONET_FP64 = 3      /* not accepted by conet_create: no FP64 build of the kernels */
 } conet_dtype;
 
 typedef struct {

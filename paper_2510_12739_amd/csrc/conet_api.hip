@@ -65,8 +65,7 @@ static OpFmt op_fmt(int dtype) {
   switch (dtype) {
     case DT_F32: return {4, 1, 4};
     case DT_BF16: return {8, 1, 2};
-    case DT_FP8: return {16, 2, 1};
-    default: return {2, 1, 8};
+    default: return {16, 2, 1};  // DT_FP8
   }
 }
 
@@ -108,8 +107,7 @@ void pack_filter(int dtype, int cin, int cout, const float* W, uint8_t* dst, flo
             switch (dtype) {
               case DT_F32: memcpy(out + 4 * e, &w, 4); break;
               case DT_BF16: { uint16_t b = bf16_bits(w); memcpy(out + 2 * e, &b, 2); } break;
-              case DT_FP8: out[e] = e4m3_bits(w / sc[o]); break;
-              default: { double d = w; memcpy(out + 8 * e, &d, 8); } break;
+              default: out[e] = e4m3_bits(w / sc[o]); break;  // DT_FP8
             }
           }
         }

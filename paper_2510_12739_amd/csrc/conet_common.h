@@ -13,7 +13,6 @@ namespace conet {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -27,7 +26,6 @@ typedef uint8_t fp8;             // OCP e4m3fn bit pattern
 
 // ---------------------------------------------------------------- scalar converts
 __device__ __forceinline__ float to_f(float v) { return v; }
-__device__ __forceinline__ float to_f(double v) { return (float)v; }
 __device__ __forceinline__ float to_f(__bf16 v) { return (float)v; }
 
 // RNE float -> bf16 (the hardware conversion rounds to nearest even).
@@ -81,19 +79,6 @@ struct ArithFP8 {
 #pragma unroll
     for (int i = 0; i < 4; ++i) { av[i] = a[0][i]; av[4 + i] = a[1][i]; bv[i] = b[0][i]; bv[4 + i] = b[1][i]; }
     return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, c, 0, 0, 0, 0, 0, 0);
-  }
-};
-
-struct ArithF64 {
-  using Op = double; using Acc = double; using AccV = f64x4; using Act = double; using Hid = double;
-  static constexpr int VEC = 2, CPL = 1;
-  static constexpr bool QUANT = false;
-  __device__ __forceinline__ static AccV mma(const i32x4* a, const i32x4* b, AccV c) {
-    const double* da = reinterpret_cast<const double*>(a);
-    const double* db = reinterpret_cast<const double*>(b);
-    c = __builtin_amdgcn_mfma_f64_16x16x4f64(da[0], db[0], c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f64_16x16x4f64(da[1], db[1], c, 0, 0, 0);
-    return c;
   }
 };
 

@@ -5,7 +5,7 @@
 
 namespace conet {
 
-enum { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2, DT_F64 = 3 };
+enum { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2 };
 constexpr int KMAX_ARGS = 8;
 constexpr int CONV_NW = 4;  // waves per work-group of the conv kernels
 
