@@ -14,7 +14,10 @@ on the same slots (common random numbers). This script evaluates the FP64 side o
     point averages many channel realisations; slot s of point i is slot i * 1000 + s of
     the evaluation seed 2000 + the workload's simulator seed (training used 1000 + it);
   * per point: data bits, bit errors of the FP64 network, and for context the errors of
-    the classical receiver (MRC + max-log) with the LS-interpolated and the true channel.
+    the classical receiver (MRC + max-log) with the LS-interpolated and the true channel;
+    with --fp8-contract also those of the oracle's FP8 emulation (the FP8 precision
+    contract with static activation scales), which separates what the number format
+    costs from what the GPU kernels add.
 
 Writes tests/golden/ber_<workload>.json.
 """
@@ -52,6 +55,9 @@ def main():
     ap.add_argument("workload")
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--F", type=int, default=288)
+    ap.add_argument("--fp8-contract", action="store_true",
+                    help="also count the errors of the oracle's FP8 emulation (the precision contract alone), "
+                         "with static scales calibrated on the slots the GPU test calibrates on")
     args = ap.parse_args()
     wl = args.workload
     w = workload(wl)
@@ -59,6 +65,11 @@ def main():
     blob = np.load(os.path.join(HERE, f"trained_{wl}.npy"))
     p = o.unpack(blob.astype(np.float32), mc.K, mc.L, mc.C, mc.C_in, mc.m)
     dm = data_mask(w.sim.T, args.F)
+    q8 = None
+    if args.fp8_contract:
+        from synth import features_fast
+        cal = features_fast(SimConfig(**{**w.sim.__dict__, "F": args.F}), 8).astype(np.float64)
+        q8 = o.Quant("fp8", o.calibrate(p, cal))
     rows = []
     t0 = time.time()
     for i, snr in enumerate(SNR_GRID[wl]):
@@ -79,7 +90,10 @@ def main():
                     e_ls += e
                 else:
                     e_pc += e
-        rows.append({"snr_db": snr, "bits": n_bits, "errors_fp64": err, "errors_mrc_ls": e_ls, "errors_mrc_true_h": e_pc})
+        row = {"snr_db": snr, "bits": n_bits, "errors_fp64": err, "errors_mrc_ls": e_ls, "errors_mrc_true_h": e_pc}
+        if q8 is not None:
+            row["errors_fp8_contract"] = int(((cl.hard_bits(o.forward(p, X, quant=q8)) != bits) & mask).sum())
+        rows.append(row)
         print(f"{wl} SNR {snr:+d} dB: BER fp64 {err / n_bits:.3e}, MRC-LS {e_ls / n_bits:.3e}, "
               f"MRC-true {e_pc / n_bits:.3e} ({time.time() - t0:.0f} s)", flush=True)
     out = {"workload": wl, "weights": f"trained_{wl}.npy", "F": args.F, "slots_per_point": args.slots,
