@@ -146,6 +146,51 @@ def test_fp32_gradient_vs_finite_differences_of_gpu_forward():
     assert abs(fd - an) <= 2e-3 * max(1.0, abs(an)), (fd, an)
 
 
+@pytest.mark.parametrize("group", ["input_layer", "block1_conv1", "block1_affines", "block1_conv2", "norm1", "head"])
+def test_fp32_gradient_vs_fp64_finite_differences_every_parameter_group(group):
+    """The GPU backward against central differences of the network itself, along a random
+    direction over one parameter group at a time (every branch's input layer, the first
+    block's convs and affines, the first fusion's norm, the head; K=2, L=2, C=16 on a 24 x 14
+    grid). The differences are taken on the FP64 forward (the oracle's forward only, not its
+    backward) at h = 1e-6 of the group's scale, where no ReLU kink is crossed in practice and FP64
+    round-off is ~1e-10 of the result, so they stand for the exact directional derivative; the
+    FP32 GPU gradient must match it within 1e-4 relative (its own accumulation error). The
+    FP32 forward cannot be differenced this finely: its round-off swamps h, and a larger h
+    crosses kinks."""
+    mc = ModelConfig(2, 2, 16, 16, 2)
+    blob = make_blob(mc, seed=64, perturb=True).astype(np.float32).astype(np.float64)
+    X = features(SimConfig(F=24, n_rx=4, bits_per_symbol=2, seed=10), 1)
+    d = np.random.default_rng(65).standard_normal((1, 14, 24, 2))
+    rng = np.random.default_rng(66)
+    sel = {
+        "input_layer": lambda n: n.endswith(".W_in") or n.endswith(".b_in"),
+        "block1_conv1": lambda n: ".l1.W1" in n or ".l1.b1" in n,
+        "block1_affines": lambda n: any(f".l1.{a}" in n for a in ("s0", "o0", "s1", "o1")),
+        "block1_conv2": lambda n: ".l1.W2" in n or ".l1.b2" in n,
+        "norm1": lambda n: n in ("l1.gamma", "l1.beta"),
+        "head": lambda n: n in ("W_h", "b_h"),
+    }[group]
+    v = np.zeros(blob.size)
+    off = 0
+    for name, shape in blob_layout(mc):
+        n = int(np.prod(shape))
+        if sel(name):
+            v[off:off + n] = rng.standard_normal(n) * max(1e-2, float(np.abs(blob[off:off + n]).mean()))
+        off += n
+    assert np.any(v != 0)
+    say(f"fp32 gradient vs fp64 finite differences, group {group}")
+    _, g = _gpu_grad(_model(mc, blob.astype(np.float32), "f32"), X, d)
+    X64 = X.astype(np.float64)
+
+    def f(bl):
+        return float(np.sum(o.forward(o.unpack(bl, mc.K, mc.L, mc.C, mc.C_in, mc.m), X64) * d))
+    h = 1e-6
+    fd = (f(blob + h * v) - f(blob - h * v)) / (2 * h)
+    an = float(g @ v)
+    say(f"  central difference (FP64) {fd:.7f}, GPU backward {an:.7f}")
+    assert abs(fd - an) <= 1e-4 * abs(an) + 1e-6, (group, fd, an)
+
+
 def test_bce_matches_oracle():
     mc = ModelConfig(1, 1, 16, 16, 4)
     model = _model(mc, make_blob(mc, seed=1), "f32")
