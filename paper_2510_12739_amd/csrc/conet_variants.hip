@@ -253,30 +253,59 @@ __global__ void __launch_bounds__(256, (DsShape<A, C>::LDS <= 80 * 1024 ? 2 : 1)
   }
   __syncthreads();
   separable<A, C>(acc, mid, S::W1, DS_TW, T, args.dw2[k], reinterpret_cast<const i32x4*>(args.pw2[k]));
+  // Epilogue through LDS: conv 2 + bias goes to an FP32 tile [position][C] (every wave has read
+  // h, so the LDS is free), then each thread adds x and stores 8 consecutive channels of one
+  // RE, so the residual reads and the output writes are contiguous 16-byte accesses.
+  constexpr int OP = C * 4 + 16;
+  static_assert(TMAX * DS_TW * OP <= S::LDS, "output tile must fit the LDS");
+  __syncthreads();
   {
     const float* b2 = args.b2[k];
-    const bool f32 = args.out_f32[k] != 0;
 #pragma unroll
     for (int mt = 0; mt < S::MT; ++mt) {
       const int pos = (wave + 4 * mt) * 16 + (lane & 15);
       if (pos >= T * DS_TW) continue;
-      const int t = pos / DS_TW, f = td.f0 + pos % DS_TW;
-      if (f >= td.F) continue;
-      const int64_t re = td.re_base + (int64_t)t * td.F + f;
 #pragma unroll
       for (int ot = 0; ot < S::NOT; ++ot) {
         const int o0 = 16 * ot + 4 * g;
-        float v[4];
+        *reinterpret_cast<float4*>(lds + pos * OP + o0 * 4) =
+            make_float4(acc[mt][ot][0] + b2[o0], acc[mt][ot][1] + b2[o0 + 1], acc[mt][ot][2] + b2[o0 + 2],
+                        acc[mt][ot][3] + b2[o0 + 3]);
+      }
+    }
+  }
+  __syncthreads();
+  {
+    constexpr int C8 = C / 8;
+    const bool f32 = args.out_f32[k] != 0;
+    for (int i = threadIdx.x; i < T * DS_TW * C8; i += 256) {
+      const int pos = i / C8, c0 = (i - pos * C8) * 8;
+      const int t = pos / DS_TW, f = td.f0 + pos % DS_TW;
+      if (f >= td.F) continue;
+      const int64_t re = td.re_base + (int64_t)t * td.F + f;
+      const float4 lo = *reinterpret_cast<const float4*>(lds + pos * OP + c0 * 4);
+      const float4 hi = *reinterpret_cast<const float4*>(lds + pos * OP + c0 * 4 + 16);
+      float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+      const i32x4* xp = reinterpret_cast<const i32x4*>(x + re * C + c0);
+      float xv[8];
+      if constexpr (sizeof(Op) == 2) {
+        chunk_to_f<A>(xp[0], xv);
+      } else {
+        chunk_to_f<A>(xp[0], xv);
+        chunk_to_f<A>(xp[1], xv + 4);
+      }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = acc[mt][ot][q] + b2[o0 + q] + (float)x[re * C + o0 + q];
-        if (f32) {
-          *reinterpret_cast<float4*>(reinterpret_cast<float*>(args.out[k]) + re * C + o0) =
-              make_float4(v[0], v[1], v[2], v[3]);
-        } else {
-          Op* dst = reinterpret_cast<Op*>(args.out[k]) + re * C + o0;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) dst[q] = (Op)v[q];
-        }
+      for (int j = 0; j < 8; ++j) v[j] += xv[j];
+      if (f32) {
+        float4* dst = reinterpret_cast<float4*>(reinterpret_cast<float*>(args.out[k]) + re * C + c0);
+        dst[0] = make_float4(v[0], v[1], v[2], v[3]);
+        dst[1] = make_float4(v[4], v[5], v[6], v[7]);
+      } else if constexpr (sizeof(Op) == 2) {
+        *reinterpret_cast<i32x4*>(reinterpret_cast<Op*>(args.out[k]) + re * C + c0) = f_to_chunk<A>(v);
+      } else {
+        i32x4* dst = reinterpret_cast<i32x4*>(reinterpret_cast<Op*>(args.out[k]) + re * C + c0);
+        dst[0] = f_to_chunk<A>(v);
+        dst[1] = f_to_chunk<A>(v + 4);
       }
     }
   }
