@@ -686,8 +686,7 @@ def ber_leg(wl, dtypes):
     F, n_sl, T = g["F"], g["slots_per_point"], g["T"]
     X, bits = [], []
     for i, v in enumerate(snr):
-        sim = SimConfig(F=F, n_rx=s0.n_rx, bits_per_symbol=s0.bits_per_symbol, n_taps=s0.n_taps,
-                        max_doppler_hz=s0.max_doppler_hz, snr_db=float(v), seed=g["sim_seed"])
+        sim = SimConfig(**{**s0.__dict__, "F": F, "snr_db": float(v), "seed": g["sim_seed"]})
         for s in range(n_sl):
             sl = simulate_slot(sim, i * 1000 + s)
             X.append(sl.features)
@@ -701,6 +700,11 @@ def ber_leg(wl, dtypes):
     out = {"workload": wl, "weights": g["weights"], "slots": f"{len(snr)} SNR points x {n_sl} slots of {T}x{F} REs",
            "target_ber": target, "snr_db_at_target": {"fp64": s64}, "delta_db": {}, "ber": {"snr_db": snr,
            "fp64": [float(v) for v in ber64]}}
+    if "errors_fp8_contract" in g["points"][0]:  # the FP8 contract alone (oracle emulation)
+        ber8 = np.array([r["errors_fp8_contract"] / r["bits"] for r in g["points"]])
+        s8 = snr_at(snr, ber8, target)
+        out["ber"]["fp8_contract_oracle"] = [float(v) for v in ber8]
+        out["delta_db"]["fp8_contract_oracle"] = None if (s8 is None or s64 is None) else round(s8 - s64, 4)
     x = torch.from_numpy(X).cuda()
     for dt in dtypes:
         model = Conet(mc.K, mc.L, mc.C, mc.C_in, mc.m, blob, dtype=dt, max_res=X.shape[0] * T * F)
@@ -803,7 +807,8 @@ def headline(args):
         result["cpu_baseline"] = None
     if full:
         ber = {}
-        for wl, dts in (("bf16_b64_f3276", ("f32", "bf16")), ("fp8_b128_f3276", ("f32", "bf16", "fp8"))):
+        for wl, dts in (("bf16_b64_f3276", ("f32", "bf16")), ("fp8_b128_f3276", ("f32", "bf16", "fp8")),
+                        ("interf_bf16_b64_f3276", ("f32", "bf16"))):
             b = ber_leg(wl, dts)
             if b is not None:
                 ber[wl] = b

@@ -10,6 +10,9 @@ hipError_t launch_conv_fp8(int mode, int cin, int cout, ConvArgs& a, int n_tiles
 int conv_tile_width_f32(int cin, int cout);
 int conv_tile_width_bf16(int cin, int cout);
 int conv_tile_width_fp8(int cin, int cout);
+int conv_tile_width_narrow_f32(int cin, int cout);
+int conv_tile_width_narrow_bf16(int cin, int cout);
+int conv_tile_width_narrow_fp8(int cin, int cout);
 hipError_t launch_block_bf16(int kind, int wclass, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
 int block_tile_width_bf16(int C, int wclass);
 hipError_t launch_block_fp8(int kind, int wclass, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s);
@@ -29,6 +32,15 @@ int conv_tile_width(int dtype, int cin, int cout) {
     case DT_F32: return conv_tile_width_f32(cin, cout);
     case DT_BF16: return conv_tile_width_bf16(cin, cout);
     case DT_FP8: return conv_tile_width_fp8(cin, cout);
+  }
+  return 0;
+}
+
+int conv_tile_width_narrow(int dtype, int cin, int cout) {
+  switch (dtype) {
+    case DT_F32: return conv_tile_width_narrow_f32(cin, cout);
+    case DT_BF16: return conv_tile_width_narrow_bf16(cin, cout);
+    case DT_FP8: return conv_tile_width_narrow_fp8(cin, cout);
   }
   return 0;
 }

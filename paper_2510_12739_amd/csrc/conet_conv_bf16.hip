@@ -9,6 +9,7 @@ hipError_t launch_conv_bf16(int mode, int cin, int cout, ConvArgs& a, int n_tile
 }
 
 int conv_tile_width_bf16(int cin, int cout) { return tile_width_dtype<ArithBF16>(cin, cout); }
+int conv_tile_width_narrow_bf16(int cin, int cout) { return tile_width_narrow_dtype<ArithBF16>(cin, cout); }
 
 // 96 channels: the 32x32x16 kernel (its own filter packing); 16, 32, 64: the 16x16x32 one.
 hipError_t launch_block_bf16(int kind, int wclass, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {

@@ -8,5 +8,6 @@ hipError_t launch_conv_f32(int mode, int cin, int cout, ConvArgs& a, int n_tiles
 }
 
 int conv_tile_width_f32(int cin, int cout) { return tile_width_dtype<ArithF32>(cin, cout); }
+int conv_tile_width_narrow_f32(int cin, int cout) { return tile_width_narrow_dtype<ArithF32>(cin, cout); }
 
 }  // namespace conet

@@ -9,6 +9,7 @@ hipError_t launch_conv_fp8(int mode, int cin, int cout, ConvArgs& a, int n_tiles
 }
 
 int conv_tile_width_fp8(int cin, int cout) { return tile_width_dtype<ArithFP8>(cin, cout); }
+int conv_tile_width_narrow_fp8(int cin, int cout) { return tile_width_narrow_dtype<ArithFP8>(cin, cout); }
 
 // 96 channels: the 32x32x64 kernel (its own filter packing); no other width is fused in FP8.
 hipError_t launch_block_fp8(int kind, int wclass, int C, BlockArgs& a, int n_tiles, int grid_y, hipStream_t s) {

@@ -672,13 +672,30 @@ __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
 }
 
 // ---------------------------------------------------------------- launch
-template <class A, int MODE, int CIN, int COUT>
-static hipError_t launch_one(ConvArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+// FP32 convs wider than 16 subcarriers also have a 16-wide build (forward modes only), for
+// batches whose tiles cannot fill the GPU: on a single small slot each stage is a handful of
+// work-groups, each doing a whole tile's GEMM, so narrower tiles cut the stage time.
+template <class A, int CIN, int COUT>
+constexpr int tile_w_narrow() {
   constexpr int TW = tile_w<A, CIN, COUT>();
+  return (std::is_same<A, ArithF32>::value && TW > 16) ? 16 : TW;
+}
+
+template <class A, int MODE, int CIN, int COUT, int TW>
+static hipError_t launch_tw(ConvArgs& a, int n_tiles, int grid_y, hipStream_t s) {
   a.tw = TW;
   hipLaunchKernelGGL((conv3x3_kernel<A, MODE, CIN, COUT, TW, CONV_NW>), dim3(n_tiles, grid_y), dim3(CONV_NW * 64), 0,
                      s, a);
   return hipGetLastError();
+}
+
+template <class A, int MODE, int CIN, int COUT>
+static hipError_t launch_one(ConvArgs& a, int n_tiles, int grid_y, hipStream_t s) {
+  constexpr int TW = tile_w<A, CIN, COUT>(), TWN = tile_w_narrow<A, CIN, COUT>();
+  if constexpr (TWN != TW && MODE <= 4) {
+    if (a.narrow) return launch_tw<A, MODE, CIN, COUT, TWN>(a, n_tiles, grid_y, s);
+  }
+  return launch_tw<A, MODE, CIN, COUT, TW>(a, n_tiles, grid_y, s);
 }
 
 template <class A, int CIN, int COUT>
@@ -717,6 +734,19 @@ hipError_t launch_dtype(int mode, int cin, int cout, ConvArgs& a, int n_tiles, i
   }
 #undef CONET_CASE
   return hipErrorInvalidValue;
+}
+
+template <class A>
+int tile_width_narrow_dtype(int cin, int cout) {
+#define CONET_TWN(CI, CO) \
+  if (cin == CI && cout == CO) return tile_w_narrow<A, CI, CO>();
+  if constexpr (sizeof(typename A::Op) == 1) {
+    CONET_PAIRS_FP8(CONET_TWN)
+  } else {
+    CONET_PAIRS(CONET_TWN)
+  }
+#undef CONET_TWN
+  return 0;
 }
 
 template <class A>

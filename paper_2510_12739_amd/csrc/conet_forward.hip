@@ -217,7 +217,13 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
   uint8_t* ws = M->ws;
   float* vec = reinterpret_cast<float*>(ws + lay.vec);
   std::vector<float>& sc = M->act_scales;
-  const int tw_in = conv_tile_width(dt, Ci, C), tw_blk = conv_tile_width(dt, C, C);
+  // a uniform inference batch whose block tiles cannot give every CU a work-group runs the
+  // convs on their narrow tiles (FP32: 16 subcarriers; the same arithmetic per RE)
+  const bool narrow = geo.uniform && !calib && !save &&
+                      (int64_t)geo.B * ((geo.F + conv_tile_width(dt, C, C) - 1) / conv_tile_width(dt, C, C)) * K <
+                          (int64_t)M->n_cu;
+  const int tw_in = narrow ? conv_tile_width_narrow(dt, Ci, C) : conv_tile_width(dt, Ci, C);
+  const int tw_blk = narrow ? conv_tile_width_narrow(dt, C, C) : conv_tile_width(dt, C, C);
   // Inference runs each block as one fused launch when a fused kernel exists for
   // (dtype, C); calibration and the training forward (which stores h) use two convs.
   const bool ds = c.block_type == CONET_BLOCK_SEPARABLE;
@@ -308,6 +314,7 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
 
   auto geom = [&](ConvArgs& a, bool in_layer) {
     const int tw = in_layer ? tw_in : tw_blk;
+    a.narrow = narrow ? 1 : 0;
     a.T = geo.T;
     a.F = geo.uniform ? geo.F : 0;
     a.tiles_per_slot = geo.uniform ? (geo.F + tw - 1) / tw : 0;

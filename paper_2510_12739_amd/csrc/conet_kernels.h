@@ -52,6 +52,8 @@ struct ConvArgs {
                                    // (one staged feature tile; launch with grid.y = 1)
   int grid_rx;                     // mode 0: > 0 => in[] is the received grid, FP32 [RE][grid_rx][2],
                                    // and the features are formed while staging (LS + interpolation)
+  int narrow;                      // modes 0-4, FP32: 1 => the narrow tile width of
+                                   // conv_tile_width_narrow (a batch too small to fill the GPU)
   int fusion_sum;                  // mode 4: fuse by addition instead of the product
   int norm_affine;                 // mode 4: gamma/beta are a per-channel affine (BatchNorm with
                                    // running statistics folded in) instead of LayerNorm's
@@ -60,6 +62,9 @@ struct ConvArgs {
 
 // Subcarriers per tile used for a (dtype, C_in, C_out) conv.
 int conv_tile_width(int dtype, int cin, int cout);
+// The width with ConvArgs::narrow set: 16 for FP32 convs whose default is wider (more, shorter
+// work-groups for a batch whose tiles cannot fill the GPU), else the default.
+int conv_tile_width_narrow(int dtype, int cin, int cout);
 bool conv_supported(int dtype, int cin, int cout);
 // mode: 0 input layer, 1 block conv 1, 2 block conv 2 (+ residual, + head on branch 0
 // if llr is set), 4 block conv 2 of the main net + product with the stored support

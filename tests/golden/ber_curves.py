@@ -41,13 +41,14 @@ from oracle import conet64 as o  # noqa: E402
 from synth import SimConfig, simulate_slot, workload  # noqa: E402
 from synth.ofdm import data_mask  # noqa: E402
 
-SNR_GRID = {"bf16_b64_f3276": list(range(-5, 26)), "fp8_b128_f3276": list(range(-5, 26))}
+SNR_GRID = {"bf16_b64_f3276": list(range(-5, 26)), "fp8_b128_f3276": list(range(-5, 26)),
+            "interf_bf16_b64_f3276": list(range(-5, 26))}
 
 
 def eval_sim(wl: str, F: int, snr_db: float) -> SimConfig:
+    """The workload's simulator (interferer and variance channels included) at one SNR."""
     s = workload(wl).sim
-    return SimConfig(F=F, n_rx=s.n_rx, bits_per_symbol=s.bits_per_symbol, n_taps=s.n_taps,
-                     max_doppler_hz=s.max_doppler_hz, snr_db=float(snr_db), seed=2000 + s.seed)
+    return SimConfig(**{**s.__dict__, "F": F, "snr_db": float(snr_db), "seed": 2000 + s.seed})
 
 
 def main():

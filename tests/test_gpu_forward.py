@@ -82,6 +82,24 @@ def test_fp32_variants_perturbed(K, L, C, Ci, m, mask, B, T, F):
     assert rel_l2(got, ref) <= 1e-5 and max_over_rms(got, ref) <= 1e-4, (rel_l2(got, ref), max_over_rms(got, ref))
 
 
+def test_fp32_narrow_and_default_tiles_agree_bitwise():
+    """FP32 convs run on 16-subcarrier tiles when a batch cannot give every CU a work-group and on
+    their default 32-subcarrier tiles otherwise; the arithmetic per RE is the same, so a slot
+    gives the same LLRs bit for bit alone (narrow) and in a 4-slot batch (default), and both
+    match the oracle."""
+    K, L, C, Ci, m = 2, 2, 32, 8, 2
+    blob = make_blob(ModelConfig(K, L, C, Ci, m), seed=12, perturb=True)
+    X = features(SimConfig(F=1040, n_rx=2, bits_per_symbol=2, seed=13), 4)
+    model = _model(K, L, C, Ci, m, "f32", blob, max_res=4 * 14 * 1040)
+    say("fp32 narrow vs default tiles, 4 x 14 x 1040")
+    big = _run(model, X)
+    alone = _run(model, X[:1])
+    np.testing.assert_array_equal(big[:1], alone)
+    ref = _oracle(K, L, C, Ci, m, blob, X[:1])
+    assert rel_l2(alone, ref) <= 1e-5 and max_over_rms(alone, ref) <= 1e-4, (rel_l2(alone, ref), max_over_rms(alone, ref))
+    model.close()
+
+
 @pytest.mark.parametrize("dtype,K,L,C,Ci,m", [
     ("bf16", 2, 2, 32, 8, 2),     # 16x16 fused kernel, 44-subcarrier tiles
     ("bf16", 3, 2, 96, 16, 4),    # 32x32x16 fused kernel, 18-subcarrier tiles
