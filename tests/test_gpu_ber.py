@@ -7,8 +7,9 @@ slots (common random numbers). Target BER: the lowest of 1e-3, 1e-2, 1e-1 that t
 reaches (the 256-QAM network, trained on the CPU, floors near 5e-2, so its gap is taken at 1e-1,
 on the steep part of its curve). FP32 and BF16 must be within 0.1 dB of FP64. The FP8 contract
 (e4m3 conv operands, static activation scales) loses more than that on the 256-QAM network even
-after FP8-aware fine-tuning, so FP8 is held to the contract: its gap may exceed the gap of the
-oracle's FP8 emulation on the same slots (stored beside the FP64 counts) by at most 0.25 dB;
+after FP8-aware fine-tuning (0.46 dB at 1e-1), so FP8 is held to the contract: its gap must be
+within 0.1 dB of the gap of the oracle's FP8 emulation on the same slots (stored beside the
+FP64 counts);
 curves are interpolated linearly in log10 BER over a 1 dB SNR grid. Bar: |gap| <= 0.1 dB.
 
 The FP64 curve is stored (tests/golden/ber_<workload>.json, written by
@@ -100,10 +101,10 @@ def test_ber_delta_vs_fp64(wl, dtypes):
             # The FP8 precision contract itself (e4m3 operands with static activation scales, the
             # oracle's emulation on the same slots) does not reach the 0.1 dB bar on this 256-QAM
             # network; the GPU is held to the contract: its gap may exceed the contract's by at
-            # most 0.25 dB (accumulation-order roundings flip a few more decisions).
+            # most 0.1 dB (the same bar, applied to what the kernels add).
             ber8 = np.array([r["errors_fp8_contract"] / r["bits"] for r in g["points"]])
             gap8 = cl.snr_gap_db(snr, ber8, ber64, target)
             say(f"  fp8 contract (oracle emulation): gap to FP64 {gap8:+.4f} dB")
-            assert gap <= gap8 + 0.25, (wl, dt, gap, gap8)
+            assert abs(gap - gap8) <= 0.1, (wl, dt, gap, gap8)
             continue
         assert abs(gap) <= 0.1, (wl, dt, gap)
