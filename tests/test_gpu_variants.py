@@ -151,3 +151,36 @@ def test_variant_configurations_refused():
         K, L, C, Ci, m = dims
         with pytest.raises(ConetError):
             Conet(K, L, C, Ci, m, np.zeros(10, np.float32), **kw)
+
+
+@pytest.mark.parametrize("kw", [{"block": "ds"}, {"fusion": "concat", "support_blocks": 2}])
+def test_variant_models_serve_and_run_without_allocation(kw):
+    """A separable model and a concatenation model with shallower supports behind the
+    continuous-batching server (ragged batches of uneven requests) and the allocation-free
+    forward: each request's LLRs equal the model's own forward of that slot bit for bit."""
+    from paper_2510_12739_amd import Conet, Server
+    from synth.requests import make_requests
+    K, L, C, Ci, m = 3, 3, 64, 16, 6
+    mc = ModelConfig(K, L, C, Ci, m, -1, kw.get("support_blocks", 0), kw.get("fusion", "product"),
+                     kw.get("block", "standard"))
+    model = Conet(K, L, C, Ci, m, make_blob(mc, seed=95), dtype="bf16", max_res=14 * 3276, **kw)
+    reqs = make_requests(12, seed=96)
+    say(f"serving a variant model {kw}")
+    srv = Server(model, mem_budget=2 << 30, n_streams=2, max_batch_res=200_000)
+    tickets = [srv.submit(r.x, r.n_prb, r.n_rx, r.m) for r in reqs]
+    for t, _ in tickets:
+        srv.wait(t)
+    srv.close()
+    for r, (_, llr) in zip(reqs, tickets):
+        x = np.zeros((1, 14, r.x.shape[1], Ci), np.float32)
+        x[0, ..., :r.x.shape[2]] = r.x
+        xt = torch.from_numpy(x).cuda()
+        alone = model(xt)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(llr, alone.cpu().numpy()[0, ..., :r.m])
+        if 14 * r.x.shape[1] <= model.noalloc_capacity:  # the static array's capacity
+            out = torch.empty_like(alone)
+            model.forward_noalloc(xt, out)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(out.cpu().numpy(), alone.cpu().numpy())
+    model.close()
