@@ -62,6 +62,11 @@ bool ds_supported(int dtype, int C) { return (dtype == DT_F32 || dtype == DT_BF1
 bool concat_supported(int dtype, int C, int K) { return ds_supported(dtype, C) && K >= 1 && K <= 4; }
 
 // ---------------------------------------------------------------- separable block
+// Waves per work-group: 8, so that with two work-groups per CU every SIMD holds four waves to
+// hide the staging and LDS latencies (the block is latency-bound at four waves per work-group:
+// 45 % of wave cycles waited on memory counters).
+constexpr int DS_NW = 8;
+
 template <class A, int C>
 struct DsShape {
   using Op = typename A::Op;
@@ -73,10 +78,11 @@ struct DsShape {
   static constexpr int PRE = TMAX * W0 * PITCH;       // pre(x)
   static constexpr int MID = TMAX * W1 * PITCH;       // h
   static constexpr int LDS = PRE + MID;
-  static constexpr int NSTAGE = (TMAX * W0 * CH + 255) / 256;  // staging items per thread
+  static constexpr int NT = DS_NW * 64;               // threads per work-group
+  static constexpr int NSTAGE = (TMAX * W0 * CH + NT - 1) / NT;  // staging items per thread
   static constexpr int NOT = C / 16;
   static constexpr int NS = C / (4 * VEC);            // K steps of a 1x1 conv
-  static constexpr int MT = 4;                        // RE tiles of 16 per wave and conv
+  static constexpr int MT = (16 + DS_NW - 1) / DS_NW;  // RE tiles of 16 per wave and conv (<= 16 tiles)
   using AccTile = typename A::AccV[MT][NOT];
   static_assert(C % (4 * VEC) == 0, "1x1 conv K steps must be whole");
   static_assert(LDS <= 160 * 1024, "LDS budget");
@@ -105,7 +111,7 @@ __device__ __forceinline__ i32x4 f_to_chunk(const float* f) {
 // columns wider; rows outside [0, T) read as zero) feeds the 1x1 conv's B fragments straight
 // from registers -- each depthwise output is one lane's operand chunk and is used once -- so
 // it is never stored. Per K step s the lane's chunk is 4 s + l / 16; its 9 x VEC taps are
-// loaded once per step. acc[mt][ot] covers RE tiles wave + 4 mt (tiles past the region
+// loaded once per step. acc[mt][ot] covers RE tiles wave + DS_NW mt (tiles past the region
 // compute position 0 and are discarded).
 template <class A, int C>
 __device__ __forceinline__ void separable(typename DsShape<A, C>::AccTile& acc, const uint8_t* in, int in_w,
@@ -117,7 +123,7 @@ __device__ __forceinline__ void separable(typename DsShape<A, C>::AccTile& acc, 
   int tt0[S::MT], cc0[S::MT];
 #pragma unroll
   for (int mt = 0; mt < S::MT; ++mt) {
-    int pos = (wave + 4 * mt) * 16 + (lane & 15);
+    int pos = (wave + DS_NW * mt) * 16 + (lane & 15);
     if (pos >= n_pos) pos = 0;
     tt0[mt] = pos / n_cols;
     cc0[mt] = pos - tt0[mt] * n_cols;
@@ -130,18 +136,21 @@ __device__ __forceinline__ void separable(typename DsShape<A, C>::AccTile& acc, 
     i32x4 a[S::NOT];
 #pragma unroll
     for (int ot = 0; ot < S::NOT; ++ot) a[ot] = wp[(s * S::NOT + ot) * 64 + lane];
-    float w[9][A::VEC];
+    float d[S::MT][A::VEC];
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap)
+    for (int mt = 0; mt < S::MT; ++mt)
 #pragma unroll
-      for (int j = 0; j < A::VEC; ++j) w[tap][j] = dw[tap * C + chunk * A::VEC + j];
+      for (int j = 0; j < A::VEC; ++j) d[mt][j] = 0.f;
+    // one filter row (3 taps) at a time, shared by the lane's RE tiles: fewer live registers
 #pragma unroll
-    for (int mt = 0; mt < S::MT; ++mt) {
-      float d[A::VEC];
+    for (int dt = -1; dt <= 1; ++dt) {
+      float w[3][A::VEC];
 #pragma unroll
-      for (int j = 0; j < A::VEC; ++j) d[j] = 0.f;
+      for (int df = 0; df < 3; ++df)
 #pragma unroll
-      for (int dt = -1; dt <= 1; ++dt) {
+        for (int j = 0; j < A::VEC; ++j) w[df][j] = dw[((dt + 1) * 3 + df) * C + chunk * A::VEC + j];
+#pragma unroll
+      for (int mt = 0; mt < S::MT; ++mt) {
         const int tt = tt0[mt] + dt;
         if (tt < 0 || tt >= T) continue;
 #pragma unroll
@@ -149,10 +158,13 @@ __device__ __forceinline__ void separable(typename DsShape<A, C>::AccTile& acc, 
           float v[A::VEC];
           chunk_to_f<A>(*reinterpret_cast<const i32x4*>(in + (tt * in_w + cc0[mt] + df) * S::PITCH + chunk * 16), v);
 #pragma unroll
-          for (int j = 0; j < A::VEC; ++j) d[j] = fmaf(w[(dt + 1) * 3 + df][j], v[j], d[j]);
+          for (int j = 0; j < A::VEC; ++j) d[mt][j] = fmaf(w[df][j], v[j], d[mt][j]);
         }
       }
-      const i32x4 b = f_to_chunk<A>(d);  // the 1x1 conv's operand, rounded
+    }
+#pragma unroll
+    for (int mt = 0; mt < S::MT; ++mt) {
+      const i32x4 b = f_to_chunk<A>(d[mt]);  // the 1x1 conv's operand, rounded
 #pragma unroll
       for (int ot = 0; ot < S::NOT; ++ot) acc[mt][ot] = A::mma(&a[ot], &b, acc[mt][ot]);
     }
@@ -169,9 +181,11 @@ __device__ __forceinline__ TileDesc ds_tile(const DsArgs& a, int bid) {
   return d;
 }
 
-// two work-groups per CU where the LDS allows it (not at C = 64 in FP32: 149 KB)
+// two work-groups per CU where the LDS allows it (not at C = 64 in FP32: 149 KB); the second
+// launch bound is the waves per SIMD that implies, which caps the registers per lane
 template <class A, int C>
-__global__ void __launch_bounds__(256, (DsShape<A, C>::LDS <= 80 * 1024 ? 2 : 1)) ds_block_kernel(DsArgs args) {
+__global__ void __launch_bounds__(DS_NW * 64, (DsShape<A, C>::LDS <= 80 * 1024 ? 2 : 1) * DS_NW / 4)
+    ds_block_kernel(DsArgs args) {
   using S = DsShape<A, C>;
   using Op = typename A::Op;
   __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS];
@@ -197,7 +211,7 @@ __global__ void __launch_bounds__(256, (DsShape<A, C>::LDS <= 80 * 1024 ? 2 : 1)
     i32x4 raw[S::NSTAGE];
 #pragma unroll
     for (int it = 0; it < S::NSTAGE; ++it) {
-      const int i = threadIdx.x + it * 256;
+      const int i = threadIdx.x + it * S::NT;
       const int pos = i / S::CH, col = pos % S::W0, t = pos / S::W0;
       const int f = td.f0 - 2 + col;
       raw[it] = i32x4{0, 0, 0, 0};
@@ -206,7 +220,7 @@ __global__ void __launch_bounds__(256, (DsShape<A, C>::LDS <= 80 * 1024 ? 2 : 1)
     }
 #pragma unroll
     for (int it = 0; it < S::NSTAGE; ++it) {
-      const int i = threadIdx.x + it * 256;
+      const int i = threadIdx.x + it * S::NT;
       if (i >= TMAX * S::W0 * S::CH) break;
       const int pos = i / S::CH, col = pos % S::W0, t = pos / S::W0;
       const int f = td.f0 - 2 + col;
@@ -231,7 +245,7 @@ __global__ void __launch_bounds__(256, (DsShape<A, C>::LDS <= 80 * 1024 ? 2 : 1)
     const float* o1 = args.post_o[k];
 #pragma unroll
     for (int mt = 0; mt < S::MT; ++mt) {
-      const int pos = (wave + 4 * mt) * 16 + (lane & 15);
+      const int pos = (wave + DS_NW * mt) * 16 + (lane & 15);
       if (pos >= T * S::W1) continue;
       const int col = pos % S::W1;
       const int f = td.f0 - 1 + col;
@@ -263,7 +277,7 @@ __global__ void __launch_bounds__(256, (DsShape<A, C>::LDS <= 80 * 1024 ? 2 : 1)
     const float* b2 = args.b2[k];
 #pragma unroll
     for (int mt = 0; mt < S::MT; ++mt) {
-      const int pos = (wave + 4 * mt) * 16 + (lane & 15);
+      const int pos = (wave + DS_NW * mt) * 16 + (lane & 15);
       if (pos >= T * DS_TW) continue;
 #pragma unroll
       for (int ot = 0; ot < S::NOT; ++ot) {
@@ -278,7 +292,7 @@ __global__ void __launch_bounds__(256, (DsShape<A, C>::LDS <= 80 * 1024 ? 2 : 1)
   {
     constexpr int C8 = C / 8;
     const bool f32 = args.out_f32[k] != 0;
-    for (int i = threadIdx.x; i < T * DS_TW * C8; i += 256) {
+    for (int i = threadIdx.x; i < T * DS_TW * C8; i += S::NT) {
       const int pos = i / C8, c0 = (i - pos * C8) * 8;
       const int t = pos / DS_TW, f = td.f0 + pos % DS_TW;
       if (f >= td.F) continue;
@@ -314,7 +328,7 @@ __global__ void __launch_bounds__(256, (DsShape<A, C>::LDS <= 80 * 1024 ? 2 : 1)
 template <class A, int C>
 static hipError_t launch_ds_t(DsArgs& a, int n_tiles, int grid_y, hipStream_t s) {
   a.tw = DS_TW;
-  hipLaunchKernelGGL((ds_block_kernel<A, C>), dim3(n_tiles, grid_y), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((ds_block_kernel<A, C>), dim3(n_tiles, grid_y), dim3(DS_NW * 64), 0, s, a);
   return hipGetLastError();
 }
 
