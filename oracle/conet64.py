@@ -395,7 +395,8 @@ def forward(p: Dict, X: np.ndarray, fuse_mask: Optional[int] = None, quant: Opti
     fusion. Support nets shallower than the main net (p["Ls"] < L) take part in the fusions
     after their own blocks only. norm: "ln", "bn" (running statistics of
     p) or "bn_batch" (this batch's statistics, recorded into bn_stats[l - 1] = (mean, var)
-    if given); default: p's own. The backward covers the defaults only.
+    if given); default: p's own. The backward covers product fusion without feedback, standard
+    blocks of full depth, with "ln" or "bn_batch".
     acc_noise: a numpy Generator; every conv and the head then carry the FP32-accumulation
     error model of _conv_acc, and every value rounded to BF16 or e4m3 the FP32 error of the
     operations that formed it (_fp32_formed); for deriving tolerances, never for results.
@@ -549,12 +550,22 @@ def backward(p: Dict, cache: Dict, dllr: np.ndarray) -> Dict:
     Returns a parameter dict with the same structure as unpack(); pack() flattens it.
     The product adjoint is dO[k] = dP * prod_{j != k} O[j], formed without division.
     ReLU derivatives use the strict rule (pre-activation > 0).
+    The normalisation adjoint is the same expression for both norms, with the means taken
+    over what the statistics were taken over: the C channels of each RE (LayerNorm), or every
+    RE of the batch per channel (BatchNorm with batch statistics, where the statistics depend
+    on every RE and so does each RE's gradient). Running statistics get zero gradient.
     """
     K, L = p["K"], p["L"]
     mask = cache["mask"]
-    if cache.get("variant", ("product", False, "ln")) != ("product", False, "ln"):
-        raise NotImplementedError("the backward covers product fusion without feedback, with LayerNorm")
-    g = {"branch": [], "gamma": [None] * L, "beta": [None] * L}
+    variant = cache.get("variant", ("product", False, "ln"))
+    if variant not in (("product", False, "ln"), ("product", False, "bn_batch")):
+        raise NotImplementedError("the backward covers product fusion without feedback, with LayerNorm or "
+                                  "BatchNorm by batch statistics")
+    stat_axes = (0, 1, 2) if variant[2] == "bn_batch" else (-1,)
+    g = {"branch": [], "gamma": [None] * L, "beta": [None] * L, "norm": p.get("norm", "ln")}
+    if g["norm"] == "bn":
+        g["bn_mean"] = [np.zeros(p["C"]) for _ in range(L)]
+        g["bn_var"] = [np.zeros(p["C"]) for _ in range(L)]
     for _k in range(K):
         g["branch"].append({"W_in": None, "b_in": None, "blocks": [dict() for _ in range(L)]})
 
@@ -573,8 +584,8 @@ def backward(p: Dict, cache: Dict, dllr: np.ndarray) -> Dict:
             g["gamma"][l - 1] = (dA * ahat).reshape(-1, ahat.shape[-1]).sum(axis=0)
             g["beta"][l - 1] = dA.reshape(-1, dA.shape[-1]).sum(axis=0)
             dh_ = p["gamma"][l - 1] * dA
-            dP = (dh_ - dh_.mean(axis=-1, keepdims=True)
-                  - ahat * (dh_ * ahat).mean(axis=-1, keepdims=True)) / sig
+            dP = (dh_ - dh_.mean(axis=stat_axes, keepdims=True)
+                  - ahat * (dh_ * ahat).mean(axis=stat_axes, keepdims=True)) / sig
             dO = []
             for k in range(K):
                 others = np.ones_like(O[0])
@@ -625,9 +636,10 @@ def backward(p: Dict, cache: Dict, dllr: np.ndarray) -> Dict:
     return g
 
 
-def grad_blob(p: Dict, X: np.ndarray, dllr: np.ndarray, fuse_mask: Optional[int] = None) -> np.ndarray:
-    """Gradient of sum(LLR * dllr) with respect to the blob, in blob order."""
-    _, cache = forward(p, X, fuse_mask=fuse_mask, keep=True)
+def grad_blob(p: Dict, X: np.ndarray, dllr: np.ndarray, fuse_mask: Optional[int] = None,
+              norm: Optional[str] = None) -> np.ndarray:
+    """Gradient of sum(LLR * dllr) with respect to the blob, in blob order (norm: forward()'s)."""
+    _, cache = forward(p, X, fuse_mask=fuse_mask, keep=True, norm=norm)
     g = backward(p, cache, dllr)
     return pack(g)
 
