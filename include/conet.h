@@ -77,10 +77,16 @@ typedef struct {
                               training calls support fusion_op = 0, feedback = 0 only          */
   int32_t norm;            /* normalisation after each fusion (Sec. III allows BN or LN):
                               CONET_NORM_LN (0): per-RE LayerNorm over C, gamma/beta affine;
-                              CONET_NORM_BN (1): BatchNorm with stored running statistics,
-                              gamma (P - mean) / sqrt(var + ln_eps) + beta per channel; the
-                              blob then ends with mean_l, var_l (C each) for l = 1..L.
-                              Inference only (train = 1 needs CONET_NORM_LN)                   */
+                              CONET_NORM_BN (1): BatchNorm, gamma (P - mean) / sqrt(var +
+                              ln_eps) + beta per channel; the blob then ends with the running
+                              statistics mean_l, var_l (C each) for l = 1..L. With train = 0
+                              mean/var are those running statistics. With train = 1 (C in
+                              {32, 64}) every forward normalises by the batch's own statistics
+                              (over all B T F REs of the call, variance biased), conet_backward
+                              differentiates through them, and each save_for_backward forward
+                              moves the running statistics by CONET_BN_MOMENTUM towards the
+                              batch's (variance unbiased, n/(n-1)); conet_get_weights returns
+                              them for an inference model                                      */
   int32_t support_blocks;  /* blocks of every support branch, 1..L; 0 => L. Sec. III lets the
                               support net be shallower than the main net: after block
                               support_blocks the main branch continues alone, so fuse_mask may
@@ -96,6 +102,8 @@ typedef struct {
  * inference only. */
 enum { CONET_FUSE_PRODUCT = 0, CONET_FUSE_SUM = 1, CONET_FUSE_CONCAT = 2 };
 enum { CONET_NORM_LN = 0, CONET_NORM_BN = 1 };
+/* running <- (1 - momentum) running + momentum batch, per BatchNorm training forward */
+#define CONET_BN_MOMENTUM 0.1f
 enum { CONET_BLOCK_STANDARD = 0, CONET_BLOCK_SEPARABLE = 1 };
 
 typedef struct conet_model conet_model;
@@ -170,7 +178,8 @@ conet_status conet_forward_ragged(conet_model* model, const float* x, int32_t n_
  * (any model, any stream) race and must be serialised by the caller. Inference only (no
  * save_for_backward). Errors: as conet_forward, plus ESHAPE when B*T*F exceeds
  * conet_forward_noalloc_capacity(model), EDEVICE when the current device is not the
- * model's. */
+ * model's, EINVAL for a BatchNorm model created with train = 1 (its batch statistics live
+ * in the model's workspace). */
 conet_status conet_forward_noalloc(conet_model* model, const float* x, int32_t B, int32_t T, int32_t F, float* llr,
                                    void* stream);
 
@@ -407,8 +416,9 @@ typedef struct {
 /* Start a server on `model` (which must outlive it): n_streams lanes of up to
  * max_batch_res REs each, reduced until all lanes' device buffers fit mem_budget_bytes;
  * at most max_queue requests wait. Allocates its device and pinned host buffers here,
- * once. Errors: EINVAL, ENOMEM (budget too small for one RE per lane), ESTATE (FP8
- * model without scales), EDEVICE. */
+ * once. Errors: EINVAL (also for a BatchNorm model created with train = 1: batch
+ * statistics would make a request's LLRs depend on the others in its batch), ENOMEM
+ * (budget too small for one RE per lane), ESTATE (FP8 model without scales), EDEVICE. */
 conet_status conet_serve_create(conet_model* model, size_t mem_budget_bytes, int32_t n_streams, int32_t max_batch_res,
                                 int32_t max_queue, conet_server** out);
 

@@ -216,7 +216,8 @@ conet_status check_config(const conet_config* c) {
     if (c->blocks > 16) return fail(CONET_EINVAL, "training supports L <= 16");
     if (c->fusion_op != CONET_FUSE_PRODUCT || c->feedback)
       return fail(CONET_EINVAL, "training supports product fusion without feedback");
-    if (c->norm != CONET_NORM_LN) return fail(CONET_EINVAL, "training supports LayerNorm after the fusion");
+    if (c->norm == CONET_NORM_BN && c->channels != 32 && c->channels != 64)
+      return fail(CONET_EINVAL, "training with BatchNorm supports C = 32, 64");
     if (support_depth(*c) != c->blocks || c->block_type != CONET_BLOCK_STANDARD)
       return fail(CONET_EINVAL, "training supports standard blocks and support branches of depth L");
   }
@@ -418,8 +419,9 @@ conet_status conet_create(const conet_config* cfg, const float* w, size_t n_weig
     }
   if (cfg->norm == CONET_NORM_BN) {
     // BatchNorm with running statistics is a per-channel affine: fold it into gamma/beta,
-    // gamma' = gamma / sqrt(var + eps), beta' = beta - mean gamma'
-    for (int l = 0; l < L; ++l) {
+    // gamma' = gamma / sqrt(var + eps), beta' = beta - mean gamma'. A training model keeps
+    // gamma and beta as given: it normalises by each batch's own statistics.
+    for (int l = 0; l < L && !cfg->train; ++l) {
       const float* mean = p + (size_t)l * 2 * C;
       const float* var = mean + C;
       float* g = vec + lay.v_gamma[l];

@@ -35,6 +35,8 @@ void blob_offsets(const conet_config& c, BlobOffsets& bo) {
   for (int l = 0; l < L; ++l) { bo.gamma[l] = p; p += C; bo.beta[l] = p; p += C; }
   bo.wh = p; p += m * C;
   bo.bh = p; p += m;
+  if (c.norm == CONET_NORM_BN)
+    for (int l = 0; l < L; ++l) { bo.bn_mean[l] = p; p += C; bo.bn_var[l] = p; p += C; }
   bo.n = p;
 }
 
@@ -73,6 +75,8 @@ size_t train_bytes(const conet_config& c, Layout& lay, size_t base) {
   lay.tr_segs = take((size_t)MAX_SEGS * sizeof(ReduceSeg));
   lay.tr_red_tmp_floats = (size_t)K * 64 * 1024 + (size_t)K * 2 * C * 9 * std::max(C, Ci) + 65536;
   lay.tr_red_tmp = take(lay.tr_red_tmp_floats * 4);
+  lay.tr_bn = take((size_t)4 * L * C * 4);
+  lay.tr_bn_part = take((size_t)1024 * C * 4);
   const size_t t_act = align256(R * C * act_bytes_of(c.dtype));
   lay.tr_levels = off;
   lay.tr_levels_bytes = t_act * ((size_t)(L + 1) * K + (size_t)L * K + L + 4 * (size_t)K);
@@ -333,8 +337,22 @@ static conet_status run_backward(conet_model* M, const float* dllr, hipStream_t 
       fa.eps = c.ln_eps;
       fa.n_re = n_re;
       fa.part = part_fuse;
-      e = launch_fuse_bwd(dt, fa, FUSE_GRID, s);
-      if (e == hipSuccess) e = reduce(ri);
+      if (fuse && c.norm == CONET_NORM_BN) {  // batch statistics: two passes around the reduction
+        const float* bn = reinterpret_cast<const float*>(ws + lay.tr_bn) + (size_t)4 * C * l;
+        fa.bn_mu = bn;
+        fa.bn_rs = bn + C;
+        fa.bn_pass = 1;
+        e = launch_fuse_bwd(dt, fa, FUSE_GRID, s);
+        if (e == hipSuccess) e = reduce(ri);
+        fa.bn_pass = 2;
+        fa.bn_dgamma = grad + bo.gamma[l];
+        fa.bn_dbeta = grad + bo.beta[l];
+        fa.part = nullptr;
+        if (e == hipSuccess) e = launch_fuse_bwd(dt, fa, FUSE_GRID, s);
+      } else {
+        e = launch_fuse_bwd(dt, fa, FUSE_GRID, s);
+        if (e == hipSuccess) e = reduce(ri);
+      }
       if (e != hipSuccess) return hip_fail(e, "head / fusion backward");
       for (int k = 0; k < nk; ++k) dO[k] = ar.g_dO[k];
     } else {

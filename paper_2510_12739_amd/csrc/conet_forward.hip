@@ -229,6 +229,10 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
   const bool ds = c.block_type == CONET_BLOCK_SEPARABLE;
   const bool concat = c.fusion_op == CONET_FUSE_CONCAT;
   const int Ls = support_depth(c);
+  // a training model with BatchNorm normalises by the batch's own statistics: at its fused
+  // levels the block launches store every branch output, and the fusion epilogue runs as a
+  // pass of its own after the per-channel statistics of the product (bn_epilogue below)
+  const bool bn_batch = c.train && c.norm == CONET_NORM_BN;
   int tw_fb = (calib || ds) ? 0 : block_tile_width(dt, C, K, TW_WIDE, c.train != 0);
   // a batch whose wide tiles cannot fill the GPU once (a slot, a serving batch) runs on
   // narrow tiles: more, shorter work-groups per launch; if its paired launches (K branches
@@ -384,7 +388,8 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
   // the fusion epilogue pass that follows a level's block launches when no block kernel folds
   // the fusion in (by concatenation, or after separable blocks), or that runs the head after
   // an unfused last separable block: reads the stored outputs at out_p, writes A in place
-  auto epilogue = [&](int l, bool fuse, bool last, int out_p, const void* main, bool main_f32) -> conet_status {
+  auto epilogue = [&](int l, bool fuse, bool last, int out_p, const void* main, bool main_f32,
+                      const float* scale = nullptr, const float* shift = nullptr) -> conet_status {
     FuseArgs f = {};
     f.main = main;
     f.main_f32 = main_f32 ? 1 : 0;
@@ -392,8 +397,8 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
     f.K = K;
     f.wcat = ws + lay.w_cat[l];
     f.bcat = vec + lay.v_bcat[l];
-    f.gamma = vec + lay.v_gamma[l];
-    f.beta = vec + lay.v_beta[l];
+    f.gamma = scale ? scale : vec + lay.v_gamma[l];
+    f.beta = shift ? shift : vec + lay.v_beta[l];
     f.norm_affine = c.norm == CONET_NORM_BN;
     f.eps = c.ln_eps;
     f.out = last ? nullptr : actp(out_p, 0);
@@ -406,6 +411,37 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
     const int mode = !fuse ? EPI_NONE : concat ? EPI_CONCAT : c.fusion_op == CONET_FUSE_SUM ? EPI_SUM : EPI_PRODUCT;
     const hipError_t e2 = launch_fuse_epilogue(dt, C, mode, f, s);
     return e2 == hipSuccess ? CONET_OK : hip_fail(e2, "fusion epilogue launch");
+  };
+  // BatchNorm by batch statistics after block l: mean, then variance of the product over the
+  // batch (work-group partials summed in a fixed order), the folded per-channel affine, the
+  // running statistics (training forwards only), then the epilogue with that affine. Mean and
+  // 1/sqrt(var + eps) stay in the workspace for the backward.
+  auto bn_epilogue = [&](int l, bool last, int out_p, const void* main) -> conet_status {
+    float* bn = reinterpret_cast<float*>(ws + lay.tr_bn) + (size_t)4 * C * l;
+    float* part = reinterpret_cast<float*>(ws + lay.tr_bn_part);
+    float* master = reinterpret_cast<float*>(ws + lay.tr_master);
+    const int G = bn_stats_grid(n_re);
+    BnStatsArgs sa = {};
+    sa.main = main;
+    for (int k = 1; k < K; ++k) sa.sup[k] = actp(out_p, k);
+    sa.K = K; sa.C = C; sa.n_re = n_re; sa.part = part; sa.mean = bn;
+    BnFinishArgs fa = {};
+    fa.part = part; fa.groups = G; fa.C = C; fa.n_re = n_re;
+    fa.eps = c.ln_eps; fa.momentum = CONET_BN_MOMENTUM;
+    fa.gamma = vec + lay.v_gamma[l];
+    fa.beta = vec + lay.v_beta[l];
+    fa.mean = bn; fa.rs = bn + C; fa.scale = bn + 2 * C; fa.shift = bn + 3 * C;
+    fa.running_mean = save ? master + M->bo.bn_mean[l] : nullptr;
+    fa.running_var = save ? master + M->bo.bn_var[l] : nullptr;
+    hipError_t e2 = hipSuccess;
+    for (int pass = 0; pass < 2 && e2 == hipSuccess; ++pass) {
+      sa.pass = pass;
+      fa.pass = pass;
+      e2 = launch_bn_stats(dt, sa, G, s);
+      if (e2 == hipSuccess) e2 = launch_bn_finish(fa, s);
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "BatchNorm statistics");
+    return epilogue(l, true, last, out_p, main, false, bn + 2 * C, bn + 3 * C);
   };
 
   int cur = 0;
@@ -459,17 +495,22 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
       fused_prev = fuse;
       continue;
     }
-    // fusion by concatenation: the block kernels store every branch output, the epilogue fuses
-    const bool fuse_k = fuse && !concat;
-    const bool last_k = last && !(fuse && concat);
+    // fusion by concatenation, or BatchNorm by batch statistics: the block kernels store every
+    // branch output (a training forward keeps the main one where the backward reads it), then
+    // the epilogue pass fuses
+    const bool bn_lvl = bn_batch && fuse;
+    const bool fuse_k = fuse && !concat && !bn_lvl;
+    const bool last_k = last && !(fuse && (concat || bn_lvl));
     const int nk = (last_k && !fuse_k) ? 1 : Kl;
+    auto out_at = [&](int p, int k) -> void* { return (bn_lvl && save && k == 0) ? ar.lvl_o0[l] : actp(p, k); };
     if (tw_fb) {
       const int in_p = cur, out_p = 1 - cur;
       conet_status st = fsched.block(l, fuse_k, fused_prev, last_k, Kl, [&](int k) { return actp(in_p, k); },
-                                     [&](int k) { return actp(out_p, k); },
+                                     [&](int k) { return out_at(out_p, k); },
                                      [&](int k) -> void* { return save ? hidp(k) : nullptr; },
                                      save ? ar.lvl_o0[l] : nullptr, mark);
       if (st == CONET_OK && fuse && concat) st = epilogue(l, true, last, out_p, actp(out_p, 0), false);
+      if (st == CONET_OK && bn_lvl) st = bn_epilogue(l, last, out_p, out_at(out_p, 0));
       if (st != CONET_OK) return st;
       cur = 1 - cur;
       fused_prev = fuse;
@@ -571,7 +612,7 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
       if (e != hipSuccess) return hip_fail(e, "fused conv 2 launch");
       add_units(1);
     } else {
-      for (int k = 0; k < nk; ++k) a2.out[k] = last_k ? nullptr : actp(1 - cur, k);
+      for (int k = 0; k < nk; ++k) a2.out[k] = last_k ? nullptr : out_at(1 - cur, k);
       a2.llr = (last_k && !calib) ? llr : nullptr;
       a2.save_o0 = (save && last_k) ? ar.lvl_o0[l] : nullptr;
       e = mark();
@@ -582,6 +623,10 @@ conet_status run_forward(conet_model* M, const Arena& ar, const float* x, const 
     }
     if (fuse && concat) {
       conet_status st = epilogue(l, true, last, 1 - cur, actp(1 - cur, 0), false);
+      if (st != CONET_OK) return st;
+    }
+    if (bn_lvl) {
+      conet_status st = bn_epilogue(l, last, 1 - cur, out_at(1 - cur, 0));
       if (st != CONET_OK) return st;
     }
     cur = 1 - cur;

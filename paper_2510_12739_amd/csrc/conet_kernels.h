@@ -217,8 +217,49 @@ struct FuseBwdArgs {
   float eps;
   int64_t n_re;
   float* part;                     // [gridDim.x][NP] partial sums: dgamma C, dbeta C, dWh m*C, dbh m
+  // BatchNorm by batch statistics (bn_mu non-null): per-channel mean and 1/sqrt(var + eps) of
+  // the forward. The adjoint needs the batch sums of dA and dA ahat, which are the gamma and
+  // beta gradients: pass 1 forms them (partial sums only, no dO), pass 2 reads them back
+  // (bn_dgamma, bn_dbeta, already reduced) and writes dO
+  const float* bn_mu;
+  const float* bn_rs;
+  const float* bn_dgamma;
+  const float* bn_dbeta;
+  int bn_pass;
 };
 hipError_t launch_fuse_bwd(int dtype, FuseBwdArgs& a, int grid, hipStream_t s);
+
+// BatchNorm statistics of the product P = O_0 O_1 ... O_{K-1} over every RE of a batch, per
+// channel. Pass 0: work-group partial sums of P; pass 1: of (P - mean)^2 (mean from pass 0).
+struct BnStatsArgs {
+  const void* main;                // [RE][C] O_0 as stored (compute dtype)
+  const void* sup[KMAX_ARGS];      // [RE][C] O_k, k >= 1
+  int K, C, pass;
+  int64_t n_re;
+  const float* mean;               // pass 1: the batch mean
+  float* part;                     // [gridDim.x][C]
+};
+// Sums the partials in a fixed order. Pass 0 writes the mean; pass 1 writes 1/sqrt(var + eps),
+// the folded scale gamma / sqrt(var + eps) and shift beta - mean scale, and, if running_mean is
+// non-null, moves the running statistics by `momentum` towards the batch's (the variance
+// unbiased, n / (n - 1)).
+struct BnFinishArgs {
+  const float* part;
+  int groups, C, pass;
+  int64_t n_re;
+  float eps, momentum;
+  const float* gamma;
+  const float* beta;
+  float* mean;                     // [C]
+  float* rs;                       // [C]
+  float* scale;                    // [C]
+  float* shift;                    // [C]
+  float* running_mean;             // [C] or null
+  float* running_var;              // [C]
+};
+int bn_stats_grid(int64_t n_re);
+hipError_t launch_bn_stats(int dtype, BnStatsArgs& a, int grid, hipStream_t s);
+hipError_t launch_bn_finish(BnFinishArgs& a, hipStream_t s);
 
 // Sum of `rows` rows of `cols` floats (row stride `ld`) into dst[map(j)], in a fixed
 // order: stage 1 sums chunks of 256 rows into tmp[chunk][cols], stage 2 sums the chunks.

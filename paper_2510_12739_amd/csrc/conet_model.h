@@ -34,6 +34,10 @@ struct Layout {
   size_t tr_part_conv, tr_part_conv_rows, tr_part_w, tr_part_b, tr_part_fuse, tr_part_bce, tr_loss, tr_segs;
   size_t tr_red_tmp, tr_red_tmp_floats;
   size_t tr_levels, tr_levels_bytes;
+  // BatchNorm by batch statistics (norm = CONET_NORM_BN in a training model): per block,
+  // mean, 1/sqrt(var + eps), and the folded scale and shift (4 C floats), plus the
+  // work-groups' partial sums of one statistics pass
+  size_t tr_bn, tr_bn_part;
   size_t total;
 };
 
@@ -43,6 +47,7 @@ struct BlobOffsets {
   size_t s0[KMAX_ARGS][LMAX], o0[KMAX_ARGS][LMAX], w1[KMAX_ARGS][LMAX], b1[KMAX_ARGS][LMAX];
   size_t s1[KMAX_ARGS][LMAX], o1[KMAX_ARGS][LMAX], w2[KMAX_ARGS][LMAX], b2[KMAX_ARGS][LMAX];
   size_t gamma[LMAX], beta[LMAX], wh, bh, n;
+  size_t bn_mean[LMAX], bn_var[LMAX];  // BatchNorm running statistics (norm = CONET_NORM_BN)
 };
 
 // Activation buffers of one forward in flight (the model's own, or a serving lane's).

@@ -67,6 +67,8 @@ extern "C" conet_status conet_forward_noalloc(conet_model* M, const float* x, in
     return fail(CONET_ESHAPE, "B*T*F = %lld exceeds the %lld REs the %llu-byte static scratch holds for this model",
                 (long long)n_re, (long long)cap, (unsigned long long)CONET_NOALLOC_SCRATCH_BYTES);
   if (M->cfg.dtype == DT_FP8 && !M->scales_set) return fail(CONET_ESTATE, "FP8 model needs activation scales (set or calibrate)");
+  if (M->cfg.train && M->cfg.norm == CONET_NORM_BN)
+    return fail(CONET_EINVAL, "a BatchNorm model in training keeps its batch statistics in the model's workspace");
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");

@@ -472,6 +472,9 @@ conet_status conet_serve_create(conet_model* M, size_t mem_budget_bytes, int32_t
   if (max_batch_res < 1 || max_queue < 1) return fail(CONET_EINVAL, "max_batch_res and max_queue must be positive");
   const conet_config& c = M->cfg;
   if (c.dtype == DT_FP8 && !M->scales_set) return fail(CONET_ESTATE, "FP8 model needs activation scales");
+  if (c.train && c.norm == CONET_NORM_BN)  // batch statistics would couple the requests of a batch
+    return fail(CONET_EINVAL, "a BatchNorm model in training normalises by batch statistics: serve a model created "
+                              "from its weights with train = 0");
   // admission by memory: every lane holds buffers for lane_res REs within the budget
   int64_t lane_res = max_batch_res;
   while (lane_res > 1 && (size_t)n_streams * lane_bytes(c, lane_res) > mem_budget_bytes) lane_res /= 2;

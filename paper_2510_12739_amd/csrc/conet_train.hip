@@ -9,10 +9,16 @@
 //    at a time made the staging three times longer than the MFMAs). Each work-group
 //    loops over a share of the tiles and writes one partial row; the rows are summed in
 //    a fixed order by reduce_kernel (deterministic, no atomics).
-//  * fuse_bwd_kernel: adjoint of the head, the per-RE LayerNorm and the K-way product,
-//    dO[k] = dP * prod_{j != k} O[j] (no division, so exact zeros are handled).
+//  * fuse_bwd_kernel: adjoint of the head, the per-RE LayerNorm (or BatchNorm by batch
+//    statistics) and the K-way product, dO[k] = dP * prod_{j != k} O[j] (no division, so
+//    exact zeros are handled).
+//  * bn_stats_kernel, bn_finish_kernel: BatchNorm's per-channel batch mean and variance of
+//    the product (two passes, fixed-order sums), the folded affine the fusion epilogue
+//    applies, and the running statistics.
 //  * bce_kernel, adam_kernel, repack_kernel, gather_kernel, reduce_kernel.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "conet_common.h"
 #include "conet_kernels.h"
@@ -254,24 +260,41 @@ hipError_t launch_wgrad(int dtype, bool in_f32, int cin, int cout, WgradArgs& a,
   return hipErrorInvalidValue;
 }
 
-// ---------------------------------------------------------------- head / LN / product adjoint
+// ---------------------------------------------------------------- head / norm / product adjoint
 // HEAD: this launch also back-propagates through the LLR head (the last block) and
 // accumulates the head's gradients; the other launches leave those registers out, which
-// lets two waves share a SIMD.
-template <class Act, int C, int KB, bool HEAD>
+// lets two waves share a SIMD. BN: the norm is BatchNorm by batch statistics (per channel,
+// over the batch) instead of the per-RE LayerNorm; both share
+//   dP = (g - mean(g) - ahat mean(g ahat)) / sigma,  g = gamma dA,
+// with the means over what the statistics were taken over. For BN those batch means are
+// gamma dbeta / n and gamma dgamma / n, so pass 1 accumulates dgamma and dbeta and pass 2,
+// after their reduction, forms dP.
+template <class Act, int C, int KB, bool HEAD, bool BN>
 __global__ void __launch_bounds__(256) fuse_bwd_kernel(FuseBwdArgs a) {
   constexpr int QC = C / 4;
   const int tid = threadIdx.x, q = tid & 3, wave = tid >> 6;
   const int c0 = q * QC;
   const int m = a.m;
   constexpr int NH = HEAD ? 8 : 1;  // head outputs accumulated by this launch
+  constexpr int QB = BN ? QC : 1;
   float gam[QC], bet[QC], bet_acc[QC], gam_acc[QC], wh_acc[NH][QC], bh_acc[NH];
+  float bmu[QB], brs[QB], bg1[QB], bg2[QB];
 #pragma unroll
   for (int i = 0; i < QC; ++i) {
     gam[i] = a.fused ? a.gamma[c0 + i] : 1.f;
     bet[i] = a.fused ? a.beta[c0 + i] : 0.f;
     bet_acc[i] = 0.f;
     gam_acc[i] = 0.f;
+  }
+  if constexpr (BN) {
+    const float inv_n = 1.f / (float)a.n_re;
+#pragma unroll
+    for (int i = 0; i < QC; ++i) {
+      bmu[i] = a.bn_mu[c0 + i];
+      brs[i] = a.bn_rs[c0 + i];
+      bg1[i] = a.bn_pass == 2 ? gam[i] * a.bn_dbeta[c0 + i] * inv_n : 0.f;
+      bg2[i] = a.bn_pass == 2 ? gam[i] * a.bn_dgamma[c0 + i] * inv_n : 0.f;
+    }
   }
 #pragma unroll
   for (int j = 0; j < NH; ++j) {
@@ -297,7 +320,10 @@ __global__ void __launch_bounds__(256) fuse_bwd_kernel(FuseBwdArgs a) {
       P[i] = p;
     }
     float ah[QC], rs = 1.f;
-    if (a.fused) {
+    if constexpr (BN) {
+#pragma unroll
+      for (int i = 0; i < QC; ++i) ah[i] = (P[i] - bmu[i]) * brs[i];
+    } else if (a.fused) {
       float s = 0.f;
 #pragma unroll
       for (int i = 0; i < QC; ++i) s += P[i];
@@ -344,7 +370,26 @@ __global__ void __launch_bounds__(256) fuse_bwd_kernel(FuseBwdArgs a) {
       for (int i = 0; i < QC; ++i) dA[i] = (float)src[i];
     }
     float dO[KB][QC];
-    if (a.fused) {
+    if constexpr (BN) {
+#pragma unroll
+      for (int i = 0; i < QC; ++i) {
+        gam_acc[i] += dA[i] * ah[i];
+        bet_acc[i] += dA[i];
+      }
+      if (a.bn_pass == 1) continue;  // the batch sums are not known yet: no dO in this pass
+#pragma unroll
+      for (int i = 0; i < QC; ++i) {
+        const float dP = (gam[i] * dA[i] - bg1[i] - ah[i] * bg2[i]) * brs[i];
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) {
+          float others = 1.f;
+#pragma unroll
+          for (int jj = 0; jj < KB; ++jj)
+            if (jj != kk) others *= O[jj][i];
+          dO[kk][i] = dP * others;
+        }
+      }
+    } else if (a.fused) {
       float g1 = 0.f, g2 = 0.f, gv[QC];
 #pragma unroll
       for (int i = 0; i < QC; ++i) {
@@ -419,23 +464,123 @@ __global__ void __launch_bounds__(256) fuse_bwd_kernel(FuseBwdArgs a) {
     if ((tid & 63) == 0) red[wave][10 * C + j] = bsum;
   }
   __syncthreads();
+  if (!a.part) return;
   for (int i = tid; i < NP; i += 256)
     a.part[(size_t)blockIdx.x * NP + i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
 }
 
 hipError_t launch_fuse_bwd(int dtype, FuseBwdArgs& a, int grid, hipStream_t s) {
-#define CONET_FB(E, C_, K_) \
-  if (a.C == C_ && a.K == K_) {                                                                          \
-    if (a.head) hipLaunchKernelGGL((fuse_bwd_kernel<E, C_, K_, true>), dim3(grid), dim3(256), 0, s, a);     \
-    else hipLaunchKernelGGL((fuse_bwd_kernel<E, C_, K_, false>), dim3(grid), dim3(256), 0, s, a);           \
+  if (a.bn_mu && (!a.fused || !a.bn_rs || (a.bn_pass != 1 && a.bn_pass != 2) ||
+                  (a.bn_pass == 2 && (!a.bn_dgamma || !a.bn_dbeta))))
+    return hipErrorInvalidValue;
+#define CONET_FB(E, C_, K_, BN_)                                                                           \
+  if (a.C == C_ && a.K == K_ && (a.bn_mu != nullptr) == BN_) {                                           \
+    if (a.head) hipLaunchKernelGGL((fuse_bwd_kernel<E, C_, K_, true, BN_>), dim3(grid), dim3(256), 0, s, a); \
+    else hipLaunchKernelGGL((fuse_bwd_kernel<E, C_, K_, false, BN_>), dim3(grid), dim3(256), 0, s, a);       \
     return hipGetLastError();                                                                            \
   }
-#define CONET_FBC(E, C_) CONET_FB(E, C_, 1) CONET_FB(E, C_, 2) CONET_FB(E, C_, 3) CONET_FB(E, C_, 4)
-  if (dtype == DT_BF16) { CONET_FBC(__bf16, 16) CONET_FBC(__bf16, 32) CONET_FBC(__bf16, 64) }
-  if (dtype == DT_F32) { CONET_FBC(float, 16) CONET_FBC(float, 32) CONET_FBC(float, 64) }
+#define CONET_FBC(E, C_, BN_) CONET_FB(E, C_, 1, BN_) CONET_FB(E, C_, 2, BN_) CONET_FB(E, C_, 3, BN_) CONET_FB(E, C_, 4, BN_)
+  if (dtype == DT_BF16) {
+    CONET_FBC(__bf16, 16, false) CONET_FBC(__bf16, 32, false) CONET_FBC(__bf16, 64, false)
+    CONET_FBC(__bf16, 32, true) CONET_FBC(__bf16, 64, true)
+  }
+  if (dtype == DT_F32) {
+    CONET_FBC(float, 16, false) CONET_FBC(float, 32, false) CONET_FBC(float, 64, false)
+    CONET_FBC(float, 32, true) CONET_FBC(float, 64, true)
+  }
 #undef CONET_FBC
 #undef CONET_FB
   return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- BatchNorm statistics
+// Threads as in the adjoint above: four per RE, each over C/4 consecutive channels; the
+// product is formed in the order the fusion epilogue forms it, so both see the same P.
+template <class Act, int C>
+__global__ void __launch_bounds__(256) bn_stats_kernel(BnStatsArgs a) {
+  constexpr int QC = C / 4;
+  const int tid = threadIdx.x, q = tid & 3, wave = tid >> 6, c0 = q * QC;
+  float mu[QC], acc[QC];
+#pragma unroll
+  for (int i = 0; i < QC; ++i) {
+    mu[i] = a.pass ? a.mean[c0 + i] : 0.f;
+    acc[i] = 0.f;
+  }
+  const int64_t nthr = (int64_t)gridDim.x * 64;
+  for (int64_t re = (int64_t)blockIdx.x * 64 + (tid >> 2); re < a.n_re; re += nthr) {
+    float P[QC];
+    const Act* src = reinterpret_cast<const Act*>(a.main) + re * C + c0;
+#pragma unroll
+    for (int i = 0; i < QC; ++i) P[i] = (float)src[i];
+    for (int k = 1; k < a.K; ++k) {
+      const Act* sk = reinterpret_cast<const Act*>(a.sup[k]) + re * C + c0;
+#pragma unroll
+      for (int i = 0; i < QC; ++i) P[i] *= (float)sk[i];
+    }
+#pragma unroll
+    for (int i = 0; i < QC; ++i) {
+      const float d = P[i] - mu[i];
+      acc[i] = a.pass ? fmaf(d, d, acc[i]) : acc[i] + P[i];
+    }
+  }
+  __shared__ float red[4][C];
+#pragma unroll
+  for (int i = 0; i < QC; ++i) {
+    float x = acc[i];
+    x += __shfl_xor(x, 4);
+    x += __shfl_xor(x, 8);
+    x += __shfl_xor(x, 16);
+    x += __shfl_xor(x, 32);
+    if ((tid & 63) < 4) red[wave][c0 + i] = x;
+  }
+  __syncthreads();
+  for (int c = tid; c < C; c += 256)
+    a.part[(size_t)blockIdx.x * C + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+}
+
+// One work-group: four threads per channel sum every fourth partial, then combine.
+__global__ void __launch_bounds__(256) bn_finish_kernel(BnFinishArgs a) {
+  const int tid = threadIdx.x, c = tid >> 2, j = tid & 3;
+  float s = 0.f;
+  if (c < a.C)
+    for (int g = j; g < a.groups; g += 4) s += a.part[(size_t)g * a.C + c];
+  s += __shfl_xor(s, 1);
+  s += __shfl_xor(s, 2);
+  if (c >= a.C || j != 0) return;
+  const float n = (float)a.n_re;
+  if (a.pass == 0) {
+    a.mean[c] = s / n;
+    return;
+  }
+  const float var = s / n;
+  const float rs = 1.f / sqrtf(var + a.eps);
+  const float sc = a.gamma[c] * rs;
+  a.rs[c] = rs;
+  a.scale[c] = sc;
+  a.shift[c] = a.beta[c] - a.mean[c] * sc;
+  if (a.running_mean) {
+    const float unbiased = a.n_re > 1 ? var * (n / (n - 1.f)) : var;
+    a.running_mean[c] = (1.f - a.momentum) * a.running_mean[c] + a.momentum * a.mean[c];
+    a.running_var[c] = (1.f - a.momentum) * a.running_var[c] + a.momentum * unbiased;
+  }
+}
+
+int bn_stats_grid(int64_t n_re) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n_re + 63) / 64)); }
+
+hipError_t launch_bn_stats(int dtype, BnStatsArgs& a, int grid, hipStream_t s) {
+  if (a.n_re <= 0 || a.K < 1 || a.K > KMAX_ARGS) return hipErrorInvalidValue;
+  if (dtype == DT_BF16 && a.C == 64) hipLaunchKernelGGL((bn_stats_kernel<__bf16, 64>), dim3(grid), dim3(256), 0, s, a);
+  else if (dtype == DT_BF16 && a.C == 32) hipLaunchKernelGGL((bn_stats_kernel<__bf16, 32>), dim3(grid), dim3(256), 0, s, a);
+  else if (dtype == DT_F32 && a.C == 64) hipLaunchKernelGGL((bn_stats_kernel<float, 64>), dim3(grid), dim3(256), 0, s, a);
+  else if (dtype == DT_F32 && a.C == 32) hipLaunchKernelGGL((bn_stats_kernel<float, 32>), dim3(grid), dim3(256), 0, s, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_bn_finish(BnFinishArgs& a, hipStream_t s) {
+  if (a.C < 1 || a.C > 64 || a.groups < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(bn_finish_kernel, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- reductions

@@ -50,7 +50,7 @@ def test_workspace_grows_with_max_res():
     (dict(K=2, L=2, C=48, C_in=8, m=2), "no kernel"),
     (dict(K=2, L=2, C=32, C_in=8, m=9), "bits_per_symbol"),
     (dict(K=2, L=2, C=32, C_in=8, m=2, fuse_mask=0b100), "fuse_mask"),
-    (dict(K=2, L=2, C=32, C_in=16, m=2, norm="bn", train=True), "LayerNorm"),
+    (dict(K=2, L=2, C=16, C_in=16, m=2, norm="bn", train=True), "BatchNorm"),
 ])
 def test_invalid_configs_are_rejected_with_a_message(kw, msg):
     lib = b.load()
