@@ -337,20 +337,28 @@ static conet_status run_backward(conet_model* M, const float* dllr, hipStream_t 
       fa.eps = c.ln_eps;
       fa.n_re = n_re;
       fa.part = part_fuse;
+      fa.a_out = last ? ar.g_dc1[0] : nullptr;  // the head's input (g_dc1 is free until conv 2's adjoint)
+      HeadWgradArgs hw = {};
+      hw.A = ar.g_dc1[0]; hw.dllr = dllr; hw.m = m; hw.n_re = n_re;
+      hw.part = part_fuse; hw.ld = 10 * C + 8; hw.col0 = 2 * C;
+      auto head_wgrad = [&]() { return last ? launch_head_wgrad(dt, C, hw, FUSE_GRID, s) : hipSuccess; };
       if (fuse && c.norm == CONET_NORM_BN) {  // batch statistics: two passes around the reduction
         const float* bn = reinterpret_cast<const float*>(ws + lay.tr_bn) + (size_t)4 * C * l;
         fa.bn_mu = bn;
         fa.bn_rs = bn + C;
         fa.bn_pass = 1;
         e = launch_fuse_bwd(dt, fa, FUSE_GRID, s);
+        if (e == hipSuccess) e = head_wgrad();
         if (e == hipSuccess) e = reduce(ri);
         fa.bn_pass = 2;
         fa.bn_dgamma = grad + bo.gamma[l];
         fa.bn_dbeta = grad + bo.beta[l];
         fa.part = nullptr;
+        fa.a_out = nullptr;
         if (e == hipSuccess) e = launch_fuse_bwd(dt, fa, FUSE_GRID, s);
       } else {
         e = launch_fuse_bwd(dt, fa, FUSE_GRID, s);
+        if (e == hipSuccess) e = head_wgrad();
         if (e == hipSuccess) e = reduce(ri);
       }
       if (e != hipSuccess) return hip_fail(e, "head / fusion backward");

@@ -226,8 +226,21 @@ struct FuseBwdArgs {
   const float* bn_dgamma;
   const float* bn_dbeta;
   int bn_pass;
+  void* a_out;                     // head launch: [RE][C] the head's input A (compute dtype), or null
 };
 hipError_t launch_fuse_bwd(int dtype, FuseBwdArgs& a, int grid, hipStream_t s);
+
+// Head weight gradient from the stored head input: part[row][col0 + j C + c] = this row's share
+// of sum_re dllr[re][j] A[re][c] (one row per work-group, row stride ld floats).
+struct HeadWgradArgs {
+  const void* A;                   // [RE][C] compute dtype
+  const float* dllr;               // [RE][m]
+  int m;
+  int64_t n_re;
+  float* part;
+  int ld, col0;
+};
+hipError_t launch_head_wgrad(int dtype, int C, HeadWgradArgs& a, int grid, hipStream_t s);
 
 // BatchNorm statistics of the product P = O_0 O_1 ... O_{K-1} over every RE of a batch, per
 // channel. Pass 0: work-group partial sums of P; pass 1: of (P - mean)^2 (mean from pass 0).

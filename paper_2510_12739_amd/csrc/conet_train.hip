@@ -69,34 +69,52 @@ __device__ __forceinline__ i32x4 shift_window(const i32x4& lo, const i32x4& hi, 
 template <class A>
 constexpr int wg_tw() { return 4 * A::VEC; }  // subcarriers per tile: one MFMA K step per OFDM symbol
 
+// Eight waves, two per SIMD: while one waits on its LDS reads the other issues MFMAs (with four
+// waves, one per SIMD, every fragment read stalled its wave's MFMAs). Waves w and w + 4 own the
+// same filter-gradient tile (all output channels x every fourth 16-wide (tap, channel) tile)
+// over the even and the odd OFDM symbols, so each fragment read from LDS still feeds as many
+// MFMAs as with four waves; the two halves are added through LDS at the end.
+constexpr int WG_NW = 8, WG_NWK = 8;
+
 template <class A, class InT, int CIN, int COUT>
-__global__ void __launch_bounds__(256, 1) wgrad_kernel(WgradArgs args) {
+__global__ void __launch_bounds__(WG_NW * 64, 2) wgrad_kernel(WgradArgs args) {
   using E = typename A::Op;
   using Act = typename A::Act;
   using AccV = typename A::AccV;
-  constexpr int VEC = A::VEC, TW = wg_tw<A>(), NW = 4, NT = 256;
+  constexpr int VEC = A::VEC, TW = wg_tw<A>(), NW = WG_NW, NT = NW * 64;
   constexpr int ICOLS = TW + 8;                                    // TW+2 staged, room for shifted reads
   constexpr int DS = TMAX * TW * (int)sizeof(E) + 16;              // dOut channel stride (bytes)
   constexpr int IS = TROWS * ICOLS * (int)sizeof(E) + 16;          // In channel stride (bytes)
-  constexpr int NOT = COUT / 16, NKT = 9 * CIN / 16, KTW = (NKT + NW - 1) / NW;
+  constexpr int NWK = WG_NWK, NWT = NW / NWK;                       // waves along (tap, ch) and along symbols
+  constexpr int NOT = COUT / 16, NKT = 9 * CIN / 16, KTW = (NKT + NWK - 1) / NWK;
   constexpr int EPD = 16 / (int)sizeof(Act), CPD = COUT / EPD;     // dOut: elements / chunks per RE
   constexpr int EPI = 16 / (int)sizeof(InT) < 4 ? 4 : 16 / (int)sizeof(InT), CPI = CIN / EPI;
   static_assert(NT % CPD == 0 && NT % CPI == 0 && CIN % 16 == 0 && COUT % 16 == 0, "shape");
+  // Bank swizzle. A staging store instruction writes one channel of each of the wave's channel
+  // chunks (8 lanes per RE); the chunks' channel rows lie a multiple of 32 banks apart, so
+  // without it every chunk hit the same banks (an 8-way conflict). The 16-byte position block
+  // of a channel row is XORed with the channel's chunk index (mod 8): stores spread over the
+  // banks, and a fragment read (8 consecutive positions of one row) stays one aligned block.
+  // Both tiles' rows hold a whole number of 8-block groups, so the XOR stays inside the row.
+  static_assert((TMAX * TW) % (8 * VEC) == 0 && (TROWS * ICOLS) % (8 * VEC) == 0, "swizzle groups");
+  auto swzD = [](int ch) { return ((ch / EPD) & 7) * VEC; };
+  auto swzI = [](int ch) { return ((ch / EPI) & 7) * VEC; };
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   uint8_t* ldsD = lds;
   uint8_t* ldsI = lds + COUT * DS;
 
   const int k = blockIdx.y;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, col = lane & 15;
+  const int wk = wave % NWK, wt = wave / NWK;
   const Act* dout = reinterpret_cast<const Act*>(args.dout[k]);
   const InT* in = reinterpret_cast<const InT*>(args.in[k]);
   const int pro = args.prologue == 0 ? 0 : (args.pre_s[k] ? 1 : 2);
   const int ccD = tid % CPD, ccI = tid % CPI;
-  float sv[EPI], ov[EPI];
-  if (pro == 1) {
-#pragma unroll
-    for (int i = 0; i < EPI; ++i) { sv[i] = args.pre_s[k][ccI * EPI + i]; ov[i] = args.pre_o[k][ccI * EPI + i]; }
-  }
+  // the prologue's per-channel affine sits in LDS behind the tiles and is read where it is
+  // applied (in registers for the whole kernel it pushed the accumulators into scratch)
+  float* pre_lds = reinterpret_cast<float*>(lds + COUT * DS + CIN * IS);
+  if (pro == 1)
+    for (int i = tid; i < 2 * CIN; i += NT) pre_lds[i] = i < CIN ? args.pre_s[k][i] : args.pre_o[k][i - CIN];
   AccV acc[NOT][KTW];
 #pragma unroll
   for (int ot = 0; ot < NOT; ++ot)
@@ -112,112 +130,141 @@ __global__ void __launch_bounds__(256, 1) wgrad_kernel(WgradArgs args) {
     const int f0 = (tile - b * args.tiles_per_slot) * TW;
     const int64_t re_base = (int64_t)b * T * args.F;
     __syncthreads();  // the previous tile's LDS reads are done
-    // dOut tile [TMAX][TW] transposed to [o][t][c]. All of a thread's 16-byte loads are
-    // issued before any is consumed, so their latencies overlap.
-    {
-      constexpr int ND = (TMAX * TW * CPD + NT - 1) / NT;
-      i32x4 raw[ND];
+    // dOut tile [TMAX][TW] transposed to [o][t][c]. A thread's 16-byte loads are issued in
+    // batches of up to SB before any of the batch is consumed, so their latencies overlap.
+    constexpr int SB = 4;
+    constexpr int ND = (TMAX * TW * CPD + NT - 1) / NT;
 #pragma unroll
-      for (int u = 0; u < ND; ++u) {
+    for (int u0 = 0; u0 < ND; u0 += SB) {
+      i32x4 raw[SB];
+#pragma unroll
+      for (int u = u0; u < u0 + SB && u < ND; ++u) {
         const int idx = tid + u * NT;
         const int pos = idx / CPD;
         const int t = pos / TW, c = pos - t * TW, f = f0 + c;
-        raw[u] = i32x4{0, 0, 0, 0};
+        raw[u - u0] = i32x4{0, 0, 0, 0};
         if (idx < TMAX * TW * CPD && t < T && f < args.F)
-          raw[u] = *reinterpret_cast<const i32x4*>(dout + (re_base + (int64_t)t * args.F + f) * COUT + ccD * EPD);
+          raw[u - u0] = *reinterpret_cast<const i32x4*>(dout + (re_base + (int64_t)t * args.F + f) * COUT + ccD * EPD);
       }
 #pragma unroll
-      for (int u = 0; u < ND; ++u) {
+      for (int u = u0; u < u0 + SB && u < ND; ++u) {
         const int idx = tid + u * NT;
         if (idx >= TMAX * TW * CPD) break;
         const int pos = idx / CPD;
         const int t = pos / TW, c = pos - t * TW;
         float v[EPD];
-        to_elems(raw[u], v, (const Act*)nullptr);  // zero outside the slot
+        to_elems(raw[u - u0], v, (const Act*)nullptr);  // zero outside the slot
 #pragma unroll
         for (int i = 0; i < EPD; ++i) {
           bsum[i] += v[i];
-          st_elem<E>(ldsD + (ccD * EPD + i) * DS + (t * TW + c) * (int)sizeof(E), v[i]);
+          st_elem<E>(ldsD + (ccD * EPD + i) * DS + ((t * TW + c) ^ swzD(ccD * EPD + i)) * (int)sizeof(E), v[i]);
         }
       }
     }
     // In halo tile [TROWS][TW+2] (prologue, then zero padding) transposed to [ch][r][c]
-    {
-      constexpr int NI = (TROWS * (TW + 2) * CPI + NT - 1) / NT;
-      i32x4 raw[NI];
-      bool ok[NI];
+    constexpr int NI = (TROWS * (TW + 2) * CPI + NT - 1) / NT;
 #pragma unroll
-      for (int u = 0; u < NI; ++u) {
+    for (int u0 = 0; u0 < NI; u0 += SB) {
+      i32x4 raw[SB];
+      bool ok[SB];
+#pragma unroll
+      for (int u = u0; u < u0 + SB && u < NI; ++u) {
         const int idx = tid + u * NT;
         const int pos = idx / CPI;
         const int r = pos / (TW + 2), c = pos - r * (TW + 2);
         const int t = r - 1, f = f0 + c - 1;
-        ok[u] = idx < TROWS * (TW + 2) * CPI && t >= 0 && t < T && f >= 0 && f < args.F;
-        raw[u] = i32x4{0, 0, 0, 0};
-        if (ok[u]) raw[u] = *reinterpret_cast<const i32x4*>(in + (re_base + (int64_t)t * args.F + f) * CIN + ccI * EPI);
+        ok[u - u0] = idx < TROWS * (TW + 2) * CPI && t >= 0 && t < T && f >= 0 && f < args.F;
+        raw[u - u0] = i32x4{0, 0, 0, 0};
+        if (ok[u - u0])
+          raw[u - u0] = *reinterpret_cast<const i32x4*>(in + (re_base + (int64_t)t * args.F + f) * CIN + ccI * EPI);
       }
 #pragma unroll
-      for (int u = 0; u < NI; ++u) {
+      for (int u = u0; u < u0 + SB && u < NI; ++u) {
         const int idx = tid + u * NT;
         if (idx >= TROWS * (TW + 2) * CPI) break;
         const int pos = idx / CPI;
         const int r = pos / (TW + 2), c = pos - r * (TW + 2);
         float v[EPI];
         if constexpr (sizeof(InT) == 4) {
-          const float* q = reinterpret_cast<const float*>(&raw[u]);
+          const float* q = reinterpret_cast<const float*>(&raw[u - u0]);
 #pragma unroll
           for (int i = 0; i < EPI; ++i) v[i] = i < 4 ? q[i] : 0.f;
         } else {
-          to_elems(raw[u], v, (const InT*)nullptr);
+          to_elems(raw[u - u0], v, (const InT*)nullptr);
         }
-        if (ok[u]) {
+        if (ok[u - u0]) {
           if (pro == 1) {
 #pragma unroll
-            for (int i = 0; i < EPI; ++i) v[i] = fmaxf(sv[i] * v[i] + ov[i], 0.f);
+            for (int i = 0; i < EPI; ++i)
+              v[i] = fmaxf(pre_lds[ccI * EPI + i] * v[i] + pre_lds[CIN + ccI * EPI + i], 0.f);
           } else if (pro == 2) {
 #pragma unroll
             for (int i = 0; i < EPI; ++i) v[i] = fmaxf(v[i], 0.f);
           }
         }  // else: zero padding (the raw value is zero)
 #pragma unroll
-        for (int i = 0; i < EPI; ++i) st_elem<E>(ldsI + (ccI * EPI + i) * IS + (r * ICOLS + c) * (int)sizeof(E), v[i]);
+        for (int i = 0; i < EPI; ++i)
+          st_elem<E>(ldsI + (ccI * EPI + i) * IS + ((r * ICOLS + c) ^ swzI(ccI * EPI + i)) * (int)sizeof(E), v[i]);
       }
     }
     __syncthreads();
-    for (int t = 0; t < T; ++t) {  // one MFMA K step per OFDM symbol: TW REs = 4 lane groups x VEC
+    for (int t = wt; t < T; t += NWT) {  // one MFMA K step per OFDM symbol: TW REs = 4 lane groups x VEC
       i32x4 af[NOT];
 #pragma unroll
       for (int ot = 0; ot < NOT; ++ot)
-        af[ot] = *reinterpret_cast<const i32x4*>(ldsD + (ot * 16 + col) * DS + (t * TW + g * VEC) * (int)sizeof(E));
+        af[ot] = *reinterpret_cast<const i32x4*>(ldsD + (ot * 16 + col) * DS +
+                                                  ((t * TW + g * VEC) ^ swzD(ot * 16 + col)) * (int)sizeof(E));
 #pragma unroll
       for (int j = 0; j < KTW; ++j) {
-        const int kt = wave + NW * j;
+        const int kt = wk + NWK * j;
         if (kt >= NKT) break;
         const int tap = kt / (CIN / 16), ch = (kt - tap * (CIN / 16)) * 16 + col;
         const int dt = tap / 3, s = tap - dt * 3;
-        const uint8_t* base = ldsI + ch * IS + ((t + dt) * ICOLS + g * VEC) * (int)sizeof(E);
-        const i32x4 lo = *reinterpret_cast<const i32x4*>(base);
+        const uint8_t* row = ldsI + ch * IS;
+        const int p0 = (t + dt) * ICOLS + g * VEC, sw = swzI(ch);
+        const i32x4 lo = *reinterpret_cast<const i32x4*>(row + (p0 ^ sw) * (int)sizeof(E));
         i32x4 bfr = lo;
-        if (s != 0) bfr = shift_window<E>(lo, *reinterpret_cast<const i32x4*>(base + 16), s);
+        if (s != 0) bfr = shift_window<E>(lo, *reinterpret_cast<const i32x4*>(row + ((p0 + VEC) ^ sw) * (int)sizeof(E)), s);
 #pragma unroll
         for (int ot = 0; ot < NOT; ++ot) acc[ot][j] = A::mma(&af[ot], &bfr, acc[ot][j]);
       }
     }
   }
-  // partial dW: D[o][k] in lane (col = k within the k-tile, rows 4g + i)
+  // partial dW: D[o][k] in lane (col = k within the k-tile, rows 4g + i). The odd-symbol waves
+  // hand their sums to the even-symbol waves through LDS, JH k-tiles per round.
   float* pw = args.part_w[k] + (size_t)blockIdx.x * COUT * 9 * CIN;
+  float* red = reinterpret_cast<float*>(lds);
+  constexpr int JH = (KTW + 1) / 2;
+  static_assert((size_t)NWK * JH * NOT * 4 * 64 * 4 <= (size_t)COUT * DS + (size_t)CIN * IS &&
+                (size_t)NT * EPD * 4 <= (size_t)COUT * DS + (size_t)CIN * IS, "reduction area exceeds the tiles' LDS");
 #pragma unroll
-  for (int j = 0; j < KTW; ++j) {
-    const int kt = wave + NW * j;
-    if (kt >= NKT) break;
+  for (int j0 = 0; j0 < KTW; j0 += JH) {
+    __syncthreads();  // the MFMA loop's (or the previous round's) LDS reads are done
+    if (NWT > 1 && wt == 1) {
 #pragma unroll
-    for (int ot = 0; ot < NOT; ++ot)
+      for (int j = j0; j < j0 + JH && j < KTW; ++j)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) pw[(size_t)(ot * 16 + 4 * g + i) * 9 * CIN + kt * 16 + col] = acc[ot][j][i];
+        for (int ot = 0; ot < NOT; ++ot)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) red[(((wk * JH + j - j0) * NOT + ot) * 4 + i) * 64 + lane] = acc[ot][j][i];
+    }
+    __syncthreads();
+    if (wt == 0) {
+#pragma unroll
+      for (int j = j0; j < j0 + JH && j < KTW; ++j) {
+        const int kt = wk + NWK * j;
+        if (kt >= NKT) break;
+#pragma unroll
+        for (int ot = 0; ot < NOT; ++ot)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            pw[(size_t)(ot * 16 + 4 * g + i) * 9 * CIN + kt * 16 + col] =
+                acc[ot][j][i] + (NWT > 1 ? red[(((wk * JH + j - j0) * NOT + ot) * 4 + i) * 64 + lane] : 0.f);
+      }
+    }
   }
   // partial db: threads with the same channel chunk hold disjoint RE sums
   __syncthreads();
-  float* red = reinterpret_cast<float*>(lds);
 #pragma unroll
   for (int i = 0; i < EPD; ++i) red[tid * EPD + i] = bsum[i];
   __syncthreads();
@@ -233,14 +280,15 @@ template <class A, class InT, int CIN, int COUT>
 static hipError_t launch_wgrad_t(WgradArgs& a, int grid_y, hipStream_t s) {
   using E = typename A::Op;
   constexpr int TW = wg_tw<A>();
-  constexpr size_t lds = (size_t)COUT * (TMAX * TW * sizeof(E) + 16) + (size_t)CIN * (TROWS * (TW + 8) * sizeof(E) + 16);
+  constexpr size_t lds = (size_t)COUT * (TMAX * TW * sizeof(E) + 16) + (size_t)CIN * (TROWS * (TW + 8) * sizeof(E) + 16) +
+                        2 * CIN * sizeof(float);
   static_assert(lds <= 160 * 1024, "wgrad tiles exceed LDS");
   a.tw = TW;
   const int grid = wgrad_grid(a.n_tiles);
   hipError_t e = hipFuncSetAttribute((const void*)wgrad_kernel<A, InT, CIN, COUT>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((wgrad_kernel<A, InT, CIN, COUT>), dim3(grid, grid_y), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((wgrad_kernel<A, InT, CIN, COUT>), dim3(grid, grid_y), dim3(WG_NW * 64), lds, s, a);
   return hipGetLastError();
 }
 
@@ -261,9 +309,10 @@ hipError_t launch_wgrad(int dtype, bool in_f32, int cin, int cout, WgradArgs& a,
 }
 
 // ---------------------------------------------------------------- head / norm / product adjoint
-// HEAD: this launch also back-propagates through the LLR head (the last block) and
-// accumulates the head's gradients; the other launches leave those registers out, which
-// lets two waves share a SIMD. BN: the norm is BatchNorm by batch statistics (per channel,
+// HEAD: this launch also back-propagates through the LLR head (the last block), accumulates
+// the head bias gradient and stores the head's input A for head_wgrad_kernel, which forms the
+// head weight gradient (held here, its m x C/4 accumulators per thread left one wave per
+// SIMD: 2.7x the time of the other launches). BN: the norm is BatchNorm by batch statistics (per channel,
 // over the batch) instead of the per-RE LayerNorm; both share
 //   dP = (g - mean(g) - ahat mean(g ahat)) / sigma,  g = gamma dA,
 // with the means over what the statistics were taken over. For BN those batch means are
@@ -277,7 +326,7 @@ __global__ void __launch_bounds__(256) fuse_bwd_kernel(FuseBwdArgs a) {
   const int m = a.m;
   constexpr int NH = HEAD ? 8 : 1;  // head outputs accumulated by this launch
   constexpr int QB = BN ? QC : 1;
-  float gam[QC], bet[QC], bet_acc[QC], gam_acc[QC], wh_acc[NH][QC], bh_acc[NH];
+  float gam[QC], bet[QC], bet_acc[QC], gam_acc[QC], bh_acc[NH];
   float bmu[QB], brs[QB], bg1[QB], bg2[QB];
 #pragma unroll
   for (int i = 0; i < QC; ++i) {
@@ -297,11 +346,7 @@ __global__ void __launch_bounds__(256) fuse_bwd_kernel(FuseBwdArgs a) {
     }
   }
 #pragma unroll
-  for (int j = 0; j < NH; ++j) {
-    bh_acc[j] = 0.f;
-#pragma unroll
-    for (int i = 0; i < QC; ++i) wh_acc[j][i] = 0.f;
-  }
+  for (int j = 0; j < NH; ++j) bh_acc[j] = 0.f;
   const float invC = 1.f / (float)C;
   const int64_t nthr = (int64_t)gridDim.x * 64;
   for (int64_t re = (int64_t)blockIdx.x * 64 + (tid >> 2); re < a.n_re; re += nthr) {
@@ -353,16 +398,14 @@ __global__ void __launch_bounds__(256) fuse_bwd_kernel(FuseBwdArgs a) {
           if (j < m) t += a.Wh[j * C + c0 + i] * dl[j];
         dA[i] = t;
       }
-      // head parameters: A = gamma ahat + beta (fused) or O[0] (unfused)
+      // head bias; the head's input A = gamma ahat + beta (fused) or O[0] (unfused) is stored
 #pragma unroll
-      for (int j = 0; j < NH; ++j) {
-        if (j >= m) continue;
-        if (q == 0) bh_acc[j] += dl[j];
+      for (int j = 0; j < NH; ++j)
+        if (j < m && q == 0) bh_acc[j] += dl[j];
+      if (a.a_out) {
+        Act* dst = reinterpret_cast<Act*>(a.a_out) + re * C + c0;
 #pragma unroll
-        for (int i = 0; i < QC; ++i) {
-          const float Av = a.fused ? gam[i] * ah[i] + bet[i] : O[0][i];
-          wh_acc[j][i] += dl[j] * Av;
-        }
+        for (int i = 0; i < QC; ++i) dst[i] = (Act)(a.fused ? gam[i] * ah[i] + bet[i] : O[0][i]);
       }
     } else {
       const Act* src = reinterpret_cast<const Act*>(a.dA) + re * C + c0;
@@ -454,12 +497,10 @@ __global__ void __launch_bounds__(256) fuse_bwd_kernel(FuseBwdArgs a) {
     if ((tid & 63) < 4) { red[wave][c0 + i] = ga; red[wave][C + c0 + i] = ba; }
   }
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {  // head gradients (zero rows for the other launches)
+  for (int j = 0; j < 8; ++j) {  // head weight columns: zero here (head_wgrad_kernel writes them)
 #pragma unroll
-    for (int i = 0; i < QC; ++i) {
-      const float w = j < NH ? wsum(wh_acc[j < NH ? j : 0][i]) : 0.f;
-      if ((tid & 63) < 4) red[wave][2 * C + j * C + c0 + i] = w;
-    }
+    for (int i = 0; i < QC; ++i)
+      if ((tid & 63) < 4) red[wave][2 * C + j * C + c0 + i] = 0.f;
     const float bsum = j < NH ? wsum(bh_acc[j < NH ? j : 0]) : 0.f;
     if ((tid & 63) == 0) red[wave][10 * C + j] = bsum;
   }
@@ -490,6 +531,62 @@ hipError_t launch_fuse_bwd(int dtype, FuseBwdArgs& a, int grid, hipStream_t s) {
   }
 #undef CONET_FBC
 #undef CONET_FB
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- head weight gradient
+// dWh[j][c] = sum over REs of dLLR[re][j] A[re][c], written into the head-weight columns of
+// the fusion adjoint's partial rows (same grid, one row per work-group). A lane owns one
+// 16-byte chunk of channels of one RE per step (a wave covers 64 / (C / EPV) REs), keeps
+// m x EPV sums, and the lanes and waves of a work-group are summed in a fixed order.
+template <class Act, int C>
+__global__ void __launch_bounds__(256) head_wgrad_kernel(HeadWgradArgs a) {
+  constexpr int EPV = 16 / (int)sizeof(Act), CPR = C / EPV, RPW = 64 / CPR;
+  static_assert(C % EPV == 0 && 64 % CPR == 0, "shape");
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int cc = lane % CPR, rsub = lane / CPR;
+  const int m = a.m;
+  float acc[8][EPV];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int e = 0; e < EPV; ++e) acc[j][e] = 0.f;
+  const int64_t step = (int64_t)gridDim.x * 4 * RPW;
+  for (int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * RPW; r0 < a.n_re; r0 += step) {
+    const int64_t re = r0 + rsub;
+    if (re >= a.n_re) continue;
+    const i32x4 raw = *reinterpret_cast<const i32x4*>(reinterpret_cast<const Act*>(a.A) + re * C + cc * EPV);
+    const Act* av = reinterpret_cast<const Act*>(&raw);
+    float dl[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) dl[j] = j < m ? a.dllr[re * m + j] : 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int e = 0; e < EPV; ++e) acc[j][e] = fmaf(dl[j], (float)av[e], acc[j][e]);
+  }
+  __shared__ float red[4][8 * C];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int e = 0; e < EPV; ++e) {
+      float x = acc[j][e];
+#pragma unroll
+      for (int o = CPR; o < 64; o <<= 1) x += __shfl_xor(x, o);
+      if (rsub == 0) red[wave][j * C + cc * EPV + e] = x;
+    }
+  __syncthreads();
+  for (int i = tid; i < m * C; i += 256)
+    a.part[(size_t)blockIdx.x * a.ld + a.col0 + i] = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+}
+
+hipError_t launch_head_wgrad(int dtype, int C, HeadWgradArgs& a, int grid, hipStream_t s) {
+  if (a.m < 1 || a.m > 8 || a.n_re <= 0) return hipErrorInvalidValue;
+#define CONET_HW(E, C_) \
+  if (C == C_) { hipLaunchKernelGGL((head_wgrad_kernel<E, C_>), dim3(grid), dim3(256), 0, s, a); return hipGetLastError(); }
+  if (dtype == DT_BF16) { CONET_HW(__bf16, 16) CONET_HW(__bf16, 32) CONET_HW(__bf16, 64) }
+  if (dtype == DT_F32) { CONET_HW(float, 16) CONET_HW(float, 32) CONET_HW(float, 64) }
+#undef CONET_HW
   return hipErrorInvalidValue;
 }
 
