@@ -70,11 +70,23 @@ template <class A>
 constexpr int wg_tw() { return 4 * A::VEC; }  // subcarriers per tile: one MFMA K step per OFDM symbol
 
 // Eight waves, two per SIMD: while one waits on its LDS reads the other issues MFMAs (with four
-// waves, one per SIMD, every fragment read stalled its wave's MFMAs). Waves w and w + 4 own the
-// same filter-gradient tile (all output channels x every fourth 16-wide (tap, channel) tile)
-// over the even and the odd OFDM symbols, so each fragment read from LDS still feeds as many
-// MFMAs as with four waves; the two halves are added through LDS at the end.
-constexpr int WG_NW = 8, WG_NWK = 8;
+// waves, one per SIMD, every fragment read stalled its wave's MFMAs). Wave w owns 16-wide
+// (tap, channel) tiles kt = w, w + 8, ...: channel chunk w % (CIN/16) of taps w / (CIN/16) +
+// j 8 / (CIN/16); each wave group's taps are compile-time constants of its own instantiation
+// of the MFMA loop, so the tap offsets and the funnel shifts fold.
+constexpr int WG_NW = 8;
+
+// f(std::integral_constant<int, g>) for the runtime g in [0, N)
+template <int N, class F>
+__device__ __forceinline__ void dispatch_group(int g, F&& f) {
+  if constexpr (N > 0) {
+    if (g == N - 1) {
+      f(std::integral_constant<int, N - 1>{});
+      return;
+    }
+    dispatch_group<N - 1>(g, f);
+  }
+}
 
 template <class A, class InT, int CIN, int COUT>
 __global__ void __launch_bounds__(WG_NW * 64, 2) wgrad_kernel(WgradArgs args) {
@@ -85,8 +97,9 @@ __global__ void __launch_bounds__(WG_NW * 64, 2) wgrad_kernel(WgradArgs args) {
   constexpr int ICOLS = TW + 8;                                    // TW+2 staged, room for shifted reads
   constexpr int DS = TMAX * TW * (int)sizeof(E) + 16;              // dOut channel stride (bytes)
   constexpr int IS = TROWS * ICOLS * (int)sizeof(E) + 16;          // In channel stride (bytes)
-  constexpr int NWK = WG_NWK, NWT = NW / NWK;                       // waves along (tap, ch) and along symbols
-  constexpr int NOT = COUT / 16, NKT = 9 * CIN / 16, KTW = (NKT + NWK - 1) / NWK;
+  constexpr int NOT = COUT / 16, NKT = 9 * CIN / 16, KTW = (NKT + NW - 1) / NW;
+  constexpr int CPT16 = CIN / 16, NG = NW / CPT16;                 // 16-channel chunks per tap, wave groups
+  static_assert(NW % CPT16 == 0, "waves must cover whole taps");
   constexpr int EPD = 16 / (int)sizeof(Act), CPD = COUT / EPD;     // dOut: elements / chunks per RE
   constexpr int EPI = 16 / (int)sizeof(InT) < 4 ? 4 : 16 / (int)sizeof(InT), CPI = CIN / EPI;
   static_assert(NT % CPD == 0 && NT % CPI == 0 && CIN % 16 == 0 && COUT % 16 == 0, "shape");
@@ -105,7 +118,6 @@ __global__ void __launch_bounds__(WG_NW * 64, 2) wgrad_kernel(WgradArgs args) {
 
   const int k = blockIdx.y;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, col = lane & 15;
-  const int wk = wave % NWK, wt = wave / NWK;
   const Act* dout = reinterpret_cast<const Act*>(args.dout[k]);
   const InT* in = reinterpret_cast<const InT*>(args.in[k]);
   const int pro = args.prologue == 0 ? 0 : (args.pre_s[k] ? 1 : 2);
@@ -208,61 +220,46 @@ __global__ void __launch_bounds__(WG_NW * 64, 2) wgrad_kernel(WgradArgs args) {
       }
     }
     __syncthreads();
-    for (int t = wt; t < T; t += NWT) {  // one MFMA K step per OFDM symbol: TW REs = 4 lane groups x VEC
-      i32x4 af[NOT];
+    const int ch = (wave % CPT16) * 16 + col;  // this lane's input channel in every tap
+    const uint8_t* row = ldsI + ch * IS;
+    const int sw = swzI(ch);
+    dispatch_group<NG>(wave / CPT16, [&](auto group) {
+      constexpr int G = decltype(group)::value;  // taps G, G + NG, G + 2 NG, ...
+      for (int t = 0; t < T; ++t) {  // one MFMA K step per OFDM symbol: TW REs = 4 lane groups x VEC
+        i32x4 af[NOT];
 #pragma unroll
-      for (int ot = 0; ot < NOT; ++ot)
-        af[ot] = *reinterpret_cast<const i32x4*>(ldsD + (ot * 16 + col) * DS +
-                                                  ((t * TW + g * VEC) ^ swzD(ot * 16 + col)) * (int)sizeof(E));
+        for (int ot = 0; ot < NOT; ++ot)
+          af[ot] = *reinterpret_cast<const i32x4*>(ldsD + (ot * 16 + col) * DS +
+                                                    ((t * TW + g * VEC) ^ swzD(ot * 16 + col)) * (int)sizeof(E));
 #pragma unroll
-      for (int j = 0; j < KTW; ++j) {
-        const int kt = wk + NWK * j;
-        if (kt >= NKT) break;
-        const int tap = kt / (CIN / 16), ch = (kt - tap * (CIN / 16)) * 16 + col;
-        const int dt = tap / 3, s = tap - dt * 3;
-        const uint8_t* row = ldsI + ch * IS;
-        const int p0 = (t + dt) * ICOLS + g * VEC, sw = swzI(ch);
-        const i32x4 lo = *reinterpret_cast<const i32x4*>(row + (p0 ^ sw) * (int)sizeof(E));
-        i32x4 bfr = lo;
-        if (s != 0) bfr = shift_window<E>(lo, *reinterpret_cast<const i32x4*>(row + ((p0 + VEC) ^ sw) * (int)sizeof(E)), s);
+        for (int j = 0; j < KTW; ++j) {
+          const int tap = G + NG * j;
+          if (tap >= 9) break;
+          const int dt = tap / 3, s = tap - dt * 3;
+          const int p0 = (t + dt) * ICOLS + g * VEC;
+          const i32x4 lo = *reinterpret_cast<const i32x4*>(row + (p0 ^ sw) * (int)sizeof(E));
+          i32x4 bfr = lo;
+          if (s != 0)
+            bfr = shift_window<E>(lo, *reinterpret_cast<const i32x4*>(row + ((p0 + VEC) ^ sw) * (int)sizeof(E)), s);
 #pragma unroll
-        for (int ot = 0; ot < NOT; ++ot) acc[ot][j] = A::mma(&af[ot], &bfr, acc[ot][j]);
+          for (int ot = 0; ot < NOT; ++ot) acc[ot][j] = A::mma(&af[ot], &bfr, acc[ot][j]);
+        }
       }
-    }
+    });
   }
-  // partial dW: D[o][k] in lane (col = k within the k-tile, rows 4g + i). The odd-symbol waves
-  // hand their sums to the even-symbol waves through LDS, JH k-tiles per round.
+  // partial dW: D[o][k] in lane (col = k within the k-tile, rows 4g + i)
   float* pw = args.part_w[k] + (size_t)blockIdx.x * COUT * 9 * CIN;
-  float* red = reinterpret_cast<float*>(lds);
-  constexpr int JH = (KTW + 1) / 2;
-  static_assert((size_t)NWK * JH * NOT * 4 * 64 * 4 <= (size_t)COUT * DS + (size_t)CIN * IS &&
-                (size_t)NT * EPD * 4 <= (size_t)COUT * DS + (size_t)CIN * IS, "reduction area exceeds the tiles' LDS");
 #pragma unroll
-  for (int j0 = 0; j0 < KTW; j0 += JH) {
-    __syncthreads();  // the MFMA loop's (or the previous round's) LDS reads are done
-    if (NWT > 1 && wt == 1) {
+  for (int j = 0; j < KTW; ++j) {
+    const int kt = wave + NW * j;
+    if (kt >= NKT) break;
 #pragma unroll
-      for (int j = j0; j < j0 + JH && j < KTW; ++j)
+    for (int ot = 0; ot < NOT; ++ot)
 #pragma unroll
-        for (int ot = 0; ot < NOT; ++ot)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) red[(((wk * JH + j - j0) * NOT + ot) * 4 + i) * 64 + lane] = acc[ot][j][i];
-    }
-    __syncthreads();
-    if (wt == 0) {
-#pragma unroll
-      for (int j = j0; j < j0 + JH && j < KTW; ++j) {
-        const int kt = wk + NWK * j;
-        if (kt >= NKT) break;
-#pragma unroll
-        for (int ot = 0; ot < NOT; ++ot)
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            pw[(size_t)(ot * 16 + 4 * g + i) * 9 * CIN + kt * 16 + col] =
-                acc[ot][j][i] + (NWT > 1 ? red[(((wk * JH + j - j0) * NOT + ot) * 4 + i) * 64 + lane] : 0.f);
-      }
-    }
+      for (int i = 0; i < 4; ++i) pw[(size_t)(ot * 16 + 4 * g + i) * 9 * CIN + kt * 16 + col] = acc[ot][j][i];
   }
+  float* red = reinterpret_cast<float*>(lds);
+  static_assert((size_t)NT * EPD * 4 <= (size_t)COUT * DS + (size_t)CIN * IS, "bias reduction exceeds the tiles' LDS");
   // partial db: threads with the same channel chunk hold disjoint RE sums
   __syncthreads();
 #pragma unroll
