@@ -95,8 +95,11 @@ __global__ void __launch_bounds__(WG_NW * 64, 2) wgrad_kernel(WgradArgs args) {
   using AccV = typename A::AccV;
   constexpr int VEC = A::VEC, TW = wg_tw<A>(), NW = WG_NW, NT = NW * 64;
   constexpr int ICOLS = TW + 8;                                    // TW+2 staged, room for shifted reads
-  constexpr int DS = TMAX * TW * (int)sizeof(E) + 16;              // dOut channel stride (bytes)
-  constexpr int IS = TROWS * ICOLS * (int)sizeof(E) + 16;          // In channel stride (bytes)
+  // channel strides (bytes): the rows plus 32 bytes, so that with the swizzle below the 16
+  // channel rows of a fragment read start 16 x 8 banks apart on 64 banks (16 bytes left the
+  // reads of the swizzled rows 2-way conflicted)
+  constexpr int DS = TMAX * TW * (int)sizeof(E) + 32;              // dOut
+  constexpr int IS = TROWS * ICOLS * (int)sizeof(E) + 32;          // In
   constexpr int NOT = COUT / 16, NKT = 9 * CIN / 16, KTW = (NKT + NW - 1) / NW;
   constexpr int CPT16 = CIN / 16, NG = NW / CPT16;                 // 16-channel chunks per tap, wave groups
   static_assert(NW % CPT16 == 0, "waves must cover whole taps");
@@ -277,7 +280,7 @@ template <class A, class InT, int CIN, int COUT>
 static hipError_t launch_wgrad_t(WgradArgs& a, int grid_y, hipStream_t s) {
   using E = typename A::Op;
   constexpr int TW = wg_tw<A>();
-  constexpr size_t lds = (size_t)COUT * (TMAX * TW * sizeof(E) + 16) + (size_t)CIN * (TROWS * (TW + 8) * sizeof(E) + 16) +
+  constexpr size_t lds = (size_t)COUT * (TMAX * TW * sizeof(E) + 32) + (size_t)CIN * (TROWS * (TW + 8) * sizeof(E) + 32) +
                         2 * CIN * sizeof(float);
   static_assert(lds <= 160 * 1024, "wgrad tiles exceed LDS");
   a.tw = TW;
