@@ -145,81 +145,182 @@ __global__ void __launch_bounds__(WG_NW * 64, 2) wgrad_kernel(WgradArgs args) {
     const int f0 = (tile - b * args.tiles_per_slot) * TW;
     const int64_t re_base = (int64_t)b * T * args.F;
     __syncthreads();  // the previous tile's LDS reads are done
-    // dOut tile [TMAX][TW] transposed to [o][t][c]. A thread's 16-byte loads are issued in
-    // batches of up to SB before any of the batch is consumed, so their latencies overlap.
-    constexpr int SB = 4;
-    constexpr int ND = (TMAX * TW * CPD + NT - 1) / NT;
+    // dOut tile [TMAX][TW] transposed to [o][t][c] and In halo tile [TROWS][TW+2] (prologue
+    // inside the slot, zero padding outside) transposed to [ch][r][c]. A thread's 16-byte loads
+    // are issued in batches before any of the batch is consumed, so their latencies overlap.
+    // 2-byte elements: a lane loads one channel chunk of two adjacent subcarriers and writes
+    // each channel's pair as one 4-byte word (2-byte stores of two lanes into one word conflict).
+    if constexpr (sizeof(E) == 2) {
+      constexpr int SB = 2;
+      constexpr int NPD = TMAX * (TW / 2) * CPD, ND = (NPD + NT - 1) / NT;
 #pragma unroll
-    for (int u0 = 0; u0 < ND; u0 += SB) {
-      i32x4 raw[SB];
+      for (int u0 = 0; u0 < ND; u0 += SB) {
+        i32x4 r0[SB], r1[SB];
 #pragma unroll
-      for (int u = u0; u < u0 + SB && u < ND; ++u) {
-        const int idx = tid + u * NT;
-        const int pos = idx / CPD;
-        const int t = pos / TW, c = pos - t * TW, f = f0 + c;
-        raw[u - u0] = i32x4{0, 0, 0, 0};
-        if (idx < TMAX * TW * CPD && t < T && f < args.F)
-          raw[u - u0] = *reinterpret_cast<const i32x4*>(dout + (re_base + (int64_t)t * args.F + f) * COUT + ccD * EPD);
-      }
+        for (int u = u0; u < u0 + SB && u < ND; ++u) {
+          const int idx = tid + u * NT;
+          const int pp = idx / CPD;
+          const int t = pp / (TW / 2), c = 2 * (pp - t * (TW / 2)), f = f0 + c;
+          r0[u - u0] = i32x4{0, 0, 0, 0};
+          r1[u - u0] = i32x4{0, 0, 0, 0};
+          if (idx < NPD && t < T) {
+            const Act* src = dout + (re_base + (int64_t)t * args.F + f) * COUT + ccD * EPD;
+            if (f < args.F) r0[u - u0] = *reinterpret_cast<const i32x4*>(src);
+            if (f + 1 < args.F) r1[u - u0] = *reinterpret_cast<const i32x4*>(src + COUT);
+          }
+        }
 #pragma unroll
-      for (int u = u0; u < u0 + SB && u < ND; ++u) {
-        const int idx = tid + u * NT;
-        if (idx >= TMAX * TW * CPD) break;
-        const int pos = idx / CPD;
-        const int t = pos / TW, c = pos - t * TW;
-        float v[EPD];
-        to_elems(raw[u - u0], v, (const Act*)nullptr);  // zero outside the slot
+        for (int u = u0; u < u0 + SB && u < ND; ++u) {
+          const int idx = tid + u * NT;
+          if (idx >= NPD) break;
+          const int pp = idx / CPD;
+          const int t = pp / (TW / 2), c = 2 * (pp - t * (TW / 2));
+          const int sw = swzD(ccD * EPD);
 #pragma unroll
-        for (int i = 0; i < EPD; ++i) {
-          bsum[i] += v[i];
-          st_elem<E>(ldsD + (ccD * EPD + i) * DS + ((t * TW + c) ^ swzD(ccD * EPD + i)) * (int)sizeof(E), v[i]);
+          for (int d = 0; d < 4; ++d) {
+            const uint32_t a = (uint32_t)r0[u - u0][d], bb = (uint32_t)r1[u - u0][d];
+            bsum[2 * d] += __uint_as_float(a << 16) + __uint_as_float(bb << 16);
+            bsum[2 * d + 1] += __uint_as_float(a & 0xffff0000u) + __uint_as_float(bb & 0xffff0000u);
+            uint8_t* dst = ldsD + (ccD * EPD + 2 * d) * DS + ((t * TW + c) ^ sw) * 2;
+            *reinterpret_cast<uint32_t*>(dst) = (a & 0xffffu) | (bb << 16);
+            *reinterpret_cast<uint32_t*>(dst + DS) = (a >> 16) | (bb & 0xffff0000u);
+          }
         }
       }
-    }
-    // In halo tile [TROWS][TW+2] (prologue, then zero padding) transposed to [ch][r][c]
-    constexpr int NI = (TROWS * (TW + 2) * CPI + NT - 1) / NT;
+      constexpr int PPR = (TW + 2) / 2, NPI = TROWS * PPR * CPI, NI = (NPI + NT - 1) / NT;
+      static_assert((TW + 2) % 2 == 0, "pairs per row");
 #pragma unroll
-    for (int u0 = 0; u0 < NI; u0 += SB) {
-      i32x4 raw[SB];
-      bool ok[SB];
+      for (int u0 = 0; u0 < NI; u0 += SB) {
+        i32x4 r0[SB], r1[SB];
+        bool ok0[SB], ok1[SB];
 #pragma unroll
-      for (int u = u0; u < u0 + SB && u < NI; ++u) {
-        const int idx = tid + u * NT;
-        const int pos = idx / CPI;
-        const int r = pos / (TW + 2), c = pos - r * (TW + 2);
-        const int t = r - 1, f = f0 + c - 1;
-        ok[u - u0] = idx < TROWS * (TW + 2) * CPI && t >= 0 && t < T && f >= 0 && f < args.F;
-        raw[u - u0] = i32x4{0, 0, 0, 0};
-        if (ok[u - u0])
-          raw[u - u0] = *reinterpret_cast<const i32x4*>(in + (re_base + (int64_t)t * args.F + f) * CIN + ccI * EPI);
-      }
-#pragma unroll
-      for (int u = u0; u < u0 + SB && u < NI; ++u) {
-        const int idx = tid + u * NT;
-        if (idx >= TROWS * (TW + 2) * CPI) break;
-        const int pos = idx / CPI;
-        const int r = pos / (TW + 2), c = pos - r * (TW + 2);
-        float v[EPI];
-        if constexpr (sizeof(InT) == 4) {
-          const float* q = reinterpret_cast<const float*>(&raw[u - u0]);
-#pragma unroll
-          for (int i = 0; i < EPI; ++i) v[i] = i < 4 ? q[i] : 0.f;
-        } else {
-          to_elems(raw[u - u0], v, (const InT*)nullptr);
+        for (int u = u0; u < u0 + SB && u < NI; ++u) {
+          const int idx = tid + u * NT;
+          const int pp = idx / CPI;
+          const int r = pp / PPR, c = 2 * (pp - r * PPR);
+          const int t = r - 1, f = f0 + c - 1;
+          const bool row_ok = idx < NPI && t >= 0 && t < T;
+          ok0[u - u0] = row_ok && f >= 0 && f < args.F;
+          ok1[u - u0] = row_ok && f + 1 >= 0 && f + 1 < args.F;
+          r0[u - u0] = i32x4{0, 0, 0, 0};
+          r1[u - u0] = i32x4{0, 0, 0, 0};
+          const InT* src = in + (re_base + (int64_t)t * args.F + f) * CIN + ccI * EPI;
+          if (ok0[u - u0]) r0[u - u0] = *reinterpret_cast<const i32x4*>(src);
+          if (ok1[u - u0]) r1[u - u0] = *reinterpret_cast<const i32x4*>(src + CIN);
         }
-        if (ok[u - u0]) {
+#pragma unroll
+        for (int u = u0; u < u0 + SB && u < NI; ++u) {
+          const int idx = tid + u * NT;
+          if (idx >= NPI) break;
+          const int pp = idx / CPI;
+          const int r = pp / PPR, c = 2 * (pp - r * PPR);
+          float v0[EPI], v1[EPI];
+          if constexpr (sizeof(InT) == 4) {
+            const float* q0 = reinterpret_cast<const float*>(&r0[u - u0]);
+            const float* q1 = reinterpret_cast<const float*>(&r1[u - u0]);
+#pragma unroll
+            for (int i = 0; i < EPI; ++i) { v0[i] = i < 4 ? q0[i] : 0.f; v1[i] = i < 4 ? q1[i] : 0.f; }
+          } else {
+            to_elems(r0[u - u0], v0, (const InT*)nullptr);
+            to_elems(r1[u - u0], v1, (const InT*)nullptr);
+          }
           if (pro == 1) {
 #pragma unroll
-            for (int i = 0; i < EPI; ++i)
-              v[i] = fmaxf(pre_lds[ccI * EPI + i] * v[i] + pre_lds[CIN + ccI * EPI + i], 0.f);
+            for (int i = 0; i < EPI; ++i) {
+              const float sc = pre_lds[ccI * EPI + i], of = pre_lds[CIN + ccI * EPI + i];
+              if (ok0[u - u0]) v0[i] = fmaxf(sc * v0[i] + of, 0.f);
+              if (ok1[u - u0]) v1[i] = fmaxf(sc * v1[i] + of, 0.f);
+            }
           } else if (pro == 2) {
 #pragma unroll
-            for (int i = 0; i < EPI; ++i) v[i] = fmaxf(v[i], 0.f);
-          }
-        }  // else: zero padding (the raw value is zero)
+            for (int i = 0; i < EPI; ++i) { v0[i] = fmaxf(v0[i], 0.f); v1[i] = fmaxf(v1[i], 0.f); }
+          }  // outside the slot the raw values are zero: zero padding
+          const int sw = swzI(ccI * EPI);
 #pragma unroll
-        for (int i = 0; i < EPI; ++i)
-          st_elem<E>(ldsI + (ccI * EPI + i) * IS + ((r * ICOLS + c) ^ swzI(ccI * EPI + i)) * (int)sizeof(E), v[i]);
+          for (int i = 0; i < EPI; ++i) {
+            const uint32_t w = (uint32_t)__builtin_bit_cast(uint16_t, f2bf(v0[i])) |
+                               ((uint32_t)__builtin_bit_cast(uint16_t, f2bf(v1[i])) << 16);
+            *reinterpret_cast<uint32_t*>(ldsI + (ccI * EPI + i) * IS + ((r * ICOLS + c) ^ sw) * 2) = w;
+          }
+        }
+      }
+    } else {
+      // dOut tile [TMAX][TW] transposed to [o][t][c]. A thread's 16-byte loads are issued in
+      // batches of up to SB before any of the batch is consumed, so their latencies overlap.
+      constexpr int SB = 4;
+      constexpr int ND = (TMAX * TW * CPD + NT - 1) / NT;
+#pragma unroll
+      for (int u0 = 0; u0 < ND; u0 += SB) {
+        i32x4 raw[SB];
+#pragma unroll
+        for (int u = u0; u < u0 + SB && u < ND; ++u) {
+          const int idx = tid + u * NT;
+          const int pos = idx / CPD;
+          const int t = pos / TW, c = pos - t * TW, f = f0 + c;
+          raw[u - u0] = i32x4{0, 0, 0, 0};
+          if (idx < TMAX * TW * CPD && t < T && f < args.F)
+            raw[u - u0] = *reinterpret_cast<const i32x4*>(dout + (re_base + (int64_t)t * args.F + f) * COUT + ccD * EPD);
+        }
+#pragma unroll
+        for (int u = u0; u < u0 + SB && u < ND; ++u) {
+          const int idx = tid + u * NT;
+          if (idx >= TMAX * TW * CPD) break;
+          const int pos = idx / CPD;
+          const int t = pos / TW, c = pos - t * TW;
+          float v[EPD];
+          to_elems(raw[u - u0], v, (const Act*)nullptr);  // zero outside the slot
+#pragma unroll
+          for (int i = 0; i < EPD; ++i) {
+            bsum[i] += v[i];
+            st_elem<E>(ldsD + (ccD * EPD + i) * DS + ((t * TW + c) ^ swzD(ccD * EPD + i)) * (int)sizeof(E), v[i]);
+          }
+        }
+      }
+      // In halo tile [TROWS][TW+2] (prologue, then zero padding) transposed to [ch][r][c]
+      constexpr int NI = (TROWS * (TW + 2) * CPI + NT - 1) / NT;
+#pragma unroll
+      for (int u0 = 0; u0 < NI; u0 += SB) {
+        i32x4 raw[SB];
+        bool ok[SB];
+#pragma unroll
+        for (int u = u0; u < u0 + SB && u < NI; ++u) {
+          const int idx = tid + u * NT;
+          const int pos = idx / CPI;
+          const int r = pos / (TW + 2), c = pos - r * (TW + 2);
+          const int t = r - 1, f = f0 + c - 1;
+          ok[u - u0] = idx < TROWS * (TW + 2) * CPI && t >= 0 && t < T && f >= 0 && f < args.F;
+          raw[u - u0] = i32x4{0, 0, 0, 0};
+          if (ok[u - u0])
+            raw[u - u0] = *reinterpret_cast<const i32x4*>(in + (re_base + (int64_t)t * args.F + f) * CIN + ccI * EPI);
+        }
+#pragma unroll
+        for (int u = u0; u < u0 + SB && u < NI; ++u) {
+          const int idx = tid + u * NT;
+          if (idx >= TROWS * (TW + 2) * CPI) break;
+          const int pos = idx / CPI;
+          const int r = pos / (TW + 2), c = pos - r * (TW + 2);
+          float v[EPI];
+          if constexpr (sizeof(InT) == 4) {
+            const float* q = reinterpret_cast<const float*>(&raw[u - u0]);
+#pragma unroll
+            for (int i = 0; i < EPI; ++i) v[i] = i < 4 ? q[i] : 0.f;
+          } else {
+            to_elems(raw[u - u0], v, (const InT*)nullptr);
+          }
+          if (ok[u - u0]) {
+            if (pro == 1) {
+#pragma unroll
+              for (int i = 0; i < EPI; ++i)
+                v[i] = fmaxf(pre_lds[ccI * EPI + i] * v[i] + pre_lds[CIN + ccI * EPI + i], 0.f);
+            } else if (pro == 2) {
+#pragma unroll
+              for (int i = 0; i < EPI; ++i) v[i] = fmaxf(v[i], 0.f);
+            }
+          }  // else: zero padding (the raw value is zero)
+#pragma unroll
+          for (int i = 0; i < EPI; ++i)
+            st_elem<E>(ldsI + (ccI * EPI + i) * IS + ((r * ICOLS + c) ^ swzI(ccI * EPI + i)) * (int)sizeof(E), v[i]);
+        }
       }
     }
     __syncthreads();
