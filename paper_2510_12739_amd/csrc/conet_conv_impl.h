@@ -531,7 +531,38 @@ __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
   for (int kb = 0; kb < nb; ++kb) {
   const int k = k0 + kb;
   AccV acc[MT][NOT];
+  // Backward through the second conv: the epilogue's mask operand h is loaded one M-tile ahead
+  // as raw words into two alternating buffers and converted element by element where used, so
+  // its latency overlaps the epilogue of the M-tile before; the first M-tile's is issued right
+  // after the MFMA loop. (The same for x in mode 6 measured 5 % slower; x and dO together
+  // did not fit the registers.)
+  constexpr bool PREF = MODE == 5;
+  using RawW = typename std::conditional<(EPL * sizeof(Act)) % 16 == 0, i32x4, uint2>::type;
+  constexpr int NRW = PREF ? EPL * (int)sizeof(Act) / (int)sizeof(RawW) : 1;
+  static_assert(!PREF || (EPL * sizeof(Act)) % sizeof(RawW) == 0, "epilogue operands fill whole words");
+  RawW pra[2][NRW];
+  auto epi_re = [&](int mt, int64_t& re) -> bool {
+    const int idx = wave + NW * mt;
+    const int t = idx / (TW / 16);
+    const int f = td.f0 + (idx - t * (TW / 16)) * 16 + col;
+    if (idx >= G::MTOT || t >= T || f >= td.F) return false;
+    re = td.re_base + (int64_t)t * td.F + f;
+    return true;
+  };
+  auto prefetch = [&](int mt) {
+    int64_t re = 0;
+    if (!epi_re(mt, re)) return;
+    const RawW* a = reinterpret_cast<const RawW*>(reinterpret_cast<const Act*>(args.aux[k]) + re * COUT + c0);
+#pragma unroll
+    for (int w = 0; w < NRW; ++w) pra[mt & 1][w] = a[w];
+  };
+  // element i of a raw buffer, as the epilogue's type
+  auto elem = [](const RawW* w, int i) -> Acc {
+    const Act* e = reinterpret_cast<const Act*>(w);
+    return (Acc)e[i];
+  };
   G::run(acc, lds, reinterpret_cast<const i32x4*>(args.wpack[k]), wave, lane);
+  if constexpr (PREF) prefetch(0);
 
   // per-lane epilogue parameters (this lane's EPL channels), loaded once
   float pb[EPL], pq[EPL];
@@ -568,11 +599,12 @@ __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
 
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
-    const int idx = wave + NW * mt;
-    const int t = idx / (TW / 16);
-    const int f = td.f0 + (idx - t * (TW / 16)) * 16 + col;
-    if (idx >= G::MTOT || t >= T || f >= td.F) continue;
-    const int64_t re = td.re_base + (int64_t)t * td.F + f;
+    int64_t re = 0;
+    const bool ok = epi_re(mt, re);
+    if constexpr (PREF) {
+      if (mt + 1 < MT) prefetch(mt + 1);
+    }
+    if (!ok) continue;
     Acc v[EPL];
 #pragma unroll
     for (int ot = 0; ot < NOT; ++ot)
@@ -580,32 +612,32 @@ __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
       for (int i = 0; i < 4; ++i) {
         Acc a = acc[mt][ot][i];
         if constexpr (A::QUANT) a = a * (Acc)pq[4 * ot + i];
-        v[4 * ot + i] = a + (Acc)pb[4 * ot + i];
+        v[4 * ot + i] = (MODE == 5 || MODE == 6) ? a : a + (Acc)pb[4 * ot + i];  // input-gradient convs have no bias
       }
     if constexpr (MODE == 5) {  // dv = dh (the bias slot holds zeros for input-gradient convs)
-      Acc h[EPL];
-      load_vals(reinterpret_cast<const Hid*>(args.aux[k]) + re * COUT + c0, h, EPL);
 #pragma unroll
       for (int i = 0; i < EPL; ++i) {
-        const Acc dz = h[i] > (Acc)0 ? v[i] : (Acc)0;
+        const Acc h = elem(pra[mt & 1], i);
+        const Acc dz = h > (Acc)0 ? v[i] : (Acc)0;
         const Acc dc = dz * (Acc)ps1[i];
-        sums[0][i] += (float)(dz * (h[i] - (Acc)po1[i]) / (Acc)ps1[i]);
+        sums[0][i] += (float)(dz * (h - (Acc)po1[i]));  // divided by s1 once, after the sums
         sums[1][i] += (float)dz;
         sums[2][i] += (float)dc;
         v[i] = dc;
       }
       store_vals(reinterpret_cast<Act*>(args.out[k]) + re * COUT + c0, v, EPL, 1.f);
     } else if constexpr (MODE == 6) {
-      Acc x[EPL], dO[EPL];
-      load_vals(reinterpret_cast<const Act*>(args.aux[k]) + re * COUT + c0, x, EPL);
-      load_vals(reinterpret_cast<const Act*>(args.resid[k]) + re * COUT + c0, dO, EPL);
+      Acc xv[EPL], dOv[EPL];
+      load_vals(reinterpret_cast<const Act*>(args.aux[k]) + re * COUT + c0, xv, EPL);
+      load_vals(reinterpret_cast<const Act*>(args.resid[k]) + re * COUT + c0, dOv, EPL);
 #pragma unroll
       for (int i = 0; i < EPL; ++i) {
-        const Acc z0 = (Acc)ps1[i] * x[i] + (Acc)po1[i];
+        const Acc x = xv[i], dO = dOv[i];
+        const Acc z0 = (Acc)ps1[i] * x + (Acc)po1[i];
         const Acc dz = z0 > (Acc)0 ? v[i] : (Acc)0;
-        Acc dx = dO[i] + (Acc)ps1[i] * dz;
-        if (args.mask_out && !(x[i] > (Acc)0)) dx = (Acc)0;
-        sums[0][i] += mrb ? 0.f : (float)(dz * x[i]);
+        Acc dx = dO + (Acc)ps1[i] * dz;
+        if (args.mask_out && !(x > (Acc)0)) dx = (Acc)0;
+        sums[0][i] += mrb ? 0.f : (float)(dz * x);
         sums[1][i] += mrb ? 0.f : (float)dz;
         sums[2][i] += (float)dx;
         v[i] = dx;
@@ -654,6 +686,10 @@ __global__ void __launch_bounds__(NW * 64, 2) conv3x3_kernel(ConvArgs args) {
         t += __shfl_xor(t, 8);
         sums[q][i] = t;
       }
+    if constexpr (MODE == 5) {  // ds1 = sum dz (h - o1) / s1: the conv output recovered from h
+#pragma unroll
+      for (int i = 0; i < EPL; ++i) sums[0][i] /= ps1[i];
+    }
     if (col == 0) {
       float* row = args.part[k] + ((size_t)blockIdx.x * NW + wave) * NPART * COUT;
 #pragma unroll
