@@ -218,7 +218,7 @@ static conet_status run_backward(conet_model* M, const float* dllr, hipStream_t 
   const int n_tiles_blk = B * ((F + tw_blk - 1) / tw_blk);
   const int wtw = wgrad_tile_width(dt);
   const int n_tiles_wg = B * ((F + wtw - 1) / wtw);
-  const int wg_grid = wgrad_grid(n_tiles_wg);
+  auto wg_grid = [&](int nk) { return wgrad_grid(n_tiles_wg, nk, M->n_cu); };
   if ((int64_t)n_tiles_blk * CONV_NW > (int64_t)lay.tr_part_conv_rows)
     return fail(CONET_ESHAPE, "batch needs %lld partial rows, capacity %zu", (long long)n_tiles_blk * CONV_NW,
                 lay.tr_part_conv_rows);
@@ -281,8 +281,8 @@ static conet_status run_backward(conet_model* M, const float* dllr, hipStream_t 
     }
     begin_range();
     for (int k = 0; k < nk; ++k) {
-      add(part_w + k * w_stride, grad + bo.w2[k][l], wg_grid, C * 9 * C, C * 9 * C, 1, C);
-      add(part_b + k * b_stride, grad + bo.b2[k][l], wg_grid, C, C, 0, 0);
+      add(part_w + k * w_stride, grad + bo.w2[k][l], wg_grid(nk), C * 9 * C, C * 9 * C, 1, C);
+      add(part_b + k * b_stride, grad + bo.b2[k][l], wg_grid(nk), C, C, 0, 0);
     }
     begin_range();
     for (int k = 0; k < nk; ++k) {
@@ -291,14 +291,14 @@ static conet_status run_backward(conet_model* M, const float* dllr, hipStream_t 
     }
     begin_range();
     for (int k = 0; k < nk; ++k) {
-      add(part_w + k * w_stride, grad + bo.w1[k][l], wg_grid, C * 9 * C, C * 9 * C, 1, C);
-      add(part_b + k * b_stride, grad + bo.b1[k][l], wg_grid, C, C, 0, 0);
+      add(part_w + k * w_stride, grad + bo.w1[k][l], wg_grid(nk), C * 9 * C, C * 9 * C, 1, C);
+      add(part_b + k * b_stride, grad + bo.b1[k][l], wg_grid(nk), C, C, 0, 0);
     }
   }
   begin_range();
   for (int k = 0; k < nk_of[0]; ++k) {
-    add(part_w + k * w_stride, grad + bo.w_in[k], wg_grid, C * 9 * Ci, C * 9 * Ci, 1, Ci);
-    add(part_b + k * b_stride, grad + bo.b_in[k], wg_grid, C, C, 0, 0);
+    add(part_w + k * w_stride, grad + bo.w_in[k], wg_grid(nk_of[0]), C * 9 * Ci, C * 9 * Ci, 1, Ci);
+    add(part_b + k * b_stride, grad + bo.b_in[k], wg_grid(nk_of[0]), C, C, 0, 0);
   }
   if ((int)segs.size() > MAX_SEGS) return fail(CONET_EINVAL, "too many reductions");
   if (tmp_overflow) return fail(CONET_ESHAPE, "reduction scratch too small for this batch");
@@ -394,7 +394,7 @@ static conet_status run_backward(conet_model* M, const float* dllr, hipStream_t 
       w2.part_b[k] = part_b + k * b_stride;
     }
     w2.prologue = 0;
-    w2.T = T; w2.F = F; w2.tiles_per_slot = (F + wtw - 1) / wtw; w2.n_tiles = n_tiles_wg;
+    w2.T = T; w2.F = F; w2.tiles_per_slot = (F + wtw - 1) / wtw; w2.n_tiles = n_tiles_wg; w2.grid = wg_grid(nk);
     e = launch_wgrad(dt, false, C, C, w2, nk, s);
     if (e == hipSuccess) e = reduce(ri++);
     if (e != hipSuccess) return hip_fail(e, "conv 2 filter gradient");
@@ -432,7 +432,7 @@ static conet_status run_backward(conet_model* M, const float* dllr, hipStream_t 
       w1.part_b[k] = part_b + k * b_stride;
     }
     w1.prologue = 1;
-    w1.T = T; w1.F = F; w1.tiles_per_slot = (F + wtw - 1) / wtw; w1.n_tiles = n_tiles_wg;
+    w1.T = T; w1.F = F; w1.tiles_per_slot = (F + wtw - 1) / wtw; w1.n_tiles = n_tiles_wg; w1.grid = wg_grid(nk);
     e = launch_wgrad(dt, false, C, C, w1, nk, s);
     if (e == hipSuccess) e = reduce(ri++);
     if (e != hipSuccess) return hip_fail(e, "conv 1 filter gradient");
@@ -448,7 +448,7 @@ static conet_status run_backward(conet_model* M, const float* dllr, hipStream_t 
     wi.part_b[k] = part_b + k * b_stride;
   }
   wi.prologue = 0;
-  wi.T = T; wi.F = F; wi.tiles_per_slot = (F + wtw - 1) / wtw; wi.n_tiles = n_tiles_wg;
+  wi.T = T; wi.F = F; wi.tiles_per_slot = (F + wtw - 1) / wtw; wi.n_tiles = n_tiles_wg; wi.grid = wg_grid(nk_of[0]);
   e = launch_wgrad(dt, true, Ci, C, wi, nk_of[0], s);
   if (e == hipSuccess) e = reduce(ri++);
   if (e != hipSuccess) return hip_fail(e, "input layer filter gradient");

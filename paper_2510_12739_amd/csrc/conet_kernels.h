@@ -197,9 +197,12 @@ struct WgradArgs {
   float* part_w[KMAX_ARGS];        // [gridDim.x][COUT][9 * CIN]
   float* part_b[KMAX_ARGS];        // [gridDim.x][COUT]
   int T, F, tiles_per_slot, n_tiles, tw;
+  int grid;                        // work-groups per branch (wgrad_grid), one partial row each
 };
 int wgrad_tile_width(int dtype);
-int wgrad_grid(int n_tiles);
+// Work-groups per branch of a filter-gradient launch over `branches` branches: one round of one
+// work-group per CU over all branches (each loops over its share of the tiles), at most 256.
+int wgrad_grid(int n_tiles, int branches, int n_cu);
 hipError_t launch_wgrad(int dtype, bool in_f32, int cin, int cout, WgradArgs& a, int grid_y, hipStream_t s);
 
 // Head / LayerNorm / product adjoint of one block (or the head alone after an unfused

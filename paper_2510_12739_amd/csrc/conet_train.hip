@@ -385,7 +385,8 @@ static hipError_t launch_wgrad_t(WgradArgs& a, int grid_y, hipStream_t s) {
                         2 * CIN * sizeof(float);
   static_assert(lds <= 160 * 1024, "wgrad tiles exceed LDS");
   a.tw = TW;
-  const int grid = wgrad_grid(a.n_tiles);
+  const int grid = a.grid;
+  if (grid < 1 || grid > 256 || grid > a.n_tiles) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute((const void*)wgrad_kernel<A, InT, CIN, COUT>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -394,7 +395,10 @@ static hipError_t launch_wgrad_t(WgradArgs& a, int grid_y, hipStream_t s) {
 }
 
 int wgrad_tile_width(int dtype) { return dtype == DT_BF16 ? wg_tw<ArithBF16>() : wg_tw<ArithF32>(); }
-int wgrad_grid(int n_tiles) { return n_tiles < 256 ? n_tiles : 256; }
+int wgrad_grid(int n_tiles, int branches, int n_cu) {
+  const int per = std::max(1, std::min(256, n_cu / std::max(1, branches)));
+  return std::min(n_tiles, per);
+}
 
 hipError_t launch_wgrad(int dtype, bool in_f32, int cin, int cout, WgradArgs& a, int grid_y, hipStream_t s) {
 #define CONET_WG(CI, CO)                                                                          \
