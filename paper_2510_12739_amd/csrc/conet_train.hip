@@ -140,6 +140,32 @@ __global__ void __launch_bounds__(WG_NW * 64, 2) wgrad_kernel(WgradArgs args) {
   for (int i = 0; i < EPD; ++i) bsum[i] = 0.f;
   const int T = args.T;
 
+  // 2-byte elements: the output-gradient tile of the work-group's next tile is loaded into
+  // registers before the current tile's MFMAs (its latency then overlaps them)
+  constexpr int NPD2 = TMAX * (TW / 2) * CPD, ND2 = sizeof(E) == 2 ? (NPD2 + NT - 1) / NT : 1;
+  i32x4 pd0[ND2], pd1[ND2];
+  auto load_dout_pairs = [&](int tile) {
+    const int b = tile / args.tiles_per_slot;
+    const int f0 = (tile - b * args.tiles_per_slot) * TW;
+    const int64_t re_base = (int64_t)b * T * args.F;
+#pragma unroll
+    for (int u = 0; u < ND2; ++u) {
+      const int idx = tid + u * NT;
+      const int pp = idx / CPD;
+      const int t = pp / (TW / 2), c = 2 * (pp - t * (TW / 2)), f = f0 + c;
+      pd0[u] = i32x4{0, 0, 0, 0};
+      pd1[u] = i32x4{0, 0, 0, 0};
+      if (idx < NPD2 && t < T) {
+        const Act* src = dout + (re_base + (int64_t)t * args.F + f) * COUT + ccD * EPD;
+        if (f < args.F) pd0[u] = *reinterpret_cast<const i32x4*>(src);
+        if (f + 1 < args.F) pd1[u] = *reinterpret_cast<const i32x4*>(src + COUT);
+      }
+    }
+  };
+  if constexpr (sizeof(E) == 2) {
+    if ((int)blockIdx.x < args.n_tiles) load_dout_pairs(blockIdx.x);
+  }
+
   for (int tile = blockIdx.x; tile < args.n_tiles; tile += gridDim.x) {
     const int b = tile / args.tiles_per_slot;
     const int f0 = (tile - b * args.tiles_per_slot) * TW;
@@ -152,39 +178,21 @@ __global__ void __launch_bounds__(WG_NW * 64, 2) wgrad_kernel(WgradArgs args) {
     // each channel's pair as one 4-byte word (2-byte stores of two lanes into one word conflict).
     if constexpr (sizeof(E) == 2) {
       constexpr int SB = 2;
-      constexpr int NPD = TMAX * (TW / 2) * CPD, ND = (NPD + NT - 1) / NT;
 #pragma unroll
-      for (int u0 = 0; u0 < ND; u0 += SB) {
-        i32x4 r0[SB], r1[SB];
+      for (int u = 0; u < ND2; ++u) {
+        const int idx = tid + u * NT;
+        if (idx >= NPD2) break;
+        const int pp = idx / CPD;
+        const int t = pp / (TW / 2), c = 2 * (pp - t * (TW / 2));
+        const int sw = swzD(ccD * EPD);
 #pragma unroll
-        for (int u = u0; u < u0 + SB && u < ND; ++u) {
-          const int idx = tid + u * NT;
-          const int pp = idx / CPD;
-          const int t = pp / (TW / 2), c = 2 * (pp - t * (TW / 2)), f = f0 + c;
-          r0[u - u0] = i32x4{0, 0, 0, 0};
-          r1[u - u0] = i32x4{0, 0, 0, 0};
-          if (idx < NPD && t < T) {
-            const Act* src = dout + (re_base + (int64_t)t * args.F + f) * COUT + ccD * EPD;
-            if (f < args.F) r0[u - u0] = *reinterpret_cast<const i32x4*>(src);
-            if (f + 1 < args.F) r1[u - u0] = *reinterpret_cast<const i32x4*>(src + COUT);
-          }
-        }
-#pragma unroll
-        for (int u = u0; u < u0 + SB && u < ND; ++u) {
-          const int idx = tid + u * NT;
-          if (idx >= NPD) break;
-          const int pp = idx / CPD;
-          const int t = pp / (TW / 2), c = 2 * (pp - t * (TW / 2));
-          const int sw = swzD(ccD * EPD);
-#pragma unroll
-          for (int d = 0; d < 4; ++d) {
-            const uint32_t a = (uint32_t)r0[u - u0][d], bb = (uint32_t)r1[u - u0][d];
-            bsum[2 * d] += __uint_as_float(a << 16) + __uint_as_float(bb << 16);
-            bsum[2 * d + 1] += __uint_as_float(a & 0xffff0000u) + __uint_as_float(bb & 0xffff0000u);
-            uint8_t* dst = ldsD + (ccD * EPD + 2 * d) * DS + ((t * TW + c) ^ sw) * 2;
-            *reinterpret_cast<uint32_t*>(dst) = (a & 0xffffu) | (bb << 16);
-            *reinterpret_cast<uint32_t*>(dst + DS) = (a >> 16) | (bb & 0xffff0000u);
-          }
+        for (int d = 0; d < 4; ++d) {
+          const uint32_t a = (uint32_t)pd0[u][d], bb = (uint32_t)pd1[u][d];
+          bsum[2 * d] += __uint_as_float(a << 16) + __uint_as_float(bb << 16);
+          bsum[2 * d + 1] += __uint_as_float(a & 0xffff0000u) + __uint_as_float(bb & 0xffff0000u);
+          uint8_t* dst = ldsD + (ccD * EPD + 2 * d) * DS + ((t * TW + c) ^ sw) * 2;
+          *reinterpret_cast<uint32_t*>(dst) = (a & 0xffffu) | (bb << 16);
+          *reinterpret_cast<uint32_t*>(dst + DS) = (a >> 16) | (bb & 0xffff0000u);
         }
       }
       constexpr int PPR = (TW + 2) / 2, NPI = TROWS * PPR * CPI, NI = (NPI + NT - 1) / NT;
@@ -324,6 +332,9 @@ __global__ void __launch_bounds__(WG_NW * 64, 2) wgrad_kernel(WgradArgs args) {
       }
     }
     __syncthreads();
+    if constexpr (sizeof(E) == 2) {
+      if (tile + (int)gridDim.x < args.n_tiles) load_dout_pairs(tile + gridDim.x);
+    }
     const int ch = (wave % CPT16) * 16 + col;  // this lane's input channel in every tap
     const uint8_t* row = ldsI + ch * IS;
     const int sw = swzI(ch);
