@@ -223,6 +223,12 @@ static conet_status run_backward(conet_model* M, const float* dllr, hipStream_t 
     return fail(CONET_ESHAPE, "batch needs %lld partial rows, capacity %zu", (long long)n_tiles_blk * CONV_NW,
                 lay.tr_part_conv_rows);
   const int conv_rows = n_tiles_blk * CONV_NW;
+  // both input-gradient convs of a block in one launch where that kernel exists (BF16, 32 or 64
+  // channels) and its two sets of partial rows fit the buffer
+  const int tw_bb = bwd_block_tile_width(dt, C);
+  const int n_tiles_bb = tw_bb ? B * ((F + tw_bb - 1) / tw_bb) : 0;
+  const bool fused_bwd = tw_bb > 0 && 2LL * n_tiles_bb * CONV_NW <= (int64_t)lay.tr_part_conv_rows;
+  const int bb_rows = n_tiles_bb * CONV_NW;
   const size_t conv_stride = lay.tr_part_conv_rows * 3 * C;     // floats per branch
   const size_t w_stride = (size_t)256 * C * 9 * std::max(C, Ci);
   const size_t b_stride = (size_t)256 * C;
@@ -274,20 +280,33 @@ static conet_status run_backward(conet_model* M, const float* dllr, hipStream_t 
         add(part_fuse + 10 * C, grad + bo.bh, FUSE_GRID, m, 10 * C + 8, 0, 0);
       }
     }
-    begin_range();
-    for (int k = 0; k < nk; ++k) {
-      add(part_conv + k * conv_stride + 0 * C, grad + bo.s1[k][l], conv_rows, C, 3 * C, 0, 0);
-      add(part_conv + k * conv_stride + 1 * C, grad + bo.o1[k][l], conv_rows, C, 3 * C, 0, 0);
+    if (fused_bwd) {  // one launch: rows [0, bb_rows) hold the s1 / o1 sums, the next bb_rows the s0 / o0 sums
+      begin_range();
+      for (int k = 0; k < nk; ++k) {
+        float* pk = part_conv + k * conv_stride;
+        add(pk + 0 * C, grad + bo.s1[k][l], bb_rows, C, 3 * C, 0, 0);
+        add(pk + 1 * C, grad + bo.o1[k][l], bb_rows, C, 3 * C, 0, 0);
+        add(pk + (size_t)bb_rows * 3 * C + 0 * C, grad + bo.s0[k][l], bb_rows, C, 3 * C, 0, 0);
+        add(pk + (size_t)bb_rows * 3 * C + 1 * C, grad + bo.o0[k][l], bb_rows, C, 3 * C, 0, 0);
+      }
+    } else {
+      begin_range();
+      for (int k = 0; k < nk; ++k) {
+        add(part_conv + k * conv_stride + 0 * C, grad + bo.s1[k][l], conv_rows, C, 3 * C, 0, 0);
+        add(part_conv + k * conv_stride + 1 * C, grad + bo.o1[k][l], conv_rows, C, 3 * C, 0, 0);
+      }
     }
     begin_range();
     for (int k = 0; k < nk; ++k) {
       add(part_w + k * w_stride, grad + bo.w2[k][l], wg_grid(nk), C * 9 * C, C * 9 * C, 1, C);
       add(part_b + k * b_stride, grad + bo.b2[k][l], wg_grid(nk), C, C, 0, 0);
     }
-    begin_range();
-    for (int k = 0; k < nk; ++k) {
-      add(part_conv + k * conv_stride + 0 * C, grad + bo.s0[k][l], conv_rows, C, 3 * C, 0, 0);
-      add(part_conv + k * conv_stride + 1 * C, grad + bo.o0[k][l], conv_rows, C, 3 * C, 0, 0);
+    if (!fused_bwd) {
+      begin_range();
+      for (int k = 0; k < nk; ++k) {
+        add(part_conv + k * conv_stride + 0 * C, grad + bo.s0[k][l], conv_rows, C, 3 * C, 0, 0);
+        add(part_conv + k * conv_stride + 1 * C, grad + bo.o0[k][l], conv_rows, C, 3 * C, 0, 0);
+      }
     }
     begin_range();
     for (int k = 0; k < nk; ++k) {
@@ -367,25 +386,7 @@ static conet_status run_backward(conet_model* M, const float* dllr, hipStream_t 
       for (int k = 0; k < K; ++k) dO[k] = dx_next[k];
     }
     if (fuse || last) ++ri;
-    // through the second conv: dc1
-    ConvArgs a5 = {};
-    a5.T = T; a5.F = F; a5.tiles_per_slot = (F + tw_blk - 1) / tw_blk;
-    for (int k = 0; k < nk; ++k) {
-      const float* vb = vec + lay.v_blk[k][l];
-      a5.in[k] = dO[k];
-      a5.wpack[k] = ws + lay.tr_wt2[k][l];
-      a5.bias[k] = zero;
-      a5.wscale[k] = zero;
-      a5.aux[k] = ar.lvl_hid[l][k];
-      a5.post_s[k] = vb + 3 * C;
-      a5.post_o[k] = vb + 4 * C;
-      a5.out[k] = ar.g_dc1[k];
-      a5.part[k] = part_conv + k * conv_stride;
-    }
-    e = launch_conv(dt, 5, C, C, a5, n_tiles_blk, nk, s);
-    if (e == hipSuccess) e = reduce(ri++);
-    if (e != hipSuccess) return hip_fail(e, "conv 2 input gradient");
-    // W2, b2
+    // W2, b2 (independent of the input gradients)
     WgradArgs w2 = {};
     for (int k = 0; k < nk; ++k) {
       w2.dout[k] = dO[k];
@@ -395,30 +396,77 @@ static conet_status run_backward(conet_model* M, const float* dllr, hipStream_t 
     }
     w2.prologue = 0;
     w2.T = T; w2.F = F; w2.tiles_per_slot = (F + wtw - 1) / wtw; w2.n_tiles = n_tiles_wg; w2.grid = wg_grid(nk);
-    e = launch_wgrad(dt, false, C, C, w2, nk, s);
-    if (e == hipSuccess) e = reduce(ri++);
-    if (e != hipSuccess) return hip_fail(e, "conv 2 filter gradient");
-    // through the first conv: dx of the block input
-    ConvArgs a6 = {};
-    a6.T = T; a6.F = F; a6.tiles_per_slot = (F + tw_blk - 1) / tw_blk;
-    for (int k = 0; k < nk; ++k) {
-      const float* vb = vec + lay.v_blk[k][l];
-      const bool mrb = (k == 0 && fused_prev);
-      a6.in[k] = ar.g_dc1[k];
-      a6.wpack[k] = ws + lay.tr_wt1[k][l];
-      a6.bias[k] = zero;
-      a6.wscale[k] = zero;
-      a6.aux[k] = ar.lvl_act[l][k];
-      a6.pre_s[k] = mrb ? nullptr : vb + 0 * C;
-      a6.pre_o[k] = mrb ? nullptr : vb + 1 * C;
-      a6.resid[k] = dO[k];
-      a6.out[k] = ar.g_dx[dxbuf][k];
-      a6.part[k] = part_conv + k * conv_stride;
+    if (fused_bwd) {  // through both convs: dc1 and dx of the block input
+      BwdBlockArgs bb = {};
+      bb.T = T; bb.F = F; bb.tiles_per_slot = (F + tw_bb - 1) / tw_bb;
+      bb.rows = bb_rows;
+      bb.mask_out = l == 0;
+      for (int k = 0; k < nk; ++k) {
+        const float* vb = vec + lay.v_blk[k][l];
+        const bool mrb = (k == 0 && fused_prev);
+        bb.dO[k] = dO[k];
+        bb.h[k] = ar.lvl_hid[l][k];
+        bb.x[k] = ar.lvl_act[l][k];
+        bb.wt1[k] = ws + lay.tr_wt1[k][l];
+        bb.wt2[k] = ws + lay.tr_wt2[k][l];
+        bb.s1[k] = vb + 3 * C;
+        bb.o1[k] = vb + 4 * C;
+        bb.s0[k] = mrb ? nullptr : vb + 0 * C;
+        bb.o0[k] = mrb ? nullptr : vb + 1 * C;
+        bb.dc1[k] = ar.g_dc1[k];
+        bb.dx[k] = ar.g_dx[dxbuf][k];
+        bb.part[k] = part_conv + k * conv_stride;
+      }
+      e = launch_bwd_block(dt, C, bb, n_tiles_bb, nk, s);
+      if (e == hipSuccess) e = reduce(ri++);
+      if (e != hipSuccess) return hip_fail(e, "block input gradient");
+      e = launch_wgrad(dt, false, C, C, w2, nk, s);
+      if (e == hipSuccess) e = reduce(ri++);
+      if (e != hipSuccess) return hip_fail(e, "conv 2 filter gradient");
+    } else {
+      // through the second conv: dc1
+      ConvArgs a5 = {};
+      a5.T = T; a5.F = F; a5.tiles_per_slot = (F + tw_blk - 1) / tw_blk;
+      for (int k = 0; k < nk; ++k) {
+        const float* vb = vec + lay.v_blk[k][l];
+        a5.in[k] = dO[k];
+        a5.wpack[k] = ws + lay.tr_wt2[k][l];
+        a5.bias[k] = zero;
+        a5.wscale[k] = zero;
+        a5.aux[k] = ar.lvl_hid[l][k];
+        a5.post_s[k] = vb + 3 * C;
+        a5.post_o[k] = vb + 4 * C;
+        a5.out[k] = ar.g_dc1[k];
+        a5.part[k] = part_conv + k * conv_stride;
+      }
+      e = launch_conv(dt, 5, C, C, a5, n_tiles_blk, nk, s);
+      if (e == hipSuccess) e = reduce(ri++);
+      if (e != hipSuccess) return hip_fail(e, "conv 2 input gradient");
+      e = launch_wgrad(dt, false, C, C, w2, nk, s);
+      if (e == hipSuccess) e = reduce(ri++);
+      if (e != hipSuccess) return hip_fail(e, "conv 2 filter gradient");
+      // through the first conv: dx of the block input
+      ConvArgs a6 = {};
+      a6.T = T; a6.F = F; a6.tiles_per_slot = (F + tw_blk - 1) / tw_blk;
+      for (int k = 0; k < nk; ++k) {
+        const float* vb = vec + lay.v_blk[k][l];
+        const bool mrb = (k == 0 && fused_prev);
+        a6.in[k] = ar.g_dc1[k];
+        a6.wpack[k] = ws + lay.tr_wt1[k][l];
+        a6.bias[k] = zero;
+        a6.wscale[k] = zero;
+        a6.aux[k] = ar.lvl_act[l][k];
+        a6.pre_s[k] = mrb ? nullptr : vb + 0 * C;
+        a6.pre_o[k] = mrb ? nullptr : vb + 1 * C;
+        a6.resid[k] = dO[k];
+        a6.out[k] = ar.g_dx[dxbuf][k];
+        a6.part[k] = part_conv + k * conv_stride;
+      }
+      a6.mask_out = l == 0;
+      e = launch_conv(dt, 6, C, C, a6, n_tiles_blk, nk, s);
+      if (e == hipSuccess) e = reduce(ri++);
+      if (e != hipSuccess) return hip_fail(e, "conv 1 input gradient");
     }
-    a6.mask_out = l == 0;
-    e = launch_conv(dt, 6, C, C, a6, n_tiles_blk, nk, s);
-    if (e == hipSuccess) e = reduce(ri++);
-    if (e != hipSuccess) return hip_fail(e, "conv 1 input gradient");
     // W1, b1 (In = the block's pre-activation, recomputed while staging)
     WgradArgs w1 = {};
     for (int k = 0; k < nk; ++k) {
