@@ -115,43 +115,76 @@ __global__ void __launch_bounds__(CONV_NW * 64, 2) bwd_block_kernel(BwdBlockArgs
   }
 #pragma unroll
   for (int mt = 1; mt < MT1; ++mt) load_h(mt);
-  // the per-channel affines are read from LDS where used (registers hold the accumulators)
-  const float* ps = par + P_S1 * C + c0;
-  const float* po = par + P_O1 * C + c0;
-  float sa[EPL], sb[EPL];
+
+  // 3. dc1 = s1 [h > 0] dh, formed in place of the accumulators one group of four channels at
+  //    a time (the group's affine and sums in registers), with the s1 / o1 gradient sums over
+  //    this tile's own REs; then written into LDS row t + 1 (symbol t), column j, zero for REs
+  //    outside the slot (the second transposed conv's zero padding), and stored for the
+  //    tile's own REs.
+  auto region_re = [&](int mt, int& t, int& j, bool& live, bool& valid) -> int64_t {
+    const int q = (wave + NW * mt) * 16 + col;
+    live = wave + NW * mt < M1 && q < Q1;
+    return h_at(mt, t, j, valid);
+  };
+  float* row1 = args.part[k] + ((size_t)blockIdx.x * NW + wave) * 3 * C;
 #pragma unroll
-  for (int i = 0; i < EPL; ++i) {
-    sa[i] = 0.f;
-    sb[i] = 0.f;
+  for (int ot = 0; ot < NOT; ++ot) {
+    float s1v[4], o1v[4], sa[4], sb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      s1v[i] = par[P_S1 * C + c0 + 4 * ot + i];
+      o1v[i] = par[P_O1 * C + c0 + 4 * ot + i];
+      sa[i] = 0.f;
+      sb[i] = 0.f;
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT1; ++mt) {
+      int t, j;
+      bool live, valid;
+      region_re(mt, t, j, live, valid);
+      const bool own = live && valid && j >= 1 && j <= TWO;  // this tile's own REs carry the sums
+      const Act* hv = reinterpret_cast<const Act*>(hr[mt]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float h = (float)hv[4 * ot + i];
+        const float dz = h > 0.f ? (float)acc1[mt][ot][i] : 0.f;
+        acc1[mt][ot][i] = valid ? dz * s1v[i] : 0.f;
+        if (own) {
+          sa[i] += dz * (h - o1v[i]);  // divided by s1 once, after the sums
+          sb[i] += dz;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {  // over the 16 lanes that hold the same channels
+      float a = sa[i], b = sb[i];
+      a += __shfl_xor(a, 1);
+      a += __shfl_xor(a, 2);
+      a += __shfl_xor(a, 4);
+      a += __shfl_xor(a, 8);
+      b += __shfl_xor(b, 1);
+      b += __shfl_xor(b, 2);
+      b += __shfl_xor(b, 4);
+      b += __shfl_xor(b, 8);
+      if (col == 0) {
+        row1[c0 + 4 * ot + i] = a / s1v[i];
+        row1[C + c0 + 4 * ot + i] = b;
+      }
+    }
   }
   __syncthreads();  // every wave has read its last dO operand: dc1 may overwrite the tile
-
-  // 3. dc1 = s1 [h > 0] dh into LDS row t + 1 (symbol t), column j; zero for REs outside the
-  //    slot (the second transposed conv's zero padding)
 #pragma unroll
   for (int mt = 0; mt < MT1; ++mt) {
     int t, j;
-    bool valid;
-    const int64_t re = h_at(mt, t, j, valid);
-    const int q = (wave + NW * mt) * 16 + col;
-    if (wave + NW * mt >= M1 || q >= Q1) continue;
-    const bool own = valid && j >= 1 && j <= TWO;  // this tile's own REs carry the sums and the store
-    const Act* hv = reinterpret_cast<const Act*>(hr[mt]);
+    bool live, valid;
+    const int64_t re = region_re(mt, t, j, live, valid);
+    if (!live) continue;
     float v[EPL];
 #pragma unroll
     for (int ot = 0; ot < NOT; ++ot)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int e = 4 * ot + i;
-        const float h = (float)hv[e];
-        const float dz = h > 0.f ? (float)acc1[mt][ot][i] : 0.f;
-        v[e] = valid ? dz * ps[e] : 0.f;
-        if (own) {
-          sa[e] += dz * (h - po[e]);  // divided by s1 once, after the sums
-          sb[e] += dz;
-        }
-      }
-    if (own) store_vals(reinterpret_cast<Act*>(args.dc1[k]) + re * C + c0, v, EPL, 1.f);
+      for (int i = 0; i < 4; ++i) v[4 * ot + i] = acc1[mt][ot][i];
+    if (valid && j >= 1 && j <= TWO) store_vals(reinterpret_cast<Act*>(args.dc1[k]) + re * C + c0, v, EPL, 1.f);
     uint8_t* dst = lds + ((t + 1) * HW + j) * PITCH + c0 * (int)sizeof(Op);
 #pragma unroll
     for (int i = 0; i < EPL; i += 8) {
@@ -169,32 +202,6 @@ __global__ void __launch_bounds__(CONV_NW * 64, 2) bwd_block_kernel(BwdBlockArgs
       *reinterpret_cast<i32x4*>(lds + ((rr ? TROWS - 1 : 0) * HW + j) * PITCH + ch * 16) = i32x4{0, 0, 0, 0};
     }
   }
-  // one row of partial sums per (work-group, wave): reduce over the 16 lanes of each channel group
-  auto write_row = [&](size_t row, const float* div) {
-#pragma unroll
-    for (int i = 0; i < EPL; ++i) {
-      float a = sa[i], b = sb[i];
-      a += __shfl_xor(a, 1);
-      a += __shfl_xor(a, 2);
-      a += __shfl_xor(a, 4);
-      a += __shfl_xor(a, 8);
-      b += __shfl_xor(b, 1);
-      b += __shfl_xor(b, 2);
-      b += __shfl_xor(b, 4);
-      b += __shfl_xor(b, 8);
-      sa[i] = div ? a / div[i] : a;
-      sb[i] = b;
-    }
-    if (col == 0) {
-      float* dst = args.part[k] + row * 3 * C;
-#pragma unroll
-      for (int i = 0; i < EPL; ++i) {
-        dst[c0 + i] = sa[i];
-        dst[C + c0 + i] = sb[i];
-      }
-    }
-  };
-  write_row((size_t)blockIdx.x * NW + wave, ps);
   __syncthreads();
 
   // 4. W1^T on RE q = t * TWO + j of the output region (symbol t, subcarrier f0 + j). The
@@ -236,10 +243,11 @@ __global__ void __launch_bounds__(CONV_NW * 64, 2) bwd_block_kernel(BwdBlockArgs
   }
 #pragma unroll
   for (int d = 1; d < PD; ++d) issue(d);
-  ps = par + P_S0 * C + c0;
-  po = par + P_O0 * C + c0;
+  float ps[EPL], po[EPL], sa[EPL], sb[EPL];
 #pragma unroll
   for (int i = 0; i < EPL; ++i) {
+    ps[i] = par[P_S0 * C + c0 + i];
+    po[i] = par[P_O0 * C + c0 + i];
     sa[i] = 0.f;
     sb[i] = 0.f;
   }
@@ -270,7 +278,28 @@ __global__ void __launch_bounds__(CONV_NW * 64, 2) bwd_block_kernel(BwdBlockArgs
     }
     if (mt + PD < MT2) issue(mt + PD);
   }
-  write_row((size_t)args.rows + (size_t)blockIdx.x * NW + wave, nullptr);
+#pragma unroll
+  for (int i = 0; i < EPL; ++i) {  // over the 16 lanes that hold the same channels
+    float a = sa[i], b = sb[i];
+    a += __shfl_xor(a, 1);
+    a += __shfl_xor(a, 2);
+    a += __shfl_xor(a, 4);
+    a += __shfl_xor(a, 8);
+    b += __shfl_xor(b, 1);
+    b += __shfl_xor(b, 2);
+    b += __shfl_xor(b, 4);
+    b += __shfl_xor(b, 8);
+    sa[i] = a;
+    sb[i] = b;
+  }
+  if (col == 0) {
+    float* row0 = args.part[k] + ((size_t)args.rows + (size_t)blockIdx.x * NW + wave) * 3 * C;
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+      row0[c0 + i] = sa[i];
+      row0[C + c0 + i] = sb[i];
+    }
+  }
 }
 
 template <class A, int C>
