@@ -11,6 +11,7 @@
 
 #include "conet.h"
 #include "conet_model.h"
+#include "conet_bwd_block.h"
 
 namespace conet {
 

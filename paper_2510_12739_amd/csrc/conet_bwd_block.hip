@@ -18,6 +18,7 @@
 // The arithmetic per RE is that of the two-conv path, so dc1 and dx are bit-identical to it;
 // only the grouping of the per-channel partial sums differs (other tiles).
 #include "conet_block_impl.h"
+#include "conet_bwd_block.h"
 
 namespace conet {
 
