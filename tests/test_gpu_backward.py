@@ -110,6 +110,31 @@ def test_bf16_gradient_training_model():
         assert rel_l2(gg[k], rg[k]) <= 0.25
 
 
+@pytest.mark.parametrize("K,L,C,mask,F", [(3, 2, 32, -1, 50), (2, 3, 64, 0b101, 62), (3, 2, 64, 0b10, 34)])
+def test_bf16_gradient_block_input_gradient_in_one_launch(K, L, C, mask, F):
+    """BF16 models at 32 and 64 channels, whose two input-gradient convs per block run as one
+    launch: ragged last tiles (F not a multiple of the 44- or 30-subcarrier tile), partial fusion
+    masks (blocks with and without the plain-ReLU pre-activation of a main branch after a fusion,
+    the input layer's mask at block 0), against the oracle backward at the BF16-emulated forward
+    state with the training-model test's bounds."""
+    mc = ModelConfig(K, L, C, 16, 4)
+    blob = make_blob(mc, seed=60 + K + L, perturb=True)
+    X = features(SimConfig(F=F, n_rx=4, bits_per_symbol=4, seed=12), 2)
+    d = np.random.default_rng(K + 3 * L).standard_normal((2, 14, F, 4))
+    fm = None if mask < 0 else mask
+    say(f"bf16 backward, one-launch input gradient: K={K} L={L} C={C} mask={mask} F={F}")
+    model = _model(mc, blob, "bf16", mask)
+    _, g = _gpu_grad(model, X, d)
+    p = o.unpack(blob, K, L, C, 16, 4)
+    _, cache = o.forward(p, X.astype(np.float64), fuse_mask=fm, quant=o.Quant("bf16"), keep=True)
+    emu = o.pack(o.backward(p, cache, d))
+    gg, eg = _groups(mc, g), _groups(mc, emu)
+    for k in eg:
+        cos = float(gg[k] @ eg[k] / (np.linalg.norm(gg[k]) * np.linalg.norm(eg[k])))
+        say(f"  {k}: cosine {cos:.5f}, rel-L2 {rel_l2(gg[k], eg[k]):.2e}")
+        assert cos >= 0.999 and rel_l2(gg[k], eg[k]) <= 3e-2, (k, cos, rel_l2(gg[k], eg[k]))
+
+
 def test_fp32_gradient_vs_finite_differences_of_gpu_forward():
     """Directional derivative of the GPU FP32 forward vs the GPU backward, along a random direction
     over the parameters that follow the last ReLU (last block's second conv of every branch, its
