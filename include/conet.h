@@ -316,8 +316,9 @@ conet_status conet_mfma_dot(int32_t dtype, int32_t shape, const void* a_host, co
  * Reverse mode of the forward above (hand-written): the head, the per-RE LayerNorm,
  * the product fusion (d O[k] = dP * prod_{j != k} O[j]), and per block the input
  * gradient through both convs (flipped, transposed filters on the same implicit-GEMM
- * kernels) and the filter gradients (a reduction over REs, in two deterministic
- * stages). */
+ * core; in BF16 at C = 32 and 64 both convs of a block run in one launch that keeps the
+ * gradient between them on chip) and the filter gradients (a reduction over REs, in two
+ * deterministic stages). */
 
 /* Gradient of sum(llr * dllr) w.r.t. every parameter, from the last forward with
  * save_for_backward = 1 (dllr: device FP32 [B][T][F][m] of that forward). Overwrites
