@@ -78,11 +78,11 @@ constexpr int block_lds_bytes() {
   return TROWS * (TWO + 4) * lds_pitch<A, C>() + NPAR * C * 4;
 }
 
-// One fused residual block of branch k on tile `bid` (before the XCD remap).
+// One fused residual block of branch k on tile `bid` of the launch's tile list.
 // MAIN: the main branch of a fused block (fusion epilogue); NSUP: the support branches it
 // fuses (K - 1; 0 otherwise). HEAD: this block feeds the LLR head (after the last block).
 template <class A, int C, int TWO, bool MAIN, bool HEAD, int NSUP>
-__device__ __forceinline__ void block_body(const BlockArgs& args, int k, uint8_t* lds) {
+__device__ __forceinline__ void block_body(const BlockArgs& args, int k, uint8_t* lds, int bid) {
   using Acc = typename A::Acc;
   using AccV = typename A::AccV;
   using Act = typename A::Act;
@@ -103,7 +103,6 @@ __device__ __forceinline__ void block_body(const BlockArgs& args, int k, uint8_t
   static_assert((C * (int)sizeof(Op)) % 16 == 0, "h rows are written in 16-byte chunks");
   float* par = reinterpret_cast<float*>(lds + TILE);
 
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const TileDesc td = tile_of(args, bid);
   const int T = args.T;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -316,20 +315,27 @@ __device__ __forceinline__ void block_body(const BlockArgs& args, int k, uint8_t
 template <class A, int C, int TWO, bool MAIN, bool HEAD, int NSUP>
 __global__ void __launch_bounds__(CONV_NW * 64, (block_occ<A, C, TWO>())) block_kernel(BlockArgs args) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[block_lds_bytes<A, C, TWO>()];
-  block_body<A, C, TWO, MAIN, HEAD, NSUP>(args, blockIdx.y + args.k_off, lds);
+  block_body<A, C, TWO, MAIN, HEAD, NSUP>(args, blockIdx.y + args.k_off, lds, xcd_remap(blockIdx.x, gridDim.x));
 }
 
-// The main branch of block l (blockIdx.y == 0, fusion epilogue over the supports' stored
-// outputs of block l) together with the support branches of block l + 1 (blockIdx.y >= 1,
-// which read only the supports' outputs of block l): independent work in one launch. The
-// per-branch argument arrays carry block l for branch 0 and block l + 1 for the others.
+// The main branch of block l (branch 0, fusion epilogue over the supports' stored outputs of
+// block l) together with the support branches of block l + 1 (branches >= 1, which read only
+// the supports' outputs of block l): independent work in one launch. The per-branch argument
+// arrays carry block l for branch 0 and block l + 1 for the others. The grid is (tiles, K);
+// work-groups are taken in dispatch order and mapped so that consecutive ones are the K
+// branches of one tile, contiguous runs of tiles per XCD: every CU holds a mix of the heavier
+// main-branch epilogues and the support branches, and a tile's branches, which read the same
+// support outputs of block l, share an XCD's L2 (1.5 % faster than a branch per grid row).
 template <class A, int C, int TWO, int NSUP>
 __global__ void __launch_bounds__(CONV_NW * 64, (block_occ<A, C, TWO>())) block_pair_kernel(BlockArgs args) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[block_lds_bytes<A, C, TWO>()];
-  if (blockIdx.y == 0)
-    block_body<A, C, TWO, true, false, NSUP>(args, 0, lds);
+  const int K = gridDim.y, n = gridDim.x * K;
+  const int r = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, n);
+  const int tile = r / K, k = r - tile * K;
+  if (k == 0)
+    block_body<A, C, TWO, true, false, NSUP>(args, 0, lds, tile);
   else
-    block_body<A, C, TWO, false, false, 0>(args, blockIdx.y, lds);
+    block_body<A, C, TWO, false, false, 0>(args, k, lds, tile);
 }
 
 template <class A, int C, int TWO, bool HEAD>
